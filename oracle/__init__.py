@@ -1,0 +1,178 @@
+"""CPU oracle for the OHM ray-integration path -- TEST INFRASTRUCTURE ONLY.
+
+Plain, slow, single-threaded reference implementations (C in
+``ohm_oracle.c``, loaded with ctypes) of what the HIP library computes.  Only
+``tests/``, ``__graft_entry__.smoke()`` and the benchmark's CPU-baseline leg
+may import this package; the product path never does, and this package never
+imports the product package.
+
+Functions follow the paper (Stepanas et al., "OHM: GPU Based Occupancy Map
+Generation"): Sec. II-B Eq. (2)-(3) and the clamping paragraph for the
+log-odds update, Sec. III-B for the per-ray line walk with misses along the
+ray and a hit at the sample, Sec. IV-A for max-range truncation.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Optional, Tuple
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_LIB_PATH = os.path.join(_HERE, "libohm_oracle.so")
+_lib = None
+
+# per-ray flag bits (orc_trace)
+F_TRUNCATED = 1
+F_CLIPPED = 2
+F_HAS_HIT = 4
+F_INVALID = 8
+F_ORIGIN_OOB = 16
+
+STATS_FIELDS = ("rays", "invalid", "origin_oob", "truncated", "clipped", "hits", "updates")
+
+
+class OrcParams(ctypes.Structure):
+    _fields_ = [
+        ("voxel_size", ctypes.c_double),
+        ("map_origin", ctypes.c_double * 3),
+        ("key_min", ctypes.c_int32 * 3),
+        ("key_max", ctypes.c_int32 * 3),
+        ("fixed_bits", ctypes.c_int32),
+        ("l_hit", ctypes.c_float),
+        ("l_miss", ctypes.c_float),
+        ("l_min", ctypes.c_float),
+        ("l_max", ctypes.c_float),
+        ("l_init", ctypes.c_float),
+        ("max_range", ctypes.c_double),
+        ("sensor_noise", ctypes.c_double),
+        ("adaptation_rate", ctypes.c_double),
+        ("ndt_min_samples", ctypes.c_int32),
+        ("ndt_clear_below", ctypes.c_double),
+    ]
+
+
+def _load():
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(_LIB_PATH):
+        from . import build as _b
+        _b.build()
+    lib = ctypes.CDLL(_LIB_PATH)
+    P = ctypes.POINTER
+    vp = ctypes.c_void_p
+    lib.orc_trace.restype = ctypes.c_int64
+    lib.orc_trace.argtypes = [P(OrcParams), ctypes.c_int32, vp, vp, vp, vp, vp, vp]
+    lib.orc_integrate_count.restype = ctypes.c_int
+    lib.orc_integrate_count.argtypes = [P(OrcParams), ctypes.c_int32, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp]
+    lib.orc_integrate_envelope.restype = ctypes.c_int
+    lib.orc_integrate_envelope.argtypes = [P(OrcParams), ctypes.c_int32, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp]
+    _lib = lib
+    return lib
+
+
+def make_params(mp) -> OrcParams:
+    """Build the oracle's parameter struct from a ``workloads.MapParams``."""
+    p = OrcParams()
+    p.voxel_size = float(mp.voxel_size)
+    for a in range(3):
+        p.map_origin[a] = float(mp.map_origin[a])
+        p.key_min[a] = int(mp.key_min[a])
+        p.key_max[a] = int(mp.key_max[a])
+    p.fixed_bits = int(mp.fixed_bits)
+    p.l_hit, p.l_miss = float(mp.l_hit), float(mp.l_miss)
+    p.l_min, p.l_max, p.l_init = float(mp.l_min), float(mp.l_max), float(mp.l_init)
+    p.max_range = float(mp.max_range)
+    p.sensor_noise = float(mp.sensor_noise)
+    p.adaptation_rate = float(mp.adaptation_rate)
+    p.ndt_min_samples = int(mp.ndt_min_samples)
+    p.ndt_clear_below = float(mp.ndt_clear_below)
+    return p
+
+
+def _ptr(a: Optional[np.ndarray]):
+    return None if a is None else a.ctypes.data_as(ctypes.c_void_p)
+
+
+def _batch_arrays(batch):
+    o = np.ascontiguousarray(batch.origins, np.float32)
+    s = np.ascontiguousarray(batch.samples, np.float32)
+    off = np.ascontiguousarray(batch.offsets, np.uint32)
+    w = None if batch.weights is None else np.ascontiguousarray(batch.weights, np.float32)
+    return o, s, off, w
+
+
+def trace(mp, batch) -> Tuple[np.ndarray, np.ndarray, np.ndarray, np.ndarray]:
+    """Per-ray update lists.
+
+    Returns ``(counts int64[N], flags int32[N], offsets int64[N+1],
+    updates int32[total, 4])`` where each update row is (kx, ky, kz, kind),
+    kind 0 = miss, 1 = hit, in walk order from the sensor."""
+    lib = _load()
+    p = make_params(mp)
+    o, s, off, _ = _batch_arrays(batch)
+    n = s.shape[0]
+    counts = np.zeros(n, np.int64)
+    flags = np.zeros(n, np.int32)
+    total = lib.orc_trace(ctypes.byref(p), batch.n_scans, _ptr(off), _ptr(o), _ptr(s),
+                          _ptr(counts), _ptr(flags), None)
+    keys = np.zeros((max(total, 1), 4), np.int32)
+    lib.orc_trace(ctypes.byref(p), batch.n_scans, _ptr(off), _ptr(o), _ptr(s), None, None, _ptr(keys))
+    offs = np.zeros(n + 1, np.int64)
+    np.cumsum(counts, out=offs[1:])
+    return counts, flags, offs, keys[:total]
+
+
+def integrate_count(mp, batch, box_min=None, box_dim=None, occ=None):
+    """Count-then-clamp integration into a dense box window (default: the
+    whole map).  Returns ``(occ [dz,dy,dx] float32, last_hit, last_miss,
+    stats dict)``; ``last_*`` are the last scan's per-voxel hit and miss
+    weights (counts without weights)."""
+    lib = _load()
+    p = make_params(mp)
+    if box_min is None:
+        box_min = tuple(mp.key_min)
+        box_dim = tuple(b - a for a, b in zip(mp.key_min, mp.key_max))
+    bmin = np.asarray(box_min, np.int32)
+    bdim = np.asarray(box_dim, np.int32)
+    shape = (int(bdim[2]), int(bdim[1]), int(bdim[0]))
+    if occ is None:
+        occ = np.full(shape, np.float32(mp.l_init), np.float32)
+    else:
+        occ = np.ascontiguousarray(occ, np.float32).copy()
+    last_hit = np.zeros(shape, np.float32)
+    last_miss = np.zeros(shape, np.float32)
+    stats = np.zeros(len(STATS_FIELDS), np.uint64)
+    o, s, off, w = _batch_arrays(batch)
+    rc = lib.orc_integrate_count(ctypes.byref(p), batch.n_scans, _ptr(off), _ptr(o), _ptr(s), _ptr(w),
+                                 _ptr(bmin), _ptr(bdim), _ptr(occ), _ptr(last_hit), _ptr(last_miss),
+                                 _ptr(stats))
+    if rc != 0:
+        raise MemoryError("oracle box allocation failed")
+    return occ, last_hit, last_miss, dict(zip(STATS_FIELDS, (int(v) for v in stats)))
+
+
+def integrate_envelope(mp, batch, box_min=None, box_dim=None, lo=None, hi=None):
+    """Per-update (any-order CAS) semantics: returns ``(lo, hi, n_updates,
+    stats)``, the fp64 bracket of every reachable result per voxel and the
+    number of updates each voxel received."""
+    lib = _load()
+    p = make_params(mp)
+    if box_min is None:
+        box_min = tuple(mp.key_min)
+        box_dim = tuple(b - a for a, b in zip(mp.key_min, mp.key_max))
+    bmin = np.asarray(box_min, np.int32)
+    bdim = np.asarray(box_dim, np.int32)
+    shape = (int(bdim[2]), int(bdim[1]), int(bdim[0]))
+    lo = np.full(shape, float(np.float32(mp.l_init)), np.float64) if lo is None else lo.astype(np.float64).copy()
+    hi = np.full(shape, float(np.float32(mp.l_init)), np.float64) if hi is None else hi.astype(np.float64).copy()
+    nupd = np.zeros(shape, np.uint32)
+    stats = np.zeros(len(STATS_FIELDS), np.uint64)
+    o, s, off, w = _batch_arrays(batch)
+    rc = lib.orc_integrate_envelope(ctypes.byref(p), batch.n_scans, _ptr(off), _ptr(o), _ptr(s), _ptr(w),
+                                    _ptr(bmin), _ptr(bdim), _ptr(lo), _ptr(hi), _ptr(nupd), _ptr(stats))
+    if rc != 0:
+        raise MemoryError("oracle box allocation failed")
+    return lo, hi, nupd, dict(zip(STATS_FIELDS, (int(v) for v in stats)))

@@ -1,0 +1,458 @@
+/*
+ * CPU oracle for OHM lidar ray integration -- TEST INFRASTRUCTURE ONLY.
+ *
+ * A plain, slow, single-threaded reference of what the GPU path computes.
+ * Only the test suite, the package smoke check and the benchmark's CPU
+ * baseline may load this library; the product path never calls it.  It
+ * shares no code, header or table with the HIP library.
+ *
+ * What it follows (paper: "OHM: GPU Based Occupancy Map Generation"):
+ *   - Sec. II-B, Eq. (2)-(3): log-odds occupancy, hit increment positive,
+ *     miss increment negative; the clamping paragraph after Eq. (3).
+ *   - Sec. III-B: one ray from sensor origin to sample, walked voxel by voxel
+ *     with the Amanatides & Woo line walk, one voxel per step; misses along
+ *     the ray, a hit in the sample's voxel.
+ *   - Sec. IV-A: rays truncated to a maximum range.
+ * Readings where the paper is silent are fixed as follows (all are listed
+ * in the design notes):
+ *   - Points are quantised to fixed point, q = rint((p - m) * 2^F / s) in
+ *     IEEE double, key = floor(q / 2^F).  No float enters a key decision
+ *     after that.
+ *   - The walk visits the start voxel and then applies every voxel-boundary
+ *     crossing of the segment in increasing order of its ray parameter t;
+ *     simultaneous crossings go to the lower axis first (x, y, z).  This
+ *     oracle lists all crossings and sorts them by exact 128-bit
+ *     cross-multiplication.
+ *   - The walk stops at the first key outside the map bounds (no hit then).
+ *     Rays whose origin key lies outside the bounds are rejected whole.
+ *   - A ray longer than max_range is shortened to max_range and carries no
+ *     hit: every voxel it visits, the last included, takes a miss.
+ *   - The sample voxel takes the hit and no miss.
+ *   - Count-then-clamp batch semantics: per scan, per voxel,
+ *     l <- clamp((l + H*l_hit) + M*l_miss) in fp32.
+ *   - Per-update semantics (the paper's CAS updates in an unspecified order):
+ *     the set of reachable results is bracketed by applying all hits before
+ *     all misses (lower bound) and all misses before all hits (upper bound).
+ * Parity pins for this file live in tests/test_oracle_*.py.
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+typedef struct {
+  double voxel_size;
+  double map_origin[3];
+  int32_t key_min[3];
+  int32_t key_max[3];
+  int32_t fixed_bits;
+  float l_hit, l_miss, l_min, l_max, l_init;
+  double max_range;
+  double sensor_noise;
+  double adaptation_rate;
+  int32_t ndt_min_samples;
+  double ndt_clear_below;
+} orc_params;
+
+enum { ORC_RAY_OK = 0, ORC_RAY_INVALID = 1, ORC_RAY_ORIGIN_OOB = 2 };
+
+/* per-ray flag bits reported by orc_trace */
+enum {
+  ORC_F_TRUNCATED = 1,
+  ORC_F_CLIPPED = 2,
+  ORC_F_HAS_HIT = 4,
+  ORC_F_INVALID = 8,
+  ORC_F_ORIGIN_OOB = 16
+};
+
+/* stats vector layout */
+enum {
+  ORC_S_RAYS = 0,
+  ORC_S_INVALID,
+  ORC_S_ORIGIN_OOB,
+  ORC_S_TRUNCATED,
+  ORC_S_CLIPPED,
+  ORC_S_HITS,
+  ORC_S_UPDATES,
+  ORC_S_COUNT
+};
+
+typedef struct {
+  int status;
+  int truncated;
+  int64_t q0[3], q1[3];
+  int64_t k0[3], k1[3];
+  double end[3]; /* world endpoint after truncation */
+} orc_ray;
+
+typedef struct {
+  int64_t num; /* crossing parameter t = num / den */
+  int64_t den;
+  int axis;
+} orc_event;
+
+static int64_t floor_div_pow2(int64_t q, int f) {
+  /* floor(q / 2^f) for either sign */
+  int64_t d = (int64_t)1 << f;
+  int64_t r = q / d;
+  if ((q % d) != 0 && q < 0) r -= 1;
+  return r;
+}
+
+/* Quantise one coordinate; returns 0 when the value is not representable. */
+static int quantise(double p, double m, double scale, int64_t* q) {
+  double x = (p - m) * scale;
+  if (!(fabs(x) < 0x1p46)) return 0;
+  *q = (int64_t)rint(x);
+  return 1;
+}
+
+static int in_bounds(const orc_params* p, const int64_t k[3]) {
+  for (int a = 0; a < 3; ++a)
+    if (k[a] < p->key_min[a] || k[a] >= p->key_max[a]) return 0;
+  return 1;
+}
+
+static void prepare_ray(const orc_params* p, const float o[3], const float e[3], orc_ray* r) {
+  memset(r, 0, sizeof(*r));
+  for (int a = 0; a < 3; ++a)
+    if (!isfinite(o[a]) || !isfinite(e[a])) {
+      r->status = ORC_RAY_INVALID;
+      return;
+    }
+  double end[3];
+  for (int a = 0; a < 3; ++a) end[a] = (double)e[a];
+  if (p->max_range > 0.0) {
+    double d[3];
+    for (int a = 0; a < 3; ++a) d[a] = (double)e[a] - (double)o[a];
+    double d2 = d[0] * d[0];
+    d2 = d2 + d[1] * d[1];
+    d2 = d2 + d[2] * d[2];
+    if (d2 > p->max_range * p->max_range) {
+      double f = p->max_range / sqrt(d2);
+      for (int a = 0; a < 3; ++a) end[a] = (double)o[a] + d[a] * f;
+      r->truncated = 1;
+    }
+  }
+  double scale = ldexp(1.0, p->fixed_bits) / p->voxel_size;
+  for (int a = 0; a < 3; ++a) {
+    if (!quantise((double)o[a], p->map_origin[a], scale, &r->q0[a]) ||
+        !quantise(end[a], p->map_origin[a], scale, &r->q1[a])) {
+      r->status = ORC_RAY_INVALID;
+      return;
+    }
+    int64_t span = r->q1[a] - r->q0[a];
+    if (span >= ((int64_t)1 << 31) || -span >= ((int64_t)1 << 31)) {
+      r->status = ORC_RAY_INVALID;
+      return;
+    }
+    r->k0[a] = floor_div_pow2(r->q0[a], p->fixed_bits);
+    r->k1[a] = floor_div_pow2(r->q1[a], p->fixed_bits);
+    r->end[a] = end[a];
+  }
+  if (!in_bounds(p, r->k0)) {
+    r->status = ORC_RAY_ORIGIN_OOB;
+    return;
+  }
+  r->status = ORC_RAY_OK;
+}
+
+static int cmp_event(const void* va, const void* vb) {
+  const orc_event* x = (const orc_event*)va;
+  const orc_event* y = (const orc_event*)vb;
+  __int128 l = (__int128)x->num * (__int128)y->den;
+  __int128 r = (__int128)y->num * (__int128)x->den;
+  if (l < r) return -1;
+  if (l > r) return 1;
+  return (x->axis > y->axis) - (x->axis < y->axis);
+}
+
+typedef struct {
+  orc_event* ev;
+  size_t ev_cap;
+  int32_t* keys;
+  size_t key_cap;
+} orc_scratch;
+
+static void scratch_free(orc_scratch* s) {
+  free(s->ev);
+  free(s->keys);
+  memset(s, 0, sizeof(*s));
+}
+
+/*
+ * Walk one prepared ray.  Writes the in-bounds visited keys (x,y,z triples)
+ * into s->keys and returns how many there are; *clipped is set when the walk
+ * left the map before reaching the end voxel.
+ */
+static int64_t walk_ray(const orc_params* p, const orc_ray* r, orc_scratch* s, int* clipped) {
+  const int F = p->fixed_bits;
+  const int64_t one = (int64_t)1 << F;
+  int64_t sg[3], n[3], b[3], A[3];
+  size_t total = 0;
+  for (int a = 0; a < 3; ++a) {
+    int64_t D = r->q1[a] - r->q0[a];
+    sg[a] = (D > 0) - (D < 0);
+    A[a] = D < 0 ? -D : D;
+    n[a] = r->k1[a] - r->k0[a];
+    if (n[a] < 0) n[a] = -n[a];
+    b[a] = (sg[a] > 0) ? ((r->k0[a] + 1) * one - r->q0[a]) : (r->q0[a] - r->k0[a] * one);
+    total += (size_t)n[a];
+  }
+  if (total > s->ev_cap) {
+    s->ev_cap = total + 64;
+    s->ev = (orc_event*)realloc(s->ev, s->ev_cap * sizeof(orc_event));
+  }
+  if (3 * (total + 1) > s->key_cap) {
+    s->key_cap = 3 * (total + 1) + 192;
+    s->keys = (int32_t*)realloc(s->keys, s->key_cap * sizeof(int32_t));
+  }
+  size_t ne = 0;
+  for (int a = 0; a < 3; ++a)
+    for (int64_t j = 0; j < n[a]; ++j) {
+      s->ev[ne].num = b[a] + j * one;
+      s->ev[ne].den = A[a];
+      s->ev[ne].axis = a;
+      ++ne;
+    }
+  qsort(s->ev, ne, sizeof(orc_event), cmp_event);
+
+  int64_t k[3] = {r->k0[0], r->k0[1], r->k0[2]};
+  int64_t nk = 0;
+  *clipped = 0;
+  for (int a = 0; a < 3; ++a) s->keys[a] = (int32_t)k[a];
+  nk = 1;
+  for (size_t i = 0; i < ne; ++i) {
+    int a = s->ev[i].axis;
+    k[a] += sg[a];
+    if (!in_bounds(p, k)) {
+      *clipped = 1;
+      break;
+    }
+    for (int c = 0; c < 3; ++c) s->keys[3 * nk + c] = (int32_t)k[c];
+    ++nk;
+  }
+  return nk;
+}
+
+static int64_t box_index(const int32_t* key, const int32_t box_min[3], const int32_t box_dim[3]) {
+  int64_t x = (int64_t)key[0] - box_min[0];
+  int64_t y = (int64_t)key[1] - box_min[1];
+  int64_t z = (int64_t)key[2] - box_min[2];
+  if (x < 0 || y < 0 || z < 0 || x >= box_dim[0] || y >= box_dim[1] || z >= box_dim[2]) return -1;
+  return (z * box_dim[1] + y) * box_dim[0] + x;
+}
+
+/* ---------------------------------------------------------------------- */
+/* Per-ray trace                                                           */
+/* ---------------------------------------------------------------------- */
+
+/*
+ * For every ray: its update list (kx, ky, kz, kind) with kind 0 = miss,
+ * 1 = hit, in walk order.  ray_counts[i] receives the number of updates of
+ * ray i and ray_flags[i] its ORC_F_* bits.  keys may be NULL (count pass).
+ * Returns the total number of updates.
+ */
+int64_t orc_trace(const orc_params* p, int32_t n_scans, const uint32_t* offsets, const float* origins,
+                  const float* samples, int64_t* ray_counts, int32_t* ray_flags, int32_t* keys) {
+  orc_scratch s = {0};
+  int64_t written = 0;
+  for (int32_t sc = 0; sc < n_scans; ++sc) {
+    for (uint32_t i = offsets[sc]; i < offsets[sc + 1]; ++i) {
+      orc_ray r;
+      prepare_ray(p, origins + 3 * sc, samples + 3 * (size_t)i, &r);
+      int flags = 0;
+      int64_t nk = 0;
+      if (r.status == ORC_RAY_INVALID) flags |= ORC_F_INVALID;
+      if (r.status == ORC_RAY_ORIGIN_OOB) flags |= ORC_F_ORIGIN_OOB;
+      if (r.status == ORC_RAY_OK) {
+        int clipped = 0;
+        nk = walk_ray(p, &r, &s, &clipped);
+        int has_hit = !r.truncated && !clipped;
+        flags |= (r.truncated ? ORC_F_TRUNCATED : 0) | (clipped ? ORC_F_CLIPPED : 0) | (has_hit ? ORC_F_HAS_HIT : 0);
+        if (keys) {
+          for (int64_t j = 0; j < nk; ++j) {
+            int32_t* out = keys + 4 * (written + j);
+            out[0] = s.keys[3 * j + 0];
+            out[1] = s.keys[3 * j + 1];
+            out[2] = s.keys[3 * j + 2];
+            out[3] = (has_hit && j == nk - 1) ? 1 : 0;
+          }
+        }
+      }
+      if (ray_counts) ray_counts[i] = nk;
+      if (ray_flags) ray_flags[i] = flags;
+      written += nk;
+    }
+  }
+  scratch_free(&s);
+  return written;
+}
+
+/* ---------------------------------------------------------------------- */
+/* Batch integration                                                       */
+/* ---------------------------------------------------------------------- */
+
+static float clampf_(float v, float lo, float hi) {
+  if (v < lo) v = lo;
+  if (v > hi) v = hi;
+  return v;
+}
+
+static double clampd_(double v, double lo, double hi) {
+  if (v < lo) v = lo;
+  if (v > hi) v = hi;
+  return v;
+}
+
+/*
+ * Shared driver: walks every ray of one scan and accumulates, per voxel of the
+ * box window, the hit weight and the miss weight (unit weights when weights is
+ * NULL).  Voxels outside the window are still walked (and counted in stats)
+ * but not recorded.
+ */
+static void accumulate_scan(const orc_params* p, const float* origin, uint32_t r0, uint32_t r1,
+                            const float* samples, const float* weights, const int32_t box_min[3],
+                            const int32_t box_dim[3], double* wh, double* wm, uint64_t* stats,
+                            orc_scratch* s) {
+  for (uint32_t i = r0; i < r1; ++i) {
+    orc_ray r;
+    prepare_ray(p, origin, samples + 3 * (size_t)i, &r);
+    if (stats) stats[ORC_S_RAYS] += 1;
+    if (r.status == ORC_RAY_INVALID) {
+      if (stats) stats[ORC_S_INVALID] += 1;
+      continue;
+    }
+    if (r.status == ORC_RAY_ORIGIN_OOB) {
+      if (stats) stats[ORC_S_ORIGIN_OOB] += 1;
+      continue;
+    }
+    int clipped = 0;
+    int64_t nk = walk_ray(p, &r, s, &clipped);
+    int has_hit = !r.truncated && !clipped;
+    double w = weights ? (double)weights[i] : 1.0;
+    if (stats) {
+      stats[ORC_S_TRUNCATED] += r.truncated ? 1 : 0;
+      stats[ORC_S_CLIPPED] += clipped ? 1 : 0;
+      stats[ORC_S_HITS] += has_hit ? 1 : 0;
+      stats[ORC_S_UPDATES] += (uint64_t)nk;
+    }
+    for (int64_t j = 0; j < nk; ++j) {
+      int64_t v = box_index(s->keys + 3 * j, box_min, box_dim);
+      if (v < 0) continue;
+      if (has_hit && j == nk - 1)
+        wh[v] += w;
+      else
+        wm[v] += w;
+    }
+  }
+}
+
+/*
+ * Count-then-clamp integration of n_scans scans into the box window.
+ *   occ       [dz][dy][dx] fp32, in/out (callers initialise it to l_init)
+ *   last_hit, last_miss   optional outputs: the hit / miss weight of the last
+ *             scan per voxel (integer counts when weights is NULL)
+ *   stats     ORC_S_COUNT uint64 counters (accumulated)
+ * Without weights the update is the exact fp32 expression
+ *   t = (float)H * l_hit; u = (float)M * l_miss; l = clamp((l + t) + u).
+ * With weights the per-voxel sums and the update are evaluated in fp64.
+ */
+int orc_integrate_count(const orc_params* p, int32_t n_scans, const uint32_t* offsets, const float* origins,
+                        const float* samples, const float* weights, const int32_t box_min[3],
+                        const int32_t box_dim[3], float* occ, float* last_hit, float* last_miss,
+                        uint64_t* stats) {
+  size_t nv = (size_t)box_dim[0] * box_dim[1] * box_dim[2];
+  double* wh = (double*)calloc(nv, sizeof(double));
+  double* wm = (double*)calloc(nv, sizeof(double));
+  if (!wh || !wm) {
+    free(wh);
+    free(wm);
+    return -1;
+  }
+  orc_scratch s = {0};
+  for (int32_t sc = 0; sc < n_scans; ++sc) {
+    memset(wh, 0, nv * sizeof(double));
+    memset(wm, 0, nv * sizeof(double));
+    accumulate_scan(p, origins + 3 * sc, offsets[sc], offsets[sc + 1], samples, weights, box_min, box_dim, wh,
+                    wm, stats, &s);
+    for (size_t v = 0; v < nv; ++v) {
+      if (wh[v] == 0.0 && wm[v] == 0.0) continue;
+      if (!weights) {
+        float t = (float)wh[v] * p->l_hit;
+        float u = (float)wm[v] * p->l_miss;
+        float l = occ[v] + t;
+        l = l + u;
+        occ[v] = clampf_(l, p->l_min, p->l_max);
+      } else {
+        double l = ((double)occ[v] + wh[v] * (double)p->l_hit) + wm[v] * (double)p->l_miss;
+        occ[v] = (float)clampd_(l, (double)p->l_min, (double)p->l_max);
+      }
+    }
+  }
+  if (last_hit)
+    for (size_t v = 0; v < nv; ++v) last_hit[v] = (float)wh[v];
+  if (last_miss)
+    for (size_t v = 0; v < nv; ++v) last_miss[v] = (float)wm[v];
+  scratch_free(&s);
+  free(wh);
+  free(wm);
+  return 0;
+}
+
+/*
+ * Per-update semantics: each hit (+w*l_hit) and miss (+w*l_miss) is applied
+ * as l <- clamp(l + delta) in some order.  For each scan, a voxel's result over
+ * all orders lies between applying its hits first then its misses (lo) and its
+ * misses first then its hits (hi); these maps are monotone, so the bracket
+ * carries from scan to scan.  Same-sign runs are summed before clamping (the
+ * same value as clamping after each, since a same-sign run can cross a bound
+ * only once).  Evaluated in fp64.
+ *   lo, hi       [dz][dy][dx] fp64, in/out (initialise both to l_init)
+ *   n_updates    [dz][dy][dx] uint32, in/out: updates applied per voxel
+ */
+int orc_integrate_envelope(const orc_params* p, int32_t n_scans, const uint32_t* offsets, const float* origins,
+                           const float* samples, const float* weights, const int32_t box_min[3],
+                           const int32_t box_dim[3], double* lo, double* hi, uint32_t* n_updates,
+                           uint64_t* stats) {
+  size_t nv = (size_t)box_dim[0] * box_dim[1] * box_dim[2];
+  double* wh = (double*)calloc(nv, sizeof(double));
+  double* wm = (double*)calloc(nv, sizeof(double));
+  if (!wh || !wm) {
+    free(wh);
+    free(wm);
+    return -1;
+  }
+  orc_scratch s = {0};
+  double lmin = (double)p->l_min, lmax = (double)p->l_max;
+  for (int32_t sc = 0; sc < n_scans; ++sc) {
+    memset(wh, 0, nv * sizeof(double));
+    memset(wm, 0, nv * sizeof(double));
+    accumulate_scan(p, origins + 3 * sc, offsets[sc], offsets[sc + 1], samples, weights, box_min, box_dim, wh,
+                    wm, stats, &s);
+    if (n_updates) {
+      /* re-walk with unit weights to count updates */
+      double* ch = (double*)calloc(nv, sizeof(double));
+      double* cm = (double*)calloc(nv, sizeof(double));
+      accumulate_scan(p, origins + 3 * sc, offsets[sc], offsets[sc + 1], samples, NULL, box_min, box_dim, ch, cm,
+                      NULL, &s);
+      for (size_t v = 0; v < nv; ++v) n_updates[v] += (uint32_t)(ch[v] + cm[v]);
+      free(ch);
+      free(cm);
+    }
+    for (size_t v = 0; v < nv; ++v) {
+      if (wh[v] == 0.0 && wm[v] == 0.0) continue;
+      double a = wh[v] * (double)p->l_hit;
+      double b = wm[v] * (double)p->l_miss;
+      lo[v] = clampd_(clampd_(lo[v] + a, lmin, lmax) + b, lmin, lmax);
+      hi[v] = clampd_(clampd_(hi[v] + b, lmin, lmax) + a, lmin, lmax);
+    }
+  }
+  scratch_free(&s);
+  free(wh);
+  free(wm);
+  return 0;
+}
+
+/* Library self-identification for the loaders. */
+int orc_abi_version(void) { return 1; }

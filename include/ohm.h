@@ -1,0 +1,206 @@
+/*
+ * ohm.h -- C ABI of the MI355X lidar ray-integration library.
+ *
+ * The library integrates batches of lidar rays (sensor origin -> sample
+ * point) into a 3D log-odds occupancy map held in GPU memory, following
+ * Stepanas et al., "OHM: GPU Based Occupancy Map Generation":
+ *   - Sec. II-B, Eq. (2)-(3) and the clamping paragraph: each voxel keeps a
+ *     log-odds value l; a ray adds l_miss (< 0) to every voxel it passes
+ *     through and l_hit (> 0) to the voxel holding its sample, and l is kept
+ *     inside [l_min, l_max].
+ *   - Sec. III-A: space is split into dense cubic regions (here 32^3 voxels)
+ *     found through a region table, each region holding contiguous per-voxel
+ *     layers.
+ *   - Sec. III-B: one GPU thread per ray walks the ray voxel by voxel (the
+ *     Amanatides & Woo line walk, one face-adjacent voxel per step) and
+ *     updates global memory atomically.
+ *   - Sec. II-D and III-C: the NDT-OM variant keeps per-voxel sample
+ *     statistics and weights a miss by how well the ray agrees with them;
+ *     misses are applied first, then all of a batch's samples per voxel.
+ *   - Sec. IV-A: rays are truncated to a maximum range.
+ *
+ * Conventions (all entry points):
+ *   - Device pointers (prefix d_) are HIP device pointers owned by the
+ *     caller.  Host pointers (prefix h_) are read before the call returns.
+ *   - `stream` is a hipStream_t passed as void* (NULL = default stream).
+ *     Calls enqueue their kernels on it and return without synchronising,
+ *     except ohm_map_sync_status and the *_size queries.
+ *   - The library allocates no device memory: a map lives in a caller-
+ *     provided workspace whose size ohm_map_workspace_size reports.  The
+ *     handle (host memory) is owned by the library until ohm_map_destroy.
+ *   - Argument errors are returned synchronously and enqueue nothing.
+ *     Data-dependent conditions are not errors: non-finite or unrepresentable
+ *     rays and rays whose origin is outside the map are skipped and counted;
+ *     updates into regions that do not fit in the region pool are dropped,
+ *     counted and flag `sticky_error` (see ohm_map_stats).
+ *   - A handle is not thread-safe; use one stream per map at a time.
+ *   - No C++ exception crosses this interface.
+ *
+ * Frame and exactness.  A voxel key k covers [m + k s, m + (k+1) s) per axis
+ * (m = map_origin, s = voxel_size).  Each point is quantised once to fixed
+ * point, q = rint((p - m) * 2^F / s) in IEEE double (F = fixed_bits); its key
+ * is floor(q / 2^F).  The walk then decides every step with exact 64-bit
+ * integer arithmetic: it visits the start voxel and applies each voxel-face
+ * crossing of the segment in increasing order of its ray parameter,
+ * simultaneous crossings taking the lower axis (x, y, z) first.  A ray is
+ * clipped at the first key outside [key_min, key_max) and then carries no hit.
+ * A ray longer than max_range is shortened to max_range and carries no hit;
+ * every voxel it visits, the last included, takes a miss.
+ */
+#ifndef OHM_H
+#define OHM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct ohm_map_s* ohm_map;
+
+typedef enum {
+  OHM_OK = 0,
+  OHM_E_INVALID_ARG = -1,
+  OHM_E_NO_DEVICE = -2,
+  OHM_E_HIP = -3,
+  OHM_E_WORKSPACE_TOO_SMALL = -4,
+  OHM_E_UNSUPPORTED = -5
+} ohm_status;
+
+/* Batch semantics.
+ * OHM_MODE_PER_UPDATE: every hit and miss is applied as l <- clamp(l + delta)
+ *   with an atomic compare-and-swap, in whatever order the GPU produces
+ *   (the paper's CAS update, Sec. III-B).  Where clamping never engages the
+ *   result equals the plain sum; elsewhere it lies between "all hits first"
+ *   and "all misses first".
+ * OHM_MODE_COUNT_CLAMP: per scan, each voxel's hit and miss weights are
+ *   accumulated and applied once, l <- clamp((l + H*l_hit) + M*l_miss) in
+ *   fp32 without contraction.  Deterministic; bit-exact for unit weights. */
+enum { OHM_MODE_PER_UPDATE = 0, OHM_MODE_COUNT_CLAMP = 1 };
+
+/* Optional layers requested at map creation (bit mask). */
+enum {
+  OHM_LAYER_OCC = 1,     /* always present */
+  OHM_LAYER_NDT = 2,     /* NDT-OM sample count, mean and covariance */
+  OHM_LAYER_ADJOINT = 4  /* last scan at which the clamp was active */
+};
+
+/* Quantities readable with ohm_map_read_dense (output element type). */
+enum {
+  OHM_READ_OCC = 0,        /* float   log-odds (l_init where never touched) */
+  OHM_READ_HITS = 1,       /* float   hit weight of the last scan (count mode) */
+  OHM_READ_MISSES = 2,     /* float   miss weight of the last scan (count mode; NDT: summed miss delta) */
+  OHM_READ_NDT_COUNT = 3,  /* uint32  NDT sample count */
+  OHM_READ_NDT_MEAN = 4,   /* float[3] NDT mean, metres, relative to the voxel centre */
+  OHM_READ_NDT_COV = 5,    /* float[6] NDT covariance xx, xy, xz, yy, yz, zz (m^2) */
+  OHM_READ_CLAMP_SCAN = 6  /* uint32  1 + last scan index whose pre-clamp value left [l_min, l_max], 0 = never */
+};
+
+typedef struct {
+  double voxel_size;       /* metres, > 0 */
+  double map_origin[3];    /* world position of key (0,0,0)'s min corner */
+  int32_t key_min[3];      /* map bounds in keys, half-open [key_min, key_max) */
+  int32_t key_max[3];
+  int32_t region_log2;     /* region edge = 2^region_log2 voxels; must be 5 */
+  int32_t fixed_bits;      /* F in [8, 20]; 16 gives 1/65536-voxel resolution */
+  float l_hit;             /* > 0 (paper's example values: +0.847) */
+  float l_miss;            /* < 0 (-0.405) */
+  float l_min, l_max;      /* clamp bounds, l_min < l_max */
+  float l_init;            /* value of never-touched voxels, in [l_min, l_max] */
+  double max_range;        /* metres; <= 0 disables truncation */
+  int32_t mode;            /* OHM_MODE_* */
+  float sensor_noise;      /* NDT: sensor noise sigma in metres (> 0) */
+  float adaptation_rate;   /* NDT: lambda in [0, 1] */
+  uint32_t ndt_min_samples;/* NDT: samples needed before a voxel's Gaussian is used (>= 2) */
+  float ndt_clear_below;   /* NDT: clear sample data where l < this after a scan's
+                              misses; -INFINITY disables */
+} ohm_params;
+
+typedef struct {
+  uint64_t rays_in;             /* rays submitted */
+  uint64_t rays_invalid;        /* non-finite or unrepresentable (skipped) */
+  uint64_t rays_origin_oob;     /* origin outside the map (skipped) */
+  uint64_t rays_truncated;      /* shortened to max_range */
+  uint64_t rays_clipped;        /* left the map before their sample */
+  uint64_t rays_hit;            /* applied a hit */
+  uint64_t voxel_updates;       /* hits + misses applied (dropped ones excluded) */
+  uint64_t updates_dropped_pool;/* updates lost to a full region pool */
+  uint32_t regions_used;
+  uint32_t region_capacity;
+  int32_t sticky_error;         /* bit 0: region pool exhausted */
+  int32_t reserved;
+} ohm_map_stats;
+
+/* Bytes of device workspace a map needs.  region_capacity is the number of
+ * 32^3 regions the map can hold; layers is an OHM_LAYER_* mask. */
+ohm_status ohm_map_workspace_size(const ohm_params* params, uint32_t region_capacity, uint32_t layers,
+                                  size_t* bytes);
+
+/* Create a map in d_workspace (>= ohm_map_workspace_size bytes, 256-byte
+ * aligned, owned by the caller and untouched by ohm_map_destroy).  Enqueues
+ * the map's initialisation on `stream`. */
+ohm_status ohm_map_create(const ohm_params* params, uint32_t region_capacity, uint32_t layers, void* d_workspace,
+                          size_t workspace_bytes, void* stream, ohm_map* out);
+
+ohm_status ohm_map_destroy(ohm_map map);
+
+/* Return every voxel to l_init (and NDT/adjoint layers to zero), free all
+ * regions and clear the statistics. */
+ohm_status ohm_map_reset(ohm_map map, void* stream);
+
+/* Update parameters that do not change the map layout (l_*, max_range, mode,
+ * NDT parameters).  Frame, bounds, region size and fixed_bits must match. */
+ohm_status ohm_map_set_params(ohm_map map, const ohm_params* params);
+
+/*
+ * Integrate n_scans scans of rays (occupancy update, paper Sec. III-B).
+ *   d_origins       float[n_scans][3]   sensor position of each scan
+ *   d_samples       float[N][3]         sample points, N = h_scan_offsets[n_scans]
+ *   h_scan_offsets  uint32[n_scans+1]   HOST array; scan s owns rays
+ *                                       [h_scan_offsets[s], h_scan_offsets[s+1])
+ *   d_weights       float[N] or NULL    per-ray weight scaling that ray's hit and
+ *                                       miss increments (NULL = 1)
+ * Scans are applied in order; in count mode each scan is one batch with one
+ * clamp per voxel.  In count mode the last scan's hit/miss weights remain
+ * readable (OHM_READ_HITS / OHM_READ_MISSES) until the next call.
+ */
+ohm_status ohm_integrate_rays(ohm_map map, const float* d_origins, const float* d_samples,
+                              const uint32_t* h_scan_offsets, uint32_t n_scans, const float* d_weights,
+                              void* stream);
+
+
+/*
+ * Copy a dense box of one quantity to d_out, laid out [box_dim z][y][x]
+ * (x fastest) with the element type listed for `what`.  Voxels outside the
+ * map or in unallocated regions read as never touched.
+ */
+ohm_status ohm_map_read_dense(ohm_map map, int32_t what, const int32_t h_box_min[3], const int32_t h_box_dim[3],
+                              void* d_out, void* stream);
+
+/*
+ * Debug / verification: the update list of every ray, produced by the same
+ * walk the integration kernels run.  Two passes:
+ *   pass 1 (d_updates == NULL): writes d_ray_counts[i] (uint32, updates of
+ *     ray i) and d_ray_flags[i] (bit 0 truncated, 1 clipped, 2 hit,
+ *     3 invalid, 4 origin outside the map);
+ *   pass 2: with d_ray_offsets[i] (int64, exclusive prefix sum of the counts)
+ *     writes ray i's updates to d_updates[d_ray_offsets[i] + j] as int32
+ *     (kx, ky, kz, kind), kind 0 = miss, 1 = hit, in walk order.
+ * The map is not modified.
+ */
+ohm_status ohm_debug_trace_rays(ohm_map map, const float* d_origins, const float* d_samples,
+                                const uint32_t* h_scan_offsets, uint32_t n_scans, uint32_t* d_ray_counts,
+                                int32_t* d_ray_flags, const int64_t* d_ray_offsets, int32_t* d_updates,
+                                void* stream);
+
+/* Synchronise `stream` and read the map's statistics. */
+ohm_status ohm_map_sync_status(ohm_map map, void* stream, ohm_map_stats* out);
+
+const char* ohm_status_string(ohm_status status);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* OHM_H */

@@ -1,0 +1,14 @@
+"""MI355X (gfx950) lidar ray integration into region-chunked 3D log-odds
+occupancy maps: a HIP C-ABI library (include/ohm.h) with a thin torch binding.
+
+Follows Stepanas et al., "OHM: GPU Based Occupancy Map Generation": exact
+per-ray voxel walks (Sec. III-B) updating log-odds occupancy (Sec. II-B) and
+NDT-OM statistics (Sec. II-D, III-C) in dense 32^3 regions (Sec. III-A).
+"""
+from . import _lib  # noqa: F401
+from ._lib import (  # noqa: F401
+    LAYER_ADJOINT, LAYER_NDT, LAYER_OCC, MODE_COUNT_CLAMP, MODE_PER_UPDATE,
+    READ_CLAMP_SCAN, READ_HITS, READ_MISSES, READ_NDT_COUNT, READ_NDT_COV, READ_NDT_MEAN, READ_OCC,
+    OhmError,
+)
+from .ohm import OhmMap, regions_needed  # noqa: F401

@@ -1,0 +1,155 @@
+"""ctypes declarations of the C ABI in include/ohm.h (argument marshalling only)."""
+from __future__ import annotations
+
+import ctypes
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libohm_hip.so")
+
+OHM_OK = 0
+OHM_E_INVALID_ARG = -1
+OHM_E_NO_DEVICE = -2
+OHM_E_HIP = -3
+OHM_E_WORKSPACE_TOO_SMALL = -4
+OHM_E_UNSUPPORTED = -5
+
+MODE_PER_UPDATE = 0
+MODE_COUNT_CLAMP = 1
+
+LAYER_OCC = 1
+LAYER_NDT = 2
+LAYER_ADJOINT = 4
+
+READ_OCC = 0
+READ_HITS = 1
+READ_MISSES = 2
+READ_NDT_COUNT = 3
+READ_NDT_MEAN = 4
+READ_NDT_COV = 5
+READ_CLAMP_SCAN = 6
+
+# Every symbol include/ohm.h declares.
+EXPORTS = (
+    "ohm_map_workspace_size", "ohm_map_create", "ohm_map_destroy", "ohm_map_reset",
+    "ohm_map_set_params", "ohm_integrate_rays", "ohm_map_read_dense",
+    "ohm_debug_trace_rays", "ohm_map_sync_status", "ohm_status_string",
+)
+
+
+class OhmParams(ctypes.Structure):
+    _fields_ = [
+        ("voxel_size", ctypes.c_double),
+        ("map_origin", ctypes.c_double * 3),
+        ("key_min", ctypes.c_int32 * 3),
+        ("key_max", ctypes.c_int32 * 3),
+        ("region_log2", ctypes.c_int32),
+        ("fixed_bits", ctypes.c_int32),
+        ("l_hit", ctypes.c_float),
+        ("l_miss", ctypes.c_float),
+        ("l_min", ctypes.c_float),
+        ("l_max", ctypes.c_float),
+        ("l_init", ctypes.c_float),
+        ("max_range", ctypes.c_double),
+        ("mode", ctypes.c_int32),
+        ("sensor_noise", ctypes.c_float),
+        ("adaptation_rate", ctypes.c_float),
+        ("ndt_min_samples", ctypes.c_uint32),
+        ("ndt_clear_below", ctypes.c_float),
+    ]
+
+
+class OhmStats(ctypes.Structure):
+    _fields_ = [
+        ("rays_in", ctypes.c_uint64),
+        ("rays_invalid", ctypes.c_uint64),
+        ("rays_origin_oob", ctypes.c_uint64),
+        ("rays_truncated", ctypes.c_uint64),
+        ("rays_clipped", ctypes.c_uint64),
+        ("rays_hit", ctypes.c_uint64),
+        ("voxel_updates", ctypes.c_uint64),
+        ("updates_dropped_pool", ctypes.c_uint64),
+        ("regions_used", ctypes.c_uint32),
+        ("region_capacity", ctypes.c_uint32),
+        ("sticky_error", ctypes.c_int32),
+        ("reserved", ctypes.c_int32),
+    ]
+
+    def as_dict(self):
+        return {name: int(getattr(self, name)) for name, _ in self._fields_ if name != "reserved"}
+
+
+_lib = None
+
+
+class OhmError(RuntimeError):
+    def __init__(self, status: int, where: str):
+        self.status = status
+        super().__init__(f"{where}: {status_string(status)} ({status})")
+
+
+def load() -> ctypes.CDLL:
+    """Load the HIP library; raises when it has not been built (there is no
+    fallback implementation)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"HIP library {LIB_PATH} is missing: build it with "
+                           "`python -m paper_2206_06079_amd.build`")
+    lib = ctypes.CDLL(LIB_PATH)
+    vp, P = ctypes.c_void_p, ctypes.POINTER
+    st = ctypes.c_int
+    sig = {
+        "ohm_map_workspace_size": [P(OhmParams), ctypes.c_uint32, ctypes.c_uint32, P(ctypes.c_size_t)],
+        "ohm_map_create": [P(OhmParams), ctypes.c_uint32, ctypes.c_uint32, vp, ctypes.c_size_t, vp, P(vp)],
+        "ohm_map_destroy": [vp],
+        "ohm_map_reset": [vp, vp],
+        "ohm_map_set_params": [vp, P(OhmParams)],
+        "ohm_integrate_rays": [vp, vp, vp, vp, ctypes.c_uint32, vp, vp],
+        "ohm_map_read_dense": [vp, ctypes.c_int32, vp, vp, vp, vp],
+        "ohm_debug_trace_rays": [vp, vp, vp, vp, ctypes.c_uint32, vp, vp, vp, vp, vp],
+        "ohm_map_sync_status": [vp, vp, P(OhmStats)],
+    }
+    for name, args in sig.items():
+        fn = getattr(lib, name)
+        fn.argtypes = args
+        fn.restype = st
+    lib.ohm_status_string.argtypes = [ctypes.c_int]
+    lib.ohm_status_string.restype = ctypes.c_char_p
+    _lib = lib
+    return lib
+
+
+def status_string(status: int) -> str:
+    try:
+        return load().ohm_status_string(status).decode()
+    except Exception:  # pragma: no cover - library missing
+        return "status %d" % status
+
+
+def check(status: int, where: str) -> None:
+    if status != OHM_OK:
+        raise OhmError(status, where)
+
+
+def make_params(mp) -> OhmParams:
+    """Marshal any object with the ohm_params field names (for instance
+    ``workloads.MapParams``) into the C struct."""
+    p = OhmParams()
+    p.voxel_size = float(mp.voxel_size)
+    for a in range(3):
+        p.map_origin[a] = float(mp.map_origin[a])
+        p.key_min[a] = int(mp.key_min[a])
+        p.key_max[a] = int(mp.key_max[a])
+    p.region_log2 = int(getattr(mp, "region_log2", 5))
+    p.fixed_bits = int(mp.fixed_bits)
+    p.l_hit, p.l_miss = float(mp.l_hit), float(mp.l_miss)
+    p.l_min, p.l_max, p.l_init = float(mp.l_min), float(mp.l_max), float(mp.l_init)
+    p.max_range = float(mp.max_range)
+    p.mode = int(mp.mode)
+    p.sensor_noise = float(mp.sensor_noise)
+    p.adaptation_rate = float(mp.adaptation_rate)
+    p.ndt_min_samples = int(mp.ndt_min_samples)
+    p.ndt_clear_below = float(mp.ndt_clear_below)
+    return p

@@ -1,0 +1,212 @@
+// Device-side definitions shared by the library's kernels: the map view that
+// kernels receive by value, ray preparation (quantisation, truncation,
+// validity) and the exact integer line walk.
+//
+// The walk is the Amanatides & Woo traversal the paper uses (Sec. III-B), in
+// exact arithmetic: along each axis a the segment crosses voxel faces at ray
+// parameters t = (b_a + j 2^S) / A_a (j = 0, 1, ...), with A_a = |q1_a - q0_a|
+// and b_a the fixed-point distance from the start point to the first face.
+// Comparing two axes' next crossings is the sign of N_a A_b - N_b A_a with
+// N_a = b_a + j_a 2^S; the walk keeps the three pairwise differences as int64
+// error terms and moves each by a constant when an axis steps, so every step
+// is three compares and three adds.  Ties go to the lower axis.  With
+// |q1 - q0| < 2^31 per axis all terms stay below 2^63.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace ohm {
+
+constexpr int kRegionLog2 = 5;
+constexpr int kRegionEdge = 1 << kRegionLog2;
+constexpr int kRegionMask = kRegionEdge - 1;
+constexpr int kRegionVoxels = kRegionEdge * kRegionEdge * kRegionEdge;
+constexpr uint32_t kMaxCapacity = 65534;  // keeps (slot * V + v) * 2 + 1 below the lane sentinels
+
+enum : int32_t { kSlotEmpty = -1, kSlotClaimed = -2, kSlotExhausted = -3 };
+enum : int { kRayOk = 0, kRayInvalid = 1, kRayOriginOob = 2 };
+
+// header words at the start of the workspace
+enum : int {
+  kHdrPoolCount = 0,
+  kHdrTouched0 = 1,
+  kHdrTouched1 = 2,
+  kHdrSticky = 3,
+  kHdrWords = 64
+};
+enum : int {
+  kStatRays = 0,
+  kStatInvalid,
+  kStatOriginOob,
+  kStatTruncated,
+  kStatClipped,
+  kStatHits,
+  kStatUpdates,
+  kStatDropped,
+  kStatCount
+};
+
+struct NdtVoxel {       // 40 bytes, one per voxel of an NDT map
+  uint32_t n;           // samples folded in
+  float mean[3];        // metres, relative to the voxel centre
+  float cov[6];         // xx, xy, xz, yy, yz, zz  (population covariance, m^2)
+};
+
+struct DevMap {
+  double origin[3];
+  double scale;       // 2^F / voxel_size
+  double voxel_size;
+  double max_range;   // <= 0: none
+  double max_range2;
+  int32_t kmin[3], kmax[3];
+  int32_t rlo[3], rdim[3];
+  int32_t F;
+  uint32_t capacity;
+  float l_hit, l_miss, l_min, l_max, l_init;
+  float sensor_noise, adaptation_rate, ndt_clear_below;
+  uint32_t ndt_min_samples;
+  uint32_t* hdr;
+  unsigned long long* stats;
+  int32_t* table;
+  uint32_t* stamp;
+  uint32_t* touched;  // [2][capacity]
+  float* occ;         // [capacity][V]
+  float* acc;         // [capacity][V][2]: miss weight, hit weight
+  NdtVoxel* ndt;      // [capacity][V] or null
+  long long* mom;     // NDT per-scan sample moments [capacity][V][kMomWords] or null
+  uint32_t* clampscan;// [capacity][V] or null
+};
+
+// per-voxel sample-moment accumulator of one scan (integers, exact):
+// n, sum u (3), sum u u^T (6), u = fixed-point offset from the voxel centre
+constexpr int kMomWords = 10;
+
+__device__ __forceinline__ uint32_t lane_id() {
+  return __builtin_amdgcn_mbcnt_hi(~0u, __builtin_amdgcn_mbcnt_lo(~0u, 0u));
+}
+
+struct Ray {
+  int64_t q0[3], q1[3];
+  int32_t k0[3], k1[3];
+  bool truncated;
+};
+
+// Quantise one coordinate to fixed point; false when unrepresentable.
+__device__ __forceinline__ bool quantise(double p, double m, double scale, int64_t& q) {
+#pragma clang fp contract(off)
+  double x = (p - m) * scale;
+  if (!(fabs(x) < 0x1p46)) return false;
+  q = (int64_t)rint(x);
+  return true;
+}
+
+// Validate, truncate and quantise one ray (origin o, sample e).
+__device__ __forceinline__ int prepare_ray(const DevMap& m, const float o[3], const float e[3], Ray& r) {
+#pragma clang fp contract(off)
+  r.truncated = false;
+  bool finite = true;
+  for (int a = 0; a < 3; ++a) finite = finite && __builtin_isfinite(o[a]) && __builtin_isfinite(e[a]);
+  if (!finite) return kRayInvalid;
+  double end[3] = {(double)e[0], (double)e[1], (double)e[2]};
+  if (m.max_range > 0.0) {
+    double d0 = (double)e[0] - (double)o[0];
+    double d1 = (double)e[1] - (double)o[1];
+    double d2v = (double)e[2] - (double)o[2];
+    double d2 = d0 * d0;
+    d2 = d2 + d1 * d1;
+    d2 = d2 + d2v * d2v;
+    if (d2 > m.max_range2) {
+      double f = m.max_range / __dsqrt_rn(d2);
+      end[0] = (double)o[0] + d0 * f;
+      end[1] = (double)o[1] + d1 * f;
+      end[2] = (double)o[2] + d2v * f;
+      r.truncated = true;
+    }
+  }
+  for (int a = 0; a < 3; ++a) {
+    if (!quantise((double)o[a], m.origin[a], m.scale, r.q0[a]) || !quantise(end[a], m.origin[a], m.scale, r.q1[a]))
+      return kRayInvalid;
+    int64_t span = r.q1[a] - r.q0[a];
+    if (span >= (int64_t(1) << 31) || -span >= (int64_t(1) << 31)) return kRayInvalid;
+    r.k0[a] = (int32_t)(r.q0[a] >> m.F);
+    r.k1[a] = (int32_t)(r.q1[a] >> m.F);
+  }
+  for (int a = 0; a < 3; ++a)
+    if (r.k0[a] < m.kmin[a] || r.k0[a] >= m.kmax[a]) return kRayOriginOob;
+  return kRayOk;
+}
+
+// Exact walk state at one level of detail: S = F for voxels, F + 5 for regions.
+struct Walk {
+  int64_t dxy, dxz, dyz;   // pairwise error terms
+  int64_t cx, cy, cz;      // A_a << S
+  int32_t rem[3];          // crossings still to apply per axis
+  int32_t total;           // sum of rem
+  int32_t sg[3];           // step direction per axis
+  uint32_t clip;           // bit a: axis a's last counted crossing leaves the bounds
+};
+
+// k0/k1 are the start/end cells at this level; lo/hi the inclusive cell
+// bounds (hi inclusive) at this level.
+__device__ __forceinline__ void walk_init(Walk& w, const int64_t q0[3], const int64_t q1[3], const int32_t k0[3],
+                                          const int32_t k1[3], const int32_t lo[3], const int32_t hi[3], int S) {
+  int64_t b[3], A[3];
+  w.total = 0;
+  w.clip = 0;
+  for (int a = 0; a < 3; ++a) {
+    int64_t D = q1[a] - q0[a];
+    w.sg[a] = (D > 0) - (D < 0);
+    A[a] = D < 0 ? -D : D;
+    int32_t n = k1[a] - k0[a];
+    n = n < 0 ? -n : n;
+    b[a] = (w.sg[a] > 0) ? ((int64_t)(k0[a] + 1) << S) - q0[a] : q0[a] - ((int64_t)k0[a] << S);
+    int32_t inb = (w.sg[a] > 0) ? (hi[a] - k0[a]) : (k0[a] - lo[a]);
+    if (n > inb) {
+      n = inb + 1;
+      w.clip |= 1u << a;
+    }
+    w.rem[a] = n;
+    w.total += n;
+  }
+  w.dxy = b[0] * A[1] - b[1] * A[0];
+  w.dxz = b[0] * A[2] - b[2] * A[0];
+  w.dyz = b[1] * A[2] - b[2] * A[1];
+  w.cx = A[0] << S;
+  w.cy = A[1] << S;
+  w.cz = A[2] << S;
+}
+
+// Pick the axis of the next crossing (ties to the lower axis) and advance the
+// error terms.  Requires w.total > 0.
+__device__ __forceinline__ int walk_step(Walk& w) {
+  bool ex = w.rem[0] > 0, ey = w.rem[1] > 0, ez = w.rem[2] > 0;
+  bool sx = ex && (!ey || w.dxy <= 0) && (!ez || w.dxz <= 0);
+  bool sy = !sx && ey && (!ez || w.dyz <= 0);
+  bool sz = !sx && !sy;
+  w.dxy += sx ? w.cy : (sy ? -w.cx : 0);
+  w.dxz += sx ? w.cz : (sz ? -w.cx : 0);
+  w.dyz += sy ? w.cz : (sz ? -w.cy : 0);
+  w.rem[0] -= sx ? 1 : 0;
+  w.rem[1] -= sy ? 1 : 0;
+  w.rem[2] -= sz ? 1 : 0;
+  w.total -= 1;
+  return sx ? 0 : (sy ? 1 : 2);
+}
+
+__device__ __forceinline__ int32_t region_index(const DevMap& m, int32_t rx, int32_t ry, int32_t rz) {
+  return ((rz - m.rlo[2]) * m.rdim[1] + (ry - m.rlo[1])) * m.rdim[0] + (rx - m.rlo[0]);
+}
+
+__device__ __forceinline__ uint32_t local_index(int32_t kx, int32_t ky, int32_t kz) {
+  return ((uint32_t)(kz & kRegionMask) << (2 * kRegionLog2)) | ((uint32_t)(ky & kRegionMask) << kRegionLog2) |
+         (uint32_t)(kx & kRegionMask);
+}
+
+// Slot of the region holding key k (negative when not allocated).
+__device__ __forceinline__ int32_t lookup_slot(const DevMap& m, int32_t kx, int32_t ky, int32_t kz) {
+  int32_t r = region_index(m, kx >> kRegionLog2, ky >> kRegionLog2, kz >> kRegionLog2);
+  return __hip_atomic_load(m.table + r, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+}  // namespace ohm

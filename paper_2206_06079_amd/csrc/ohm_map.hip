@@ -1,0 +1,812 @@
+// Map storage, region allocation, the ray-walk kernels for occupancy
+// integration and the host side of the C ABI declared in include/ohm.h.
+//
+// Layout (all inside the caller's workspace, see layout()):
+//   header      64 u32 words + 8 u64 statistics
+//   table       int32 per region of the map's bounding box: slot or <0
+//   stamp       u32 per slot: tag of the last count-mode scan that touched it
+//   touched     u32 [2][capacity]: slots touched by the current / previous scan
+//   occ         f32 [capacity][32^3] log-odds
+//   acc         f32 [capacity][32^3][2] per-scan miss / hit weight (count mode)
+//   ndt, mom    NDT-OM voxel statistics and per-scan sample moments (optional)
+//   clampscan   u32 [capacity][32^3] (optional, adjoint)
+//
+// Per scan the library runs (paper Sec. III-B, with the region pass of the
+// CPU-side region walk moved onto the GPU):
+//   prepass   exact walk over 32^3 regions; allocates missing regions and
+//             lists the regions this scan touches
+//   walk      one thread per ray: exact voxel walk, one update per voxel;
+//             equal updates of adjacent lanes are merged before the atomic
+//   finalize  (count mode) one clamp per touched voxel: l = clamp(l + t + u)
+#include <hip/hip_runtime.h>
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+#include <new>
+
+#include "ohm.h"
+#include "ohm_device.h"
+#include "ohm_host.h"
+
+namespace ohm {
+
+// ---------------------------------------------------------------------------
+// small wave helpers
+// ---------------------------------------------------------------------------
+
+// value of lane (l - 1); lane 0 receives `fill`
+__device__ __forceinline__ uint32_t wave_shr1(uint32_t v, uint32_t fill) {
+  return (uint32_t)__builtin_amdgcn_update_dpp((int)fill, (int)v, 0x138, 0xf, 0xf, false);
+}
+
+__device__ __forceinline__ uint32_t wave_sum_u32(uint32_t v) {
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
+  return v;
+}
+
+// Accumulate statistics of a block into the map's counters with one atomic
+// per counter per block.
+__device__ __forceinline__ void flush_stats(const DevMap& m, const uint32_t (&vals)[kStatCount]) {
+  __shared__ uint32_t part[kStatCount];
+  if (threadIdx.x < kStatCount) part[threadIdx.x] = 0;
+  __syncthreads();
+  uint32_t lane = lane_id();
+#pragma unroll
+  for (int c = 0; c < kStatCount; ++c) {
+    uint32_t s = wave_sum_u32(vals[c]);
+    if (lane == 0 && s) atomicAdd(&part[c], s);
+  }
+  __syncthreads();
+  if (threadIdx.x < kStatCount && part[threadIdx.x])
+    atomicAdd(m.stats + threadIdx.x, (unsigned long long)part[threadIdx.x]);
+}
+
+// ---------------------------------------------------------------------------
+// initialisation
+// ---------------------------------------------------------------------------
+
+__global__ void fill_u32_kernel(uint32_t* p, size_t n, uint32_t v) {
+  size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  size_t stride = (size_t)gridDim.x * blockDim.x;
+  for (; i < n; i += stride) p[i] = v;
+}
+
+// ---------------------------------------------------------------------------
+// region pass
+// ---------------------------------------------------------------------------
+
+__device__ __forceinline__ void append_touched(const DevMap& m, uint32_t parity, int32_t slot) {
+  uint32_t idx = atomicAdd(m.hdr + kHdrTouched0 + parity, 1u);
+  m.touched[(size_t)parity * m.capacity + idx] = (uint32_t)slot;
+}
+
+// Make sure region (rx, ry, rz) has a slot; with kTouch also record it once
+// in this scan's touched list.
+template <bool kTouch>
+__device__ void touch_region(const DevMap& m, int32_t rx, int32_t ry, int32_t rz, uint32_t tag, uint32_t parity) {
+  int32_t r = region_index(m, rx, ry, rz);
+  int32_t slot = __hip_atomic_load(m.table + r, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  if (slot == kSlotEmpty) {
+    int32_t old = atomicCAS(m.table + r, kSlotEmpty, kSlotClaimed);
+    if (old == kSlotEmpty) {
+      uint32_t s = atomicAdd(m.hdr + kHdrPoolCount, 1u);
+      if (s < m.capacity) {
+        slot = (int32_t)s;
+        if (kTouch && atomicExch(m.stamp + s, tag) != tag) append_touched(m, parity, slot);
+        __hip_atomic_store(m.table + r, slot, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      } else {
+        __hip_atomic_store(m.table + r, (int32_t)kSlotExhausted, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        atomicOr((int32_t*)(m.hdr + kHdrSticky), 1);
+      }
+      return;
+    }
+    slot = old;
+  }
+  if (kTouch && slot >= 0) {
+    if (__hip_atomic_load(m.stamp + slot, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != tag)
+      if (atomicExch(m.stamp + slot, tag) != tag) append_touched(m, parity, slot);
+  }
+}
+
+template <bool kTouch>
+__global__ __launch_bounds__(256) void prepass_kernel(DevMap m, const float* __restrict__ origins, uint32_t scan,
+                                                      const float* __restrict__ samples, uint32_t r0, uint32_t n,
+                                                      uint32_t tag, uint32_t parity) {
+  uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const float o[3] = {origins[3 * scan + 0], origins[3 * scan + 1], origins[3 * scan + 2]};
+  size_t ray = (size_t)r0 + i;
+  const float e[3] = {samples[3 * ray + 0], samples[3 * ray + 1], samples[3 * ray + 2]};
+  Ray r;
+  if (prepare_ray(m, o, e, r) != kRayOk) return;
+  int32_t k0[3], k1[3], lo[3], hi[3];
+  for (int a = 0; a < 3; ++a) {
+    k0[a] = r.k0[a] >> kRegionLog2;
+    k1[a] = r.k1[a] >> kRegionLog2;
+    lo[a] = m.kmin[a] >> kRegionLog2;
+    hi[a] = (m.kmax[a] - 1) >> kRegionLog2;
+  }
+  Walk w;
+  walk_init(w, r.q0, r.q1, k0, k1, lo, hi, m.F + kRegionLog2);
+  int32_t rx = k0[0], ry = k0[1], rz = k0[2];
+  for (;;) {
+    touch_region<kTouch>(m, rx, ry, rz, tag, parity);
+    if (w.total == 0) break;
+    int a = walk_step(w);
+    int32_t ra = a == 0 ? w.rem[0] : (a == 1 ? w.rem[1] : w.rem[2]);
+    if (ra == 0 && ((w.clip >> a) & 1u)) break;
+    rx += a == 0 ? w.sg[0] : 0;
+    ry += a == 1 ? w.sg[1] : 0;
+    rz += a == 2 ? w.sg[2] : 0;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// voxel walk
+// ---------------------------------------------------------------------------
+
+enum : int { kSinkCount = 0, kSinkCas = 1, kSinkTraceCount = 2, kSinkTraceWrite = 3 };
+
+// Per-update clamp-add by compare-and-swap, retried until it lands.
+__device__ __forceinline__ void cas_clamp_add(float* p, float delta, float lo, float hi) {
+  uint32_t* u = reinterpret_cast<uint32_t*>(p);
+  uint32_t old = __hip_atomic_load(u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  for (;;) {
+    float nv = fminf(fmaxf(__uint_as_float(old) + delta, lo), hi);
+    uint32_t prev = atomicCAS(u, old, __float_as_uint(nv));
+    if (prev == old) break;
+    old = prev;
+  }
+}
+
+template <int kSink, bool kWeighted>
+__global__ __launch_bounds__(256) void walk_kernel(DevMap m, const float* __restrict__ origins, uint32_t scan,
+                                                   const float* __restrict__ samples,
+                                                   const float* __restrict__ weights, uint32_t r0, uint32_t n,
+                                                   uint32_t* __restrict__ ray_counts,
+                                                   int32_t* __restrict__ ray_flags,
+                                                   const int64_t* __restrict__ ray_offsets,
+                                                   int32_t* __restrict__ updates) {
+  const uint32_t lane = lane_id();
+  const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+  const bool inrange = i < n;
+  const size_t ray = (size_t)r0 + i;
+  const float o[3] = {origins[3 * scan + 0], origins[3 * scan + 1], origins[3 * scan + 2]};
+  float e[3] = {0.f, 0.f, 0.f};
+  if (inrange) {
+    e[0] = samples[3 * ray + 0];
+    e[1] = samples[3 * ray + 1];
+    e[2] = samples[3 * ray + 2];
+  }
+  Ray r;
+  int st = inrange ? prepare_ray(m, o, e, r) : kRayInvalid;
+  bool alive = inrange && st == kRayOk;
+  const float wt = (kWeighted && inrange) ? weights[ray] : 1.0f;
+
+  Walk w;
+  int32_t kx = 0, ky = 0, kz = 0;
+  int32_t slot = -1;
+  uint32_t lidx = 0;
+  if (alive) {
+    int32_t hi[3] = {m.kmax[0] - 1, m.kmax[1] - 1, m.kmax[2] - 1};
+    walk_init(w, r.q0, r.q1, r.k0, r.k1, m.kmin, hi, m.F);
+    kx = r.k0[0];
+    ky = r.k0[1];
+    kz = r.k0[2];
+    if (kSink == kSinkCount || kSink == kSinkCas) slot = lookup_slot(m, kx, ky, kz);
+    lidx = local_index(kx, ky, kz);
+  }
+  uint32_t n_upd = 0, n_drop = 0, n_hit = 0;
+  bool clipped = false;
+  int64_t out_base = 0;
+  if (kSink == kSinkTraceWrite && inrange) out_base = ray_offsets[ray];
+
+  while (__ballot(alive)) {
+    const bool last = alive && w.total == 0;
+    const bool is_hit = last && !r.truncated;
+    if (kSink == kSinkCount || kSink == kSinkCas) {
+      const bool has = alive && slot >= 0;
+      const uint32_t id = has ? (((uint32_t)slot * (uint32_t)kRegionVoxels + lidx) << 1) | (is_hit ? 1u : 0u)
+                              : (0xFFFFFFFFu - lane);
+      const uint32_t prev = wave_shr1(id, ~id);
+      const bool head = (lane == 0) || (prev != id);
+      const unsigned long long heads = __ballot(head);
+      const unsigned long long above = lane == 63 ? 0ull : (heads >> (lane + 1));
+      if (!kWeighted) {
+        if (has && head) {
+          const uint32_t run = above ? (uint32_t)__builtin_ctzll(above) + 1u : 64u - lane;
+          if (kSink == kSinkCount) {
+            unsafeAtomicAdd(m.acc + id, (float)run);
+          } else {
+            const float delta = (float)run * (is_hit ? m.l_hit : m.l_miss);
+            cas_clamp_add(m.occ + (id >> 1), delta, m.l_min, m.l_max);
+          }
+        }
+      } else {
+        // segmented inclusive sum of the weights over each run of equal ids;
+        // the run's last lane holds the total
+        float v = has ? wt : 0.f;
+        uint32_t f = head ? 1u : 0u;
+#pragma unroll
+        for (int off = 1; off < 64; off <<= 1) {
+          float vu = __shfl_up(v, off);
+          uint32_t fu = __shfl_up(f, off);
+          if (lane >= (uint32_t)off && !f) {
+            v += vu;
+            f |= fu;
+          }
+        }
+        const bool tail = (lane == 63) || (above & 1ull);
+        if (has && tail) {
+          if (kSink == kSinkCount) {
+            unsafeAtomicAdd(m.acc + id, v);
+          } else {
+            cas_clamp_add(m.occ + (id >> 1), v * (is_hit ? m.l_hit : m.l_miss), m.l_min, m.l_max);
+          }
+        }
+      }
+      if (alive) {
+        if (slot >= 0) {
+          ++n_upd;
+          n_hit += is_hit ? 1u : 0u;
+        } else {
+          ++n_drop;
+        }
+      }
+    } else {
+      if (alive) {
+        if (kSink == kSinkTraceWrite) {
+          int32_t* out = updates + 4 * (out_base + n_upd);
+          out[0] = kx;
+          out[1] = ky;
+          out[2] = kz;
+          out[3] = is_hit ? 1 : 0;
+        }
+        ++n_upd;
+        n_hit += is_hit ? 1u : 0u;
+      }
+    }
+    // advance
+    if (alive) {
+      if (last) {
+        alive = false;
+      } else {
+        const int a = walk_step(w);
+        const int32_t ra = a == 0 ? w.rem[0] : (a == 1 ? w.rem[1] : w.rem[2]);
+        if (ra == 0 && ((w.clip >> a) & 1u)) {
+          alive = false;
+          clipped = true;
+        } else {
+          const int32_t sg = a == 0 ? w.sg[0] : (a == 1 ? w.sg[1] : w.sg[2]);
+          kx += a == 0 ? sg : 0;
+          ky += a == 1 ? sg : 0;
+          kz += a == 2 ? sg : 0;
+          const int32_t kn = a == 0 ? kx : (a == 1 ? ky : kz);
+          const bool wrap = (kn & kRegionMask) == (sg > 0 ? 0 : kRegionMask);
+          if (wrap) {
+            if (kSink == kSinkCount || kSink == kSinkCas) slot = lookup_slot(m, kx, ky, kz);
+            lidx = local_index(kx, ky, kz);
+          } else {
+            lidx += (uint32_t)(a == 0 ? sg : (a == 1 ? sg * kRegionEdge : sg * kRegionEdge * kRegionEdge));
+          }
+        }
+      }
+    }
+  }
+
+  if (kSink == kSinkTraceCount || kSink == kSinkTraceWrite) {
+    if (kSink == kSinkTraceCount && inrange) {
+      int32_t flags = 0;
+      if (st == kRayInvalid) flags |= 8;
+      if (st == kRayOriginOob) flags |= 16;
+      if (st == kRayOk) {
+        flags |= r.truncated ? 1 : 0;
+        flags |= clipped ? 2 : 0;
+        flags |= n_hit ? 4 : 0;
+      }
+      ray_counts[ray] = n_upd;
+      ray_flags[ray] = flags;
+    }
+    return;
+  }
+  uint32_t vals[kStatCount];
+  vals[kStatRays] = inrange ? 1u : 0u;
+  vals[kStatInvalid] = (inrange && st == kRayInvalid) ? 1u : 0u;
+  vals[kStatOriginOob] = (inrange && st == kRayOriginOob) ? 1u : 0u;
+  vals[kStatTruncated] = (st == kRayOk && inrange && r.truncated) ? 1u : 0u;
+  vals[kStatClipped] = clipped ? 1u : 0u;
+  vals[kStatHits] = n_hit;
+  vals[kStatUpdates] = n_upd;
+  vals[kStatDropped] = n_drop;
+  flush_stats(m, vals);
+}
+
+// ---------------------------------------------------------------------------
+// per-scan finalize (count mode)
+// ---------------------------------------------------------------------------
+
+constexpr int kFinalChunk = 4096;  // voxels per work unit
+constexpr int kFinalUnits = kRegionVoxels / kFinalChunk;
+
+// Applies l <- clamp((l + H l_hit) + M') to every voxel of the touched
+// regions, where M' = M l_miss (plain) or the summed NDT miss delta.  With
+// `apply` = 0 only clears the accumulators.  Clears the accumulators when
+// `clear`, and resets the other parity's touched counter for the next scan.
+__global__ __launch_bounds__(256) void finalize_kernel(DevMap m, uint32_t parity, int apply, int clear,
+                                                       int miss_is_delta, uint32_t scan_tag) {
+  const uint32_t count = __hip_atomic_load(m.hdr + kHdrTouched0 + parity, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  const uint32_t units = count * kFinalUnits;
+  for (uint32_t u = blockIdx.x; u < units; u += gridDim.x) {
+    const uint32_t slot = m.touched[(size_t)parity * m.capacity + u / kFinalUnits];
+    const size_t base = (size_t)slot * kRegionVoxels + (size_t)(u % kFinalUnits) * kFinalChunk;
+    for (int v = threadIdx.x * 2; v < kFinalChunk; v += blockDim.x * 2) {
+      float4* ap = reinterpret_cast<float4*>(m.acc + 2 * (base + v));
+      float4 a = *ap;  // (miss0, hit0, miss1, hit1)
+      if (a.x == 0.f && a.y == 0.f && a.z == 0.f && a.w == 0.f) continue;
+      if (apply) {
+        float2* lp = reinterpret_cast<float2*>(m.occ + base + v);
+        float2 l = *lp;
+        float lv[2] = {l.x, l.y};
+        const float mw[2] = {a.x, a.z};
+        const float hw[2] = {a.y, a.w};
+#pragma unroll
+        for (int j = 0; j < 2; ++j) {
+          if (mw[j] == 0.f && hw[j] == 0.f) continue;
+          const float t = __fmul_rn(hw[j], m.l_hit);
+          const float uu = miss_is_delta ? mw[j] : __fmul_rn(mw[j], m.l_miss);
+          float s = __fadd_rn(lv[j], t);
+          s = __fadd_rn(s, uu);
+          if (m.clampscan && (s < m.l_min || s > m.l_max)) m.clampscan[base + v + j] = scan_tag;
+          lv[j] = fminf(fmaxf(s, m.l_min), m.l_max);
+        }
+        *lp = make_float2(lv[0], lv[1]);
+      }
+      if (clear) *ap = make_float4(0.f, 0.f, 0.f, 0.f);
+    }
+  }
+  if (blockIdx.x == 0 && threadIdx.x == 0)
+    __hip_atomic_store(m.hdr + kHdrTouched0 + (parity ^ 1u), 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// ---------------------------------------------------------------------------
+// dense read-back
+// ---------------------------------------------------------------------------
+
+__global__ __launch_bounds__(256) void read_dense_kernel(DevMap m, int what, int32_t bx, int32_t by, int32_t bz,
+                                                         int32_t dx, int32_t dy, int32_t dz, void* out) {
+  const size_t nvox = (size_t)dx * dy * dz;
+  size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= nvox) return;
+  const int32_t x = bx + (int32_t)(i % dx);
+  const int32_t y = by + (int32_t)((i / dx) % dy);
+  const int32_t z = bz + (int32_t)(i / ((size_t)dx * dy));
+  int32_t slot = -1;
+  if (x >= m.kmin[0] && x < m.kmax[0] && y >= m.kmin[1] && y < m.kmax[1] && z >= m.kmin[2] && z < m.kmax[2])
+    slot = lookup_slot(m, x, y, z);
+  const size_t v = slot >= 0 ? (size_t)slot * kRegionVoxels + local_index(x, y, z) : 0;
+  switch (what) {
+    case OHM_READ_OCC:
+      static_cast<float*>(out)[i] = slot >= 0 ? m.occ[v] : m.l_init;
+      break;
+    case OHM_READ_HITS:
+      static_cast<float*>(out)[i] = slot >= 0 ? m.acc[2 * v + 1] : 0.f;
+      break;
+    case OHM_READ_MISSES:
+      static_cast<float*>(out)[i] = slot >= 0 ? m.acc[2 * v] : 0.f;
+      break;
+    case OHM_READ_NDT_COUNT:
+      static_cast<uint32_t*>(out)[i] = slot >= 0 ? m.ndt[v].n : 0u;
+      break;
+    case OHM_READ_NDT_MEAN:
+      for (int c = 0; c < 3; ++c) static_cast<float*>(out)[3 * i + c] = slot >= 0 ? m.ndt[v].mean[c] : 0.f;
+      break;
+    case OHM_READ_NDT_COV:
+      for (int c = 0; c < 6; ++c) static_cast<float*>(out)[6 * i + c] = slot >= 0 ? m.ndt[v].cov[c] : 0.f;
+      break;
+    case OHM_READ_CLAMP_SCAN:
+      static_cast<uint32_t*>(out)[i] = slot >= 0 ? m.clampscan[v] : 0u;
+      break;
+    default:
+      break;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// host side
+// ---------------------------------------------------------------------------
+
+namespace {
+
+constexpr size_t kAlign = 256;
+inline size_t align_up(size_t v) { return (v + kAlign - 1) & ~(kAlign - 1); }
+
+struct Layout {
+  size_t hdr, stats, table, stamp, touched, occ, acc, ndt, mom, clampscan, total;
+  int32_t rlo[3], rdim[3];
+  size_t regions;
+};
+
+ohm_status validate_params(const ohm_params* p) {
+  if (!p) return OHM_E_INVALID_ARG;
+  if (!(p->voxel_size > 0.0) || !isfinite(p->voxel_size)) return OHM_E_INVALID_ARG;
+  if (p->region_log2 != kRegionLog2) return OHM_E_UNSUPPORTED;
+  if (p->fixed_bits < 8 || p->fixed_bits > 20) return OHM_E_INVALID_ARG;
+  const int64_t kmax_abs = int64_t(1) << (45 - p->fixed_bits);
+  for (int a = 0; a < 3; ++a) {
+    if (!isfinite(p->map_origin[a])) return OHM_E_INVALID_ARG;
+    if (p->key_min[a] >= p->key_max[a]) return OHM_E_INVALID_ARG;
+    if (p->key_min[a] < -kmax_abs || p->key_max[a] > kmax_abs) return OHM_E_INVALID_ARG;
+  }
+  if (!(p->l_hit >= 0.f) || !(p->l_miss <= 0.f) || !isfinite(p->l_hit) || !isfinite(p->l_miss))
+    return OHM_E_INVALID_ARG;
+  if (!(p->l_min < p->l_max) || !isfinite(p->l_min) || !isfinite(p->l_max)) return OHM_E_INVALID_ARG;
+  if (!(p->l_init >= p->l_min && p->l_init <= p->l_max)) return OHM_E_INVALID_ARG;
+  if (isnan(p->max_range)) return OHM_E_INVALID_ARG;
+  if (p->mode != OHM_MODE_PER_UPDATE && p->mode != OHM_MODE_COUNT_CLAMP) return OHM_E_INVALID_ARG;
+  if (!(p->sensor_noise > 0.f) || !isfinite(p->sensor_noise)) return OHM_E_INVALID_ARG;
+  if (!(p->adaptation_rate >= 0.f && p->adaptation_rate <= 1.f)) return OHM_E_INVALID_ARG;
+  if (p->ndt_min_samples < 2) return OHM_E_INVALID_ARG;
+  if (isnan(p->ndt_clear_below)) return OHM_E_INVALID_ARG;
+  return OHM_OK;
+}
+
+ohm_status compute_layout(const ohm_params* p, uint32_t capacity, uint32_t layers, Layout* L) {
+  ohm_status s = validate_params(p);
+  if (s != OHM_OK) return s;
+  if (capacity == 0 || capacity > kMaxCapacity) return OHM_E_INVALID_ARG;
+  if (layers & ~(uint32_t)(OHM_LAYER_OCC | OHM_LAYER_NDT | OHM_LAYER_ADJOINT)) return OHM_E_INVALID_ARG;
+  size_t regions = 1;
+  for (int a = 0; a < 3; ++a) {
+    L->rlo[a] = p->key_min[a] >> kRegionLog2;
+    int32_t rhi = (p->key_max[a] - 1) >> kRegionLog2;
+    L->rdim[a] = rhi - L->rlo[a] + 1;
+    regions *= (size_t)L->rdim[a];
+  }
+  if (regions > (size_t(1) << 28)) return OHM_E_UNSUPPORTED;
+  L->regions = regions;
+  const size_t V = kRegionVoxels;
+  size_t off = 0;
+  L->hdr = off;
+  off = align_up(off + kHdrWords * sizeof(uint32_t));
+  L->stats = off;
+  off = align_up(off + 16 * sizeof(unsigned long long));
+  L->table = off;
+  off = align_up(off + regions * sizeof(int32_t));
+  L->stamp = off;
+  off = align_up(off + (size_t)capacity * sizeof(uint32_t));
+  L->touched = off;
+  off = align_up(off + 2 * (size_t)capacity * sizeof(uint32_t));
+  L->occ = off;
+  off = align_up(off + (size_t)capacity * V * sizeof(float));
+  L->acc = off;
+  off = align_up(off + (size_t)capacity * V * 2 * sizeof(float));
+  L->ndt = L->mom = L->clampscan = 0;
+  if (layers & OHM_LAYER_NDT) {
+    L->ndt = off;
+    off = align_up(off + (size_t)capacity * V * sizeof(NdtVoxel));
+    L->mom = off;
+    off = align_up(off + (size_t)capacity * V * kMomWords * sizeof(long long));
+  }
+  if (layers & OHM_LAYER_ADJOINT) {
+    L->clampscan = off;
+    off = align_up(off + (size_t)capacity * V * sizeof(uint32_t));
+  }
+  L->total = off;
+  return OHM_OK;
+}
+
+void fill_params(DevMap& dm, const ohm_params* p) {
+  for (int a = 0; a < 3; ++a) {
+    dm.origin[a] = p->map_origin[a];
+    dm.kmin[a] = p->key_min[a];
+    dm.kmax[a] = p->key_max[a];
+  }
+  dm.scale = ldexp(1.0, p->fixed_bits) / p->voxel_size;
+  dm.voxel_size = p->voxel_size;
+  dm.max_range = p->max_range;
+  dm.max_range2 = p->max_range * p->max_range;
+  dm.F = p->fixed_bits;
+  dm.l_hit = p->l_hit;
+  dm.l_miss = p->l_miss;
+  dm.l_min = p->l_min;
+  dm.l_max = p->l_max;
+  dm.l_init = p->l_init;
+  dm.sensor_noise = p->sensor_noise;
+  dm.adaptation_rate = p->adaptation_rate;
+  dm.ndt_min_samples = p->ndt_min_samples;
+  dm.ndt_clear_below = p->ndt_clear_below;
+}
+
+inline hipStream_t as_stream(void* s) { return reinterpret_cast<hipStream_t>(s); }
+
+ohm_status last_hip_status() {
+  hipError_t e = hipGetLastError();
+  return e == hipSuccess ? OHM_OK : OHM_E_HIP;
+}
+
+void launch_fill(void* p, size_t bytes, uint32_t v, hipStream_t st) {
+  size_t n = bytes / sizeof(uint32_t);
+  if (n == 0) return;
+  size_t blocks = (n + 255) / 256;
+  if (blocks > 8192) blocks = 8192;
+  hipLaunchKernelGGL(fill_u32_kernel, dim3((unsigned)blocks), dim3(256), 0, st, static_cast<uint32_t*>(p), n, v);
+}
+
+}  // namespace
+
+ohm_status map_initialise(ohm_map_s* map, hipStream_t st) {
+  const DevMap& m = map->dm;
+  const size_t V = kRegionVoxels;
+  launch_fill(m.hdr, kHdrWords * sizeof(uint32_t), 0u, st);
+  launch_fill(m.stats, 16 * sizeof(unsigned long long), 0u, st);
+  launch_fill(m.table, map->regions * sizeof(int32_t), (uint32_t)kSlotEmpty, st);
+  launch_fill(m.stamp, (size_t)m.capacity * sizeof(uint32_t), 0u, st);
+  uint32_t init_bits;
+  memcpy(&init_bits, &m.l_init, sizeof(init_bits));
+  launch_fill(m.occ, (size_t)m.capacity * V * sizeof(float), init_bits, st);
+  launch_fill(m.acc, (size_t)m.capacity * V * 2 * sizeof(float), 0u, st);
+  if (m.ndt) {
+    launch_fill(m.ndt, (size_t)m.capacity * V * sizeof(NdtVoxel), 0u, st);
+    launch_fill(m.mom, (size_t)m.capacity * V * kMomWords * sizeof(long long), 0u, st);
+  }
+  if (m.clampscan) launch_fill(m.clampscan, (size_t)m.capacity * V * sizeof(uint32_t), 0u, st);
+  map->count_batches = 0;
+  map->acc_dirty = false;
+  map->scans_done = 0;
+  return last_hip_status();
+}
+
+ohm_status check_scans(ohm_map map, const float* d_origins, const float* d_samples, const uint32_t* h_offsets,
+                       uint32_t n_scans) {
+  if (!map) return OHM_E_INVALID_ARG;
+  if (n_scans == 0) return OHM_OK;
+  if (!h_offsets || !d_origins) return OHM_E_INVALID_ARG;
+  for (uint32_t s = 0; s < n_scans; ++s)
+    if (h_offsets[s + 1] < h_offsets[s]) return OHM_E_INVALID_ARG;
+  if (h_offsets[n_scans] > h_offsets[0] && !d_samples) return OHM_E_INVALID_ARG;
+  return OHM_OK;
+}
+
+// Lazy clear of the previous count-mode scan's accumulators.
+void clear_pending(ohm_map_s* map, hipStream_t st) {
+  if (!map->acc_dirty) return;
+  hipLaunchKernelGGL(finalize_kernel, dim3(kFinalizeBlocks), dim3(256), 0, st, map->dm, map->last_parity, 0, 1, 0,
+                     0u);
+  map->acc_dirty = false;
+}
+
+void launch_prepass(ohm_map_s* map, const float* d_origins, uint32_t scan, const float* d_samples, uint32_t r0,
+                    uint32_t n, bool touch, uint32_t tag, uint32_t parity, hipStream_t st) {
+  dim3 grid((n + 255) / 256);
+  if (touch)
+    hipLaunchKernelGGL(prepass_kernel<true>, grid, dim3(256), 0, st, map->dm, d_origins, scan, d_samples, r0, n, tag,
+                       parity);
+  else
+    hipLaunchKernelGGL(prepass_kernel<false>, grid, dim3(256), 0, st, map->dm, d_origins, scan, d_samples, r0, n,
+                       tag, parity);
+}
+
+}  // namespace ohm
+
+using namespace ohm;
+
+extern "C" {
+
+const char* ohm_status_string(ohm_status s) {
+  switch (s) {
+    case OHM_OK: return "ok";
+    case OHM_E_INVALID_ARG: return "invalid argument";
+    case OHM_E_NO_DEVICE: return "no HIP device";
+    case OHM_E_HIP: return "HIP runtime error";
+    case OHM_E_WORKSPACE_TOO_SMALL: return "workspace too small";
+    case OHM_E_UNSUPPORTED: return "unsupported parameter";
+  }
+  return "unknown status";
+}
+
+ohm_status ohm_map_workspace_size(const ohm_params* params, uint32_t region_capacity, uint32_t layers,
+                                  size_t* bytes) {
+  if (!bytes) return OHM_E_INVALID_ARG;
+  Layout L;
+  ohm_status s = compute_layout(params, region_capacity, layers, &L);
+  if (s != OHM_OK) return s;
+  *bytes = L.total;
+  return OHM_OK;
+}
+
+ohm_status ohm_map_create(const ohm_params* params, uint32_t region_capacity, uint32_t layers, void* d_workspace,
+                          size_t workspace_bytes, void* stream, ohm_map* out) {
+  if (!out) return OHM_E_INVALID_ARG;
+  *out = nullptr;
+  Layout L;
+  ohm_status s = compute_layout(params, region_capacity, layers, &L);
+  if (s != OHM_OK) return s;
+  if (!d_workspace || ((uintptr_t)d_workspace & (kAlign - 1))) return OHM_E_INVALID_ARG;
+  if (workspace_bytes < L.total) return OHM_E_WORKSPACE_TOO_SMALL;
+  int ndev = 0;
+  if (hipGetDeviceCount(&ndev) != hipSuccess || ndev == 0) {
+    (void)hipGetLastError();
+    return OHM_E_NO_DEVICE;
+  }
+  ohm_map_s* map = new (std::nothrow) ohm_map_s();
+  if (!map) return OHM_E_INVALID_ARG;
+  map->params = *params;
+  map->layers = layers | OHM_LAYER_OCC;
+  map->regions = L.regions;
+  map->workspace = d_workspace;
+  map->workspace_bytes = workspace_bytes;
+  if (hipGetDevice(&map->device) != hipSuccess) map->device = 0;
+  DevMap& dm = map->dm;
+  memset(&dm, 0, sizeof(dm));
+  fill_params(dm, params);
+  for (int a = 0; a < 3; ++a) {
+    dm.rlo[a] = L.rlo[a];
+    dm.rdim[a] = L.rdim[a];
+  }
+  dm.capacity = region_capacity;
+  char* base = static_cast<char*>(d_workspace);
+  dm.hdr = reinterpret_cast<uint32_t*>(base + L.hdr);
+  dm.stats = reinterpret_cast<unsigned long long*>(base + L.stats);
+  dm.table = reinterpret_cast<int32_t*>(base + L.table);
+  dm.stamp = reinterpret_cast<uint32_t*>(base + L.stamp);
+  dm.touched = reinterpret_cast<uint32_t*>(base + L.touched);
+  dm.occ = reinterpret_cast<float*>(base + L.occ);
+  dm.acc = reinterpret_cast<float*>(base + L.acc);
+  dm.ndt = (layers & OHM_LAYER_NDT) ? reinterpret_cast<NdtVoxel*>(base + L.ndt) : nullptr;
+  dm.mom = (layers & OHM_LAYER_NDT) ? reinterpret_cast<long long*>(base + L.mom) : nullptr;
+  dm.clampscan = (layers & OHM_LAYER_ADJOINT) ? reinterpret_cast<uint32_t*>(base + L.clampscan) : nullptr;
+  s = map_initialise(map, as_stream(stream));
+  if (s != OHM_OK) {
+    delete map;
+    return s;
+  }
+  *out = map;
+  return OHM_OK;
+}
+
+ohm_status ohm_map_destroy(ohm_map map) {
+  if (!map) return OHM_E_INVALID_ARG;
+  delete map;
+  return OHM_OK;
+}
+
+ohm_status ohm_map_reset(ohm_map map, void* stream) {
+  if (!map) return OHM_E_INVALID_ARG;
+  return map_initialise(map, as_stream(stream));
+}
+
+ohm_status ohm_map_set_params(ohm_map map, const ohm_params* params) {
+  if (!map) return OHM_E_INVALID_ARG;
+  ohm_status s = validate_params(params);
+  if (s != OHM_OK) return s;
+  const ohm_params& o = map->params;
+  if (params->voxel_size != o.voxel_size || params->fixed_bits != o.fixed_bits ||
+      params->region_log2 != o.region_log2)
+    return OHM_E_INVALID_ARG;
+  for (int a = 0; a < 3; ++a)
+    if (params->map_origin[a] != o.map_origin[a] || params->key_min[a] != o.key_min[a] ||
+        params->key_max[a] != o.key_max[a])
+      return OHM_E_INVALID_ARG;
+  map->params = *params;
+  fill_params(map->dm, params);
+  return OHM_OK;
+}
+
+ohm_status ohm_integrate_rays(ohm_map map, const float* d_origins, const float* d_samples,
+                              const uint32_t* h_scan_offsets, uint32_t n_scans, const float* d_weights,
+                              void* stream) {
+  ohm_status s = check_scans(map, d_origins, d_samples, h_scan_offsets, n_scans);
+  if (s != OHM_OK || n_scans == 0) return s;
+  hipStream_t st = as_stream(stream);
+  const bool count_mode = map->params.mode == OHM_MODE_COUNT_CLAMP;
+  const bool weighted = d_weights != nullptr;
+  uint32_t last = n_scans;
+  for (uint32_t sc = 0; sc < n_scans; ++sc)
+    if (h_scan_offsets[sc + 1] > h_scan_offsets[sc]) last = sc;
+  for (uint32_t sc = 0; sc < n_scans; ++sc) {
+    const uint32_t r0 = h_scan_offsets[sc];
+    const uint32_t n = h_scan_offsets[sc + 1] - r0;
+    if (n == 0) continue;
+    dim3 grid((n + 255) / 256);
+    uint32_t tag = 0, parity = 0;
+    if (count_mode) {
+      clear_pending(map, st);
+      tag = ++map->count_batches;
+      parity = tag & 1u;
+    }
+    launch_prepass(map, d_origins, sc, d_samples, r0, n, count_mode, tag, parity, st);
+    if (count_mode) {
+      if (weighted)
+        hipLaunchKernelGGL((walk_kernel<kSinkCount, true>), grid, dim3(256), 0, st, map->dm, d_origins, sc,
+                           d_samples, d_weights, r0, n, nullptr, nullptr, nullptr, nullptr);
+      else
+        hipLaunchKernelGGL((walk_kernel<kSinkCount, false>), grid, dim3(256), 0, st, map->dm, d_origins, sc,
+                           d_samples, d_weights, r0, n, nullptr, nullptr, nullptr, nullptr);
+      const bool keep = sc == last;
+      hipLaunchKernelGGL(finalize_kernel, dim3(kFinalizeBlocks), dim3(256), 0, st, map->dm, parity, 1,
+                         keep ? 0 : 1, 0, map->scans_done + 1);
+      if (keep) {
+        map->acc_dirty = true;
+        map->last_parity = parity;
+      }
+    } else {
+      if (weighted)
+        hipLaunchKernelGGL((walk_kernel<kSinkCas, true>), grid, dim3(256), 0, st, map->dm, d_origins, sc, d_samples,
+                           d_weights, r0, n, nullptr, nullptr, nullptr, nullptr);
+      else
+        hipLaunchKernelGGL((walk_kernel<kSinkCas, false>), grid, dim3(256), 0, st, map->dm, d_origins, sc,
+                           d_samples, d_weights, r0, n, nullptr, nullptr, nullptr, nullptr);
+    }
+    map->scans_done += 1;
+  }
+  return last_hip_status();
+}
+
+ohm_status ohm_map_read_dense(ohm_map map, int32_t what, const int32_t h_box_min[3], const int32_t h_box_dim[3],
+                              void* d_out, void* stream) {
+  if (!map || !h_box_min || !h_box_dim || !d_out) return OHM_E_INVALID_ARG;
+  if (what < OHM_READ_OCC || what > OHM_READ_CLAMP_SCAN) return OHM_E_INVALID_ARG;
+  if ((what == OHM_READ_NDT_COUNT || what == OHM_READ_NDT_MEAN || what == OHM_READ_NDT_COV) && !map->dm.ndt)
+    return OHM_E_INVALID_ARG;
+  if (what == OHM_READ_CLAMP_SCAN && !map->dm.clampscan) return OHM_E_INVALID_ARG;
+  for (int a = 0; a < 3; ++a)
+    if (h_box_dim[a] <= 0) return OHM_E_INVALID_ARG;
+  const size_t n = (size_t)h_box_dim[0] * h_box_dim[1] * h_box_dim[2];
+  const size_t blocks = (n + 255) / 256;
+  if (blocks > 0x7fffffff) return OHM_E_INVALID_ARG;
+  hipLaunchKernelGGL(read_dense_kernel, dim3((unsigned)blocks), dim3(256), 0, as_stream(stream), map->dm, what,
+                     h_box_min[0], h_box_min[1], h_box_min[2], h_box_dim[0], h_box_dim[1], h_box_dim[2], d_out);
+  return last_hip_status();
+}
+
+ohm_status ohm_debug_trace_rays(ohm_map map, const float* d_origins, const float* d_samples,
+                                const uint32_t* h_scan_offsets, uint32_t n_scans, uint32_t* d_ray_counts,
+                                int32_t* d_ray_flags, const int64_t* d_ray_offsets, int32_t* d_updates,
+                                void* stream) {
+  ohm_status s = check_scans(map, d_origins, d_samples, h_scan_offsets, n_scans);
+  if (s != OHM_OK || n_scans == 0) return s;
+  if (!d_updates && (!d_ray_counts || !d_ray_flags)) return OHM_E_INVALID_ARG;
+  if (d_updates && !d_ray_offsets) return OHM_E_INVALID_ARG;
+  hipStream_t st = as_stream(stream);
+  for (uint32_t sc = 0; sc < n_scans; ++sc) {
+    const uint32_t r0 = h_scan_offsets[sc];
+    const uint32_t n = h_scan_offsets[sc + 1] - r0;
+    if (n == 0) continue;
+    dim3 grid((n + 255) / 256);
+    if (!d_updates)
+      hipLaunchKernelGGL((walk_kernel<kSinkTraceCount, false>), grid, dim3(256), 0, st, map->dm, d_origins, sc,
+                         d_samples, nullptr, r0, n, d_ray_counts, d_ray_flags, nullptr, nullptr);
+    else
+      hipLaunchKernelGGL((walk_kernel<kSinkTraceWrite, false>), grid, dim3(256), 0, st, map->dm, d_origins, sc,
+                         d_samples, nullptr, r0, n, nullptr, nullptr, d_ray_offsets, d_updates);
+  }
+  return last_hip_status();
+}
+
+ohm_status ohm_map_sync_status(ohm_map map, void* stream, ohm_map_stats* out) {
+  if (!map || !out) return OHM_E_INVALID_ARG;
+  hipStream_t st = as_stream(stream);
+  uint32_t hdr[kHdrWords];
+  unsigned long long stats[16];
+  if (hipMemcpyAsync(hdr, map->dm.hdr, sizeof(hdr), hipMemcpyDeviceToHost, st) != hipSuccess) return OHM_E_HIP;
+  if (hipMemcpyAsync(stats, map->dm.stats, sizeof(stats), hipMemcpyDeviceToHost, st) != hipSuccess)
+    return OHM_E_HIP;
+  if (hipStreamSynchronize(st) != hipSuccess) return OHM_E_HIP;
+  memset(out, 0, sizeof(*out));
+  out->rays_in = stats[kStatRays];
+  out->rays_invalid = stats[kStatInvalid];
+  out->rays_origin_oob = stats[kStatOriginOob];
+  out->rays_truncated = stats[kStatTruncated];
+  out->rays_clipped = stats[kStatClipped];
+  out->rays_hit = stats[kStatHits];
+  out->voxel_updates = stats[kStatUpdates];
+  out->updates_dropped_pool = stats[kStatDropped];
+  out->regions_used = hdr[kHdrPoolCount] < map->dm.capacity ? hdr[kHdrPoolCount] : map->dm.capacity;
+  out->region_capacity = map->dm.capacity;
+  out->sticky_error = (int32_t)hdr[kHdrSticky];
+  return OHM_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,177 @@
+"""Python binding over the C ABI: torch supplies device memory and streams,
+every step of the integration runs in the library's HIP kernels."""
+from __future__ import annotations
+
+import ctypes
+from typing import Optional, Sequence
+
+import numpy as np
+import torch
+
+from . import _lib
+from ._lib import check, load, make_params
+
+
+def _stream_ptr(stream: Optional[torch.cuda.Stream] = None) -> ctypes.c_void_p:
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def _dev_ptr(t: Optional[torch.Tensor], dtype, name: str, device) -> Optional[ctypes.c_void_p]:
+    if t is None:
+        return None
+    if not t.is_cuda:
+        raise ValueError(f"{name} must be a device tensor")
+    if t.dtype != dtype:
+        raise ValueError(f"{name} must be {dtype}, got {t.dtype}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    if t.device != device:
+        raise ValueError(f"{name} is on {t.device}, map is on {device}")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _host_offsets(offsets) -> np.ndarray:
+    if isinstance(offsets, torch.Tensor):
+        offsets = offsets.detach().cpu().numpy()
+    return np.ascontiguousarray(np.asarray(offsets, dtype=np.uint32))
+
+
+class OhmMap:
+    """A region-chunked occupancy map living in a torch-allocated workspace."""
+
+    def __init__(self, params, region_capacity: int, layers: int = _lib.LAYER_OCC,
+                 device: Optional[torch.device] = None, stream: Optional[torch.cuda.Stream] = None):
+        lib = load()
+        self.device = torch.device(device) if device is not None else torch.device("cuda", torch.cuda.current_device())
+        self.params = params
+        self.layers = layers | _lib.LAYER_OCC
+        self.capacity = int(region_capacity)
+        self._cparams = make_params(params)
+        size = ctypes.c_size_t(0)
+        check(lib.ohm_map_workspace_size(ctypes.byref(self._cparams), self.capacity, self.layers,
+                                         ctypes.byref(size)), "ohm_map_workspace_size")
+        self.workspace_bytes = int(size.value)
+        with torch.cuda.device(self.device):
+            self.workspace = torch.empty(self.workspace_bytes, dtype=torch.uint8, device=self.device)
+        handle = ctypes.c_void_p()
+        check(lib.ohm_map_create(ctypes.byref(self._cparams), self.capacity, self.layers,
+                                 ctypes.c_void_p(self.workspace.data_ptr()), self.workspace_bytes,
+                                 _stream_ptr(stream), ctypes.byref(handle)), "ohm_map_create")
+        self._handle = handle
+
+    # -- lifetime -----------------------------------------------------------------
+    def close(self):
+        if getattr(self, "_handle", None):
+            load().ohm_map_destroy(self._handle)
+            self._handle = None
+
+    def __del__(self):  # pragma: no cover - interpreter shutdown order
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    @property
+    def handle(self) -> ctypes.c_void_p:
+        if not self._handle:
+            raise RuntimeError("map is closed")
+        return self._handle
+
+    def reset(self, stream=None):
+        check(load().ohm_map_reset(self.handle, _stream_ptr(stream)), "ohm_map_reset")
+
+    def set_params(self, params):
+        cp = make_params(params)
+        check(load().ohm_map_set_params(self.handle, ctypes.byref(cp)), "ohm_map_set_params")
+        self.params, self._cparams = params, cp
+
+    # -- integration ----------------------------------------------------------------
+    def _scan_args(self, origins, samples, offsets, weights):
+        h_off = _host_offsets(offsets)
+        n_scans = h_off.shape[0] - 1
+        if n_scans < 0:
+            raise ValueError("offsets needs at least one entry")
+        if origins.dim() != 2 or origins.shape[1] != 3 or origins.shape[0] < n_scans:
+            raise ValueError("origins must be [n_scans, 3]")
+        if samples.dim() != 2 or samples.shape[1] != 3 or samples.shape[0] < int(h_off[-1]):
+            raise ValueError("samples must be [N, 3] with N >= offsets[-1]")
+        if weights is not None and weights.shape[0] < int(h_off[-1]):
+            raise ValueError("weights must have one entry per ray")
+        return (_dev_ptr(origins, torch.float32, "origins", self.device),
+                _dev_ptr(samples, torch.float32, "samples", self.device),
+                h_off, n_scans, _dev_ptr(weights, torch.float32, "weights", self.device))
+
+    def integrate(self, origins: torch.Tensor, samples: torch.Tensor, offsets, weights=None, stream=None):
+        """Occupancy integration of scans (ohm_integrate_rays)."""
+        o, s, h_off, n_scans, w = self._scan_args(origins, samples, offsets, weights)
+        check(load().ohm_integrate_rays(self.handle, o, s, h_off.ctypes.data_as(ctypes.c_void_p), n_scans, w,
+                                        _stream_ptr(stream)), "ohm_integrate_rays")
+
+    def ndt_integrate(self, origins: torch.Tensor, samples: torch.Tensor, offsets, weights=None, stream=None):
+        """NDT-OM integration of scans (ohm_ndt_integrate)."""
+        o, s, h_off, n_scans, w = self._scan_args(origins, samples, offsets, weights)
+        check(load().ohm_ndt_integrate(self.handle, o, s, h_off.ctypes.data_as(ctypes.c_void_p), n_scans, w,
+                                       _stream_ptr(stream)), "ohm_ndt_integrate")
+
+    # -- read-back ------------------------------------------------------------------
+    _READ_SHAPES = {
+        _lib.READ_OCC: (torch.float32, ()), _lib.READ_HITS: (torch.float32, ()),
+        _lib.READ_MISSES: (torch.float32, ()), _lib.READ_NDT_COUNT: (torch.int32, ()),
+        _lib.READ_NDT_MEAN: (torch.float32, (3,)), _lib.READ_NDT_COV: (torch.float32, (6,)),
+        _lib.READ_CLAMP_SCAN: (torch.int32, ()),
+    }
+
+    def read_dense(self, what: int, box_min: Sequence[int], box_dim: Sequence[int], out=None, stream=None):
+        dtype, tail = self._READ_SHAPES[what]
+        shape = (int(box_dim[2]), int(box_dim[1]), int(box_dim[0])) + tail
+        if out is None:
+            out = torch.empty(shape, dtype=dtype, device=self.device)
+        bmin = (ctypes.c_int32 * 3)(*[int(v) for v in box_min])
+        bdim = (ctypes.c_int32 * 3)(*[int(v) for v in box_dim])
+        check(load().ohm_map_read_dense(self.handle, what, bmin, bdim, _dev_ptr(out, dtype, "out", self.device),
+                                        _stream_ptr(stream)), "ohm_map_read_dense")
+        return out
+
+    def occupancy(self, box_min=None, box_dim=None):
+        if box_min is None:
+            box_min = self.params.key_min
+            box_dim = [b - a for a, b in zip(self.params.key_min, self.params.key_max)]
+        return self.read_dense(_lib.READ_OCC, box_min, box_dim)
+
+    def trace(self, origins: torch.Tensor, samples: torch.Tensor, offsets, stream=None):
+        """Per-ray update lists from the library's walk: returns
+        (counts int64[N], flags int32[N], offsets int64[N+1], updates int32[T,4])."""
+        o, s, h_off, n_scans, _ = self._scan_args(origins, samples, offsets, None)
+        n = int(h_off[-1])
+        lib = load()
+        counts = torch.zeros(n, dtype=torch.int32, device=self.device)
+        flags = torch.zeros(n, dtype=torch.int32, device=self.device)
+        hp = h_off.ctypes.data_as(ctypes.c_void_p)
+        check(lib.ohm_debug_trace_rays(self.handle, o, s, hp, n_scans, ctypes.c_void_p(counts.data_ptr()),
+                                       ctypes.c_void_p(flags.data_ptr()), None, None, _stream_ptr(stream)),
+              "ohm_debug_trace_rays(count)")
+        offs = torch.zeros(n + 1, dtype=torch.int64, device=self.device)
+        offs[1:] = torch.cumsum(counts.to(torch.int64), 0)
+        total = int(offs[-1].item())
+        upd = torch.zeros((max(total, 1), 4), dtype=torch.int32, device=self.device)
+        check(lib.ohm_debug_trace_rays(self.handle, o, s, hp, n_scans, None, None,
+                                       ctypes.c_void_p(offs.data_ptr()), ctypes.c_void_p(upd.data_ptr()),
+                                       _stream_ptr(stream)), "ohm_debug_trace_rays(write)")
+        return counts.to(torch.int64), flags, offs, upd[:total]
+
+    def stats(self, stream=None) -> dict:
+        st = _lib.OhmStats()
+        check(load().ohm_map_sync_status(self.handle, _stream_ptr(stream), ctypes.byref(st)), "ohm_map_sync_status")
+        return st.as_dict()
+
+
+def regions_needed(params, margin: float = 1.25) -> int:
+    """Upper bound on regions for a map whose whole extent may be touched
+    (used for small maps where reserving every region is cheap)."""
+    n = 1
+    for a in range(3):
+        lo = params.key_min[a] >> 5
+        hi = (params.key_max[a] - 1) >> 5
+        n *= hi - lo + 1
+    return n

@@ -1,0 +1,203 @@
+#!/usr/bin/env python3
+"""Throughput benchmark of lidar ray integration on one MI355X.
+
+Workload (one "step"): the 100-scan spinning-lidar sequence -- 64 beams x
+2048 columns = 131,072 rays per scan, sensor moving 0.1 m per scan along a
+4 x 3 m box tunnel with 200 random boxes, 30 m max range -- integrated scan by
+scan into a 0.1 m occupancy map of 32^3-voxel regions over 200 x 200 x 40 m.
+Inputs are generated once (seeded) and stay resident in HBM; a step re-runs
+the whole per-scan path (region pass, voxel walk with its atomic updates,
+per-scan clamp) over all 100 scans.
+
+Prints one JSON line on stdout; progress goes to stderr.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, published
+
+
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def walk_bytes(rays, updates):
+    """Algorithmic bytes of the walk kernel: each ray reads its 12-byte sample
+    (plus the scan's 12-byte origin), and each voxel update is one 4-byte
+    read-modify-write at the coherence point (4 B read + 4 B written)."""
+    return 12.0 * rays + 12.0 + 8.0 * updates
+
+
+def run_gpu(args, params, batch, mode):
+    import torch
+
+    import paper_2206_06079_amd as ohm
+
+    dev = torch.device("cuda", 0)
+    o = torch.from_numpy(batch.origins).to(dev)
+    s = torch.from_numpy(batch.samples).to(dev)
+    off = batch.offsets
+    m = ohm.OhmMap(params.replace(mode=mode), args.capacity, device=dev)
+    stream = torch.cuda.current_stream()
+    for _ in range(args.warmup):
+        m.integrate(o, s, off)
+    torch.cuda.synchronize()
+    st0 = m.stats()
+    steps = args.steps if mode == ohm.MODE_COUNT_CLAMP else max(2, args.steps // 2)
+    m.set_profiling(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for k in range(steps):
+        m.integrate(o, s, off)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    kt = m.kernel_times()
+    m.set_profiling(False)
+    st1 = m.stats()
+    m.close()
+    ms_total = e0.elapsed_time(e1)
+    upd = (st1["voxel_updates"] - st0["voxel_updates"]) / steps
+    rays = (st1["rays_in"] - st0["rays_in"]) / steps
+    return {
+        "steps": steps,
+        "ms_per_step": ms_total / steps,
+        "wall_ms_per_step": (t1 - t0) * 1e3 / steps,
+        "rays_per_step": rays,
+        "updates_per_step": upd,
+        "kernels": kt,
+        "stats": st1,
+    }
+
+
+def cpu_baseline(params, batch, n_scans):
+    import oracle
+
+    box_min, box_dim = (690, 978, 183), (720, 44, 34)
+    sub = batch.scans(0, n_scans)
+    t0 = time.perf_counter()
+    _, _, _, st = oracle.integrate_count(params, sub, box_min, box_dim)
+    dt = time.perf_counter() - t0
+    return {
+        "value": st["rays"] / dt,
+        "unit": "rays/s",
+        "cores": 1,
+        "kind": "oracle",
+        "sample": f"first {n_scans} of the 100 scans ({st['rays']} rays, {st['updates']} voxel updates), "
+                  f"single-threaded C oracle, count-then-clamp, {dt:.1f} s",
+        "voxel_updates_per_s": st["updates"] / dt,
+    }
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--scans", type=int, default=100)
+    ap.add_argument("--capacity", type=int, default=512)
+    ap.add_argument("--cpu-scans", type=int, default=16)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-per-update", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU only: this build has no multi-GPU path "
+              "(how it would shard is described in the design notes)", file=sys.stderr)
+        return 2
+
+    import torch
+
+    import paper_2206_06079_amd as ohm
+    from workloads import scenes
+
+    if not torch.cuda.is_available():
+        print("bench.py needs a GPU", file=sys.stderr)
+        return 2
+    ohm._lib.load()  # fails loudly when the HIP library is missing
+    log(f"generating {args.scans} scans")
+    t0 = time.perf_counter()
+    params, batch = scenes.config1(n_scans=args.scans)
+    log(f"generated {batch.n_rays} rays in {time.perf_counter() - t0:.1f} s")
+
+    res = run_gpu(args, params, batch, ohm.MODE_COUNT_CLAMP)
+    log(f"count mode: {res['ms_per_step']:.3f} ms/step, kernels {res['kernels']}")
+    per_update = None
+    if not args.no_per_update:
+        pu = run_gpu(args, params, batch, ohm.MODE_PER_UPDATE)
+        log(f"per-update mode: {pu['ms_per_step']:.3f} ms/step, kernels {pu['kernels']}")
+        per_update = {
+            "rays_per_s": pu["rays_per_step"] / (pu["ms_per_step"] * 1e-3),
+            "voxel_updates_per_s": pu["updates_per_step"] / (pu["ms_per_step"] * 1e-3),
+            "ms_per_step": pu["ms_per_step"],
+            "walk_kernel_ms": pu["kernels"].get("walk", (0, 0.0))[1] / max(1, pu["kernels"].get("walk", (1, 0))[0]),
+        }
+
+    sec = res["ms_per_step"] * 1e-3
+    rays_per_s = res["rays_per_step"] / sec
+    upd_per_s = res["updates_per_step"] / sec
+    n_walk, ms_walk = res["kernels"].get("walk", (0, 0.0))
+    walk_avg_ms = ms_walk / max(1, n_walk)
+    scans = args.scans
+    rays_per_scan = res["rays_per_step"] / scans
+    upd_per_scan = res["updates_per_step"] / scans
+    achieved = walk_bytes(rays_per_scan, upd_per_scan) / (walk_avg_ms * 1e-3) / 1e9
+    roofline = {
+        "bound": "hbm",
+        "achieved": round(achieved, 1),
+        "peak": HBM_PEAK_GBS,
+        "unit": "GB/s",
+        "frac": round(achieved / HBM_PEAK_GBS, 4),
+        "traffic": None,
+        "kernel": "walk_kernel (count mode)",
+        "kernel_avg_ms": round(walk_avg_ms, 5),
+        "bytes_per_launch": walk_bytes(rays_per_scan, upd_per_scan),
+        "atomics_per_s": round(upd_per_scan / (walk_avg_ms * 1e-3), 1),
+    }
+    cpu = None
+    if not args.no_cpu_baseline:
+        log(f"timing the oracle on {args.cpu_scans} scans")
+        cpu = cpu_baseline(params, batch, min(args.cpu_scans, scans))
+        log(f"oracle: {cpu['value']:.0f} rays/s")
+    out = {
+        "metric": "rays/s (voxel-updates/s alongside), plain per-scan path, config-1 spinning-lidar scans",
+        "value": round(rays_per_s, 1),
+        "unit": "rays/s",
+        "n_gpus": 1,
+        "steps": res["steps"],
+        "warmup": args.warmup,
+        "ms_per_step": round(res["ms_per_step"], 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {
+            "workload": f"{scans} spinning-lidar scans x {int(rays_per_scan)} rays (64x2048), tunnel scene, "
+                        "0.1 m voxels, 32^3 regions over 200x200x40 m, 30 m max range",
+            "mode": "count_clamp",
+            "n_scans": scans,
+            "rays_per_scan": int(rays_per_scan),
+        },
+        "voxel_updates_per_s": round(upd_per_s, 1),
+        "voxel_updates_per_step": int(res["updates_per_step"]),
+        "kernel_ms_per_step": {k: round(v[1] / res["steps"], 4) for k, v in res["kernels"].items()},
+        "per_update_mode": per_update,
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out), flush=True)
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

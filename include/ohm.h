@@ -194,6 +194,24 @@ ohm_status ohm_debug_trace_rays(ohm_map map, const float* d_origins, const float
                                 int32_t* d_ray_flags, const int64_t* d_ray_offsets, int32_t* d_updates,
                                 void* stream);
 
+/* Kernel kinds reported by ohm_map_kernel_times. */
+enum {
+  OHM_KERNEL_PREPASS = 0,   /* region pass: allocation and touched list */
+  OHM_KERNEL_WALK = 1,      /* per-ray voxel walk with its updates */
+  OHM_KERNEL_FINALIZE = 2,  /* per-scan clamp / accumulator clear */
+  OHM_KERNEL_NDT_HIT = 3,   /* NDT sample fold (phase 2) */
+  OHM_KERNEL_OTHER = 7,
+  OHM_KERNEL_KINDS = 8
+};
+
+/* Profiling.  While enabled, each kernel the map launches is bracketed by a
+ * pair of HIP events recorded on the launch stream.  ohm_map_kernel_times
+ * waits for the recorded events, writes per kernel kind the number of
+ * launches (h_launches[OHM_KERNEL_KINDS]) and their summed duration in
+ * milliseconds (h_ms[OHM_KERNEL_KINDS]), and clears the record. */
+ohm_status ohm_map_set_profiling(ohm_map map, int enable);
+ohm_status ohm_map_kernel_times(ohm_map map, uint32_t* h_launches, double* h_ms);
+
 /* Synchronise `stream` and read the map's statistics. */
 ohm_status ohm_map_sync_status(ohm_map map, void* stream, ohm_map_stats* out);
 

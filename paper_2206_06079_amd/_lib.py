@@ -34,7 +34,11 @@ EXPORTS = (
     "ohm_map_workspace_size", "ohm_map_create", "ohm_map_destroy", "ohm_map_reset",
     "ohm_map_set_params", "ohm_integrate_rays", "ohm_map_read_dense",
     "ohm_debug_trace_rays", "ohm_map_sync_status", "ohm_status_string",
+    "ohm_map_set_profiling", "ohm_map_kernel_times",
 )
+
+KERNEL_KINDS = 8
+KERNEL_NAMES = {0: "prepass", 1: "walk", 2: "finalize", 3: "ndt_hit", 7: "other"}
 
 
 class OhmParams(ctypes.Structure):
@@ -110,6 +114,8 @@ def load() -> ctypes.CDLL:
         "ohm_map_read_dense": [vp, ctypes.c_int32, vp, vp, vp, vp],
         "ohm_debug_trace_rays": [vp, vp, vp, vp, ctypes.c_uint32, vp, vp, vp, vp, vp],
         "ohm_map_sync_status": [vp, vp, P(OhmStats)],
+        "ohm_map_set_profiling": [vp, ctypes.c_int],
+        "ohm_map_kernel_times": [vp, vp, vp],
     }
     for name, args in sig.items():
         fn = getattr(lib, name)

@@ -5,6 +5,8 @@
 #include <stddef.h>
 #include <stdint.h>
 
+#include <vector>
+
 #include "ohm.h"
 #include "ohm_device.h"
 
@@ -20,6 +22,15 @@ struct ohm_map_s {
   uint32_t scans_done;     // scans integrated since create / reset
   bool acc_dirty;          // the last count-mode scan's accumulators are still set
   uint32_t last_parity;
+  // kernel timing (ohm_map_set_profiling)
+  bool profiling;
+  std::vector<hipEvent_t> event_pool;
+  struct TimedLaunch {
+    int kind;
+    hipEvent_t start, stop;
+  };
+  std::vector<TimedLaunch> timed;
+  size_t events_used;
 };
 
 namespace ohm {
@@ -30,7 +41,17 @@ ohm_status map_initialise(ohm_map_s* map, hipStream_t st);
 ohm_status check_scans(ohm_map map, const float* d_origins, const float* d_samples, const uint32_t* h_offsets,
                        uint32_t n_scans);
 void clear_pending(ohm_map_s* map, hipStream_t st);
-void launch_prepass(ohm_map_s* map, const float* d_origins, uint32_t scan, const float* d_samples, uint32_t r0,
-                    uint32_t n, bool touch, uint32_t tag, uint32_t parity, hipStream_t st);
+// Brackets one kernel launch with HIP events when profiling is enabled.
+class ProfScope {
+ public:
+  ProfScope(ohm_map_s* map, int kind, hipStream_t st);
+  ~ProfScope();
+
+ private:
+  ohm_map_s* map_;
+  hipStream_t st_;
+  int kind_;
+  hipEvent_t stop_;
+};
 
 }  // namespace ohm

@@ -11,12 +11,12 @@
 //   ndt, mom    NDT-OM voxel statistics and per-scan sample moments (optional)
 //   clampscan   u32 [capacity][32^3] (optional, adjoint)
 //
-// Per scan the library runs (paper Sec. III-B, with the region pass of the
-// CPU-side region walk moved onto the GPU):
-//   prepass   exact walk over 32^3 regions; allocates missing regions and
-//             lists the regions this scan touches
-//   walk      one thread per ray: exact voxel walk, one update per voxel;
-//             equal updates of adjacent lanes are merged before the atomic
+// Per scan the library runs (paper Sec. III-B):
+//   walk      one thread per ray.  Prologue: the block walks its rays over
+//             32^3 regions, allocates missing regions and stages their slots
+//             in LDS (count mode also lists them for finalize).  Then the
+//             exact voxel walk, one update per voxel; equal updates of
+//             adjacent lanes are merged before they are applied.
 //   finalize  (count mode) one clamp per touched voxel: l = clamp(l + t + u)
 #include <hip/hip_runtime.h>
 #include <math.h>
@@ -29,6 +29,7 @@
 #include "ohm.h"
 #include "ohm_device.h"
 #include "ohm_host.h"
+#include "ohm_regions.h"
 
 namespace ohm {
 
@@ -74,80 +75,17 @@ __global__ void fill_u32_kernel(uint32_t* p, size_t n, uint32_t v) {
 }
 
 // ---------------------------------------------------------------------------
-// region pass
-// ---------------------------------------------------------------------------
-
-__device__ __forceinline__ void append_touched(const DevMap& m, uint32_t parity, int32_t slot) {
-  uint32_t idx = atomicAdd(m.hdr + kHdrTouched0 + parity, 1u);
-  m.touched[(size_t)parity * m.capacity + idx] = (uint32_t)slot;
-}
-
-// Make sure region (rx, ry, rz) has a slot; with kTouch also record it once
-// in this scan's touched list.
-template <bool kTouch>
-__device__ void touch_region(const DevMap& m, int32_t rx, int32_t ry, int32_t rz, uint32_t tag, uint32_t parity) {
-  int32_t r = region_index(m, rx, ry, rz);
-  int32_t slot = __hip_atomic_load(m.table + r, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-  if (slot == kSlotEmpty) {
-    int32_t old = atomicCAS(m.table + r, kSlotEmpty, kSlotClaimed);
-    if (old == kSlotEmpty) {
-      uint32_t s = atomicAdd(m.hdr + kHdrPoolCount, 1u);
-      if (s < m.capacity) {
-        slot = (int32_t)s;
-        if (kTouch && atomicExch(m.stamp + s, tag) != tag) append_touched(m, parity, slot);
-        __hip_atomic_store(m.table + r, slot, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      } else {
-        __hip_atomic_store(m.table + r, (int32_t)kSlotExhausted, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        atomicOr((int32_t*)(m.hdr + kHdrSticky), 1);
-      }
-      return;
-    }
-    slot = old;
-  }
-  if (kTouch && slot >= 0) {
-    if (__hip_atomic_load(m.stamp + slot, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != tag)
-      if (atomicExch(m.stamp + slot, tag) != tag) append_touched(m, parity, slot);
-  }
-}
-
-template <bool kTouch>
-__global__ __launch_bounds__(256) void prepass_kernel(DevMap m, const float* __restrict__ origins, uint32_t scan,
-                                                      const float* __restrict__ samples, uint32_t r0, uint32_t n,
-                                                      uint32_t tag, uint32_t parity) {
-  uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n) return;
-  const float o[3] = {origins[3 * scan + 0], origins[3 * scan + 1], origins[3 * scan + 2]};
-  size_t ray = (size_t)r0 + i;
-  const float e[3] = {samples[3 * ray + 0], samples[3 * ray + 1], samples[3 * ray + 2]};
-  Ray r;
-  if (prepare_ray(m, o, e, r) != kRayOk) return;
-  int32_t k0[3], k1[3], lo[3], hi[3];
-  for (int a = 0; a < 3; ++a) {
-    k0[a] = r.k0[a] >> kRegionLog2;
-    k1[a] = r.k1[a] >> kRegionLog2;
-    lo[a] = m.kmin[a] >> kRegionLog2;
-    hi[a] = (m.kmax[a] - 1) >> kRegionLog2;
-  }
-  Walk w;
-  walk_init(w, r.q0, r.q1, k0, k1, lo, hi, m.F + kRegionLog2);
-  int32_t rx = k0[0], ry = k0[1], rz = k0[2];
-  for (;;) {
-    touch_region<kTouch>(m, rx, ry, rz, tag, parity);
-    if (w.total == 0) break;
-    int a = walk_step(w);
-    int32_t ra = a == 0 ? w.rem[0] : (a == 1 ? w.rem[1] : w.rem[2]);
-    if (ra == 0 && ((w.clip >> a) & 1u)) break;
-    rx += a == 0 ? w.sg[0] : 0;
-    ry += a == 1 ? w.sg[1] : 0;
-    rz += a == 2 ? w.sg[2] : 0;
-  }
-}
-
-// ---------------------------------------------------------------------------
 // voxel walk
 // ---------------------------------------------------------------------------
 
 enum : int { kSinkCount = 0, kSinkCas = 1, kSinkTraceCount = 2, kSinkTraceWrite = 3 };
+
+// LDS hash table of the aggregating walk: 2^kWalkLdsLog2 (voxel, kind)
+// entries of 8 bytes; 0 applies every merged update straight to global memory.
+#ifndef OHM_WALK_LDS_LOG2
+#define OHM_WALK_LDS_LOG2 0
+#endif
+constexpr int kWalkLdsLog2 = OHM_WALK_LDS_LOG2;
 
 // Per-update clamp-add by compare-and-swap, retried until it lands.
 __device__ __forceinline__ void cas_clamp_add(float* p, float delta, float lo, float hi) {
@@ -161,14 +99,59 @@ __device__ __forceinline__ void cas_clamp_add(float* p, float delta, float lo, f
   }
 }
 
-template <int kSink, bool kWeighted>
+constexpr uint32_t kLdsEmpty = 0xFFFFFFFFu;
+
+// Adds v to entry `id` of the block's LDS hash table (open addressing,
+// linear probing).  False when the probe budget runs out; the caller then
+// applies the update to global memory itself.
+template <int kLog2>
+__device__ __forceinline__ bool lds_add(uint32_t* keys, float* vals, uint32_t id, float v) {
+  uint32_t h = (id * 0x9E3779B1u) >> (32 - kLog2);
+#pragma unroll 1
+  for (int p = 0; p < 32; ++p) {
+    uint32_t k = __hip_atomic_load(keys + h, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+    if (k == kLdsEmpty) {
+      const uint32_t old = atomicCAS(keys + h, kLdsEmpty, id);
+      k = old == kLdsEmpty ? id : old;
+    }
+    if (k == id) {
+      atomicAdd(vals + h, v);
+      return true;
+    }
+    h = (h + 1) & ((1u << kLog2) - 1);
+  }
+  return false;
+}
+
+template <int kSink, bool kWeighted, int kLdsLog2 = 0>
 __global__ __launch_bounds__(256) void walk_kernel(DevMap m, const float* __restrict__ origins, uint32_t scan,
                                                    const float* __restrict__ samples,
                                                    const float* __restrict__ weights, uint32_t r0, uint32_t n,
+                                                   uint32_t tag, uint32_t parity,
                                                    uint32_t* __restrict__ ray_counts,
                                                    int32_t* __restrict__ ray_flags,
                                                    const int64_t* __restrict__ ray_offsets,
                                                    int32_t* __restrict__ updates) {
+  constexpr bool kAccum = kSink == kSinkCount || kSink == kSinkCas;
+  constexpr bool kLds = kAccum && kLdsLog2 > 0;
+  constexpr int kEntries = kLds ? (1 << kLdsLog2) : 1;
+  __shared__ uint32_t s_key[kEntries];
+  __shared__ float s_val[kEntries];
+  if (kLds) {
+    for (int h = threadIdx.x; h < kEntries; h += blockDim.x) {
+      s_key[h] = kLdsEmpty;
+      s_val[h] = 0.f;
+    }
+    __syncthreads();
+  }
+  // applies a merged update of weight v to (voxel, kind) `id`
+  auto emit = [&](uint32_t id, float v) {
+    if (kLds && lds_add<kLds ? kLdsLog2 : 1>(s_key, s_val, id, v)) return;
+    if (kSink == kSinkCount)
+      unsafeAtomicAdd(m.acc + id, v);
+    else
+      cas_clamp_add(m.occ + (id >> 1), v * ((id & 1u) ? m.l_hit : m.l_miss), m.l_min, m.l_max);
+  };
   const uint32_t lane = lane_id();
   const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
   const bool inrange = i < n;
@@ -185,6 +168,9 @@ __global__ __launch_bounds__(256) void walk_kernel(DevMap m, const float* __rest
   bool alive = inrange && st == kRayOk;
   const float wt = (kWeighted && inrange) ? weights[ray] : 1.0f;
 
+  __shared__ RegionCache rc;
+  if (kAccum) stage_regions<kSink == kSinkCount>(m, rc, alive, r, tag, parity);
+
   Walk w;
   int32_t kx = 0, ky = 0, kz = 0;
   int32_t slot = -1;
@@ -195,7 +181,7 @@ __global__ __launch_bounds__(256) void walk_kernel(DevMap m, const float* __rest
     kx = r.k0[0];
     ky = r.k0[1];
     kz = r.k0[2];
-    if (kSink == kSinkCount || kSink == kSinkCas) slot = lookup_slot(m, kx, ky, kz);
+    if (kAccum) slot = staged_slot(m, rc, kx, ky, kz);
     lidx = local_index(kx, ky, kz);
   }
   uint32_t n_upd = 0, n_drop = 0, n_hit = 0;
@@ -206,7 +192,7 @@ __global__ __launch_bounds__(256) void walk_kernel(DevMap m, const float* __rest
   while (__ballot(alive)) {
     const bool last = alive && w.total == 0;
     const bool is_hit = last && !r.truncated;
-    if (kSink == kSinkCount || kSink == kSinkCas) {
+    if (kAccum) {
       const bool has = alive && slot >= 0;
       const uint32_t id = has ? (((uint32_t)slot * (uint32_t)kRegionVoxels + lidx) << 1) | (is_hit ? 1u : 0u)
                               : (0xFFFFFFFFu - lane);
@@ -217,12 +203,7 @@ __global__ __launch_bounds__(256) void walk_kernel(DevMap m, const float* __rest
       if (!kWeighted) {
         if (has && head) {
           const uint32_t run = above ? (uint32_t)__builtin_ctzll(above) + 1u : 64u - lane;
-          if (kSink == kSinkCount) {
-            unsafeAtomicAdd(m.acc + id, (float)run);
-          } else {
-            const float delta = (float)run * (is_hit ? m.l_hit : m.l_miss);
-            cas_clamp_add(m.occ + (id >> 1), delta, m.l_min, m.l_max);
-          }
+          emit(id, (float)run);
         }
       } else {
         // segmented inclusive sum of the weights over each run of equal ids;
@@ -239,13 +220,7 @@ __global__ __launch_bounds__(256) void walk_kernel(DevMap m, const float* __rest
           }
         }
         const bool tail = (lane == 63) || (above & 1ull);
-        if (has && tail) {
-          if (kSink == kSinkCount) {
-            unsafeAtomicAdd(m.acc + id, v);
-          } else {
-            cas_clamp_add(m.occ + (id >> 1), v * (is_hit ? m.l_hit : m.l_miss), m.l_min, m.l_max);
-          }
-        }
+        if (has && tail) emit(id, v);
       }
       if (alive) {
         if (slot >= 0) {
@@ -286,7 +261,7 @@ __global__ __launch_bounds__(256) void walk_kernel(DevMap m, const float* __rest
           const int32_t kn = a == 0 ? kx : (a == 1 ? ky : kz);
           const bool wrap = (kn & kRegionMask) == (sg > 0 ? 0 : kRegionMask);
           if (wrap) {
-            if (kSink == kSinkCount || kSink == kSinkCas) slot = lookup_slot(m, kx, ky, kz);
+            if (kAccum) slot = staged_slot(m, rc, kx, ky, kz);
             lidx = local_index(kx, ky, kz);
           } else {
             lidx += (uint32_t)(a == 0 ? sg : (a == 1 ? sg * kRegionEdge : sg * kRegionEdge * kRegionEdge));
@@ -310,6 +285,19 @@ __global__ __launch_bounds__(256) void walk_kernel(DevMap m, const float* __rest
       ray_flags[ray] = flags;
     }
     return;
+  }
+  if (kLds) {
+    // flush the block's merged updates
+    __syncthreads();
+    for (int h = threadIdx.x; h < kEntries; h += blockDim.x) {
+      const uint32_t k = s_key[h];
+      if (k == kLdsEmpty) continue;
+      const float v = s_val[h];
+      if (kSink == kSinkCount)
+        unsafeAtomicAdd(m.acc + k, v);
+      else
+        cas_clamp_add(m.occ + (k >> 1), v * ((k & 1u) ? m.l_hit : m.l_miss), m.l_min, m.l_max);
+    }
   }
   uint32_t vals[kStatCount];
   vals[kStatRays] = inrange ? 1u : 0u;
@@ -569,23 +557,44 @@ ohm_status check_scans(ohm_map map, const float* d_origins, const float* d_sampl
   return OHM_OK;
 }
 
+namespace {
+hipEvent_t take_event(ohm_map_s* map) {
+  if (map->events_used == map->event_pool.size()) {
+    hipEvent_t e = nullptr;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    map->event_pool.push_back(e);
+  }
+  return map->event_pool[map->events_used++];
+}
+}  // namespace
+
+ProfScope::ProfScope(ohm_map_s* map, int kind, hipStream_t st) : map_(map), st_(st), kind_(kind), stop_(nullptr) {
+  if (!map->profiling) return;
+  hipEvent_t start = take_event(map);
+  stop_ = take_event(map);
+  if (!start || !stop_) {
+    stop_ = nullptr;
+    return;
+  }
+  if (hipEventRecord(start, st) != hipSuccess) {
+    stop_ = nullptr;
+    return;
+  }
+  map->timed.push_back({kind, start, stop_});
+}
+
+ProfScope::~ProfScope() {
+  if (stop_ && hipEventRecord(stop_, st_) != hipSuccess) map_->timed.back().stop = nullptr;
+  (void)kind_;
+}
+
 // Lazy clear of the previous count-mode scan's accumulators.
 void clear_pending(ohm_map_s* map, hipStream_t st) {
   if (!map->acc_dirty) return;
+  ProfScope ps(map, OHM_KERNEL_FINALIZE, st);
   hipLaunchKernelGGL(finalize_kernel, dim3(kFinalizeBlocks), dim3(256), 0, st, map->dm, map->last_parity, 0, 1, 0,
                      0u);
   map->acc_dirty = false;
-}
-
-void launch_prepass(ohm_map_s* map, const float* d_origins, uint32_t scan, const float* d_samples, uint32_t r0,
-                    uint32_t n, bool touch, uint32_t tag, uint32_t parity, hipStream_t st) {
-  dim3 grid((n + 255) / 256);
-  if (touch)
-    hipLaunchKernelGGL(prepass_kernel<true>, grid, dim3(256), 0, st, map->dm, d_origins, scan, d_samples, r0, n, tag,
-                       parity);
-  else
-    hipLaunchKernelGGL(prepass_kernel<false>, grid, dim3(256), 0, st, map->dm, d_origins, scan, d_samples, r0, n,
-                       tag, parity);
 }
 
 }  // namespace ohm
@@ -668,6 +677,7 @@ ohm_status ohm_map_create(const ohm_params* params, uint32_t region_capacity, ui
 
 ohm_status ohm_map_destroy(ohm_map map) {
   if (!map) return OHM_E_INVALID_ARG;
+  for (hipEvent_t e : map->event_pool) (void)hipEventDestroy(e);
   delete map;
   return OHM_OK;
 }
@@ -716,28 +726,34 @@ ohm_status ohm_integrate_rays(ohm_map map, const float* d_origins, const float* 
       tag = ++map->count_batches;
       parity = tag & 1u;
     }
-    launch_prepass(map, d_origins, sc, d_samples, r0, n, count_mode, tag, parity, st);
     if (count_mode) {
-      if (weighted)
-        hipLaunchKernelGGL((walk_kernel<kSinkCount, true>), grid, dim3(256), 0, st, map->dm, d_origins, sc,
-                           d_samples, d_weights, r0, n, nullptr, nullptr, nullptr, nullptr);
-      else
-        hipLaunchKernelGGL((walk_kernel<kSinkCount, false>), grid, dim3(256), 0, st, map->dm, d_origins, sc,
-                           d_samples, d_weights, r0, n, nullptr, nullptr, nullptr, nullptr);
+      {
+        ProfScope ps(map, OHM_KERNEL_WALK, st);
+        if (weighted)
+          hipLaunchKernelGGL((walk_kernel<kSinkCount, true, kWalkLdsLog2>), grid, dim3(256), 0, st, map->dm, d_origins, sc,
+                           d_samples, d_weights, r0, n, tag, parity, nullptr, nullptr, nullptr, nullptr);
+        else
+          hipLaunchKernelGGL((walk_kernel<kSinkCount, false, kWalkLdsLog2>), grid, dim3(256), 0, st, map->dm, d_origins, sc,
+                             d_samples, d_weights, r0, n, tag, parity, nullptr, nullptr, nullptr, nullptr);
+      }
       const bool keep = sc == last;
-      hipLaunchKernelGGL(finalize_kernel, dim3(kFinalizeBlocks), dim3(256), 0, st, map->dm, parity, 1,
-                         keep ? 0 : 1, 0, map->scans_done + 1);
+      {
+        ProfScope ps(map, OHM_KERNEL_FINALIZE, st);
+        hipLaunchKernelGGL(finalize_kernel, dim3(kFinalizeBlocks), dim3(256), 0, st, map->dm, parity, 1,
+                           keep ? 0 : 1, 0, map->scans_done + 1);
+      }
       if (keep) {
         map->acc_dirty = true;
         map->last_parity = parity;
       }
     } else {
+      ProfScope ps(map, OHM_KERNEL_WALK, st);
       if (weighted)
-        hipLaunchKernelGGL((walk_kernel<kSinkCas, true>), grid, dim3(256), 0, st, map->dm, d_origins, sc, d_samples,
-                           d_weights, r0, n, nullptr, nullptr, nullptr, nullptr);
+        hipLaunchKernelGGL((walk_kernel<kSinkCas, true, kWalkLdsLog2>), grid, dim3(256), 0, st, map->dm, d_origins, sc, d_samples,
+                           d_weights, r0, n, tag, parity, nullptr, nullptr, nullptr, nullptr);
       else
-        hipLaunchKernelGGL((walk_kernel<kSinkCas, false>), grid, dim3(256), 0, st, map->dm, d_origins, sc,
-                           d_samples, d_weights, r0, n, nullptr, nullptr, nullptr, nullptr);
+        hipLaunchKernelGGL((walk_kernel<kSinkCas, false, kWalkLdsLog2>), grid, dim3(256), 0, st, map->dm, d_origins, sc,
+                           d_samples, d_weights, r0, n, tag, parity, nullptr, nullptr, nullptr, nullptr);
     }
     map->scans_done += 1;
   }
@@ -777,12 +793,43 @@ ohm_status ohm_debug_trace_rays(ohm_map map, const float* d_origins, const float
     dim3 grid((n + 255) / 256);
     if (!d_updates)
       hipLaunchKernelGGL((walk_kernel<kSinkTraceCount, false>), grid, dim3(256), 0, st, map->dm, d_origins, sc,
-                         d_samples, nullptr, r0, n, d_ray_counts, d_ray_flags, nullptr, nullptr);
+                         d_samples, nullptr, r0, n, 0u, 0u, d_ray_counts, d_ray_flags, nullptr, nullptr);
     else
       hipLaunchKernelGGL((walk_kernel<kSinkTraceWrite, false>), grid, dim3(256), 0, st, map->dm, d_origins, sc,
-                         d_samples, nullptr, r0, n, nullptr, nullptr, d_ray_offsets, d_updates);
+                         d_samples, nullptr, r0, n, 0u, 0u, nullptr, nullptr, d_ray_offsets, d_updates);
   }
   return last_hip_status();
+}
+
+ohm_status ohm_map_set_profiling(ohm_map map, int enable) {
+  if (!map) return OHM_E_INVALID_ARG;
+  map->profiling = enable != 0;
+  return OHM_OK;
+}
+
+ohm_status ohm_map_kernel_times(ohm_map map, uint32_t* h_launches, double* h_ms) {
+  if (!map || !h_launches || !h_ms) return OHM_E_INVALID_ARG;
+  for (int k = 0; k < OHM_KERNEL_KINDS; ++k) {
+    h_launches[k] = 0;
+    h_ms[k] = 0.0;
+  }
+  ohm_status st = OHM_OK;
+  for (const auto& t : map->timed) {
+    if (!t.stop || hipEventSynchronize(t.stop) != hipSuccess) {
+      st = OHM_E_HIP;
+      continue;
+    }
+    float ms = 0.f;
+    if (hipEventElapsedTime(&ms, t.start, t.stop) != hipSuccess) {
+      st = OHM_E_HIP;
+      continue;
+    }
+    h_launches[t.kind] += 1;
+    h_ms[t.kind] += (double)ms;
+  }
+  map->timed.clear();
+  map->events_used = 0;
+  return st;
 }
 
 ohm_status ohm_map_sync_status(ohm_map map, void* stream, ohm_map_stats* out) {

@@ -1,0 +1,152 @@
+// Region allocation and the per-block region cache ("LDS-staged region
+// keys").  Before a block walks its rays voxel by voxel it walks them region
+// by region (the same exact walk with 2^(F+5) cells), gathers the distinct
+// regions in an LDS hash set, and resolves each once: allocating a slot from
+// the pool when the region is new and, in count mode, listing it for the
+// scan's finalize.  The voxel walk then finds slots in LDS, so its inner loop
+// issues no global loads.  This replaces the paper's CPU-side region walk
+// (Sec. III-B, last paragraph) with a GPU pass fused into the walk kernel.
+#pragma once
+
+#include "ohm_device.h"
+
+namespace ohm {
+
+constexpr int kRegionCacheLog2 = 9;  // 512 entries per block
+constexpr int kRegionCacheSize = 1 << kRegionCacheLog2;
+constexpr int32_t kSlotNotCached = -4;
+constexpr int kAllocSpinLimit = 1 << 20;  // bounded wait for a slot another block is publishing
+
+struct RegionCache {
+  int32_t key[kRegionCacheSize];
+  int32_t slot[kRegionCacheSize];
+};
+
+__device__ __forceinline__ uint32_t region_hash(int32_t r) {
+  return ((uint32_t)r * 0x9E3779B1u) >> (32 - kRegionCacheLog2);
+}
+
+// Insert region r; false when the probe budget is exhausted.
+__device__ __forceinline__ bool rc_insert(RegionCache& rc, int32_t r) {
+  uint32_t h = region_hash(r);
+  for (int p = 0; p < 16; ++p) {
+    int32_t k = __hip_atomic_load(rc.key + h, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+    if (k == kSlotEmpty) {
+      const int32_t old = atomicCAS(rc.key + h, kSlotEmpty, r);
+      k = old == kSlotEmpty ? r : old;
+    }
+    if (k == r) return true;
+    h = (h + 1) & (kRegionCacheSize - 1);
+  }
+  return false;
+}
+
+__device__ __forceinline__ int32_t rc_find(const RegionCache& rc, int32_t r) {
+  uint32_t h = region_hash(r);
+  for (int p = 0; p < 16; ++p) {
+    const int32_t k = rc.key[h];
+    if (k == r) return rc.slot[h];
+    if (k == kSlotEmpty) return kSlotNotCached;
+    h = (h + 1) & (kRegionCacheSize - 1);
+  }
+  return kSlotNotCached;
+}
+
+__device__ __forceinline__ void append_touched(const DevMap& m, uint32_t parity, int32_t slot) {
+  const uint32_t idx = atomicAdd(m.hdr + kHdrTouched0 + parity, 1u);
+  m.touched[(size_t)parity * m.capacity + idx] = (uint32_t)slot;
+}
+
+// Slot of region r, allocating it when new.  With kTouch the slot is listed
+// once per scan (tag) in the touched list of `parity`.  Returns a negative
+// value when the pool is exhausted (updates to the region are dropped).
+template <bool kTouch>
+__device__ int32_t resolve_region(const DevMap& m, int32_t r, uint32_t tag, uint32_t parity) {
+  int32_t slot = __hip_atomic_load(m.table + r, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  if (slot == kSlotEmpty) {
+    const int32_t old = atomicCAS(m.table + r, kSlotEmpty, kSlotClaimed);
+    if (old == kSlotEmpty) {
+      const uint32_t s = atomicAdd(m.hdr + kHdrPoolCount, 1u);
+      slot = s < m.capacity ? (int32_t)s : kSlotExhausted;
+      if (slot == kSlotExhausted) atomicOr(reinterpret_cast<int32_t*>(m.hdr + kHdrSticky), 1);
+      __hip_atomic_store(m.table + r, slot, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    } else {
+      slot = old;
+    }
+  }
+  // another block claimed the region and is publishing its slot
+  for (int spin = 0; slot == kSlotClaimed && spin < kAllocSpinLimit; ++spin) {
+    __builtin_amdgcn_s_sleep(1);
+    slot = __hip_atomic_load(m.table + r, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  }
+  if (slot == kSlotClaimed) {
+    atomicOr(reinterpret_cast<int32_t*>(m.hdr + kHdrSticky), 2);
+    return kSlotExhausted;
+  }
+  if (kTouch && slot >= 0) {
+    if (__hip_atomic_load(m.stamp + slot, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != tag &&
+        atomicExch(m.stamp + slot, tag) != tag)
+      append_touched(m, parity, slot);
+  }
+  return slot;
+}
+
+// Region-level walk of one prepared ray: calls f(region_index) for every
+// region the voxel walk can enter, in order.
+template <typename F>
+__device__ __forceinline__ void for_each_region(const DevMap& m, const Ray& r, F&& f) {
+  int32_t k0[3], k1[3], lo[3], hi[3];
+  for (int a = 0; a < 3; ++a) {
+    k0[a] = r.k0[a] >> kRegionLog2;
+    k1[a] = r.k1[a] >> kRegionLog2;
+    lo[a] = m.kmin[a] >> kRegionLog2;
+    hi[a] = (m.kmax[a] - 1) >> kRegionLog2;
+  }
+  Walk w;
+  walk_init(w, r.q0, r.q1, k0, k1, lo, hi, m.F + kRegionLog2);
+  int32_t rx = k0[0], ry = k0[1], rz = k0[2];
+  for (;;) {
+    f(region_index(m, rx, ry, rz));
+    if (w.total == 0) break;
+    const int a = walk_step(w);
+    const int32_t ra = a == 0 ? w.rem[0] : (a == 1 ? w.rem[1] : w.rem[2]);
+    if (ra == 0 && ((w.clip >> a) & 1u)) break;
+    rx += a == 0 ? w.sg[0] : 0;
+    ry += a == 1 ? w.sg[1] : 0;
+    rz += a == 2 ? w.sg[2] : 0;
+  }
+}
+
+// Block prologue: every thread passes its prepared ray (ok = valid); on
+// return rc maps each region the block's rays enter to its slot.  Must be
+// reached by every thread of the block.
+template <bool kTouch>
+__device__ void stage_regions(const DevMap& m, RegionCache& rc, bool ok, const Ray& r, uint32_t tag,
+                              uint32_t parity) {
+  for (int h = threadIdx.x; h < kRegionCacheSize; h += blockDim.x) rc.key[h] = kSlotEmpty;
+  __syncthreads();
+  if (ok)
+    for_each_region(m, r, [&](int32_t ri) {
+      if (!rc_insert(rc, ri)) (void)resolve_region<kTouch>(m, ri, tag, parity);
+    });
+  __syncthreads();
+  for (int h = threadIdx.x; h < kRegionCacheSize; h += blockDim.x) {
+    const int32_t ri = rc.key[h];
+    rc.slot[h] = ri == kSlotEmpty ? kSlotExhausted : resolve_region<kTouch>(m, ri, tag, parity);
+  }
+  __syncthreads();
+}
+
+// Slot of the region holding key (kx, ky, kz): LDS first, table as fallback.
+__device__ __forceinline__ int32_t staged_slot(const DevMap& m, const RegionCache& rc, int32_t kx, int32_t ky,
+                                               int32_t kz) {
+  const int32_t ri = region_index(m, kx >> kRegionLog2, ky >> kRegionLog2, kz >> kRegionLog2);
+  int32_t s = rc_find(rc, ri);
+  if (s == kSlotNotCached) {
+    s = __hip_atomic_load(m.table + ri, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    s = s < kSlotExhausted ? kSlotExhausted : s;  // consume the load here
+  }
+  return s;
+}
+
+}  // namespace ohm

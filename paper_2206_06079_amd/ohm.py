@@ -160,6 +160,18 @@ class OhmMap:
                                        _stream_ptr(stream)), "ohm_debug_trace_rays(write)")
         return counts.to(torch.int64), flags, offs, upd[:total]
 
+    def set_profiling(self, enable: bool):
+        check(load().ohm_map_set_profiling(self.handle, 1 if enable else 0), "ohm_map_set_profiling")
+
+    def kernel_times(self) -> dict:
+        """{kind: (launches, total_ms)} of the kernels recorded since the last
+        call while profiling was enabled (synchronises)."""
+        launches = (ctypes.c_uint32 * _lib.KERNEL_KINDS)()
+        ms = (ctypes.c_double * _lib.KERNEL_KINDS)()
+        check(load().ohm_map_kernel_times(self.handle, launches, ms), "ohm_map_kernel_times")
+        return {_lib.KERNEL_NAMES.get(k, str(k)): (int(launches[k]), float(ms[k]))
+                for k in range(_lib.KERNEL_KINDS) if launches[k]}
+
     def stats(self, stream=None) -> dict:
         st = _lib.OhmStats()
         check(load().ohm_map_sync_status(self.handle, _stream_ptr(stream), ctypes.byref(st)), "ohm_map_sync_status")

@@ -69,6 +69,10 @@ def _load():
     lib.orc_integrate_count.argtypes = [P(OrcParams), ctypes.c_int32, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp]
     lib.orc_integrate_envelope.restype = ctypes.c_int
     lib.orc_integrate_envelope.argtypes = [P(OrcParams), ctypes.c_int32, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp]
+    lib.orc_ndt_integrate.restype = ctypes.c_int
+    lib.orc_ndt_integrate.argtypes = [P(OrcParams), ctypes.c_int32, ctypes.c_int32] + [vp] * 12
+    lib.orc_ndt_miss_delta.restype = ctypes.c_double
+    lib.orc_ndt_miss_delta.argtypes = [P(OrcParams), vp, vp, vp, vp, ctypes.c_uint32]
     _lib = lib
     return lib
 
@@ -176,3 +180,45 @@ def integrate_envelope(mp, batch, box_min=None, box_dim=None, lo=None, hi=None):
     if rc != 0:
         raise MemoryError("oracle box allocation failed")
     return lo, hi, nupd, dict(zip(STATS_FIELDS, (int(v) for v in stats)))
+
+
+class NdtState:
+    """NDT-OM voxel statistics over a box window (fp64, voxel-centred)."""
+
+    def __init__(self, shape):
+        self.n = np.zeros(shape, np.uint32)
+        self.mu = np.zeros(shape + (3,), np.float64)
+        self.cov = np.zeros(shape + (6,), np.float64)
+
+
+def ndt_miss_delta(mp, o, e, mu_w, cov6, n) -> float:
+    """The NDT-weighted miss increment of one voxel (paper Sec. II-D)."""
+    lib = _load()
+    p = make_params(mp)
+    a = [np.ascontiguousarray(np.asarray(x, np.float64)) for x in (o, e, mu_w, cov6)]
+    return float(lib.orc_ndt_miss_delta(ctypes.byref(p), *[_ptr(x) for x in a], int(n)))
+
+
+def ndt_integrate(mp, batch, box_min=None, box_dim=None, occ=None, state=None, mode=1):
+    """NDT-OM integration (paper Sec. II-D, III-C) into a box window.
+    Returns ``(occ, state, last_miss_sum, stats)``."""
+    lib = _load()
+    p = make_params(mp)
+    if box_min is None:
+        box_min = tuple(mp.key_min)
+        box_dim = tuple(b - a for a, b in zip(mp.key_min, mp.key_max))
+    bmin = np.asarray(box_min, np.int32)
+    bdim = np.asarray(box_dim, np.int32)
+    shape = (int(bdim[2]), int(bdim[1]), int(bdim[0]))
+    occ = np.full(shape, np.float32(mp.l_init), np.float32) if occ is None else np.ascontiguousarray(occ, np.float32).copy()
+    if state is None:
+        state = NdtState(shape)
+    miss = np.zeros(shape, np.float64)
+    stats = np.zeros(len(STATS_FIELDS), np.uint64)
+    o, s, off, w = _batch_arrays(batch)
+    rc = lib.orc_ndt_integrate(ctypes.byref(p), int(mode), batch.n_scans, _ptr(off), _ptr(o), _ptr(s), _ptr(w),
+                               _ptr(bmin), _ptr(bdim), _ptr(occ), _ptr(state.n), _ptr(state.mu),
+                               _ptr(state.cov), _ptr(miss), _ptr(stats))
+    if rc != 0:
+        raise MemoryError("oracle box allocation failed")
+    return occ, state, miss, dict(zip(STATS_FIELDS, (int(v) for v in stats)))

@@ -454,5 +454,216 @@ int orc_integrate_envelope(const orc_params* p, int32_t n_scans, const uint32_t*
   return 0;
 }
 
+/* ---------------------------------------------------------------------- */
+/* NDT-OM                                                                  */
+/* ---------------------------------------------------------------------- */
+/*
+ * NDT-OM (paper Sec. II-D and III-C).  Each voxel keeps a sample count n, a
+ * mean mu and a population covariance Sigma of the samples that fell in it
+ * (voxel-centred coordinates, metres).  Per scan:
+ *   1. misses: for every ray and every voxel it passes (all visited voxels
+ *      but a hit voxel), with the voxel's statistics as they were before the
+ *      scan: when n >= ndt_min_samples,
+ *        x* = the point of the ray segment closest to mu (Euclidean),
+ *        D  = x* - mu,  S = Sigma + sensor_noise^2 I,
+ *        g  = exp(-D^T S^-1 D / 2),
+ *        p  = 1/2 - adaptation_rate * g * (1/2 - sigmoid(l_miss)),
+ *        delta = ln(p / (1 - p));
+ *      otherwise delta = l_miss.  The ray weight scales delta.
+ *   2. occupancy: count mode l = clamp((l + sum_hits w l_hit) + sum_misses w delta);
+ *      per-update mode (misses applied first, then hits, as the paper's two
+ *      phases) l = clamp(clamp(l + sum_misses w delta) + sum_hits w l_hit).
+ *   3. voxels whose new l is below ndt_clear_below lose their statistics.
+ *   4. every sample of the scan is folded into its voxel, in ascending ray
+ *      order, by Welford's update:
+ *        n <- n + 1; d = x - mu; mu <- mu + d / n;
+ *        Sigma <- Sigma (n-1)/n + d d^T (n-1)/n^2.
+ * All in fp64; occupancy is stored as float after each scan.
+ */
+
+static double sigmoid_d(double x) { return 1.0 / (1.0 + exp(-x)); }
+
+/* Solve S y = D for a symmetric positive-definite 3x3 S (xx, xy, xz, yy, yz, zz)
+   by Cholesky factorisation; returns D^T y. */
+static double quad_form_inv(const double S6[6], const double D[3]) {
+  double a00 = S6[0], a10 = S6[1], a20 = S6[2], a11 = S6[3], a21 = S6[4], a22 = S6[5];
+  double l00 = sqrt(a00);
+  double l10 = a10 / l00, l20 = a20 / l00;
+  double l11 = sqrt(a11 - l10 * l10);
+  double l21 = (a21 - l20 * l10) / l11;
+  double l22 = sqrt(a22 - l20 * l20 - l21 * l21);
+  /* forward substitution L z = D; D^T S^-1 D = |z|^2 */
+  double z0 = D[0] / l00;
+  double z1 = (D[1] - l10 * z0) / l11;
+  double z2 = (D[2] - l20 * z0 - l21 * z1) / l22;
+  return z0 * z0 + z1 * z1 + z2 * z2;
+}
+
+/* The NDT-weighted miss increment for one voxel (see above).  o and e are the
+   ray's world start and (possibly truncated) end; mu_w the voxel's world
+   mean; cov its covariance. */
+double orc_ndt_miss_delta(const orc_params* p, const double o[3], const double e[3], const double mu_w[3],
+                          const double cov[6], uint32_t n) {
+  if (n < (uint32_t)p->ndt_min_samples) return (double)p->l_miss;
+  double d[3], w[3];
+  double dd = 0.0, wd = 0.0;
+  for (int a = 0; a < 3; ++a) {
+    d[a] = e[a] - o[a];
+    w[a] = mu_w[a] - o[a];
+    dd += d[a] * d[a];
+    wd += w[a] * d[a];
+  }
+  double t = dd > 0.0 ? wd / dd : 0.0;
+  if (t < 0.0) t = 0.0;
+  if (t > 1.0) t = 1.0;
+  double D[3];
+  for (int a = 0; a < 3; ++a) D[a] = (o[a] + t * d[a]) - mu_w[a];
+  double s2 = p->sensor_noise * p->sensor_noise;
+  double S[6] = {cov[0] + s2, cov[1], cov[2], cov[3] + s2, cov[4], cov[5] + s2};
+  double g = exp(-0.5 * quad_form_inv(S, D));
+  double pr = 0.5 - p->adaptation_rate * g * (0.5 - sigmoid_d((double)p->l_miss));
+  return log(pr / (1.0 - pr));
+}
+
+static void welford_add(uint32_t* n, double mu[3], double cov[6], const double x[3]) {
+  *n += 1;
+  double nn = (double)*n;
+  double d[3];
+  for (int a = 0; a < 3; ++a) {
+    d[a] = x[a] - mu[a];
+    mu[a] += d[a] / nn;
+  }
+  double f = (nn - 1.0) / nn;
+  double g = (nn - 1.0) / (nn * nn);
+  cov[0] = cov[0] * f + d[0] * d[0] * g;
+  cov[1] = cov[1] * f + d[0] * d[1] * g;
+  cov[2] = cov[2] * f + d[0] * d[2] * g;
+  cov[3] = cov[3] * f + d[1] * d[1] * g;
+  cov[4] = cov[4] * f + d[1] * d[2] * g;
+  cov[5] = cov[5] * f + d[2] * d[2] * g;
+}
+
+static void voxel_centre(const orc_params* p, const int32_t* k, double c[3]) {
+  for (int a = 0; a < 3; ++a) c[a] = p->map_origin[a] + ((double)k[a] + 0.5) * p->voxel_size;
+}
+
+/*
+ * NDT-OM integration of n_scans scans into the box window (paper Sec. II-D,
+ * III-C; formulas above).  mode 1 = count-then-clamp, 0 = per-update.
+ *   occ        [dz][dy][dx] float, in/out
+ *   nd_n       [dz][dy][dx] uint32, in/out sample counts
+ *   nd_mu      [dz][dy][dx][3] fp64, in/out means (voxel-centred, metres)
+ *   nd_cov     [dz][dy][dx][6] fp64, in/out covariances
+ *   miss_sum   optional out: last scan's summed miss increments per voxel
+ *   stats      ORC_S_COUNT counters (accumulated)
+ * Updates landing outside the window are ignored; so is the NDT state there.
+ */
+int orc_ndt_integrate(const orc_params* p, int32_t mode, int32_t n_scans, const uint32_t* offsets,
+                      const float* origins, const float* samples, const float* weights, const int32_t box_min[3],
+                      const int32_t box_dim[3], float* occ, uint32_t* nd_n, double* nd_mu, double* nd_cov,
+                      double* miss_sum, uint64_t* stats) {
+  size_t nv = (size_t)box_dim[0] * box_dim[1] * box_dim[2];
+  double* wh = (double*)calloc(nv, sizeof(double));
+  double* dm = (double*)calloc(nv, sizeof(double));
+  unsigned char* touched = (unsigned char*)calloc(nv, 1);
+  if (!wh || !dm || !touched) {
+    free(wh);
+    free(dm);
+    free(touched);
+    return -1;
+  }
+  /* pre-scan snapshot of the statistics used by the miss pass */
+  uint32_t* n0 = (uint32_t*)malloc(nv * sizeof(uint32_t));
+  double* mu0 = (double*)malloc(nv * 3 * sizeof(double));
+  double* cov0 = (double*)malloc(nv * 6 * sizeof(double));
+  orc_scratch s = {0};
+  for (int32_t sc = 0; sc < n_scans; ++sc) {
+    memset(wh, 0, nv * sizeof(double));
+    memset(dm, 0, nv * sizeof(double));
+    memset(touched, 0, nv);
+    memcpy(n0, nd_n, nv * sizeof(uint32_t));
+    memcpy(mu0, nd_mu, nv * 3 * sizeof(double));
+    memcpy(cov0, nd_cov, nv * 6 * sizeof(double));
+    const float* of = origins + 3 * sc;
+    double o[3] = {(double)of[0], (double)of[1], (double)of[2]};
+    /* phase 1: misses (and hit weights) */
+    for (uint32_t i = offsets[sc]; i < offsets[sc + 1]; ++i) {
+      orc_ray r;
+      prepare_ray(p, of, samples + 3 * (size_t)i, &r);
+      if (stats) stats[ORC_S_RAYS] += 1;
+      if (r.status != ORC_RAY_OK) {
+        if (stats) stats[r.status == ORC_RAY_INVALID ? ORC_S_INVALID : ORC_S_ORIGIN_OOB] += 1;
+        continue;
+      }
+      int clipped = 0;
+      int64_t nk = walk_ray(p, &r, &s, &clipped);
+      int has_hit = !r.truncated && !clipped;
+      double w = weights ? (double)weights[i] : 1.0;
+      if (stats) {
+        stats[ORC_S_TRUNCATED] += r.truncated ? 1 : 0;
+        stats[ORC_S_CLIPPED] += clipped ? 1 : 0;
+        stats[ORC_S_HITS] += has_hit ? 1 : 0;
+        stats[ORC_S_UPDATES] += (uint64_t)nk;
+      }
+      for (int64_t j = 0; j < nk; ++j) {
+        const int32_t* key = s.keys + 3 * j;
+        int64_t v = box_index(key, box_min, box_dim);
+        if (v < 0) continue;
+        touched[v] = 1;
+        if (has_hit && j == nk - 1) {
+          wh[v] += w;
+        } else {
+          double c[3], muw[3];
+          voxel_centre(p, key, c);
+          for (int a = 0; a < 3; ++a) muw[a] = c[a] + mu0[3 * v + a];
+          dm[v] += w * orc_ndt_miss_delta(p, o, r.end, muw, cov0 + 6 * v, n0[v]);
+        }
+      }
+    }
+    /* phase 2a: occupancy and clearing */
+    double lmin = (double)p->l_min, lmax = (double)p->l_max;
+    for (size_t v = 0; v < nv; ++v) {
+      if (!touched[v]) continue;
+      double l = (double)occ[v];
+      if (mode == 1)
+        l = clampd_((l + wh[v] * (double)p->l_hit) + dm[v], lmin, lmax);
+      else
+        l = clampd_(clampd_(l + dm[v], lmin, lmax) + wh[v] * (double)p->l_hit, lmin, lmax);
+      occ[v] = (float)l;
+      if ((double)occ[v] < p->ndt_clear_below) {
+        nd_n[v] = 0;
+        for (int a = 0; a < 3; ++a) nd_mu[3 * v + a] = 0.0;
+        for (int a = 0; a < 6; ++a) nd_cov[6 * v + a] = 0.0;
+      }
+    }
+    /* phase 2b: fold this scan's samples, ascending ray order */
+    for (uint32_t i = offsets[sc]; i < offsets[sc + 1]; ++i) {
+      orc_ray r;
+      prepare_ray(p, of, samples + 3 * (size_t)i, &r);
+      if (r.status != ORC_RAY_OK || r.truncated) continue;
+      int clipped = 0;
+      int64_t nk = walk_ray(p, &r, &s, &clipped);
+      if (clipped) continue;
+      const int32_t* key = s.keys + 3 * (nk - 1);
+      int64_t v = box_index(key, box_min, box_dim);
+      if (v < 0) continue;
+      double c[3], x[3];
+      voxel_centre(p, key, c);
+      const float* e = samples + 3 * (size_t)i;
+      for (int a = 0; a < 3; ++a) x[a] = (double)e[a] - c[a];
+      welford_add(nd_n + v, nd_mu + 3 * v, nd_cov + 6 * v, x);
+    }
+    if (miss_sum && sc == n_scans - 1) memcpy(miss_sum, dm, nv * sizeof(double));
+  }
+  scratch_free(&s);
+  free(wh);
+  free(dm);
+  free(touched);
+  free(n0);
+  free(mu0);
+  free(cov0);
+  return 0;
+}
+
 /* Library self-identification for the loaders. */
 int orc_abi_version(void) { return 1; }

@@ -171,6 +171,23 @@ ohm_status ohm_integrate_rays(ohm_map map, const float* d_origins, const float* 
 
 
 /*
+ * Integrate scans into an NDT-OM map (created with OHM_LAYER_NDT; paper
+ * Sec. II-D and III-C).  Per scan: phase 1 walks every ray and applies its
+ * misses, each weighted by the voxel's Gaussian: for a voxel holding at least
+ * ndt_min_samples samples with mean mu and covariance Sigma, with x* the point
+ * of the ray segment closest to mu, S = Sigma + sensor_noise^2 I and
+ * g = exp(-0.5 (x*-mu)^T S^-1 (x*-mu)), the miss is
+ *   delta = logit(0.5 - lambda * g * (0.5 - sigmoid(l_miss)))
+ * (plain l_miss for voxels with fewer samples).  Phase 2 folds every sample
+ * of the scan into its voxel's count, mean and covariance (population
+ * covariance, mean relative to the voxel centre) and applies the hits.
+ * Arguments as for ohm_integrate_rays.
+ */
+ohm_status ohm_ndt_integrate(ohm_map map, const float* d_origins, const float* d_samples,
+                             const uint32_t* h_scan_offsets, uint32_t n_scans, const float* d_weights,
+                             void* stream);
+
+/*
  * Copy a dense box of one quantity to d_out, laid out [box_dim z][y][x]
  * (x fastest) with the element type listed for `what`.  Voxels outside the
  * map or in unallocated regions read as never touched.

@@ -32,7 +32,7 @@ READ_CLAMP_SCAN = 6
 # Every symbol include/ohm.h declares.
 EXPORTS = (
     "ohm_map_workspace_size", "ohm_map_create", "ohm_map_destroy", "ohm_map_reset",
-    "ohm_map_set_params", "ohm_integrate_rays", "ohm_map_read_dense",
+    "ohm_map_set_params", "ohm_integrate_rays", "ohm_ndt_integrate", "ohm_map_read_dense",
     "ohm_debug_trace_rays", "ohm_map_sync_status", "ohm_status_string",
     "ohm_map_set_profiling", "ohm_map_kernel_times",
 )
@@ -111,6 +111,7 @@ def load() -> ctypes.CDLL:
         "ohm_map_reset": [vp, vp],
         "ohm_map_set_params": [vp, P(OhmParams)],
         "ohm_integrate_rays": [vp, vp, vp, vp, ctypes.c_uint32, vp, vp],
+        "ohm_ndt_integrate": [vp, vp, vp, vp, ctypes.c_uint32, vp, vp],
         "ohm_map_read_dense": [vp, ctypes.c_int32, vp, vp, vp, vp],
         "ohm_debug_trace_rays": [vp, vp, vp, vp, ctypes.c_uint32, vp, vp, vp, vp, vp],
         "ohm_map_sync_status": [vp, vp, P(OhmStats)],

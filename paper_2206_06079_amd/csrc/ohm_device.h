@@ -74,13 +74,18 @@ struct DevMap {
   float* occ;         // [capacity][V]
   float* acc;         // [capacity][V][2]: miss weight, hit weight
   NdtVoxel* ndt;      // [capacity][V] or null
-  long long* mom;     // NDT per-scan sample moments [capacity][V][kMomWords] or null
+  long long* nacc;    // NDT per-scan accumulators [capacity][V][kNaccWords] or null
+  double* mom;        // NDT per-scan sample moments [capacity][V][kMomWords] or null
   uint32_t* clampscan;// [capacity][V] or null
 };
 
-// per-voxel sample-moment accumulator of one scan (integers, exact):
-// n, sum u (3), sum u u^T (6), u = fixed-point offset from the voxel centre
-constexpr int kMomWords = 10;
+// NDT per-scan accumulators, exact integers: summed miss increment and summed
+// hit weight in Q32.32 fixed point, and the number of samples
+constexpr int kNaccWords = 4;
+enum : int { kNaccMiss = 0, kNaccHit = 1, kNaccSamples = 2 };
+// per-voxel sample moments of one scan: sum x (3), sum x x^T (6), x = sample
+// minus voxel centre (metres)
+constexpr int kMomWords = 9;
 
 __device__ __forceinline__ uint32_t lane_id() {
   return __builtin_amdgcn_mbcnt_hi(~0u, __builtin_amdgcn_mbcnt_lo(~0u, 0u));
@@ -89,6 +94,7 @@ __device__ __forceinline__ uint32_t lane_id() {
 struct Ray {
   int64_t q0[3], q1[3];
   int32_t k0[3], k1[3];
+  double end[3];  // world end point after truncation
   bool truncated;
 };
 
@@ -125,6 +131,7 @@ __device__ __forceinline__ int prepare_ray(const DevMap& m, const float o[3], co
     }
   }
   for (int a = 0; a < 3; ++a) {
+    r.end[a] = end[a];
     if (!quantise((double)o[a], m.origin[a], m.scale, r.q0[a]) || !quantise(end[a], m.origin[a], m.scale, r.q1[a]))
       return kRayInvalid;
     int64_t span = r.q1[a] - r.q0[a];

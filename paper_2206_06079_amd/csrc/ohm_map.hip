@@ -30,39 +30,13 @@
 #include "ohm_device.h"
 #include "ohm_host.h"
 #include "ohm_regions.h"
+#include "ohm_wave.h"
 
 namespace ohm {
 
 // ---------------------------------------------------------------------------
 // small wave helpers
 // ---------------------------------------------------------------------------
-
-// value of lane (l - 1); lane 0 receives `fill`
-__device__ __forceinline__ uint32_t wave_shr1(uint32_t v, uint32_t fill) {
-  return (uint32_t)__builtin_amdgcn_update_dpp((int)fill, (int)v, 0x138, 0xf, 0xf, false);
-}
-
-__device__ __forceinline__ uint32_t wave_sum_u32(uint32_t v) {
-  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
-  return v;
-}
-
-// Accumulate statistics of a block into the map's counters with one atomic
-// per counter per block.
-__device__ __forceinline__ void flush_stats(const DevMap& m, const uint32_t (&vals)[kStatCount]) {
-  __shared__ uint32_t part[kStatCount];
-  if (threadIdx.x < kStatCount) part[threadIdx.x] = 0;
-  __syncthreads();
-  uint32_t lane = lane_id();
-#pragma unroll
-  for (int c = 0; c < kStatCount; ++c) {
-    uint32_t s = wave_sum_u32(vals[c]);
-    if (lane == 0 && s) atomicAdd(&part[c], s);
-  }
-  __syncthreads();
-  if (threadIdx.x < kStatCount && part[threadIdx.x])
-    atomicAdd(m.stats + threadIdx.x, (unsigned long long)part[threadIdx.x]);
-}
 
 // ---------------------------------------------------------------------------
 // initialisation
@@ -196,31 +170,13 @@ __global__ __launch_bounds__(256) void walk_kernel(DevMap m, const float* __rest
       const bool has = alive && slot >= 0;
       const uint32_t id = has ? (((uint32_t)slot * (uint32_t)kRegionVoxels + lidx) << 1) | (is_hit ? 1u : 0u)
                               : (0xFFFFFFFFu - lane);
-      const uint32_t prev = wave_shr1(id, ~id);
-      const bool head = (lane == 0) || (prev != id);
-      const unsigned long long heads = __ballot(head);
-      const unsigned long long above = lane == 63 ? 0ull : (heads >> (lane + 1));
+      const LaneRuns run = lane_runs(id, lane);
       if (!kWeighted) {
-        if (has && head) {
-          const uint32_t run = above ? (uint32_t)__builtin_ctzll(above) + 1u : 64u - lane;
-          emit(id, (float)run);
-        }
+        if (has && run.head) emit(id, (float)run.len);
       } else {
-        // segmented inclusive sum of the weights over each run of equal ids;
-        // the run's last lane holds the total
-        float v = has ? wt : 0.f;
-        uint32_t f = head ? 1u : 0u;
-#pragma unroll
-        for (int off = 1; off < 64; off <<= 1) {
-          float vu = __shfl_up(v, off);
-          uint32_t fu = __shfl_up(f, off);
-          if (lane >= (uint32_t)off && !f) {
-            v += vu;
-            f |= fu;
-          }
-        }
-        const bool tail = (lane == 63) || (above & 1ull);
-        if (has && tail) emit(id, v);
+        // the run's last lane holds the summed weight
+        const float v = segmented_sum(has ? wt : 0.f, run.head, lane);
+        if (has && run.tail) emit(id, v);
       }
       if (alive) {
         if (slot >= 0) {
@@ -411,7 +367,7 @@ constexpr size_t kAlign = 256;
 inline size_t align_up(size_t v) { return (v + kAlign - 1) & ~(kAlign - 1); }
 
 struct Layout {
-  size_t hdr, stats, table, stamp, touched, occ, acc, ndt, mom, clampscan, total;
+  size_t hdr, stats, table, stamp, touched, occ, acc, ndt, nacc, mom, clampscan, total;
   int32_t rlo[3], rdim[3];
   size_t regions;
 };
@@ -470,12 +426,14 @@ ohm_status compute_layout(const ohm_params* p, uint32_t capacity, uint32_t layer
   off = align_up(off + (size_t)capacity * V * sizeof(float));
   L->acc = off;
   off = align_up(off + (size_t)capacity * V * 2 * sizeof(float));
-  L->ndt = L->mom = L->clampscan = 0;
+  L->ndt = L->nacc = L->mom = L->clampscan = 0;
   if (layers & OHM_LAYER_NDT) {
     L->ndt = off;
     off = align_up(off + (size_t)capacity * V * sizeof(NdtVoxel));
+    L->nacc = off;
+    off = align_up(off + (size_t)capacity * V * kNaccWords * sizeof(long long));
     L->mom = off;
-    off = align_up(off + (size_t)capacity * V * kMomWords * sizeof(long long));
+    off = align_up(off + (size_t)capacity * V * kMomWords * sizeof(double));
   }
   if (layers & OHM_LAYER_ADJOINT) {
     L->clampscan = off;
@@ -537,7 +495,8 @@ ohm_status map_initialise(ohm_map_s* map, hipStream_t st) {
   launch_fill(m.acc, (size_t)m.capacity * V * 2 * sizeof(float), 0u, st);
   if (m.ndt) {
     launch_fill(m.ndt, (size_t)m.capacity * V * sizeof(NdtVoxel), 0u, st);
-    launch_fill(m.mom, (size_t)m.capacity * V * kMomWords * sizeof(long long), 0u, st);
+    launch_fill(m.nacc, (size_t)m.capacity * V * kNaccWords * sizeof(long long), 0u, st);
+    launch_fill(m.mom, (size_t)m.capacity * V * kMomWords * sizeof(double), 0u, st);
   }
   if (m.clampscan) launch_fill(m.clampscan, (size_t)m.capacity * V * sizeof(uint32_t), 0u, st);
   map->count_batches = 0;
@@ -664,7 +623,8 @@ ohm_status ohm_map_create(const ohm_params* params, uint32_t region_capacity, ui
   dm.occ = reinterpret_cast<float*>(base + L.occ);
   dm.acc = reinterpret_cast<float*>(base + L.acc);
   dm.ndt = (layers & OHM_LAYER_NDT) ? reinterpret_cast<NdtVoxel*>(base + L.ndt) : nullptr;
-  dm.mom = (layers & OHM_LAYER_NDT) ? reinterpret_cast<long long*>(base + L.mom) : nullptr;
+  dm.nacc = (layers & OHM_LAYER_NDT) ? reinterpret_cast<long long*>(base + L.nacc) : nullptr;
+  dm.mom = (layers & OHM_LAYER_NDT) ? reinterpret_cast<double*>(base + L.mom) : nullptr;
   dm.clampscan = (layers & OHM_LAYER_ADJOINT) ? reinterpret_cast<uint32_t*>(base + L.clampscan) : nullptr;
   s = map_initialise(map, as_stream(stream));
   if (s != OHM_OK) {

@@ -1,0 +1,344 @@
+// NDT-OM integration (paper Sec. II-D and III-C).
+//
+// Each voxel of an NDT map keeps a sample count n, a mean mu and a population
+// covariance Sigma (voxel-centred, metres).  Per scan:
+//   phase 1 (ndt_walk_kernel): every ray is walked exactly as in the occupancy
+//     path.  Each miss voxel whose statistics hold >= ndt_min_samples samples
+//     weights its miss by the Gaussian agreement of the ray with the samples:
+//       x* = closest point of the segment to mu,  D = x* - mu,
+//       S = Sigma + sensor_noise^2 I,  g = exp(-D^T S^-1 D / 2),
+//       p = 1/2 - lambda g (1/2 - sigmoid(l_miss)),  delta = logit(p),
+//     (plain l_miss otherwise); statistics are only read in this phase.
+//     Increments are summed per voxel as Q32.32 integers (exact, so the
+//     result does not depend on the order the GPU adds them in); in
+//     per-update mode the misses are instead applied at once by CAS.  A hit
+//     adds its sample's offset x from the voxel centre to the voxel's
+//     moments (sum x, sum x x^T, fp64) and counts one sample.
+//   phase 2 (ndt_finalize_kernel): one thread per voxel of the scan's
+//     regions applies the occupancy update, clears the statistics of voxels
+//     that fell below ndt_clear_below, and merges the scan's sample moments
+//     into (n, mu, Sigma) (Chan et al.'s pairwise update), as the paper's
+//     per-voxel second phase does.
+#include <hip/hip_runtime.h>
+#include <math.h>
+#include <stdint.h>
+
+#include "ohm.h"
+#include "ohm_device.h"
+#include "ohm_host.h"
+#include "ohm_regions.h"
+#include "ohm_wave.h"
+
+namespace ohm {
+
+constexpr double kQ = 4294967296.0;  // 2^32: Q32.32 scale
+constexpr double kInvQ = 1.0 / 4294967296.0;
+
+// The NDT-weighted miss increment (see the file comment).  o / d: ray start
+// and direction (end - start), world, fp64; c: voxel centre; nv: statistics.
+__device__ __forceinline__ double ndt_delta(const DevMap& m, const double o[3], const double d[3], double dd,
+                                            const double c[3], const NdtVoxel& nv, double sig_miss) {
+#pragma clang fp contract(off)
+  double mu[3], w[3];
+  double wd = 0.0;
+  for (int a = 0; a < 3; ++a) {
+    mu[a] = c[a] + (double)nv.mean[a];
+    w[a] = mu[a] - o[a];
+    wd = wd + w[a] * d[a];
+  }
+  double t = dd > 0.0 ? wd / dd : 0.0;
+  t = t < 0.0 ? 0.0 : (t > 1.0 ? 1.0 : t);
+  double D[3];
+  for (int a = 0; a < 3; ++a) D[a] = (o[a] + t * d[a]) - mu[a];
+  const double s2 = (double)m.sensor_noise * (double)m.sensor_noise;
+  // Cholesky of S = Sigma + s2 I; D^T S^-1 D = |L^-1 D|^2
+  const double a00 = (double)nv.cov[0] + s2, a10 = nv.cov[1], a20 = nv.cov[2];
+  const double a11 = (double)nv.cov[3] + s2, a21 = nv.cov[4], a22 = (double)nv.cov[5] + s2;
+  const double l00 = sqrt(a00);
+  const double l10 = a10 / l00, l20 = a20 / l00;
+  const double l11 = sqrt(a11 - l10 * l10);
+  const double l21 = (a21 - l20 * l10) / l11;
+  const double l22 = sqrt(a22 - l20 * l20 - l21 * l21);
+  const double z0 = D[0] / l00;
+  const double z1 = (D[1] - l10 * z0) / l11;
+  const double z2 = (D[2] - l20 * z0 - l21 * z1) / l22;
+  const double q = z0 * z0 + z1 * z1 + z2 * z2;
+  const double g = exp(-0.5 * q);
+  const double p = 0.5 - (double)m.adaptation_rate * g * (0.5 - sig_miss);
+  return log(p / (1.0 - p));
+}
+
+template <bool kCount, bool kWeighted>
+__global__ __launch_bounds__(256) void ndt_walk_kernel(DevMap m, const float* __restrict__ origins, uint32_t scan,
+                                                       const float* __restrict__ samples,
+                                                       const float* __restrict__ weights, uint32_t r0, uint32_t n,
+                                                       uint32_t tag, uint32_t parity, double sig_miss) {
+#pragma clang fp contract(off)
+  const uint32_t lane = lane_id();
+  const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+  const bool inrange = i < n;
+  const size_t ray = (size_t)r0 + i;
+  const float o[3] = {origins[3 * scan + 0], origins[3 * scan + 1], origins[3 * scan + 2]};
+  float e[3] = {0.f, 0.f, 0.f};
+  if (inrange) {
+    e[0] = samples[3 * ray + 0];
+    e[1] = samples[3 * ray + 1];
+    e[2] = samples[3 * ray + 2];
+  }
+  Ray r;
+  const int st = inrange ? prepare_ray(m, o, e, r) : kRayInvalid;
+  bool alive = inrange && st == kRayOk;
+  const double wt = (kWeighted && inrange) ? (double)weights[ray] : 1.0;
+
+  __shared__ RegionCache rc;
+  stage_regions<true>(m, rc, alive, r, tag, parity);
+
+  const double od[3] = {(double)o[0], (double)o[1], (double)o[2]};
+  double dv[3] = {0.0, 0.0, 0.0};
+  double dd = 0.0;
+  Walk w;
+  int32_t kx = 0, ky = 0, kz = 0;
+  int32_t slot = -1;
+  uint32_t lidx = 0;
+  if (alive) {
+    for (int a = 0; a < 3; ++a) {
+      dv[a] = r.end[a] - od[a];
+      dd = dd + dv[a] * dv[a];
+    }
+    int32_t hi[3] = {m.kmax[0] - 1, m.kmax[1] - 1, m.kmax[2] - 1};
+    walk_init(w, r.q0, r.q1, r.k0, r.k1, m.kmin, hi, m.F);
+    kx = r.k0[0];
+    ky = r.k0[1];
+    kz = r.k0[2];
+    slot = staged_slot(m, rc, kx, ky, kz);
+    lidx = local_index(kx, ky, kz);
+  }
+  const long long q_plain = llrint((double)m.l_miss * wt * kQ);
+  uint32_t n_upd = 0, n_drop = 0, n_hit = 0;
+  bool clipped = false;
+
+  while (__ballot(alive)) {
+    const bool last = alive && w.total == 0;
+    const bool is_hit = last && !r.truncated;
+    const bool has = alive && slot >= 0;
+    const size_t v = has ? (size_t)slot * kRegionVoxels + lidx : 0;
+    long long q = 0;
+    if (has) {
+      if (is_hit) {
+        q = llrint(wt * kQ);
+      } else {
+        q = q_plain;
+        const uint32_t cnt = m.ndt[v].n;
+        if (cnt >= m.ndt_min_samples) {
+          const NdtVoxel nv = m.ndt[v];
+          const double c[3] = {m.origin[0] + ((double)kx + 0.5) * m.voxel_size,
+                               m.origin[1] + ((double)ky + 0.5) * m.voxel_size,
+                               m.origin[2] + ((double)kz + 0.5) * m.voxel_size};
+          q = llrint(ndt_delta(m, od, dv, dd, c, nv, sig_miss) * wt * kQ);
+        }
+      }
+    }
+    const uint32_t id = has ? (((uint32_t)slot * (uint32_t)kRegionVoxels + lidx) << 1) | (is_hit ? 1u : 0u)
+                            : (0xFFFFFFFFu - lane);
+    const LaneRuns run = lane_runs(id, lane);
+    const long long qs = segmented_sum(q, run.head, lane);
+    if (has && run.tail) {
+      if (kCount || is_hit) {
+        atomicAdd(reinterpret_cast<unsigned long long*>(m.nacc + v * kNaccWords + (is_hit ? kNaccHit : kNaccMiss)),
+                  (unsigned long long)qs);
+      } else {
+        // per-update mode: the scan's misses land first, by CAS
+        uint32_t* u = reinterpret_cast<uint32_t*>(m.occ + v);
+        const float delta = (float)((double)qs * kInvQ);
+        uint32_t old = __hip_atomic_load(u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        for (;;) {
+          const float nvv = fminf(fmaxf(__uint_as_float(old) + delta, m.l_min), m.l_max);
+          const uint32_t prev = atomicCAS(u, old, __float_as_uint(nvv));
+          if (prev == old) break;
+          old = prev;
+        }
+      }
+    }
+    if (has && is_hit) {
+      // sample moments (fp64), voxel-centred: x = sample - centre
+      const double x0 = (double)e[0] - (m.origin[0] + ((double)kx + 0.5) * m.voxel_size);
+      const double x1 = (double)e[1] - (m.origin[1] + ((double)ky + 0.5) * m.voxel_size);
+      const double x2 = (double)e[2] - (m.origin[2] + ((double)kz + 0.5) * m.voxel_size);
+      double* mo = m.mom + v * kMomWords;
+      unsafeAtomicAdd(mo + 0, x0);
+      unsafeAtomicAdd(mo + 1, x1);
+      unsafeAtomicAdd(mo + 2, x2);
+      unsafeAtomicAdd(mo + 3, x0 * x0);
+      unsafeAtomicAdd(mo + 4, x0 * x1);
+      unsafeAtomicAdd(mo + 5, x0 * x2);
+      unsafeAtomicAdd(mo + 6, x1 * x1);
+      unsafeAtomicAdd(mo + 7, x1 * x2);
+      unsafeAtomicAdd(mo + 8, x2 * x2);
+      atomicAdd(reinterpret_cast<unsigned long long*>(m.nacc + v * kNaccWords + kNaccSamples), 1ull);
+    }
+    if (alive) {
+      if (slot >= 0) {
+        ++n_upd;
+        n_hit += is_hit ? 1u : 0u;
+      } else {
+        ++n_drop;
+      }
+    }
+    if (alive) {
+      if (last) {
+        alive = false;
+      } else {
+        const int a = walk_step(w);
+        const int32_t ra = a == 0 ? w.rem[0] : (a == 1 ? w.rem[1] : w.rem[2]);
+        if (ra == 0 && ((w.clip >> a) & 1u)) {
+          alive = false;
+          clipped = true;
+        } else {
+          const int32_t sg = a == 0 ? w.sg[0] : (a == 1 ? w.sg[1] : w.sg[2]);
+          kx += a == 0 ? sg : 0;
+          ky += a == 1 ? sg : 0;
+          kz += a == 2 ? sg : 0;
+          const int32_t kn = a == 0 ? kx : (a == 1 ? ky : kz);
+          if ((kn & kRegionMask) == (sg > 0 ? 0 : kRegionMask)) {
+            slot = staged_slot(m, rc, kx, ky, kz);
+            lidx = local_index(kx, ky, kz);
+          } else {
+            lidx += (uint32_t)(a == 0 ? sg : (a == 1 ? sg * kRegionEdge : sg * kRegionEdge * kRegionEdge));
+          }
+        }
+      }
+    }
+  }
+  uint32_t vals[kStatCount];
+  vals[kStatRays] = inrange ? 1u : 0u;
+  vals[kStatInvalid] = (inrange && st == kRayInvalid) ? 1u : 0u;
+  vals[kStatOriginOob] = (inrange && st == kRayOriginOob) ? 1u : 0u;
+  vals[kStatTruncated] = (st == kRayOk && inrange && r.truncated) ? 1u : 0u;
+  vals[kStatClipped] = clipped ? 1u : 0u;
+  vals[kStatHits] = n_hit;
+  vals[kStatUpdates] = n_upd;
+  vals[kStatDropped] = n_drop;
+  flush_stats(m, vals);
+}
+
+constexpr int kNdtChunk = 2048;
+constexpr int kNdtUnits = kRegionVoxels / kNdtChunk;
+
+__global__ __launch_bounds__(256) void ndt_finalize_kernel(DevMap m, uint32_t parity, int count_mode,
+                                                           uint32_t scan_tag) {
+#pragma clang fp contract(off)
+  const uint32_t count = __hip_atomic_load(m.hdr + kHdrTouched0 + parity, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  const uint32_t units = count * kNdtUnits;
+  const double lmin = m.l_min, lmax = m.l_max;
+  for (uint32_t unit = blockIdx.x; unit < units; unit += gridDim.x) {
+    const uint32_t slot = m.touched[(size_t)parity * m.capacity + unit / kNdtUnits];
+    const size_t base = (size_t)slot * kRegionVoxels + (size_t)(unit % kNdtUnits) * kNdtChunk;
+    for (int j = threadIdx.x; j < kNdtChunk; j += blockDim.x) {
+      const size_t v = base + j;
+      longlong2* ap = reinterpret_cast<longlong2*>(m.nacc + v * kNaccWords);
+      const longlong2 a01 = ap[0];
+      const longlong2 a23 = ap[1];
+      if (a01.x == 0 && a01.y == 0 && a23.x == 0) continue;
+      const double miss = (double)a01.x * kInvQ;
+      const double hitw = (double)a01.y * kInvQ;
+      double l = (double)m.occ[v];
+      double s = count_mode ? (l + hitw * (double)m.l_hit) + miss : l + hitw * (double)m.l_hit;
+      if (m.clampscan && (s < lmin || s > lmax)) m.clampscan[v] = scan_tag;
+      s = s < lmin ? lmin : (s > lmax ? lmax : s);
+      const float lf = (float)s;
+      m.occ[v] = lf;
+      NdtVoxel nv = m.ndt[v];
+      bool dirty = false;
+      if (lf < m.ndt_clear_below && nv.n != 0) {
+        nv.n = 0;
+        for (int c = 0; c < 3; ++c) nv.mean[c] = 0.f;
+        for (int c = 0; c < 6; ++c) nv.cov[c] = 0.f;
+        dirty = true;
+      }
+      const long long nb = a23.x;
+      if (nb > 0) {
+        double* mo = m.mom + v * kMomWords;
+        const double inv = 1.0 / (double)nb;
+        // scan statistics (metres): mean and population covariance
+        double mub[3], cb[6];
+        for (int c = 0; c < 3; ++c) mub[c] = mo[c] * inv;
+        cb[0] = mo[3] * inv - mub[0] * mub[0];
+        cb[1] = mo[4] * inv - mub[0] * mub[1];
+        cb[2] = mo[5] * inv - mub[0] * mub[2];
+        cb[3] = mo[6] * inv - mub[1] * mub[1];
+        cb[4] = mo[7] * inv - mub[1] * mub[2];
+        cb[5] = mo[8] * inv - mub[2] * mub[2];
+        // pairwise merge with the stored statistics
+        const double na = (double)nv.n, nbd = (double)nb, nt = na + nbd;
+        double d[3];
+        for (int c = 0; c < 3; ++c) d[c] = mub[c] - (double)nv.mean[c];
+        const double f = na * nbd / (nt * nt);
+        const int ii[6] = {0, 0, 0, 1, 1, 2};
+        const int jj[6] = {0, 1, 2, 1, 2, 2};
+#pragma unroll
+        for (int c = 0; c < 6; ++c)
+          nv.cov[c] = (float)((na * (double)nv.cov[c] + nbd * cb[c]) / nt + d[ii[c]] * d[jj[c]] * f);
+        for (int c = 0; c < 3; ++c) nv.mean[c] = (float)((double)nv.mean[c] + d[c] * (nbd / nt));
+        nv.n = nv.n + (uint32_t)nb;
+        for (int c = 0; c < kMomWords; ++c) mo[c] = 0.0;
+        dirty = true;
+      }
+      if (dirty) m.ndt[v] = nv;
+      ap[0] = make_longlong2(0, 0);
+      ap[1] = make_longlong2(0, 0);
+    }
+  }
+  if (blockIdx.x == 0 && threadIdx.x == 0)
+    __hip_atomic_store(m.hdr + kHdrTouched0 + (parity ^ 1u), 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+}  // namespace ohm
+
+using namespace ohm;
+
+extern "C" ohm_status ohm_ndt_integrate(ohm_map map, const float* d_origins, const float* d_samples,
+                                        const uint32_t* h_scan_offsets, uint32_t n_scans, const float* d_weights,
+                                        void* stream) {
+  ohm_status s = check_scans(map, d_origins, d_samples, h_scan_offsets, n_scans);
+  if (s != OHM_OK || n_scans == 0) return s;
+  if (!map->dm.ndt) return OHM_E_INVALID_ARG;
+  hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+  const bool count_mode = map->params.mode == OHM_MODE_COUNT_CLAMP;
+  const bool weighted = d_weights != nullptr;
+  const double sig_miss = 1.0 / (1.0 + exp(-(double)map->params.l_miss));
+  for (uint32_t sc = 0; sc < n_scans; ++sc) {
+    const uint32_t r0 = h_scan_offsets[sc];
+    const uint32_t n = h_scan_offsets[sc + 1] - r0;
+    if (n == 0) continue;
+    clear_pending(map, st);
+    const uint32_t tag = ++map->count_batches;
+    const uint32_t parity = tag & 1u;
+    const dim3 grid((n + 255) / 256);
+    {
+      ProfScope ps(map, OHM_KERNEL_WALK, st);
+      if (count_mode) {
+        if (weighted)
+          hipLaunchKernelGGL((ndt_walk_kernel<true, true>), grid, dim3(256), 0, st, map->dm, d_origins, sc,
+                             d_samples, d_weights, r0, n, tag, parity, sig_miss);
+        else
+          hipLaunchKernelGGL((ndt_walk_kernel<true, false>), grid, dim3(256), 0, st, map->dm, d_origins, sc,
+                             d_samples, d_weights, r0, n, tag, parity, sig_miss);
+      } else {
+        if (weighted)
+          hipLaunchKernelGGL((ndt_walk_kernel<false, true>), grid, dim3(256), 0, st, map->dm, d_origins, sc,
+                             d_samples, d_weights, r0, n, tag, parity, sig_miss);
+        else
+          hipLaunchKernelGGL((ndt_walk_kernel<false, false>), grid, dim3(256), 0, st, map->dm, d_origins, sc,
+                             d_samples, d_weights, r0, n, tag, parity, sig_miss);
+      }
+    }
+    {
+      ProfScope ps(map, OHM_KERNEL_NDT_HIT, st);
+      hipLaunchKernelGGL(ndt_finalize_kernel, dim3(kFinalizeBlocks), dim3(256), 0, st, map->dm, parity,
+                         count_mode ? 1 : 0, map->scans_done + 1);
+    }
+    map->scans_done += 1;
+  }
+  hipError_t e = hipGetLastError();
+  return e == hipSuccess ? OHM_OK : OHM_E_HIP;
+}

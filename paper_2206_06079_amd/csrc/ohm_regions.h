@@ -9,6 +9,7 @@
 #pragma once
 
 #include "ohm_device.h"
+#include "ohm_wave.h"
 
 namespace ohm {
 
@@ -147,6 +148,23 @@ __device__ __forceinline__ int32_t staged_slot(const DevMap& m, const RegionCach
     s = s < kSlotExhausted ? kSlotExhausted : s;  // consume the load here
   }
   return s;
+}
+
+// Accumulate statistics of a block into the map's counters with one atomic
+// per counter per block.
+__device__ __forceinline__ void flush_stats(const DevMap& m, const uint32_t (&vals)[kStatCount]) {
+  __shared__ uint32_t part[kStatCount];
+  if (threadIdx.x < kStatCount) part[threadIdx.x] = 0;
+  __syncthreads();
+  uint32_t lane = lane_id();
+#pragma unroll
+  for (int c = 0; c < kStatCount; ++c) {
+    uint32_t s = wave_sum_u32(vals[c]);
+    if (lane == 0 && s) atomicAdd(&part[c], s);
+  }
+  __syncthreads();
+  if (threadIdx.x < kStatCount && part[threadIdx.x])
+    atomicAdd(m.stats + threadIdx.x, (unsigned long long)part[threadIdx.x]);
 }
 
 }  // namespace ohm

@@ -71,6 +71,9 @@ def _load():
     lib.orc_integrate_envelope.argtypes = [P(OrcParams), ctypes.c_int32, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp]
     lib.orc_ndt_integrate.restype = ctypes.c_int
     lib.orc_ndt_integrate.argtypes = [P(OrcParams), ctypes.c_int32, ctypes.c_int32] + [vp] * 12
+    lib.orc_adjoint.restype = ctypes.c_int
+    lib.orc_adjoint.argtypes = [P(OrcParams), ctypes.c_int32, ctypes.c_int32, vp, vp, vp, vp, vp, vp, vp, vp,
+                                ctypes.c_double, ctypes.c_int32, vp, vp, vp, vp, vp, vp]
     lib.orc_ndt_miss_delta.restype = ctypes.c_double
     lib.orc_ndt_miss_delta.argtypes = [P(OrcParams), vp, vp, vp, vp, ctypes.c_uint32]
     _lib = lib
@@ -222,3 +225,30 @@ def ndt_integrate(mp, batch, box_min=None, box_dim=None, occ=None, state=None, m
     if rc != 0:
         raise MemoryError("oracle box allocation failed")
     return occ, state, miss, dict(zip(STATS_FIELDS, (int(v) for v in stats)))
+
+
+def adjoint(mp, batch, box_min, box_dim, labels, mask=None, ndt=True, grads=True, near_eps=1e-3):
+    """fp64 differentiable forward over the loss box and, with ``grads``, the
+    analytic gradients (paper's count-mode update, BCE loss on sigmoid(l)).
+    Returns a dict with loss, occ, clamp_last, near, grad_w [N], grad_scalars
+    (d/d l_hit, l_miss, sensor_noise)."""
+    lib = _load()
+    p = make_params(mp)
+    bmin = np.asarray(box_min, np.int32)
+    bdim = np.asarray(box_dim, np.int32)
+    shape = (int(bdim[2]), int(bdim[1]), int(bdim[0]))
+    y = np.ascontiguousarray(labels, np.float64).reshape(shape)
+    m = np.ones(shape, np.float64) if mask is None else np.ascontiguousarray(mask, np.float64).reshape(shape)
+    loss = ctypes.c_double(0.0)
+    occ = np.zeros(shape, np.float64)
+    cl = np.zeros(shape, np.uint32)
+    near = np.zeros(shape, np.uint8)
+    gw = np.zeros(batch.n_rays, np.float64) if grads else None
+    gs = np.zeros(3, np.float64) if grads else None
+    o, s, off, w = _batch_arrays(batch)
+    rc = lib.orc_adjoint(ctypes.byref(p), 1 if ndt else 0, batch.n_scans, _ptr(off), _ptr(o), _ptr(s), _ptr(w),
+                         _ptr(bmin), _ptr(bdim), _ptr(y), _ptr(m), float(near_eps), 1 if grads else 0,
+                         ctypes.byref(loss), _ptr(occ), _ptr(cl), _ptr(near), _ptr(gw), _ptr(gs))
+    if rc != 0:
+        raise MemoryError("oracle allocation failed")
+    return dict(loss=loss.value, occ=occ, clamp_last=cl, near=near, grad_w=gw, grad_scalars=gs)

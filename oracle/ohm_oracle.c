@@ -665,5 +665,244 @@ int orc_ndt_integrate(const orc_params* p, int32_t mode, int32_t n_scans, const 
   return 0;
 }
 
+/* ---------------------------------------------------------------------- */
+/* Adjoint                                                                 */
+/* ---------------------------------------------------------------------- */
+/*
+ * Differentiable forward: count-then-clamp per scan in fp64 (no float
+ * storage), over a window (the loss box; voxels are independent, so voxels
+ * outside it cannot influence the loss).  With ndt != 0 misses use the
+ * NDT-weighted increment of orc_ndt_integrate (statistics before the scan,
+ * clearing disabled).  Per scan k (1-based tag k):
+ *     s_v = (l_v + H_v l_hit) + U_v,   l_v <- clamp(s_v),
+ * H_v = sum of hit weights, U_v = sum of weighted miss increments; c_v is
+ * the last k with s_v outside [l_min, l_max].  Loss
+ *     L = sum_v m_v BCE(sigmoid(l_v), y_v),   G_v = m_v (sigmoid(l_v) - y_v).
+ * Because the clamp passes gradients only while inactive, dL/dDelta_{k,v} =
+ * G_v [k > c_v], so for ray r of scan k
+ *     dL/dw_r      = sum_{v in walk(r)} G_v [k > c_v] delta_{r,v},
+ *     dL/dl_hit    = sum_r w_r G_{hit(r)} [k > c],
+ *     dL/dl_miss   = sum_r w_r sum_{miss v} G_v [k > c_v] d delta/d l_miss,
+ *     dL/dsigma_n  = sum_r w_r sum_{miss v} G_v [k > c_v] d delta/d sigma_n,
+ * with, for an NDT-weighted miss (q = D^T S^-1 D, g = exp(-q/2)),
+ *     d delta/d l_miss  = lambda g s(1-s) / (p (1-p)),   s = sigmoid(l_miss),
+ *     d delta/d sigma_n = -lambda (1/2 - s) g sigma_n |S^-1 D|^2 / (p (1-p)),
+ * and 1, 0 for a plain miss.  The backward replays the sample statistics
+ * scan by scan (they depend on no differentiated parameter).
+ */
+
+/* NDT miss increment and its two partial derivatives. */
+static void ndt_miss_terms(const orc_params* p, const double o[3], const double e[3], const double mu_w[3],
+                           const double cov[6], uint32_t n, double* delta, double* d_lmiss, double* d_sig) {
+  double lm = (double)p->l_miss;
+  if (n < (uint32_t)p->ndt_min_samples) {
+    *delta = lm;
+    *d_lmiss = 1.0;
+    *d_sig = 0.0;
+    return;
+  }
+  double d[3], w[3];
+  double dd = 0.0, wd = 0.0;
+  for (int a = 0; a < 3; ++a) {
+    d[a] = e[a] - o[a];
+    w[a] = mu_w[a] - o[a];
+    dd += d[a] * d[a];
+    wd += w[a] * d[a];
+  }
+  double t = dd > 0.0 ? wd / dd : 0.0;
+  if (t < 0.0) t = 0.0;
+  if (t > 1.0) t = 1.0;
+  double D[3];
+  for (int a = 0; a < 3; ++a) D[a] = (o[a] + t * d[a]) - mu_w[a];
+  double sn = p->sensor_noise, s2 = sn * sn;
+  double S[3][3] = {{cov[0] + s2, cov[1], cov[2]}, {cov[1], cov[3] + s2, cov[4]}, {cov[2], cov[4], cov[5] + s2}};
+  /* y = S^-1 D by Gaussian elimination (S is SPD, no pivoting needed) */
+  double A[3][4];
+  for (int i = 0; i < 3; ++i) {
+    for (int j = 0; j < 3; ++j) A[i][j] = S[i][j];
+    A[i][3] = D[i];
+  }
+  for (int c = 0; c < 3; ++c)
+    for (int r = c + 1; r < 3; ++r) {
+      double f = A[r][c] / A[c][c];
+      for (int j = c; j < 4; ++j) A[r][j] -= f * A[c][j];
+    }
+  double y[3];
+  for (int r = 2; r >= 0; --r) {
+    double acc = A[r][3];
+    for (int j = r + 1; j < 3; ++j) acc -= A[r][j] * y[j];
+    y[r] = acc / A[r][r];
+  }
+  double q = D[0] * y[0] + D[1] * y[1] + D[2] * y[2];
+  double yy = y[0] * y[0] + y[1] * y[1] + y[2] * y[2];
+  double g = exp(-0.5 * q);
+  double sg = sigmoid_d(lm);
+  double lam = p->adaptation_rate;
+  double pr = 0.5 - lam * g * (0.5 - sg);
+  double inv = 1.0 / (pr * (1.0 - pr));
+  *delta = log(pr / (1.0 - pr));
+  *d_lmiss = lam * g * sg * (1.0 - sg) * inv;
+  *d_sig = -lam * (0.5 - sg) * g * sn * yy * inv;
+}
+
+static double bce_logit(double l, double y) {
+  /* -[y log s(l) + (1-y) log(1 - s(l))], stable in l */
+  double a = l > 0 ? l : 0.0;
+  return a - l * y + log(exp(-a) + exp(l - a));
+}
+
+/*
+ * Forward + (optionally) analytic gradients.  Window = loss box.
+ *   labels, mask   [dz][dy][dx] fp64 (y_v, m_v)
+ *   loss           out: L
+ *   occ            optional out [dz][dy][dx] fp64: final l
+ *   clamp_last     optional out [dz][dy][dx] uint32: c_v
+ *   near           optional out [dz][dy][dx] uint8: pre-clamp value came within
+ *                  near_eps of a bound in some scan
+ *   grad_w         optional out [N] fp64 (only with grads != 0)
+ *   grad_s         optional out [3] fp64: d/d(l_hit, l_miss, sensor_noise)
+ */
+int orc_adjoint(const orc_params* p, int32_t ndt, int32_t n_scans, const uint32_t* offsets, const float* origins,
+                const float* samples, const float* weights, const int32_t box_min[3], const int32_t box_dim[3],
+                const double* labels, const double* mask, double near_eps, int32_t grads, double* loss,
+                double* occ_out, uint32_t* clamp_last_out, unsigned char* near_out, double* grad_w,
+                double* grad_s) {
+  size_t nv = (size_t)box_dim[0] * box_dim[1] * box_dim[2];
+  double* l = (double*)malloc(nv * sizeof(double));
+  double* wh = (double*)calloc(nv, sizeof(double));
+  double* um = (double*)calloc(nv, sizeof(double));
+  unsigned char* touched = (unsigned char*)calloc(nv, 1);
+  uint32_t* cl = (uint32_t*)calloc(nv, sizeof(uint32_t));
+  unsigned char* nr = (unsigned char*)calloc(nv, 1);
+  uint32_t* nn = (uint32_t*)calloc(nv, sizeof(uint32_t));
+  double* mu = (double*)calloc(nv * 3, sizeof(double));
+  double* cv = (double*)calloc(nv * 6, sizeof(double));
+  double* G = (double*)calloc(nv, sizeof(double));
+  if (!l || !wh || !um || !touched || !cl || !nr || !nn || !mu || !cv || !G) return -1;
+  for (size_t v = 0; v < nv; ++v) l[v] = (double)p->l_init;
+  double lmin = (double)p->l_min, lmax = (double)p->l_max;
+  orc_scratch s = {0};
+  for (int pass = 0; pass < (grads ? 2 : 1); ++pass) {
+    if (pass == 1) {
+      /* backward: replay statistics from empty */
+      memset(nn, 0, nv * sizeof(uint32_t));
+      memset(mu, 0, nv * 3 * sizeof(double));
+      memset(cv, 0, nv * 6 * sizeof(double));
+      if (grad_s) grad_s[0] = grad_s[1] = grad_s[2] = 0.0;
+    }
+    for (int32_t sc = 0; sc < n_scans; ++sc) {
+      uint32_t tag = (uint32_t)sc + 1;
+      if (pass == 0) {
+        memset(wh, 0, nv * sizeof(double));
+        memset(um, 0, nv * sizeof(double));
+        memset(touched, 0, nv);
+      }
+      const float* of = origins + 3 * sc;
+      double o[3] = {(double)of[0], (double)of[1], (double)of[2]};
+      for (uint32_t i = offsets[sc]; i < offsets[sc + 1]; ++i) {
+        orc_ray r;
+        prepare_ray(p, of, samples + 3 * (size_t)i, &r);
+        if (pass == 1 && grad_w) grad_w[i] = 0.0;
+        if (r.status != ORC_RAY_OK) continue;
+        int clipped = 0;
+        int64_t nk = walk_ray(p, &r, &s, &clipped);
+        int has_hit = !r.truncated && !clipped;
+        double w = weights ? (double)weights[i] : 1.0;
+        double gw = 0.0;
+        for (int64_t j = 0; j < nk; ++j) {
+          const int32_t* key = s.keys + 3 * j;
+          int64_t v = box_index(key, box_min, box_dim);
+          if (v < 0) continue;
+          int is_hit = has_hit && j == nk - 1;
+          double delta, dlm, dsig;
+          if (is_hit) {
+            delta = (double)p->l_hit;
+            dlm = dsig = 0.0;
+          } else if (ndt) {
+            double c[3], muw[3];
+            voxel_centre(p, key, c);
+            for (int a = 0; a < 3; ++a) muw[a] = c[a] + mu[3 * v + a];
+            ndt_miss_terms(p, o, r.end, muw, cv + 6 * v, nn[v], &delta, &dlm, &dsig);
+          } else {
+            delta = (double)p->l_miss;
+            dlm = 1.0;
+            dsig = 0.0;
+          }
+          if (pass == 0) {
+            touched[v] = 1;
+            if (is_hit)
+              wh[v] += w;
+            else
+              um[v] += w * delta;
+          } else if (G[v] != 0.0 && tag > cl[v]) {
+            gw += G[v] * delta;
+            if (grad_s) {
+              if (is_hit)
+                grad_s[0] += w * G[v];
+              else {
+                grad_s[1] += w * G[v] * dlm;
+                grad_s[2] += w * G[v] * dsig;
+              }
+            }
+          }
+        }
+        if (pass == 1 && grad_w) grad_w[i] = gw;
+      }
+      if (pass == 0) {
+        for (size_t v = 0; v < nv; ++v) {
+          if (!touched[v]) continue;
+          double sv = (l[v] + wh[v] * (double)p->l_hit) + um[v];
+          if (sv < lmin || sv > lmax) cl[v] = tag;
+          if (fabs(sv - lmin) < near_eps || fabs(sv - lmax) < near_eps) nr[v] = 1;
+          l[v] = clampd_(sv, lmin, lmax);
+        }
+      }
+      if (ndt) {
+        /* fold the scan's samples (ascending ray order) */
+        for (uint32_t i = offsets[sc]; i < offsets[sc + 1]; ++i) {
+          orc_ray r;
+          prepare_ray(p, of, samples + 3 * (size_t)i, &r);
+          if (r.status != ORC_RAY_OK || r.truncated) continue;
+          int clipped = 0;
+          int64_t nk = walk_ray(p, &r, &s, &clipped);
+          if (clipped) continue;
+          const int32_t* key = s.keys + 3 * (nk - 1);
+          int64_t v = box_index(key, box_min, box_dim);
+          if (v < 0) continue;
+          double c[3], x[3];
+          voxel_centre(p, key, c);
+          const float* e = samples + 3 * (size_t)i;
+          for (int a = 0; a < 3; ++a) x[a] = (double)e[a] - c[a];
+          welford_add(nn + v, mu + 3 * v, cv + 6 * v, x);
+        }
+      }
+    }
+    if (pass == 0) {
+      double L = 0.0;
+      for (size_t v = 0; v < nv; ++v) {
+        if (mask[v] == 0.0) continue;
+        L += mask[v] * bce_logit(l[v], labels[v]);
+        G[v] = mask[v] * (sigmoid_d(l[v]) - labels[v]);
+      }
+      *loss = L;
+    }
+  }
+  if (occ_out) memcpy(occ_out, l, nv * sizeof(double));
+  if (clamp_last_out) memcpy(clamp_last_out, cl, nv * sizeof(uint32_t));
+  if (near_out) memcpy(near_out, nr, nv);
+  scratch_free(&s);
+  free(l);
+  free(wh);
+  free(um);
+  free(touched);
+  free(cl);
+  free(nr);
+  free(nn);
+  free(mu);
+  free(cv);
+  free(G);
+  return 0;
+}
+
 /* Library self-identification for the loaders. */
 int orc_abi_version(void) { return 1; }

@@ -188,6 +188,30 @@ ohm_status ohm_ndt_integrate(ohm_map map, const float* d_origins, const float* d
                              void* stream);
 
 /*
+ * Adjoint of count-mode integration (the gradient of a loss on the final
+ * log-odds; forward per scan k and voxel v: s = (l + H l_hit) + U,
+ * l <- clamp(s), with H the summed hit weight and U the summed weighted miss
+ * increments).  Requirements: the map was created with OHM_LAYER_ADJOINT,
+ * mode OHM_MODE_COUNT_CLAMP, and since its last create / reset has integrated
+ * exactly these scans (same arguments) with ohm_ndt_integrate (ndt != 0,
+ * NDT clearing disabled) or ohm_integrate_rays (ndt == 0).
+ *   d_grad          float[box_dim z][y][x]: dL/dl (final log-odds) over the box
+ *                   at h_box_min; voxels outside the box have zero gradient
+ *   d_grad_weights  float[N] or NULL: receives dL/dw_r for every ray
+ *                   (0 for skipped rays)
+ *   d_grad_scalars  double[3]: receives dL/d(l_hit, l_miss, sensor_noise)
+ *                   (overwritten, not accumulated)
+ * The traversals are recomputed, not stored.  For NDT maps the sample
+ * statistics are rebuilt in place scan by scan and hold the same values
+ * afterwards.  Returns OHM_E_UNSUPPORTED for per-update mode or enabled NDT
+ * clearing (neither is differentiable here).
+ */
+ohm_status ohm_backward(ohm_map map, int32_t ndt, const float* d_grad, const int32_t h_box_min[3],
+                        const int32_t h_box_dim[3], const float* d_origins, const float* d_samples,
+                        const uint32_t* h_scan_offsets, uint32_t n_scans, const float* d_weights,
+                        float* d_grad_weights, double* d_grad_scalars, void* stream);
+
+/*
  * Copy a dense box of one quantity to d_out, laid out [box_dim z][y][x]
  * (x fastest) with the element type listed for `what`.  Voxels outside the
  * map or in unallocated regions read as never touched.

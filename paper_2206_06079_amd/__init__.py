@@ -11,4 +11,4 @@ from ._lib import (  # noqa: F401
     READ_CLAMP_SCAN, READ_HITS, READ_MISSES, READ_NDT_COUNT, READ_NDT_COV, READ_NDT_MEAN, READ_OCC,
     OhmError,
 )
-from .ohm import OhmMap, regions_needed  # noqa: F401
+from .ohm import OhmIntegrate, OhmMap, regions_needed  # noqa: F401

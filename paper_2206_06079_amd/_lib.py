@@ -34,7 +34,7 @@ EXPORTS = (
     "ohm_map_workspace_size", "ohm_map_create", "ohm_map_destroy", "ohm_map_reset",
     "ohm_map_set_params", "ohm_integrate_rays", "ohm_ndt_integrate", "ohm_map_read_dense",
     "ohm_debug_trace_rays", "ohm_map_sync_status", "ohm_status_string",
-    "ohm_map_set_profiling", "ohm_map_kernel_times",
+    "ohm_map_set_profiling", "ohm_map_kernel_times", "ohm_backward",
 )
 
 KERNEL_KINDS = 8
@@ -116,6 +116,7 @@ def load() -> ctypes.CDLL:
         "ohm_debug_trace_rays": [vp, vp, vp, vp, ctypes.c_uint32, vp, vp, vp, vp, vp],
         "ohm_map_sync_status": [vp, vp, P(OhmStats)],
         "ohm_map_set_profiling": [vp, ctypes.c_int],
+        "ohm_backward": [vp, ctypes.c_int32, vp, vp, vp, vp, vp, vp, ctypes.c_uint32, vp, vp, vp, vp],
         "ohm_map_kernel_times": [vp, vp, vp],
     }
     for name, args in sig.items():

@@ -1,0 +1,336 @@
+// Adjoint of count-mode integration: gradients of a loss on the final
+// log-odds with respect to the hit / miss increments, the NDT sensor noise
+// and every ray's weight.
+//
+// Forward (per scan k, per voxel v): s = (l + H l_hit) + U, l <- clamp(s),
+// with H the scan's summed hit weight and U its summed weighted miss
+// increments; the map records c_v, the last scan whose s left the clamp
+// range.  The clamp passes gradient only while inactive, so with
+// G_v = dL/dl_v (final) every increment of scan k into v has gradient
+// G_v [k > c_v].  The backward re-walks each ray (traversals are recomputed,
+// never stored) and gathers
+//     dL/dw_r      = sum_v G_v [k > c_v] delta_{r,v}          (no atomics)
+//     dL/dl_hit    = sum_r w_r G_hit(r) [k > c]
+//     dL/dl_miss   = sum_r w_r sum_miss G_v [k > c_v] d delta / d l_miss
+//     dL/dsigma_n  = sum_r w_r sum_miss G_v [k > c_v] d delta / d sigma_n
+// where an NDT-weighted miss delta = logit(p), p = 1/2 - lambda g (1/2 - s),
+// g = exp(-q/2), q = D^T S^-1 D, S = Sigma + sigma_n^2 I, s = sigmoid(l_miss):
+//     d delta / d l_miss  = lambda g s (1 - s) / (p (1 - p))
+//     d delta / d sigma_n = -lambda (1/2 - s) g sigma_n |S^-1 D|^2 / (p (1 - p)).
+// The NDT statistics each scan saw are replayed: the layer is emptied, and
+// after scan k's gradient walk its samples are folded in again.
+#include <hip/hip_runtime.h>
+#include <math.h>
+#include <stdint.h>
+
+#include "ohm.h"
+#include "ohm_device.h"
+#include "ohm_host.h"
+#include "ohm_regions.h"
+#include "ohm_wave.h"
+
+namespace ohm {
+
+namespace {
+
+struct GradBox {
+  const float* g;
+  int32_t bmin[3], bdim[3];
+};
+
+__device__ __forceinline__ float grad_at(const GradBox& gb, int32_t x, int32_t y, int32_t z) {
+  const int32_t dx = x - gb.bmin[0], dy = y - gb.bmin[1], dz = z - gb.bmin[2];
+  if ((uint32_t)dx >= (uint32_t)gb.bdim[0] || (uint32_t)dy >= (uint32_t)gb.bdim[1] ||
+      (uint32_t)dz >= (uint32_t)gb.bdim[2])
+    return 0.f;
+  return gb.g[((size_t)dz * gb.bdim[1] + dy) * gb.bdim[0] + dx];
+}
+
+// NDT miss increment and its derivatives with respect to l_miss and sigma_n.
+__device__ void ndt_terms(const DevMap& m, const double o[3], const double d[3], double dd, const double c[3],
+                          const NdtVoxel& nv, double sig_miss, double& delta, double& d_lm, double& d_sig) {
+#pragma clang fp contract(off)
+  double mu[3], w[3];
+  double wd = 0.0;
+  for (int a = 0; a < 3; ++a) {
+    mu[a] = c[a] + (double)nv.mean[a];
+    w[a] = mu[a] - o[a];
+    wd = wd + w[a] * d[a];
+  }
+  double t = dd > 0.0 ? wd / dd : 0.0;
+  t = t < 0.0 ? 0.0 : (t > 1.0 ? 1.0 : t);
+  double D[3];
+  for (int a = 0; a < 3; ++a) D[a] = (o[a] + t * d[a]) - mu[a];
+  const double sn = m.sensor_noise, s2 = sn * sn;
+  const double a00 = (double)nv.cov[0] + s2, a10 = nv.cov[1], a20 = nv.cov[2];
+  const double a11 = (double)nv.cov[3] + s2, a21 = nv.cov[4], a22 = (double)nv.cov[5] + s2;
+  // Cholesky S = L L^T; z = L^-1 D (q = |z|^2), y = L^-T z = S^-1 D
+  const double l00 = sqrt(a00);
+  const double l10 = a10 / l00, l20 = a20 / l00;
+  const double l11 = sqrt(a11 - l10 * l10);
+  const double l21 = (a21 - l20 * l10) / l11;
+  const double l22 = sqrt(a22 - l20 * l20 - l21 * l21);
+  const double z0 = D[0] / l00;
+  const double z1 = (D[1] - l10 * z0) / l11;
+  const double z2 = (D[2] - l20 * z0 - l21 * z1) / l22;
+  const double y2 = z2 / l22;
+  const double y1 = (z1 - l21 * y2) / l11;
+  const double y0 = (z0 - l10 * y1 - l20 * y2) / l00;
+  const double q = z0 * z0 + z1 * z1 + z2 * z2;
+  const double yy = y0 * y0 + y1 * y1 + y2 * y2;
+  const double g = exp(-0.5 * q);
+  const double lam = m.adaptation_rate;
+  const double p = 0.5 - lam * g * (0.5 - sig_miss);
+  const double inv = 1.0 / (p * (1.0 - p));
+  delta = log(p / (1.0 - p));
+  d_lm = lam * g * sig_miss * (1.0 - sig_miss) * inv;
+  d_sig = -lam * (0.5 - sig_miss) * g * sn * yy * inv;
+}
+
+template <bool kNdt, bool kWeighted>
+__global__ __launch_bounds__(256) void backward_walk_kernel(DevMap m, GradBox gb, const float* __restrict__ origins,
+                                                            uint32_t scan, const float* __restrict__ samples,
+                                                            const float* __restrict__ weights, uint32_t r0,
+                                                            uint32_t n, uint32_t tag, float* __restrict__ grad_w,
+                                                            double* __restrict__ grad_s, double sig_miss) {
+#pragma clang fp contract(off)
+  const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+  const bool inrange = i < n;
+  const size_t ray = (size_t)r0 + i;
+  const float o[3] = {origins[3 * scan + 0], origins[3 * scan + 1], origins[3 * scan + 2]};
+  float e[3] = {0.f, 0.f, 0.f};
+  if (inrange) {
+    e[0] = samples[3 * ray + 0];
+    e[1] = samples[3 * ray + 1];
+    e[2] = samples[3 * ray + 2];
+  }
+  Ray r;
+  const int st = inrange ? prepare_ray(m, o, e, r) : kRayInvalid;
+  bool alive = inrange && st == kRayOk;
+  const double wt = (kWeighted && inrange) ? (double)weights[ray] : 1.0;
+
+  __shared__ RegionCache rc;
+  stage_regions<false>(m, rc, alive, r, 0u, 0u);
+
+  const double od[3] = {(double)o[0], (double)o[1], (double)o[2]};
+  double dv[3] = {0.0, 0.0, 0.0};
+  double dd = 0.0;
+  Walk w;
+  int32_t kx = 0, ky = 0, kz = 0;
+  int32_t slot = -1;
+  uint32_t lidx = 0;
+  if (alive) {
+    for (int a = 0; a < 3; ++a) {
+      dv[a] = r.end[a] - od[a];
+      dd = dd + dv[a] * dv[a];
+    }
+    const int32_t hi[3] = {m.kmax[0] - 1, m.kmax[1] - 1, m.kmax[2] - 1};
+    walk_init(w, r.q0, r.q1, r.k0, r.k1, m.kmin, hi, m.F);
+    kx = r.k0[0];
+    ky = r.k0[1];
+    kz = r.k0[2];
+    slot = staged_slot(m, rc, kx, ky, kz);
+    lidx = local_index(kx, ky, kz);
+  }
+  double gw = 0.0, g_hit = 0.0, g_miss = 0.0, g_sig = 0.0;
+  while (alive) {
+    const bool last = w.total == 0;
+    const bool is_hit = last && !r.truncated;
+    const float G = grad_at(gb, kx, ky, kz);
+    if (G != 0.f && slot >= 0) {
+      const size_t v = (size_t)slot * kRegionVoxels + lidx;
+      if (tag > m.clampscan[v]) {
+        const double Gd = (double)G;
+        if (is_hit) {
+          gw += Gd * (double)m.l_hit;
+          g_hit += wt * Gd;
+        } else {
+          double delta = m.l_miss, dlm = 1.0, dsg = 0.0;
+          if (kNdt) {
+            const NdtVoxel nv = m.ndt[v];
+            if (nv.n >= m.ndt_min_samples) {
+              const double c[3] = {m.origin[0] + ((double)kx + 0.5) * m.voxel_size,
+                                   m.origin[1] + ((double)ky + 0.5) * m.voxel_size,
+                                   m.origin[2] + ((double)kz + 0.5) * m.voxel_size};
+              ndt_terms(m, od, dv, dd, c, nv, sig_miss, delta, dlm, dsg);
+            }
+          }
+          gw += Gd * delta;
+          g_miss += wt * Gd * dlm;
+          g_sig += wt * Gd * dsg;
+        }
+      }
+    }
+    if (last) break;
+    const int a = walk_step(w);
+    const int32_t ra = a == 0 ? w.rem[0] : (a == 1 ? w.rem[1] : w.rem[2]);
+    if (ra == 0 && ((w.clip >> a) & 1u)) break;
+    const int32_t sg = a == 0 ? w.sg[0] : (a == 1 ? w.sg[1] : w.sg[2]);
+    kx += a == 0 ? sg : 0;
+    ky += a == 1 ? sg : 0;
+    kz += a == 2 ? sg : 0;
+    const int32_t kn = a == 0 ? kx : (a == 1 ? ky : kz);
+    if ((kn & kRegionMask) == (sg > 0 ? 0 : kRegionMask)) {
+      slot = staged_slot(m, rc, kx, ky, kz);
+      lidx = local_index(kx, ky, kz);
+    } else {
+      lidx += (uint32_t)(a == 0 ? sg : (a == 1 ? sg * kRegionEdge : sg * kRegionEdge * kRegionEdge));
+    }
+  }
+  if (inrange && grad_w) grad_w[ray] = (float)gw;
+  // block reduction of the scalar gradients, one fp64 atomic per block each
+  __shared__ double part[3][4];
+  double vals[3] = {g_hit, g_miss, g_sig};
+  const uint32_t lane = lane_id();
+  const uint32_t wave = threadIdx.x >> 6;
+#pragma unroll
+  for (int c = 0; c < 3; ++c) {
+    double x = vals[c];
+    for (int off = 32; off > 0; off >>= 1) x += __shfl_xor(x, off);
+    if (lane == 0) part[c][wave] = x;
+  }
+  __syncthreads();
+  if (threadIdx.x < 3) {
+    double x = 0.0;
+    for (uint32_t k = 0; k < (blockDim.x >> 6); ++k) x += part[threadIdx.x][k];
+    if (x != 0.0) unsafeAtomicAdd(grad_s + threadIdx.x, x);
+  }
+}
+
+__global__ void zero_f64_kernel(double* p, int n) {
+  if ((int)threadIdx.x < n) p[threadIdx.x] = 0.0;
+}
+
+}  // namespace
+
+// Folds each hit's sample into its voxel's moment accumulators (the NDT
+// second phase without occupancy updates): replays the statistics.
+__global__ __launch_bounds__(256) void ndt_fold_kernel(DevMap m, const float* __restrict__ origins, uint32_t scan,
+                                                       const float* __restrict__ samples, uint32_t r0, uint32_t n,
+                                                       uint32_t tag, uint32_t parity) {
+#pragma clang fp contract(off)
+  const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+  const bool inrange = i < n;
+  const size_t ray = (size_t)r0 + i;
+  const float o[3] = {origins[3 * scan + 0], origins[3 * scan + 1], origins[3 * scan + 2]};
+  float e[3] = {0.f, 0.f, 0.f};
+  if (inrange) {
+    e[0] = samples[3 * ray + 0];
+    e[1] = samples[3 * ray + 1];
+    e[2] = samples[3 * ray + 2];
+  }
+  Ray r;
+  const int st = inrange ? prepare_ray(m, o, e, r) : kRayInvalid;
+  // a ray carries a sample when it is not truncated and its end voxel is in
+  // the map (the box is convex, so the walk then reaches it)
+  bool hit = inrange && st == kRayOk && !r.truncated;
+  for (int a = 0; a < 3; ++a) hit = hit && r.k1[a] >= m.kmin[a] && r.k1[a] < m.kmax[a];
+  __shared__ RegionCache rc;
+  for (int h = threadIdx.x; h < kRegionCacheSize; h += blockDim.x) rc.key[h] = kSlotEmpty;
+  __syncthreads();
+  int32_t ri = 0;
+  bool cached = false;
+  if (hit) {
+    ri = region_index(m, r.k1[0] >> kRegionLog2, r.k1[1] >> kRegionLog2, r.k1[2] >> kRegionLog2);
+    cached = rc_insert(rc, ri);
+  }
+  __syncthreads();
+  for (int h = threadIdx.x; h < kRegionCacheSize; h += blockDim.x) {
+    const int32_t k = rc.key[h];
+    rc.slot[h] = k == kSlotEmpty ? kSlotExhausted : resolve_region<true>(m, k, tag, parity);
+  }
+  __syncthreads();
+  if (!hit) return;
+  const int32_t slot = cached ? rc_find(rc, ri) : resolve_region<true>(m, ri, tag, parity);
+  if (slot < 0) return;
+  const size_t v = (size_t)slot * kRegionVoxels + local_index(r.k1[0], r.k1[1], r.k1[2]);
+  const double x0 = (double)e[0] - (m.origin[0] + ((double)r.k1[0] + 0.5) * m.voxel_size);
+  const double x1 = (double)e[1] - (m.origin[1] + ((double)r.k1[1] + 0.5) * m.voxel_size);
+  const double x2 = (double)e[2] - (m.origin[2] + ((double)r.k1[2] + 0.5) * m.voxel_size);
+  double* mo = m.mom + v * kMomWords;
+  unsafeAtomicAdd(mo + 0, x0);
+  unsafeAtomicAdd(mo + 1, x1);
+  unsafeAtomicAdd(mo + 2, x2);
+  unsafeAtomicAdd(mo + 3, x0 * x0);
+  unsafeAtomicAdd(mo + 4, x0 * x1);
+  unsafeAtomicAdd(mo + 5, x0 * x2);
+  unsafeAtomicAdd(mo + 6, x1 * x1);
+  unsafeAtomicAdd(mo + 7, x1 * x2);
+  unsafeAtomicAdd(mo + 8, x2 * x2);
+  atomicAdd(reinterpret_cast<unsigned long long*>(m.nacc + v * kNaccWords + kNaccSamples), 1ull);
+}
+
+}  // namespace ohm
+
+using namespace ohm;
+
+extern "C" ohm_status ohm_backward(ohm_map map, int32_t ndt, const float* d_grad, const int32_t h_box_min[3],
+                                   const int32_t h_box_dim[3], const float* d_origins, const float* d_samples,
+                                   const uint32_t* h_scan_offsets, uint32_t n_scans, const float* d_weights,
+                                   float* d_grad_weights, double* d_grad_scalars, void* stream) {
+  ohm_status s = check_scans(map, d_origins, d_samples, h_scan_offsets, n_scans);
+  if (s != OHM_OK) return s;
+  if (!d_grad || !h_box_min || !h_box_dim || !d_grad_scalars || !map->dm.clampscan) return OHM_E_INVALID_ARG;
+  if (ndt && !map->dm.ndt) return OHM_E_INVALID_ARG;
+  if (map->params.mode != OHM_MODE_COUNT_CLAMP) return OHM_E_UNSUPPORTED;
+  if (ndt && !(isinf(map->params.ndt_clear_below) && map->params.ndt_clear_below < 0)) return OHM_E_UNSUPPORTED;
+  for (int a = 0; a < 3; ++a)
+    if (h_box_dim[a] <= 0) return OHM_E_INVALID_ARG;
+  // the map must hold exactly these scans since its last create / reset
+  uint32_t nonempty = 0;
+  for (uint32_t sc = 0; sc < n_scans; ++sc) nonempty += h_scan_offsets[sc + 1] > h_scan_offsets[sc] ? 1u : 0u;
+  if (nonempty != map->scans_done) return OHM_E_INVALID_ARG;
+  hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+  GradBox gb;
+  gb.g = d_grad;
+  for (int a = 0; a < 3; ++a) {
+    gb.bmin[a] = h_box_min[a];
+    gb.bdim[a] = h_box_dim[a];
+  }
+  const double sig_miss = 1.0 / (1.0 + exp(-(double)map->params.l_miss));
+  const bool weighted = d_weights != nullptr;
+  hipLaunchKernelGGL(zero_f64_kernel, dim3(1), dim3(64), 0, st, d_grad_scalars, 3);
+  if (ndt) {
+    clear_pending(map, st);
+    // empty the statistics; they are replayed scan by scan below
+    const size_t bytes = (size_t)map->dm.capacity * kRegionVoxels * sizeof(NdtVoxel);
+    hipLaunchKernelGGL(fill_u32_kernel, dim3(8192), dim3(256), 0, st, reinterpret_cast<uint32_t*>(map->dm.ndt),
+                       bytes / 4, 0u);
+  }
+  uint32_t tag = 0;
+  for (uint32_t sc = 0; sc < n_scans; ++sc) {
+    const uint32_t r0 = h_scan_offsets[sc];
+    const uint32_t n = h_scan_offsets[sc + 1] - r0;
+    if (n == 0) continue;
+    ++tag;
+    const dim3 grid((n + 255) / 256);
+    {
+      ProfScope ps(map, OHM_KERNEL_OTHER, st);
+      if (ndt) {
+        if (weighted)
+          hipLaunchKernelGGL((backward_walk_kernel<true, true>), grid, dim3(256), 0, st, map->dm, gb, d_origins, sc,
+                             d_samples, d_weights, r0, n, tag, d_grad_weights, d_grad_scalars, sig_miss);
+        else
+          hipLaunchKernelGGL((backward_walk_kernel<true, false>), grid, dim3(256), 0, st, map->dm, gb, d_origins,
+                             sc, d_samples, d_weights, r0, n, tag, d_grad_weights, d_grad_scalars, sig_miss);
+      } else {
+        if (weighted)
+          hipLaunchKernelGGL((backward_walk_kernel<false, true>), grid, dim3(256), 0, st, map->dm, gb, d_origins,
+                             sc, d_samples, d_weights, r0, n, tag, d_grad_weights, d_grad_scalars, sig_miss);
+        else
+          hipLaunchKernelGGL((backward_walk_kernel<false, false>), grid, dim3(256), 0, st, map->dm, gb, d_origins,
+                             sc, d_samples, d_weights, r0, n, tag, d_grad_weights, d_grad_scalars, sig_miss);
+      }
+    }
+    if (ndt) {
+      const uint32_t ftag = ++map->count_batches;
+      const uint32_t parity = ftag & 1u;
+      hipLaunchKernelGGL(ndt_fold_kernel, grid, dim3(256), 0, st, map->dm, d_origins, sc, d_samples, r0, n, ftag,
+                         parity);
+      // fold only: the accumulators hold no increments, so occupancy is unchanged
+      hipLaunchKernelGGL(ndt_finalize_kernel, dim3(kFinalizeBlocks), dim3(256), 0, st, map->dm, parity, 1, 0u);
+    }
+  }
+  hipError_t e = hipGetLastError();
+  return e == hipSuccess ? OHM_OK : OHM_E_HIP;
+}

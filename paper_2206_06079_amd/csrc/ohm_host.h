@@ -37,6 +37,14 @@ namespace ohm {
 
 constexpr int kFinalizeBlocks = 2048;
 
+// kernels shared across translation units
+__global__ void fill_u32_kernel(uint32_t* p, size_t n, uint32_t v);
+__global__ __launch_bounds__(256) void ndt_finalize_kernel(DevMap m, uint32_t parity, int count_mode,
+                                                           uint32_t scan_tag);
+__global__ __launch_bounds__(256) void ndt_fold_kernel(DevMap m, const float* __restrict__ origins, uint32_t scan,
+                                                       const float* __restrict__ samples, uint32_t r0, uint32_t n,
+                                                       uint32_t tag, uint32_t parity);
+
 ohm_status map_initialise(ohm_map_s* map, hipStream_t st);
 ohm_status check_scans(ohm_map map, const float* d_origins, const float* d_samples, const uint32_t* h_offsets,
                        uint32_t n_scans);

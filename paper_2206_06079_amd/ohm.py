@@ -160,6 +160,24 @@ class OhmMap:
                                        _stream_ptr(stream)), "ohm_debug_trace_rays(write)")
         return counts.to(torch.int64), flags, offs, upd[:total]
 
+    def backward(self, grad_box: torch.Tensor, box_min, box_dim, origins, samples, offsets, weights=None,
+                 ndt: bool = True, grad_weights: Optional[torch.Tensor] = None, stream=None):
+        """ohm_backward: returns (dL/dw float32 [N] or None, dL/d(l_hit, l_miss,
+        sensor_noise) float64 [3])."""
+        o, s, h_off, n_scans, w = self._scan_args(origins, samples, offsets, weights)
+        if grad_box.shape != (int(box_dim[2]), int(box_dim[1]), int(box_dim[0])):
+            raise ValueError("grad_box must be [dz, dy, dx]")
+        gs = torch.zeros(3, dtype=torch.float64, device=self.device)
+        bmin = (ctypes.c_int32 * 3)(*[int(v) for v in box_min])
+        bdim = (ctypes.c_int32 * 3)(*[int(v) for v in box_dim])
+        gw_ptr = _dev_ptr(grad_weights, torch.float32, "grad_weights", self.device)
+        check(load().ohm_backward(self.handle, 1 if ndt else 0,
+                                  _dev_ptr(grad_box.contiguous(), torch.float32, "grad_box", self.device),
+                                  bmin, bdim, o, s, h_off.ctypes.data_as(ctypes.c_void_p), n_scans, w, gw_ptr,
+                                  _dev_ptr(gs, torch.float64, "grad_scalars", self.device), _stream_ptr(stream)),
+              "ohm_backward")
+        return grad_weights, gs
+
     def set_profiling(self, enable: bool):
         check(load().ohm_map_set_profiling(self.handle, 1 if enable else 0), "ohm_map_set_profiling")
 
@@ -187,3 +205,40 @@ def regions_needed(params, margin: float = 1.25) -> int:
         hi = (params.key_max[a] - 1) >> 5
         n *= hi - lo + 1
     return n
+
+
+class OhmIntegrate(torch.autograd.Function):
+    """Differentiable count-mode integration: maps (per-ray weights, l_hit,
+    l_miss, sensor_noise) to the final log-odds over a dense box.  The forward
+    integrates every scan into a fresh map; the backward runs the library's
+    adjoint kernel (traversals recomputed, NDT statistics replayed)."""
+
+    @staticmethod
+    def forward(ctx, weights, l_hit, l_miss, sensor_noise, params, origins, samples, offsets, box_min, box_dim,
+                ndt=True, capacity=1024):
+        p = params.replace(l_hit=float(l_hit), l_miss=float(l_miss), sensor_noise=float(sensor_noise),
+                           mode=_lib.MODE_COUNT_CLAMP)
+        layers = _lib.LAYER_OCC | _lib.LAYER_ADJOINT | (_lib.LAYER_NDT if ndt else 0)
+        m = OhmMap(p, capacity, layers=layers, device=samples.device)
+        w = weights.detach().contiguous()
+        if ndt:
+            m.ndt_integrate(origins, samples, offsets, w)
+        else:
+            m.integrate(origins, samples, offsets, w)
+        out = m.read_dense(_lib.READ_OCC, box_min, box_dim)
+        ctx.map = m
+        ctx.args = (origins, samples, offsets, w, tuple(box_min), tuple(box_dim), ndt)
+        ctx.dtypes = (l_hit.dtype, l_miss.dtype, sensor_noise.dtype)
+        return out
+
+    @staticmethod
+    def backward(ctx, grad_out):
+        origins, samples, offsets, w, box_min, box_dim, ndt = ctx.args
+        m = ctx.map
+        gw = torch.empty_like(w)
+        gw, gs = m.backward(grad_out.float().contiguous(), box_min, box_dim, origins, samples, offsets, w, ndt=ndt,
+                            grad_weights=gw)
+        m.close()
+        ctx.map = None
+        d_hit, d_miss, d_sig = (gs[i].to(dt) for i, dt in enumerate(ctx.dtypes))
+        return gw, d_hit, d_miss, d_sig, None, None, None, None, None, None, None, None

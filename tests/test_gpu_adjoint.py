@@ -1,0 +1,116 @@
+"""GPU adjoint (ohm_backward / OhmIntegrate) against the oracle's analytic
+gradients (themselves pinned to fp64 finite differences) and directly against
+fp64 central differences of the oracle's loss for the scalar parameters.
+
+Tolerance: 1e-4 relative.  Per-ray weight gradients use max(|g|, 1e-3 max|g|)
+as the scale plus the effect of the GPU forward storing fp32 log-odds: after
+K scans |l_gpu - l_fp64| <= K ulp(4) = K 2^-22, so |dG| <= K 2^-24 per voxel
+(sigmoid' <= 1/4), times |delta| <= 1 per voxel of the ray inside the box."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import paper_2206_06079_amd as ohm
+from gpu_helpers import device, to_dev
+from workloads import scenes
+
+pytestmark = pytest.mark.gpu
+
+
+def setup_case(n_scans, ndt=True, beams=64, cols=2048):
+    params, batch, box_min, box_dim, labels = scenes.config4(n_scans=n_scans, beams=beams, cols=cols)
+    first = oracle.adjoint(params, batch, box_min, box_dim, labels, None, ndt=ndt, grads=False)
+    mask = (first["near"] == 0).astype(np.float64)
+    ref = oracle.adjoint(params, batch, box_min, box_dim, labels, mask, ndt=ndt, grads=True)
+    return params, batch, box_min, box_dim, labels, mask, ref
+
+
+def gpu_grads(params, batch, box_min, box_dim, labels, mask, ndt=True):
+    dev = device()
+    layers = ohm.LAYER_ADJOINT | (ohm.LAYER_NDT if ndt else 0)
+    m = ohm.OhmMap(params, 256, layers=layers, device=dev)
+    o, s, off, w = to_dev(batch)
+    (m.ndt_integrate if ndt else m.integrate)(o, s, off, w)
+    occ = m.read_dense(ohm.READ_OCC, box_min, box_dim).double()
+    y = torch.from_numpy(labels).to(dev).double()
+    mk = torch.from_numpy(mask).to(dev)
+    G = (mk * (torch.sigmoid(occ) - y)).float().contiguous()
+    gw = torch.zeros_like(w)
+    gw, gs = m.backward(G, box_min, box_dim, o, s, off, w, ndt=ndt, grad_weights=gw)
+    # NDT statistics are rebuilt in place by the replay
+    n_after = m.read_dense(ohm.READ_NDT_COUNT, box_min, box_dim).cpu().numpy() if ndt else None
+    out = gw.cpu().numpy().astype(np.float64), gs.cpu().numpy(), occ.cpu().numpy(), n_after
+    m.close()
+    return out
+
+
+def in_box_counts(params, batch, box_min, box_dim):
+    counts, _, offs, keys = oracle.trace(params, batch)
+    lo = np.asarray(box_min)
+    hi = lo + np.asarray(box_dim)
+    inside = np.all((keys[:, :3] >= lo) & (keys[:, :3] < hi), axis=1)
+    csum = np.concatenate([[0], np.cumsum(inside)])
+    return csum[offs[1:]] - csum[offs[:-1]]
+
+
+def check(gw, gs, ref, n_box=None, n_scans=1):
+    rg = ref["grad_w"]
+    scale = np.maximum(np.abs(rg), 1e-3 * np.abs(rg).max())
+    storage = 0.0 if n_box is None else n_box * n_scans * 2.0 ** -24
+    bad = np.abs(gw - rg) > 1e-4 * scale + storage + 1e-9
+    assert not bad.any(), f"{bad.sum()} weight gradients off, worst {np.abs(gw - rg)[bad].max()}"
+    for i in range(3):
+        assert abs(gs[i] - ref["grad_scalars"][i]) <= 1e-4 * abs(ref["grad_scalars"][i]) + 1e-9, (i, gs, ref["grad_scalars"])
+
+
+def test_adjoint_config4_ndt():
+    params, batch, box_min, box_dim, labels, mask, ref = setup_case(4)
+    gw, gs, occ, n_after = gpu_grads(params, batch, box_min, box_dim, labels, mask)
+    np.testing.assert_allclose(occ, ref["occ"], atol=1e-5, rtol=0)
+    assert abs(ref["grad_scalars"][2]) > 0
+    check(gw, gs, ref, in_box_counts(params, batch, box_min, box_dim), batch.n_scans)
+    o_occ, o_state, _, _ = oracle.ndt_integrate(params, batch, box_min, box_dim)
+    assert np.array_equal(n_after.astype(np.uint32), o_state.n)
+
+
+def test_adjoint_plain():
+    params, batch, box_min, box_dim, labels, mask, ref = setup_case(3, ndt=False)
+    gw, gs, occ, _ = gpu_grads(params, batch, box_min, box_dim, labels, mask, ndt=False)
+    assert gs[2] == 0.0
+    check(gw, gs, ref, in_box_counts(params, batch, box_min, box_dim), batch.n_scans)
+
+
+def test_adjoint_scalars_vs_fd():
+    """GPU scalar gradients against fp64 central differences of the oracle's
+    forward loss (two full-size scans)."""
+    params, batch, box_min, box_dim, labels, mask, ref = setup_case(2)
+    gw, gs, _, _ = gpu_grads(params, batch, box_min, box_dim, labels, mask)
+    for i, name in enumerate(("l_hit", "l_miss", "sensor_noise")):
+        th = getattr(params, name)
+        h = 1e-5 * max(1.0, abs(th))
+        tp, tm = (float(np.float32(th + h)), float(np.float32(th - h))) if i < 2 else (th + h, th - h)
+        hi = oracle.adjoint(params.replace(**{name: tp}), batch, box_min, box_dim, labels, mask, grads=False)
+        lo = oracle.adjoint(params.replace(**{name: tm}), batch, box_min, box_dim, labels, mask, grads=False)
+        assert np.array_equal(hi["clamp_last"], lo["clamp_last"])
+        fd = (hi["loss"] - lo["loss"]) / (tp - tm)
+        assert abs(gs[i] - fd) <= 1e-4 * abs(fd) + 1e-9, (name, gs[i], fd)
+
+
+def test_autograd_function():
+    params, batch, box_min, box_dim, labels, mask, ref = setup_case(2)
+    dev = device()
+    o, s, off, w = to_dev(batch)
+    w = w.clone().requires_grad_(True)
+    l_hit = torch.tensor(params.l_hit, dtype=torch.float64, requires_grad=True)
+    l_miss = torch.tensor(params.l_miss, dtype=torch.float64, requires_grad=True)
+    sn = torch.tensor(params.sensor_noise, dtype=torch.float64, requires_grad=True)
+    out = ohm.OhmIntegrate.apply(w, l_hit, l_miss, sn, params, o, s, off, box_min, box_dim, True, 256)
+    y = torch.from_numpy(labels).to(dev).double()
+    mk = torch.from_numpy(mask).to(dev)
+    loss = (mk * torch.nn.functional.binary_cross_entropy_with_logits(out.double(), y, reduction="none")).sum()
+    loss.backward()
+    assert abs(loss.item() - ref["loss"]) <= 1e-4 * abs(ref["loss"])
+    check(w.grad.cpu().numpy().astype(np.float64),
+          np.array([l_hit.grad.item(), l_miss.grad.item(), sn.grad.item()]), ref,
+          in_box_counts(params, batch, box_min, box_dim), batch.n_scans)

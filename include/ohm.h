@@ -235,6 +235,44 @@ ohm_status ohm_debug_trace_rays(ohm_map map, const float* d_origins, const float
                                 int32_t* d_ray_flags, const int64_t* d_ray_offsets, int32_t* d_updates,
                                 void* stream);
 
+/*
+ * Batched integration (many scans of uneven size from several sensors into
+ * several maps, one graph launch).  Each set names a map (count mode, one set
+ * per map) and its scans in application order, with the same conventions as
+ * ohm_integrate_rays.  A plan copies the sets' pointers, the maps' parameters
+ * and the scan layout, so the buffers must stay valid and unchanged (contents
+ * may change) for the plan's life.  Running a plan integrates every set's
+ * scans into its map with exactly the per-scan count-then-clamp result of
+ * calling ohm_integrate_rays scan by scan; scans of different maps run
+ * concurrently.  tuning->group_scans (G, 1..64) scans per map share one walk
+ * launch and one finalize; each group needs G per-scan accumulators of
+ * capacity x 32^3 x 8 bytes per map in the plan workspace.
+ */
+typedef struct {
+  ohm_map map;
+  const float* d_origins;          /* float[n_scans][3] */
+  const float* d_samples;          /* float[N][3] */
+  const float* d_weights;          /* float[N] or NULL (all sets alike) */
+  const uint32_t* h_scan_offsets;  /* uint32[n_scans + 1], host */
+  uint32_t n_scans;
+} ohm_scan_set;
+
+typedef struct {
+  uint32_t group_scans;  /* G: scans per map per launch group */
+} ohm_batch_tuning;
+
+typedef struct ohm_batch_s* ohm_batch;
+
+ohm_status ohm_batch_workspace_size(const ohm_scan_set* sets, uint32_t n_sets, const ohm_batch_tuning* tuning,
+                                    size_t* bytes);
+/* Build the plan in d_workspace (256-byte aligned, caller-owned) and capture
+ * it as a graph; synchronises `stream` once. */
+ohm_status ohm_batch_create(const ohm_scan_set* sets, uint32_t n_sets, const ohm_batch_tuning* tuning,
+                            void* d_workspace, size_t workspace_bytes, void* stream, ohm_batch* out);
+/* Launch the captured plan on `stream` (asynchronous). */
+ohm_status ohm_batch_run(ohm_batch plan, void* stream);
+ohm_status ohm_batch_destroy(ohm_batch plan);
+
 /* Kernel kinds reported by ohm_map_kernel_times. */
 enum {
   OHM_KERNEL_PREPASS = 0,   /* region pass: allocation and touched list */

@@ -35,7 +35,23 @@ EXPORTS = (
     "ohm_map_set_params", "ohm_integrate_rays", "ohm_ndt_integrate", "ohm_map_read_dense",
     "ohm_debug_trace_rays", "ohm_map_sync_status", "ohm_status_string",
     "ohm_map_set_profiling", "ohm_map_kernel_times", "ohm_backward",
+    "ohm_batch_workspace_size", "ohm_batch_create", "ohm_batch_run", "ohm_batch_destroy",
 )
+
+
+class ScanSet(ctypes.Structure):
+    _fields_ = [
+        ("map", ctypes.c_void_p),
+        ("d_origins", ctypes.c_void_p),
+        ("d_samples", ctypes.c_void_p),
+        ("d_weights", ctypes.c_void_p),
+        ("h_scan_offsets", ctypes.c_void_p),
+        ("n_scans", ctypes.c_uint32),
+    ]
+
+
+class BatchTuning(ctypes.Structure):
+    _fields_ = [("group_scans", ctypes.c_uint32)]
 
 KERNEL_KINDS = 8
 KERNEL_NAMES = {0: "prepass", 1: "walk", 2: "finalize", 3: "ndt_hit", 7: "other"}
@@ -117,6 +133,10 @@ def load() -> ctypes.CDLL:
         "ohm_map_sync_status": [vp, vp, P(OhmStats)],
         "ohm_map_set_profiling": [vp, ctypes.c_int],
         "ohm_backward": [vp, ctypes.c_int32, vp, vp, vp, vp, vp, vp, ctypes.c_uint32, vp, vp, vp, vp],
+        "ohm_batch_workspace_size": [vp, ctypes.c_uint32, vp, P(ctypes.c_size_t)],
+        "ohm_batch_create": [vp, ctypes.c_uint32, vp, vp, ctypes.c_size_t, vp, P(vp)],
+        "ohm_batch_run": [vp, vp],
+        "ohm_batch_destroy": [vp],
         "ohm_map_kernel_times": [vp, vp, vp],
     }
     for name, args in sig.items():

@@ -1,0 +1,319 @@
+// Batched integration: many scans of uneven size from several sensors, into
+// several maps, replayed as one hipGraph launch.
+//
+// The scans of every set (one map each) are cut into groups of G consecutive
+// scans per map.  One walk launch per group covers every ray of every scan of
+// the group -- short scans share the GPU instead of each under-filling it --
+// and each scan accumulates its own exact hit / miss counts into its own
+// accumulator slot.  The group's finalize then applies, voxel by voxel, the
+// group's scans in order, each with its own clamp, so the result is exactly
+// the sequential per-scan count-then-clamp result.  The whole sequence is
+// captured once into a graph; scan tags live in device memory so that every
+// replay stays correct.
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+#include <string.h>
+
+#include <new>
+#include <vector>
+
+#include "ohm.h"
+#include "ohm_device.h"
+#include "ohm_host.h"
+#include "ohm_regions.h"
+#include "ohm_wave.h"
+
+#include "ohm_walk_body.h"
+
+namespace ohm {
+
+constexpr uint32_t kBatchTagBase = 0x80000000u;  // batched tags never meet per-scan tags
+
+struct BlockDesc {
+  uint32_t set;    // scan set (map) index
+  uint32_t pos;    // the scan's position within its group
+  uint32_t scan;   // scan index within the set
+  uint32_t r0;     // first ray of the scan
+  uint32_t n;      // rays in the scan
+  uint32_t block;  // block index within the scan
+};
+
+struct SetPtrs {
+  const float* origins;
+  const float* samples;
+  const float* weights;
+};
+
+// per-set group accumulators: G slots of [capacity][V][2] floats
+__device__ __forceinline__ size_t acc_slot_floats(const DevMap& m) { return (size_t)m.capacity * kRegionVoxels * 2; }
+
+template <bool kWeighted>
+__global__ __launch_bounds__(256) void batch_walk_kernel(const DevMap* __restrict__ maps,
+                                                         const SetPtrs* __restrict__ sets,
+                                                         const BlockDesc* __restrict__ descs) {
+  const BlockDesc d = descs[blockIdx.x];
+  DevMap m = maps[d.set];
+  m.acc += (size_t)d.pos * acc_slot_floats(m);
+  const uint32_t tag = __hip_atomic_load(m.hdr + kHdrBatchTag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  const SetPtrs sp = sets[d.set];
+  walk_body<kSinkCount, kWeighted, 0>(m, sp.origins + 3 * (size_t)d.scan, sp.samples, sp.weights, d.r0, d.n,
+                                      d.block * blockDim.x + threadIdx.x, tag, tag & 1u, nullptr, nullptr, nullptr,
+                                      nullptr);
+}
+
+// Applies the group's scans in order to every voxel of the regions the group
+// touched: for j = 0..G-1, l = clamp((l + H_j l_hit) + M_j l_miss).
+__global__ __launch_bounds__(256) void batch_finalize_kernel(const DevMap* __restrict__ maps, uint32_t n_sets,
+                                                             uint32_t group) {
+  constexpr int kChunk = 4096;
+  constexpr int kUnits = kRegionVoxels / kChunk;
+  for (uint32_t si = 0; si < n_sets; ++si) {
+    const DevMap& m = maps[si];
+    const uint32_t tag = __hip_atomic_load(m.hdr + kHdrBatchTag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    const uint32_t parity = tag & 1u;
+    const uint32_t count = __hip_atomic_load(m.hdr + kHdrTouched0 + parity, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    const uint32_t units = count * kUnits;
+    const size_t stride = acc_slot_floats(m);
+    for (uint32_t u = blockIdx.x; u < units; u += gridDim.x) {
+      const uint32_t slot = m.touched[(size_t)parity * m.capacity + u / kUnits];
+      const size_t base = (size_t)slot * kRegionVoxels + (size_t)(u % kUnits) * kChunk;
+      for (int v = threadIdx.x; v < kChunk; v += blockDim.x) {
+        const size_t vi = base + v;
+        float l = m.occ[vi];
+        bool any = false;
+        for (uint32_t j = 0; j < group; ++j) {
+          float2* ap = reinterpret_cast<float2*>(m.acc + j * stride) + vi;
+          const float2 a = *ap;
+          if (a.x == 0.f && a.y == 0.f) continue;
+          float s = __fadd_rn(l, __fmul_rn(a.y, m.l_hit));
+          s = __fadd_rn(s, __fmul_rn(a.x, m.l_miss));
+          l = fminf(fmaxf(s, m.l_min), m.l_max);
+          *ap = make_float2(0.f, 0.f);
+          any = true;
+        }
+        if (any) m.occ[vi] = l;
+      }
+    }
+  }
+}
+
+// Between groups: advance every set's batch tag and empty the touched list
+// the next group will use.
+__global__ void batch_advance_kernel(const DevMap* __restrict__ maps, uint32_t n_sets) {
+  const uint32_t si = threadIdx.x;
+  if (si >= n_sets) return;
+  const DevMap& m = maps[si];
+  const uint32_t tag = m.hdr[kHdrBatchTag] + 1u;
+  m.hdr[kHdrBatchTag] = tag;
+  m.hdr[kHdrTouched0 + (tag & 1u)] = 0u;
+}
+
+// Start of a replay: empty both touched lists; start the tag sequence once.
+__global__ void batch_begin_kernel(const DevMap* __restrict__ maps, uint32_t n_sets) {
+  const uint32_t si = threadIdx.x;
+  if (si >= n_sets) return;
+  const DevMap& m = maps[si];
+  if (m.hdr[kHdrBatchTag] < kBatchTagBase) m.hdr[kHdrBatchTag] = kBatchTagBase;
+  m.hdr[kHdrTouched0] = 0u;
+  m.hdr[kHdrTouched1] = 0u;
+}
+
+}  // namespace ohm
+
+using namespace ohm;
+
+struct ohm_batch_s {
+  std::vector<ohm_map> maps;
+  std::vector<uint32_t> nonempty;  // non-empty scans per set
+  uint32_t n_sets;
+  uint32_t group;
+  uint32_t n_groups;
+  bool weighted;
+  DevMap* d_maps;
+  SetPtrs* d_sets;
+  BlockDesc* d_descs;
+  std::vector<uint32_t> group_first, group_blocks;
+  hipStream_t capture;
+  hipGraph_t graph;
+  hipGraphExec_t exec;
+};
+
+namespace {
+
+constexpr size_t kAlignB = 256;
+inline size_t align_b(size_t v) { return (v + kAlignB - 1) & ~(kAlignB - 1); }
+
+struct BatchLayout {
+  size_t maps, sets, descs, acc_total, total;
+  std::vector<size_t> acc;  // per-set accumulator offsets
+  std::vector<BlockDesc> host_descs;
+  std::vector<uint32_t> group_first, group_blocks;
+  uint32_t n_groups;
+};
+
+ohm_status plan_layout(const ohm_scan_set* sets, uint32_t n_sets, const ohm_batch_tuning* t, BatchLayout* L) {
+  if (!sets || n_sets == 0 || n_sets > 64 || !t || t->group_scans == 0 || t->group_scans > 64)
+    return OHM_E_INVALID_ARG;
+  const uint32_t G = t->group_scans;
+  bool weighted = sets[0].d_weights != nullptr;
+  uint32_t max_scans = 0;
+  for (uint32_t si = 0; si < n_sets; ++si) {
+    const ohm_scan_set& s = sets[si];
+    ohm_status st = check_scans(s.map, s.d_origins, s.d_samples, s.h_scan_offsets, s.n_scans);
+    if (st != OHM_OK) return st;
+    if (s.map->params.mode != OHM_MODE_COUNT_CLAMP) return OHM_E_UNSUPPORTED;
+    if ((s.d_weights != nullptr) != weighted) return OHM_E_INVALID_ARG;
+    for (uint32_t sj = 0; sj < si; ++sj)
+      if (sets[sj].map == s.map) return OHM_E_INVALID_ARG;  // one set per map
+    if (s.n_scans > max_scans) max_scans = s.n_scans;
+  }
+  L->n_groups = (max_scans + G - 1) / G;
+  L->host_descs.clear();
+  L->group_first.assign(L->n_groups, 0);
+  L->group_blocks.assign(L->n_groups, 0);
+  for (uint32_t g = 0; g < L->n_groups; ++g) {
+    L->group_first[g] = (uint32_t)L->host_descs.size();
+    for (uint32_t si = 0; si < n_sets; ++si) {
+      const ohm_scan_set& s = sets[si];
+      for (uint32_t pos = 0; pos < G; ++pos) {
+        const uint32_t sc = g * G + pos;
+        if (sc >= s.n_scans) break;
+        const uint32_t r0 = s.h_scan_offsets[sc];
+        const uint32_t n = s.h_scan_offsets[sc + 1] - r0;
+        for (uint32_t b = 0; b * 256u < n; ++b) L->host_descs.push_back({si, pos, sc, r0, n, b});
+      }
+    }
+    L->group_blocks[g] = (uint32_t)L->host_descs.size() - L->group_first[g];
+  }
+  size_t off = 0;
+  L->maps = off;
+  off = align_b(off + n_sets * sizeof(DevMap));
+  L->sets = off;
+  off = align_b(off + n_sets * sizeof(SetPtrs));
+  L->descs = off;
+  off = align_b(off + L->host_descs.size() * sizeof(BlockDesc));
+  L->acc.resize(n_sets);
+  for (uint32_t si = 0; si < n_sets; ++si) {
+    L->acc[si] = off;
+    off = align_b(off + (size_t)G * sets[si].map->dm.capacity * kRegionVoxels * 2 * sizeof(float));
+  }
+  L->total = off;
+  return OHM_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+ohm_status ohm_batch_workspace_size(const ohm_scan_set* sets, uint32_t n_sets, const ohm_batch_tuning* tuning,
+                                    size_t* bytes) {
+  if (!bytes) return OHM_E_INVALID_ARG;
+  BatchLayout L;
+  ohm_status s = plan_layout(sets, n_sets, tuning, &L);
+  if (s != OHM_OK) return s;
+  *bytes = L.total;
+  return OHM_OK;
+}
+
+ohm_status ohm_batch_create(const ohm_scan_set* sets, uint32_t n_sets, const ohm_batch_tuning* tuning,
+                            void* d_workspace, size_t workspace_bytes, void* stream, ohm_batch* out) {
+  if (!out) return OHM_E_INVALID_ARG;
+  *out = nullptr;
+  BatchLayout L;
+  ohm_status s = plan_layout(sets, n_sets, tuning, &L);
+  if (s != OHM_OK) return s;
+  if (!d_workspace || ((uintptr_t)d_workspace & (kAlignB - 1))) return OHM_E_INVALID_ARG;
+  if (workspace_bytes < L.total) return OHM_E_WORKSPACE_TOO_SMALL;
+  hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+  ohm_batch_s* b = new (std::nothrow) ohm_batch_s();
+  if (!b) return OHM_E_INVALID_ARG;
+  b->n_sets = n_sets;
+  b->group = tuning->group_scans;
+  b->n_groups = L.n_groups;
+  b->weighted = sets[0].d_weights != nullptr;
+  b->group_first = L.group_first;
+  b->group_blocks = L.group_blocks;
+  char* base = static_cast<char*>(d_workspace);
+  b->d_maps = reinterpret_cast<DevMap*>(base + L.maps);
+  b->d_sets = reinterpret_cast<SetPtrs*>(base + L.sets);
+  b->d_descs = reinterpret_cast<BlockDesc*>(base + L.descs);
+  std::vector<DevMap> hm(n_sets);
+  std::vector<SetPtrs> hs(n_sets);
+  for (uint32_t si = 0; si < n_sets; ++si) {
+    b->maps.push_back(sets[si].map);
+    uint32_t ne = 0;
+    for (uint32_t sc = 0; sc < sets[si].n_scans; ++sc)
+      ne += sets[si].h_scan_offsets[sc + 1] > sets[si].h_scan_offsets[sc] ? 1u : 0u;
+    b->nonempty.push_back(ne);
+    hm[si] = sets[si].map->dm;
+    hm[si].acc = reinterpret_cast<float*>(base + L.acc[si]);
+    hm[si].clampscan = nullptr;  // per-scan clamp records are kept by the per-scan path only
+    hs[si] = {sets[si].d_origins, sets[si].d_samples, sets[si].d_weights};
+  }
+  bool ok = hipMemcpyAsync(b->d_maps, hm.data(), n_sets * sizeof(DevMap), hipMemcpyHostToDevice, st) == hipSuccess;
+  ok = ok && hipMemcpyAsync(b->d_sets, hs.data(), n_sets * sizeof(SetPtrs), hipMemcpyHostToDevice, st) == hipSuccess;
+  if (!L.host_descs.empty())
+    ok = ok && hipMemcpyAsync(b->d_descs, L.host_descs.data(), L.host_descs.size() * sizeof(BlockDesc),
+                              hipMemcpyHostToDevice, st) == hipSuccess;
+  for (uint32_t si = 0; si < n_sets && ok; ++si) {
+    const size_t nf = (size_t)b->group * hm[si].capacity * kRegionVoxels * 2;
+    hipLaunchKernelGGL(fill_u32_kernel, dim3(8192), dim3(256), 0, st, reinterpret_cast<uint32_t*>(hm[si].acc), nf,
+                       0u);
+  }
+  // the host copies above must land before `hm` / `L` go out of scope
+  ok = ok && hipStreamSynchronize(st) == hipSuccess;
+  ok = ok && hipStreamCreate(&b->capture) == hipSuccess;
+  if (!ok) {
+    delete b;
+    return OHM_E_HIP;
+  }
+  // capture the whole sequence
+  ok = hipStreamBeginCapture(b->capture, hipStreamCaptureModeThreadLocal) == hipSuccess;
+  if (ok) {
+    hipLaunchKernelGGL(batch_begin_kernel, dim3(1), dim3(64), 0, b->capture, b->d_maps, n_sets);
+    for (uint32_t g = 0; g < b->n_groups; ++g) {
+      if (b->group_blocks[g]) {
+        if (b->weighted)
+          hipLaunchKernelGGL(batch_walk_kernel<true>, dim3(b->group_blocks[g]), dim3(256), 0, b->capture,
+                             b->d_maps, b->d_sets, b->d_descs + b->group_first[g]);
+        else
+          hipLaunchKernelGGL(batch_walk_kernel<false>, dim3(b->group_blocks[g]), dim3(256), 0, b->capture,
+                             b->d_maps, b->d_sets, b->d_descs + b->group_first[g]);
+      }
+      hipLaunchKernelGGL(batch_finalize_kernel, dim3(kFinalizeBlocks), dim3(256), 0, b->capture, b->d_maps, n_sets,
+                         b->group);
+      hipLaunchKernelGGL(batch_advance_kernel, dim3(1), dim3(64), 0, b->capture, b->d_maps, n_sets);
+    }
+    ok = hipStreamEndCapture(b->capture, &b->graph) == hipSuccess;
+  }
+  ok = ok && hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0) == hipSuccess;
+  if (!ok) {
+    (void)hipGetLastError();
+    if (b->graph) (void)hipGraphDestroy(b->graph);
+    (void)hipStreamDestroy(b->capture);
+    delete b;
+    return OHM_E_HIP;
+  }
+  *out = b;
+  return OHM_OK;
+}
+
+ohm_status ohm_batch_run(ohm_batch b, void* stream) {
+  if (!b) return OHM_E_INVALID_ARG;
+  hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+  for (ohm_map m : b->maps) clear_pending(m, st);
+  if (hipGraphLaunch(b->exec, st) != hipSuccess) return OHM_E_HIP;
+  for (uint32_t si = 0; si < b->n_sets; ++si) b->maps[si]->scans_done += b->nonempty[si];
+  return OHM_OK;
+}
+
+ohm_status ohm_batch_destroy(ohm_batch b) {
+  if (!b) return OHM_E_INVALID_ARG;
+  if (b->exec) (void)hipGraphExecDestroy(b->exec);
+  if (b->graph) (void)hipGraphDestroy(b->graph);
+  if (b->capture) (void)hipStreamDestroy(b->capture);
+  delete b;
+  return OHM_OK;
+}
+
+}  // extern "C"

@@ -33,6 +33,7 @@ enum : int {
   kHdrTouched0 = 1,
   kHdrTouched1 = 2,
   kHdrSticky = 3,
+  kHdrBatchTag = 4,  // scan tag of the batched path (device-resident, survives graph replays)
   kHdrWords = 64
 };
 enum : int {

@@ -1,0 +1,125 @@
+"""Host-side checks of the C ABI (no GPU needed): the library loads, exports
+every function include/ohm.h declares, the header is valid C, and argument
+validation answers without touching a device."""
+import ctypes
+import os
+import re
+import subprocess
+
+import pytest
+
+import paper_2206_06079_amd as ohm
+from paper_2206_06079_amd import _lib
+from workloads import scenes
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "ohm.h")
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(?:ohm_status|const char\*)\s+(ohm_\w+)\s*\(", text)))
+
+
+def test_every_declared_symbol_is_exported():
+    names = declared_functions()
+    assert len(names) >= 15
+    lib = ctypes.CDLL(_lib.LIB_PATH)
+    missing = [n for n in names if not hasattr(lib, n)]
+    assert not missing, missing
+    assert set(names) == set(_lib.EXPORTS)
+
+
+def test_header_compiles_as_c():
+    subprocess.run(["gcc", "-std=c99", "-Wall", "-Werror", "-fsyntax-only", "-x", "c", HEADER], check=True)
+
+
+def test_struct_layouts_match_header():
+    src = '#include "ohm.h"\n#include <stdio.h>\n#include <stddef.h>\nint main(void){printf("%zu %zu %zu %zu\\n", sizeof(ohm_params), sizeof(ohm_map_stats), sizeof(ohm_scan_set), sizeof(ohm_batch_tuning)); return 0;}\n'
+    exe = os.path.join(ROOT, "_work", "abi_sizes")
+    os.makedirs(os.path.dirname(exe), exist_ok=True)
+    subprocess.run(["gcc", "-x", "c", "-", "-I", os.path.join(ROOT, "include"), "-o", exe], input=src.encode(), check=True)
+    out = subprocess.run([exe], capture_output=True, check=True).stdout.split()
+    sizes = [int(x) for x in out]
+    assert sizes == [ctypes.sizeof(_lib.OhmParams), ctypes.sizeof(_lib.OhmStats), ctypes.sizeof(_lib.ScanSet),
+                     ctypes.sizeof(_lib.BatchTuning)]
+
+
+def _size(mp, cap=16, layers=1):
+    lib = _lib.load()
+    p = _lib.make_params(mp)
+    sz = ctypes.c_size_t(0)
+    return lib.ohm_map_workspace_size(ctypes.byref(p), cap, layers, ctypes.byref(sz)), sz.value
+
+
+def test_workspace_size_and_validation():
+    mp, _ = scenes.config0()
+    st, bytes_ = _size(mp, 343)
+    assert st == _lib.OHM_OK
+    # 343 regions x 32^3 voxels x (4 B occupancy + 8 B accumulators) plus tables
+    assert 343 * 32768 * 12 <= bytes_ < 343 * 32768 * 12 + (1 << 22)
+    st_ndt, bytes_ndt = _size(mp, 343, _lib.LAYER_NDT | _lib.LAYER_ADJOINT)
+    assert st_ndt == _lib.OHM_OK and bytes_ndt > bytes_
+    bad = [
+        mp.replace(voxel_size=0.0),
+        mp.replace(key_max=(0, 200, 200)),
+        mp.replace(l_min=1.0, l_max=0.5),
+        mp.replace(l_init=9.0),
+        mp.replace(fixed_bits=4),
+        mp.replace(mode=7),
+        mp.replace(sensor_noise=0.0),
+        mp.replace(adaptation_rate=1.5),
+        mp.replace(l_hit=float("nan")),
+    ]
+    for b in bad:
+        assert _size(b)[0] == _lib.OHM_E_INVALID_ARG, b
+    assert _size(mp, 0)[0] == _lib.OHM_E_INVALID_ARG
+    assert _size(mp, 70000)[0] == _lib.OHM_E_INVALID_ARG
+    # region size other than 32^3 is reported as unsupported
+    p = _lib.make_params(mp)
+    p.region_log2 = 4
+    sz = ctypes.c_size_t()
+    assert _lib.load().ohm_map_workspace_size(ctypes.byref(p), 8, 1, ctypes.byref(sz)) == _lib.OHM_E_UNSUPPORTED
+
+
+def test_create_without_device_reports_no_device():
+    import torch
+    if torch.cuda.is_available():
+        pytest.skip("a GPU is present")
+    mp, _ = scenes.config0()
+    lib = _lib.load()
+    p = _lib.make_params(mp)
+    st, n = _size(mp, 8)
+    h = ctypes.c_void_p()
+    # a (fake, never dereferenced) aligned pointer: creation must stop at the device check
+    assert lib.ohm_map_create(ctypes.byref(p), 8, 1, ctypes.c_void_p(1 << 20), n, None, ctypes.byref(h)) == \
+        _lib.OHM_E_NO_DEVICE
+    assert not h.value
+    # misaligned workspace and short workspace are argument errors
+    assert lib.ohm_map_create(ctypes.byref(p), 8, 1, ctypes.c_void_p(3), n, None, ctypes.byref(h)) == \
+        _lib.OHM_E_INVALID_ARG
+    assert lib.ohm_map_create(ctypes.byref(p), 8, 1, ctypes.c_void_p(1 << 20), n - 1, None, ctypes.byref(h)) == \
+        _lib.OHM_E_WORKSPACE_TOO_SMALL
+
+
+def test_null_handles_are_rejected():
+    lib = _lib.load()
+    assert lib.ohm_map_destroy(None) == _lib.OHM_E_INVALID_ARG
+    assert lib.ohm_map_reset(None, None) == _lib.OHM_E_INVALID_ARG
+    assert lib.ohm_integrate_rays(None, None, None, None, 0, None, None) == _lib.OHM_E_INVALID_ARG
+    assert lib.ohm_ndt_integrate(None, None, None, None, 0, None, None) == _lib.OHM_E_INVALID_ARG
+    assert lib.ohm_batch_run(None, None) == _lib.OHM_E_INVALID_ARG
+    st = _lib.OhmStats()
+    assert lib.ohm_map_sync_status(None, None, ctypes.byref(st)) == _lib.OHM_E_INVALID_ARG
+    assert _lib.status_string(_lib.OHM_E_NO_DEVICE) == "no HIP device"
+
+
+def test_product_never_imports_oracle():
+    """The HIP package must not reach the CPU oracle (no fallback path)."""
+    pkg = os.path.join(ROOT, "paper_2206_06079_amd")
+    for dirpath, _, files in os.walk(pkg):
+        for f in files:
+            if f.endswith((".py", ".hip", ".h", ".cpp")):
+                text = open(os.path.join(dirpath, f)).read()
+                assert "oracle" not in re.sub(r"#.*|//.*", "", text).lower() or f == "build.py", f

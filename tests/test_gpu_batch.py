@@ -1,0 +1,85 @@
+"""Batched multi-sensor integration (one graph launch over many uneven scans
+into two maps) against the oracle and against per-scan launches: occupancy
+and last-touched results must be bit-identical (count mode, unit weights)."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import paper_2206_06079_amd as ohm
+from gpu_helpers import device, to_dev
+from workloads import scenes
+
+pytestmark = pytest.mark.gpu
+
+# windows covering everything the scans touch (x -31..41 m, |y| <= 2.2, |z| <= 1.7)
+WINDOWS = [((690, 978, 183), (720, 44, 34)), ((1380, 1956, 366), (1440, 88, 68))]
+
+
+def make_sets(params, batches, capacities=(512, 1536)):
+    maps, sets = [], []
+    for p, b, cap in zip(params, batches, capacities):
+        m = ohm.OhmMap(p, cap, device=device())
+        o, s, off, w = to_dev(b)
+        maps.append(m)
+        sets.append(ohm.ScanSetArgs(m, o, s, off, w))
+    return maps, sets
+
+
+@pytest.fixture(scope="module")
+def cfg3_small():
+    # 16 streams, 96 scans, scan sizes scaled by 0.1 (819 .. 26,214 rays)
+    return scenes.config3(n_streams=16, n_scans=96, size_scale=0.1)
+
+
+@pytest.mark.parametrize("group", [1, 3, 8])
+def test_batched_equals_oracle_and_per_scan(cfg3_small, group):
+    params, batches = cfg3_small
+    maps, sets = make_sets(params, batches)
+    plan = ohm.OhmBatch(sets, group)
+    plan.run()
+    torch.cuda.synchronize()
+    # per-scan launches on fresh maps
+    ref_maps, _ = make_sets(params, batches)
+    for m, b in zip(ref_maps, batches):
+        o, s, off, w = to_dev(b)
+        m.integrate(o, s, off, w)
+    for mi, (p, b) in enumerate(zip(params, batches)):
+        bmin, bdim = WINDOWS[mi]
+        got = maps[mi].read_dense(ohm.READ_OCC, bmin, bdim).cpu().numpy()
+        per = ref_maps[mi].read_dense(ohm.READ_OCC, bmin, bdim).cpu().numpy()
+        exp, _, _, st = oracle.integrate_count(p, b, bmin, bdim)
+        assert np.array_equal(got, exp), f"map {mi}: batched differs from the oracle"
+        assert np.array_equal(per, exp), f"map {mi}: per-scan differs from the oracle"
+        assert maps[mi].stats()["voxel_updates"] == st["updates"]
+    plan.close()
+
+
+def test_batched_graph_replays_continue(cfg3_small):
+    """Replaying the graph integrates the scans again, exactly like a second
+    per-scan pass (tags survive replays)."""
+    params, batches = cfg3_small
+    maps, sets = make_sets(params, batches)
+    plan = ohm.OhmBatch(sets, 4)
+    plan.run()
+    plan.run()
+    torch.cuda.synchronize()
+    for mi, (p, b) in enumerate(zip(params, batches)):
+        bmin, bdim = WINDOWS[mi]
+        twice = scenes.RayBatch(np.concatenate([b.origins, b.origins]), np.concatenate([b.samples, b.samples]),
+                                np.concatenate([b.offsets, b.offsets[1:] + b.offsets[-1]]).astype(np.uint32))
+        exp, _, _, _ = oracle.integrate_count(p, twice, bmin, bdim)
+        got = maps[mi].read_dense(ohm.READ_OCC, bmin, bdim).cpu().numpy()
+        assert np.array_equal(got, exp)
+    plan.close()
+
+
+def test_autotuner_picks_and_caches(cfg3_small, tmp_path):
+    params, batches = cfg3_small
+    maps, sets = make_sets(params, batches)
+    cache = str(tmp_path / "tune.json")
+    g = ohm.autotune_group(sets, candidates=(1, 4, 16), cache_path=cache, reps=1)
+    assert g in (1, 4, 16)
+    assert ohm.autotune_group(sets, candidates=(2,), cache_path=cache) == g   # served from the cache
+    # the caller's maps were not touched
+    assert all(m.stats()["rays_in"] == 0 for m in maps)

@@ -21,6 +21,7 @@ determined by the seeds, so the same arrays are produced on any host.
 from __future__ import annotations
 
 import dataclasses
+import functools
 import math
 from typing import List, Optional
 
@@ -134,8 +135,17 @@ def random_rays(n_rays: int, seed: int, lo, hi, origin, r_lo=0.0, r_hi=1.0):
 # config 1 scene: box tunnel with random boxes
 # --------------------------------------------------------------------------
 
-def tunnel_scene(n_boxes: int = 200, seed: int = 1, path_len: float = 9.9,
-                 clearance: float = 0.5):
+@functools.lru_cache(maxsize=8)
+def _tunnel_scene_cached(n_boxes, seed, path_len, clearance):
+    return _make_tunnel_scene(n_boxes, seed, path_len, clearance)
+
+
+def tunnel_scene(n_boxes: int = 200, seed: int = 1, path_len: float = 9.9, clearance: float = 0.5):
+    """Axis-aligned boxes ``[n, 2, 3]`` (min, max): see _make_tunnel_scene."""
+    return _tunnel_scene_cached(n_boxes, seed, path_len, clearance).copy()
+
+
+def _make_tunnel_scene(n_boxes, seed, path_len, clearance):
     """Axis-aligned boxes ``[n, 2, 3]`` (min, max) with centres uniform in the
     tunnel, sides U[0.2, 1] m, none within ``clearance`` of the sensor path
     (the x axis from 0 to ``path_len``)."""
@@ -277,29 +287,38 @@ def config3_schedule(n_streams: int = 16, n_scans: int = 1000, seed: int = 3,
     return scans, mounts
 
 
-def config3(n_streams: int = 16, n_scans: int = 1000, size_scale: float = 1.0):
+def _config3_scan(args):
+    stream, index, n, mount = args
+    rng = np.random.default_rng(1000 * stream + index)
+    az = rng.uniform(0.0, 2.0 * np.pi, size=n)
+    el = np.deg2rad(rng.uniform(-22.5, 22.5, size=n))
+    dirs = np.stack([np.cos(az) * np.cos(el), np.sin(az) * np.cos(el), np.sin(el)], 1)
+    pos = np.array([0.1 * (index % 100), 0.0, 0.0]) + mount
+    return pos.astype(np.float32), lidar_scan(pos, dirs, tunnel_scene(), noise_seed=[2, 1000 * stream + index])
+
+
+def config3(n_streams: int = 16, n_scans: int = 1000, size_scale: float = 1.0, jobs: int = 1):
     """Returns the two maps' params and, per map, a RayBatch whose scans are in
     the per-map application order (scan index within stream, then stream id).
-    ``size_scale`` < 1 shrinks every scan (for quick tests)."""
+    ``size_scale`` < 1 shrinks every scan (for quick tests); ``jobs`` > 1
+    generates scans in a process pool (every scan is seeded on its own, so
+    the output does not depend on it)."""
     scans, mounts = config3_schedule(n_streams, n_scans)
-    boxes = tunnel_scene()
     params = [config1_params(0.1), config1_params(0.05)]
     out = []
     for map_id in (0, 1):
         mine = sorted((s for s in scans if s.map_id == map_id), key=lambda s: (s.index, s.stream))
-        origins, chunks, offsets = [], [], [0]
-        for sc in mine:
-            n = max(1, int(round(sc.n_rays * size_scale)))
-            rng = np.random.default_rng(1000 * sc.stream + sc.index)
-            az = rng.uniform(0.0, 2.0 * np.pi, size=n)
-            el = np.deg2rad(rng.uniform(-22.5, 22.5, size=n))
-            dirs = np.stack([np.cos(az) * np.cos(el), np.sin(az) * np.cos(el), np.sin(el)], 1)
-            pos = np.array([0.1 * (sc.index % 100), 0.0, 0.0]) + mounts[sc.stream]
-            origins.append(pos.astype(np.float32))
-            chunks.append(lidar_scan(pos, dirs, boxes, noise_seed=[2, 1000 * sc.stream + sc.index]))
-            offsets.append(offsets[-1] + n)
-        out.append(RayBatch(np.asarray(origins, np.float32), np.concatenate(chunks),
-                            np.asarray(offsets, np.uint32)))
+        work = [(sc.stream, sc.index, max(1, int(round(sc.n_rays * size_scale))), mounts[sc.stream]) for sc in mine]
+        if jobs > 1:
+            import multiprocessing as mp
+            with mp.get_context("fork").Pool(jobs) as pool:
+                res = pool.map(_config3_scan, work, chunksize=4)
+        else:
+            res = [_config3_scan(w) for w in work]
+        offsets = np.zeros(len(res) + 1, np.int64)
+        offsets[1:] = np.cumsum([r[1].shape[0] for r in res])
+        out.append(RayBatch(np.asarray([r[0] for r in res], np.float32), np.concatenate([r[1] for r in res]),
+                            offsets.astype(np.uint32)))
     return params, out
 
 

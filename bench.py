@@ -80,6 +80,80 @@ def run_gpu(args, params, batch, mode):
     }
 
 
+def run_batched(args):
+    """The multi-sensor workload: 16 streams, scans of log-uniform size in
+    [8192, 262144] rays, half into a 0.1 m map and half into a 0.05 m map.
+    Times one graph launch of the batched plan (group size from the
+    autotuner) against per-scan launches of the plain path over the same
+    maps, both with inputs resident in HBM."""
+    import torch
+
+    import paper_2206_06079_amd as ohm
+    from workloads import scenes
+
+    jobs = max(1, min(16, os.cpu_count() or 1))
+    log(f"generating the batched workload ({args.batched_scans} scans, {jobs} processes)")
+    t0 = time.perf_counter()
+    params, batches = scenes.config3(n_scans=args.batched_scans, jobs=jobs)
+    n_rays = sum(b.n_rays for b in batches)
+    log(f"generated {n_rays} rays in {time.perf_counter() - t0:.1f} s")
+    dev = torch.device("cuda", 0)
+    caps = (512, 1536)
+    inputs = [(torch.from_numpy(b.origins).to(dev), torch.from_numpy(b.samples).to(dev), b.offsets)
+              for b in batches]
+
+    def fresh_sets():
+        maps = [ohm.OhmMap(p.replace(mode=ohm.MODE_COUNT_CLAMP), c, device=dev) for p, c in zip(params, caps)]
+        return maps, [ohm.ScanSetArgs(m, o, s, off) for m, (o, s, off) in zip(maps, inputs)]
+
+    maps, sets = fresh_sets()
+    choice = ohm.autotune(sets, groups=args.batched_groups, tiles=args.batched_tiles, reps=1, log=log)
+    plan = ohm.OhmBatch(sets, **choice)
+    stream = torch.cuda.current_stream()
+    plan.run(stream)
+    torch.cuda.synchronize()
+    st0 = [m.stats() for m in maps]
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    reps = args.batched_reps
+    e0.record(stream)
+    for _ in range(reps):
+        plan.run(stream)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms_batched = e0.elapsed_time(e1) / reps
+    st1 = [m.stats() for m in maps]
+    upd = sum(b["voxel_updates"] - a["voxel_updates"] for a, b in zip(st0, st1)) / reps
+    plan.close()
+    for m in maps:
+        m.close()
+    # per-scan plain launches over the same scans, in the same per-map order
+    maps, _ = fresh_sets()
+    for m, (o, s, off) in zip(maps, inputs):
+        m.integrate(o, s, off)
+    torch.cuda.synchronize()
+    e0.record(stream)
+    for _ in range(reps):
+        for m, (o, s, off) in zip(maps, inputs):
+            m.integrate(o, s, off)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms_plain = e0.elapsed_time(e1) / reps
+    for m in maps:
+        m.close()
+    log(f"batched {choice}: {ms_batched:.2f} ms per pass; per-scan launches: {ms_plain:.2f} ms per pass")
+    return {
+        "workload": f"16 sensor streams, {args.batched_scans} scans of log-uniform size in [8192, 262144] rays "
+                    f"({n_rays} rays), tunnel scene, maps at 0.1 m and 0.05 m",
+        "rays_per_s": round(n_rays / (ms_batched * 1e-3), 1),
+        "voxel_updates_per_s": round(upd / (ms_batched * 1e-3), 1),
+        "ms_per_pass": round(ms_batched, 3),
+        "schedule": choice,
+        "per_scan_plain_rays_per_s": round(n_rays / (ms_plain * 1e-3), 1),
+        "per_scan_plain_ms_per_pass": round(ms_plain, 3),
+        "speedup_vs_per_scan": round(ms_plain / ms_batched, 3),
+    }
+
+
 def cpu_baseline(params, batch, n_scans):
     import oracle
 
@@ -109,6 +183,14 @@ def main():
     ap.add_argument("--cpu-scans", type=int, default=16)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-per-update", action="store_true")
+    ap.add_argument("--no-batched", action="store_true")
+    ap.add_argument("--batched-scans", type=int, default=1000)
+    ap.add_argument("--batched-reps", type=int, default=3)
+    ap.add_argument("--batched-groups", type=lambda v: tuple(int(x) for x in v.split(",")), default=(1, 4, 16))
+    ap.add_argument("--calibrate-copy-mb", type=int, default=0,
+                    help="also run a plain device copy of this size (reference for HBM byte counters)")
+    ap.add_argument("--batched-tiles", type=lambda v: tuple(tuple(int(y) for y in x.split("/")) for x in v.split(",")),
+                    default=((16, 512), (32, 1024)), help="walk tiles K/T,K/T,...")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
@@ -158,11 +240,21 @@ def main():
         "unit": "GB/s",
         "frac": round(achieved / HBM_PEAK_GBS, 4),
         "traffic": None,
-        "kernel": "walk_kernel (count mode)",
+        "kernel": "walk_seg_kernel (count mode)",
         "kernel_avg_ms": round(walk_avg_ms, 5),
         "bytes_per_launch": walk_bytes(rays_per_scan, upd_per_scan),
         "atomics_per_s": round(upd_per_scan / (walk_avg_ms * 1e-3), 1),
     }
+    if args.calibrate_copy_mb:
+        n = args.calibrate_copy_mb << 18  # float32 elements
+        src = torch.ones(n, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        log(f"copied {args.calibrate_copy_mb} MiB three times (byte-counter reference)")
+        del src, dst
+    batched = None if args.no_batched else run_batched(args)
     cpu = None
     if not args.no_cpu_baseline:
         log(f"timing the oracle on {args.cpu_scans} scans")
@@ -192,6 +284,7 @@ def main():
         "voxel_updates_per_step": int(res["updates_per_step"]),
         "kernel_ms_per_step": {k: round(v[1] / res["steps"], 4) for k, v in res["kernels"].items()},
         "per_update_mode": per_update,
+        "batched": batched,
         "roofline": roofline,
         "cpu_baseline": cpu,
     }

@@ -258,7 +258,9 @@ typedef struct {
 } ohm_scan_set;
 
 typedef struct {
-  uint32_t group_scans;  /* G: scans per map per launch group */
+  uint32_t group_scans;      /* G: scans per map per launch group, 1..64 */
+  uint32_t seg_major_steps;  /* walk segment length, as in ohm_walk_tuning (0: 16) */
+  uint32_t tile_threads;     /* threads per 256-ray tile: 256, 512 or 1024 (0: 512) */
 } ohm_batch_tuning;
 
 typedef struct ohm_batch_s* ohm_batch;
@@ -272,6 +274,18 @@ ohm_status ohm_batch_create(const ohm_scan_set* sets, uint32_t n_sets, const ohm
 /* Launch the captured plan on `stream` (asynchronous). */
 ohm_status ohm_batch_run(ohm_batch plan, void* stream);
 ohm_status ohm_batch_destroy(ohm_batch plan);
+
+/* Walk launch shape.  Each ray's walk is cut into segments of
+ * seg_major_steps crossings of its major axis (the axis it travels furthest
+ * along); a block of tile_threads threads (256, 512 or 1024) processes the
+ * segments of 256 consecutive rays.  Affects speed only, never results.
+ * Defaults: 16 and 512. */
+typedef struct {
+  uint32_t seg_major_steps;
+  uint32_t tile_threads;
+} ohm_walk_tuning;
+
+ohm_status ohm_map_set_tuning(ohm_map map, const ohm_walk_tuning* tuning);
 
 /* Kernel kinds reported by ohm_map_kernel_times. */
 enum {

@@ -12,4 +12,4 @@ from ._lib import (  # noqa: F401
     OhmError,
 )
 from .ohm import OhmIntegrate, OhmMap, regions_needed  # noqa: F401
-from .batch import OhmBatch, ScanSetArgs, autotune_group  # noqa: F401
+from .batch import OhmBatch, ScanSetArgs, autotune  # noqa: F401

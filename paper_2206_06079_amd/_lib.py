@@ -36,7 +36,12 @@ EXPORTS = (
     "ohm_debug_trace_rays", "ohm_map_sync_status", "ohm_status_string",
     "ohm_map_set_profiling", "ohm_map_kernel_times", "ohm_backward",
     "ohm_batch_workspace_size", "ohm_batch_create", "ohm_batch_run", "ohm_batch_destroy",
+    "ohm_map_set_tuning",
 )
+
+
+class WalkTuning(ctypes.Structure):
+    _fields_ = [("seg_major_steps", ctypes.c_uint32), ("tile_threads", ctypes.c_uint32)]
 
 
 class ScanSet(ctypes.Structure):
@@ -51,7 +56,8 @@ class ScanSet(ctypes.Structure):
 
 
 class BatchTuning(ctypes.Structure):
-    _fields_ = [("group_scans", ctypes.c_uint32)]
+    _fields_ = [("group_scans", ctypes.c_uint32), ("seg_major_steps", ctypes.c_uint32),
+                ("tile_threads", ctypes.c_uint32)]
 
 KERNEL_KINDS = 8
 KERNEL_NAMES = {0: "prepass", 1: "walk", 2: "finalize", 3: "ndt_hit", 7: "other"}
@@ -136,6 +142,7 @@ def load() -> ctypes.CDLL:
         "ohm_batch_workspace_size": [vp, ctypes.c_uint32, vp, P(ctypes.c_size_t)],
         "ohm_batch_create": [vp, ctypes.c_uint32, vp, vp, ctypes.c_size_t, vp, P(vp)],
         "ohm_batch_run": [vp, vp],
+        "ohm_map_set_tuning": [vp, vp],
         "ohm_batch_destroy": [vp],
         "ohm_map_kernel_times": [vp, vp, vp],
     }

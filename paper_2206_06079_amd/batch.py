@@ -3,8 +3,9 @@
 A plan integrates, per map, that map's scans in order -- the same result as
 calling ``OhmMap.integrate`` scan by scan -- with the scans of all maps cut
 into groups of G per map, each group one walk launch, and the whole sequence
-captured as one graph.  ``autotune_group`` picks G by timing candidate plans
-on throwaway maps with the same parameters, and caches the choice."""
+captured as one graph.  ``autotune`` picks G and the walk tile by timing
+candidate plans on throwaway maps with the same parameters, and caches the
+choice."""
 from __future__ import annotations
 
 import ctypes
@@ -21,6 +22,7 @@ from ._lib import check, load
 from .ohm import OhmMap, _dev_ptr, _host_offsets, _stream_ptr
 
 DEFAULT_CANDIDATES = (1, 2, 4, 8, 16)
+DEFAULT_TILES = ((16, 512),)  # (segment major steps, threads per tile)
 
 
 class ScanSetArgs:
@@ -59,14 +61,20 @@ class ScanSetArgs:
 
 
 class OhmBatch:
-    """A captured batched-integration plan over several maps."""
+    """A captured batched-integration plan over several maps.
 
-    def __init__(self, sets: Sequence[ScanSetArgs], group_scans: int, stream=None):
+    ``group_scans`` scans per map share one walk launch; ``seg_major_steps``
+    and ``tile_threads`` set the walk's segment length and threads per
+    256-ray tile (0 keeps the library defaults).  None of them changes the
+    result."""
+
+    def __init__(self, sets: Sequence[ScanSetArgs], group_scans: int, stream=None, seg_major_steps: int = 0,
+                 tile_threads: int = 0):
         lib = load()
         self.sets = list(sets)
         arr = (_lib.ScanSet * len(self.sets))(*[s.struct() for s in self.sets])
         self._arr = arr
-        tun = _lib.BatchTuning(int(group_scans))
+        tun = _lib.BatchTuning(int(group_scans), int(seg_major_steps), int(tile_threads))
         size = ctypes.c_size_t(0)
         check(lib.ohm_batch_workspace_size(arr, len(self.sets), ctypes.byref(tun), ctypes.byref(size)),
               "ohm_batch_workspace_size")
@@ -77,6 +85,8 @@ class OhmBatch:
                                    int(size.value), _stream_ptr(stream), ctypes.byref(h)), "ohm_batch_create")
         self._handle = h
         self.group_scans = int(group_scans)
+        self.seg_major_steps = int(seg_major_steps)
+        self.tile_threads = int(tile_threads)
 
     def run(self, stream=None):
         check(load().ohm_batch_run(self._handle, _stream_ptr(stream)), "ohm_batch_run")
@@ -102,43 +112,49 @@ def _signature(sets: Sequence[ScanSetArgs]) -> str:
     return dev + "|" + "|".join(parts) + "|w%d" % int(sets[0].weights is not None)
 
 
-def autotune_group(sets: Sequence[ScanSetArgs], candidates=DEFAULT_CANDIDATES, cache_path: Optional[str] = None,
-                   reps: int = 2, log=None) -> int:
-    """Pick the group size G with the shortest plan run, timing each
-    candidate on fresh maps with the sets' parameters and capacities (the
-    caller's maps are not touched).  With ``cache_path`` the choice is read
-    from / written to a JSON cache keyed by device and workload signature."""
+def autotune(sets: Sequence[ScanSetArgs], groups=DEFAULT_CANDIDATES, tiles=DEFAULT_TILES,
+             cache_path: Optional[str] = None, reps: int = 2, log=None) -> dict:
+    """Pick the schedule -- group size G and walk tile (segment length K,
+    threads per tile) -- with the shortest plan run, timing every
+    combination on fresh maps with the sets' parameters and capacities (the
+    caller's maps are not touched).  Returns the keyword arguments of
+    ``OhmBatch``.  With ``cache_path`` the choice is read from / written to a
+    JSON cache keyed by device and workload signature."""
     key = _signature(sets)
     cache = {}
     if cache_path and os.path.exists(cache_path):
         with open(cache_path) as f:
             cache = json.load(f)
         if key in cache:
-            return int(cache[key]["group_scans"])
+            c = cache[key]
+            return {"group_scans": int(c["group_scans"]), "seg_major_steps": int(c["seg_major_steps"]),
+                    "tile_threads": int(c["tile_threads"])}
     timings = {}
-    for g in candidates:
-        maps = [OhmMap(s.map.params, s.map.capacity, device=s.map.device) for s in sets]
-        trial = [ScanSetArgs(m, s.origins, s.samples, s.offsets, s.weights) for m, s in zip(maps, sets)]
-        plan = OhmBatch(trial, g)
-        plan.run()
-        torch.cuda.synchronize()
-        best = float("inf")
-        for _ in range(reps):
-            t0 = time.perf_counter()
+    for g in groups:
+        for k, t in tiles:
+            maps = [OhmMap(s.map.params, s.map.capacity, device=s.map.device) for s in sets]
+            trial = [ScanSetArgs(m, s.origins, s.samples, s.offsets, s.weights) for m, s in zip(maps, sets)]
+            plan = OhmBatch(trial, g, seg_major_steps=k, tile_threads=t)
             plan.run()
             torch.cuda.synchronize()
-            best = min(best, time.perf_counter() - t0)
-        timings[g] = best
-        plan.close()
-        for m in maps:
-            m.close()
-        if log:
-            log(f"autotune G={g}: {best * 1e3:.2f} ms")
-    choice = min(timings, key=timings.get)
+            best = float("inf")
+            for _ in range(reps):
+                t0 = time.perf_counter()
+                plan.run()
+                torch.cuda.synchronize()
+                best = min(best, time.perf_counter() - t0)
+            timings[(g, k, t)] = best
+            plan.close()
+            for m in maps:
+                m.close()
+            if log:
+                log(f"autotune G={g} K={k} T={t}: {best * 1e3:.2f} ms")
+    g, k, t = min(timings, key=timings.get)
+    choice = {"group_scans": int(g), "seg_major_steps": int(k), "tile_threads": int(t)}
     if cache_path:
-        cache[key] = {"group_scans": int(choice), "ms": {str(k): v * 1e3 for k, v in timings.items()}}
+        cache[key] = dict(choice, ms={"%d/%d/%d" % c: v * 1e3 for c, v in timings.items()})
         tmp = cache_path + ".tmp"
         with open(tmp, "w") as f:
             json.dump(cache, f, indent=1, sort_keys=True)
         os.replace(tmp, cache_path)
-    return int(choice)
+    return choice

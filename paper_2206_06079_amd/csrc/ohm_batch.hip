@@ -23,7 +23,7 @@
 #include "ohm_regions.h"
 #include "ohm_wave.h"
 
-#include "ohm_walk_body.h"
+#include "ohm_walk_seg.h"
 
 namespace ohm {
 
@@ -48,17 +48,16 @@ struct SetPtrs {
 __device__ __forceinline__ size_t acc_slot_floats(const DevMap& m) { return (size_t)m.capacity * kRegionVoxels * 2; }
 
 template <bool kWeighted>
-__global__ __launch_bounds__(256) void batch_walk_kernel(const DevMap* __restrict__ maps,
-                                                         const SetPtrs* __restrict__ sets,
-                                                         const BlockDesc* __restrict__ descs) {
+__global__ __launch_bounds__(1024) void batch_walk_kernel(const DevMap* __restrict__ maps,
+                                                          const SetPtrs* __restrict__ sets,
+                                                          const BlockDesc* __restrict__ descs, int K) {
   const BlockDesc d = descs[blockIdx.x];
   DevMap m = maps[d.set];
   m.acc += (size_t)d.pos * acc_slot_floats(m);
   const uint32_t tag = __hip_atomic_load(m.hdr + kHdrBatchTag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   const SetPtrs sp = sets[d.set];
-  walk_body<kSinkCount, kWeighted, 0>(m, sp.origins + 3 * (size_t)d.scan, sp.samples, sp.weights, d.r0, d.n,
-                                      d.block * blockDim.x + threadIdx.x, tag, tag & 1u, nullptr, nullptr, nullptr,
-                                      nullptr);
+  walk_tile<kSinkCount, kWeighted>(m, sp.origins + 3 * (size_t)d.scan, sp.samples, sp.weights, d.r0, d.n,
+                                   d.block * kTileRays, K, tag, tag & 1u, nullptr, nullptr, nullptr, nullptr);
 }
 
 // Applies the group's scans in order to every voxel of the regions the group
@@ -128,6 +127,8 @@ struct ohm_batch_s {
   uint32_t n_sets;
   uint32_t group;
   uint32_t n_groups;
+  int seg_major_steps;
+  uint32_t tile_threads;
   bool weighted;
   DevMap* d_maps;
   SetPtrs* d_sets;
@@ -153,6 +154,9 @@ struct BatchLayout {
 
 ohm_status plan_layout(const ohm_scan_set* sets, uint32_t n_sets, const ohm_batch_tuning* t, BatchLayout* L) {
   if (!sets || n_sets == 0 || n_sets > 64 || !t || t->group_scans == 0 || t->group_scans > 64)
+    return OHM_E_INVALID_ARG;
+  if (t->seg_major_steps > 4096) return OHM_E_INVALID_ARG;
+  if (t->tile_threads != 0 && t->tile_threads != 256 && t->tile_threads != 512 && t->tile_threads != 1024)
     return OHM_E_INVALID_ARG;
   const uint32_t G = t->group_scans;
   bool weighted = sets[0].d_weights != nullptr;
@@ -180,7 +184,7 @@ ohm_status plan_layout(const ohm_scan_set* sets, uint32_t n_sets, const ohm_batc
         if (sc >= s.n_scans) break;
         const uint32_t r0 = s.h_scan_offsets[sc];
         const uint32_t n = s.h_scan_offsets[sc + 1] - r0;
-        for (uint32_t b = 0; b * 256u < n; ++b) L->host_descs.push_back({si, pos, sc, r0, n, b});
+        for (uint32_t b = 0; b * (uint32_t)kTileRays < n; ++b) L->host_descs.push_back({si, pos, sc, r0, n, b});
       }
     }
     L->group_blocks[g] = (uint32_t)L->host_descs.size() - L->group_first[g];
@@ -229,6 +233,8 @@ ohm_status ohm_batch_create(const ohm_scan_set* sets, uint32_t n_sets, const ohm
   if (!b) return OHM_E_INVALID_ARG;
   b->n_sets = n_sets;
   b->group = tuning->group_scans;
+  b->seg_major_steps = tuning->seg_major_steps ? (int)tuning->seg_major_steps : kDefaultSegMajorSteps;
+  b->tile_threads = tuning->tile_threads ? tuning->tile_threads : kDefaultTileThreads;
   b->n_groups = L.n_groups;
   b->weighted = sets[0].d_weights != nullptr;
   b->group_first = L.group_first;
@@ -274,11 +280,11 @@ ohm_status ohm_batch_create(const ohm_scan_set* sets, uint32_t n_sets, const ohm
     for (uint32_t g = 0; g < b->n_groups; ++g) {
       if (b->group_blocks[g]) {
         if (b->weighted)
-          hipLaunchKernelGGL(batch_walk_kernel<true>, dim3(b->group_blocks[g]), dim3(256), 0, b->capture,
-                             b->d_maps, b->d_sets, b->d_descs + b->group_first[g]);
+          hipLaunchKernelGGL(batch_walk_kernel<true>, dim3(b->group_blocks[g]), dim3(b->tile_threads), 0,
+                             b->capture, b->d_maps, b->d_sets, b->d_descs + b->group_first[g], b->seg_major_steps);
         else
-          hipLaunchKernelGGL(batch_walk_kernel<false>, dim3(b->group_blocks[g]), dim3(256), 0, b->capture,
-                             b->d_maps, b->d_sets, b->d_descs + b->group_first[g]);
+          hipLaunchKernelGGL(batch_walk_kernel<false>, dim3(b->group_blocks[g]), dim3(b->tile_threads), 0,
+                             b->capture, b->d_maps, b->d_sets, b->d_descs + b->group_first[g], b->seg_major_steps);
       }
       hipLaunchKernelGGL(batch_finalize_kernel, dim3(kFinalizeBlocks), dim3(256), 0, b->capture, b->d_maps, n_sets,
                          b->group);

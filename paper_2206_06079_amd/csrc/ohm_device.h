@@ -146,6 +146,7 @@ __device__ __forceinline__ int prepare_ray(const DevMap& m, const float o[3], co
 }
 
 // Exact walk state at one level of detail: S = F for voxels, F + 5 for regions.
+// walk_init and walk_step are pure integer code, callable on the host too.
 struct Walk {
   int64_t dxy, dxz, dyz;   // pairwise error terms
   int64_t cx, cy, cz;      // A_a << S
@@ -157,7 +158,7 @@ struct Walk {
 
 // k0/k1 are the start/end cells at this level; lo/hi the inclusive cell
 // bounds (hi inclusive) at this level.
-__device__ __forceinline__ void walk_init(Walk& w, const int64_t q0[3], const int64_t q1[3], const int32_t k0[3],
+__host__ __device__ __forceinline__ void walk_init(Walk& w, const int64_t q0[3], const int64_t q1[3], const int32_t k0[3],
                                           const int32_t k1[3], const int32_t lo[3], const int32_t hi[3], int S) {
   int64_t b[3], A[3];
   w.total = 0;
@@ -187,7 +188,7 @@ __device__ __forceinline__ void walk_init(Walk& w, const int64_t q0[3], const in
 
 // Pick the axis of the next crossing (ties to the lower axis) and advance the
 // error terms.  Requires w.total > 0.
-__device__ __forceinline__ int walk_step(Walk& w) {
+__host__ __device__ __forceinline__ int walk_step(Walk& w) {
   bool ex = w.rem[0] > 0, ey = w.rem[1] > 0, ez = w.rem[2] > 0;
   bool sx = ex && (!ey || w.dxy <= 0) && (!ez || w.dxz <= 0);
   bool sy = !sx && ey && (!ez || w.dyz <= 0);

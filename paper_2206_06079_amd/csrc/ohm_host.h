@@ -22,6 +22,8 @@ struct ohm_map_s {
   uint32_t scans_done;     // scans integrated since create / reset
   bool acc_dirty;          // the last count-mode scan's accumulators are still set
   uint32_t last_parity;
+  int seg_major_steps;     // walk tuning (ohm_map_set_tuning)
+  uint32_t walk_threads;
   // kernel timing (ohm_map_set_profiling)
   bool profiling;
   std::vector<hipEvent_t> event_pool;
@@ -36,6 +38,8 @@ struct ohm_map_s {
 namespace ohm {
 
 constexpr int kFinalizeBlocks = 2048;
+constexpr int kDefaultSegMajorSteps = 16;
+constexpr uint32_t kDefaultTileThreads = 512;
 
 // kernels shared across translation units
 __global__ void fill_u32_kernel(uint32_t* p, size_t n, uint32_t v);

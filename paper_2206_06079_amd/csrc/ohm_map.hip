@@ -32,6 +32,7 @@
 #include "ohm_regions.h"
 #include "ohm_wave.h"
 #include "ohm_walk_body.h"
+#include "ohm_walk_seg.h"
 
 namespace ohm {
 
@@ -47,6 +48,20 @@ __global__ void fill_u32_kernel(uint32_t* p, size_t n, uint32_t v) {
   size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
   size_t stride = (size_t)gridDim.x * blockDim.x;
   for (; i < n; i += stride) p[i] = v;
+}
+
+// Segmented walk: one block per tile of 256 rays.
+template <int kSink, bool kWeighted>
+__global__ __launch_bounds__(1024) void walk_seg_kernel(DevMap m, const float* __restrict__ origins, uint32_t scan,
+                                                        const float* __restrict__ samples,
+                                                        const float* __restrict__ weights, uint32_t r0, uint32_t n,
+                                                        int K, uint32_t tag, uint32_t parity,
+                                                        uint32_t* __restrict__ ray_counts,
+                                                        int32_t* __restrict__ ray_flags,
+                                                        const int64_t* __restrict__ ray_offsets,
+                                                        int32_t* __restrict__ updates) {
+  walk_tile<kSink, kWeighted>(m, origins + 3 * (size_t)scan, samples, weights, r0, n, blockIdx.x * kTileRays, K, tag,
+                              parity, ray_counts, ray_flags, ray_offsets, updates);
 }
 
 template <int kSink, bool kWeighted, int kLdsLog2 = 0>
@@ -397,6 +412,8 @@ ohm_status ohm_map_create(const ohm_params* params, uint32_t region_capacity, ui
   if (!map) return OHM_E_INVALID_ARG;
   map->params = *params;
   map->layers = layers | OHM_LAYER_OCC;
+  map->seg_major_steps = kDefaultSegMajorSteps;
+  map->walk_threads = kDefaultTileThreads;
   map->regions = L.regions;
   map->workspace = d_workspace;
   map->workspace_bytes = workspace_bytes;
@@ -474,22 +491,24 @@ ohm_status ohm_integrate_rays(ohm_map map, const float* d_origins, const float* 
     const uint32_t r0 = h_scan_offsets[sc];
     const uint32_t n = h_scan_offsets[sc + 1] - r0;
     if (n == 0) continue;
-    dim3 grid((n + 255) / 256);
     uint32_t tag = 0, parity = 0;
     if (count_mode) {
       clear_pending(map, st);
       tag = ++map->count_batches;
       parity = tag & 1u;
     }
+    const dim3 tiles((n + kTileRays - 1) / kTileRays);
+    const dim3 threads(map->walk_threads);
+    const int K = map->seg_major_steps;
     if (count_mode) {
       {
         ProfScope ps(map, OHM_KERNEL_WALK, st);
         if (weighted)
-          hipLaunchKernelGGL((walk_kernel<kSinkCount, true, kWalkLdsLog2>), grid, dim3(256), 0, st, map->dm, d_origins, sc,
-                           d_samples, d_weights, r0, n, tag, parity, nullptr, nullptr, nullptr, nullptr);
+          hipLaunchKernelGGL((walk_seg_kernel<kSinkCount, true>), tiles, threads, 0, st, map->dm, d_origins, sc,
+                             d_samples, d_weights, r0, n, K, tag, parity, nullptr, nullptr, nullptr, nullptr);
         else
-          hipLaunchKernelGGL((walk_kernel<kSinkCount, false, kWalkLdsLog2>), grid, dim3(256), 0, st, map->dm, d_origins, sc,
-                             d_samples, d_weights, r0, n, tag, parity, nullptr, nullptr, nullptr, nullptr);
+          hipLaunchKernelGGL((walk_seg_kernel<kSinkCount, false>), tiles, threads, 0, st, map->dm, d_origins, sc,
+                             d_samples, d_weights, r0, n, K, tag, parity, nullptr, nullptr, nullptr, nullptr);
       }
       const bool keep = sc == last;
       {
@@ -504,11 +523,11 @@ ohm_status ohm_integrate_rays(ohm_map map, const float* d_origins, const float* 
     } else {
       ProfScope ps(map, OHM_KERNEL_WALK, st);
       if (weighted)
-        hipLaunchKernelGGL((walk_kernel<kSinkCas, true, kWalkLdsLog2>), grid, dim3(256), 0, st, map->dm, d_origins, sc, d_samples,
-                           d_weights, r0, n, tag, parity, nullptr, nullptr, nullptr, nullptr);
+        hipLaunchKernelGGL((walk_seg_kernel<kSinkCas, true>), tiles, threads, 0, st, map->dm, d_origins, sc,
+                           d_samples, d_weights, r0, n, K, tag, parity, nullptr, nullptr, nullptr, nullptr);
       else
-        hipLaunchKernelGGL((walk_kernel<kSinkCas, false, kWalkLdsLog2>), grid, dim3(256), 0, st, map->dm, d_origins, sc,
-                           d_samples, d_weights, r0, n, tag, parity, nullptr, nullptr, nullptr, nullptr);
+        hipLaunchKernelGGL((walk_seg_kernel<kSinkCas, false>), tiles, threads, 0, st, map->dm, d_origins, sc,
+                           d_samples, d_weights, r0, n, K, tag, parity, nullptr, nullptr, nullptr, nullptr);
     }
     map->scans_done += 1;
   }
@@ -545,15 +564,27 @@ ohm_status ohm_debug_trace_rays(ohm_map map, const float* d_origins, const float
     const uint32_t r0 = h_scan_offsets[sc];
     const uint32_t n = h_scan_offsets[sc + 1] - r0;
     if (n == 0) continue;
-    dim3 grid((n + 255) / 256);
+    const dim3 tiles((n + kTileRays - 1) / kTileRays);
+    const dim3 threads(map->walk_threads);
     if (!d_updates)
-      hipLaunchKernelGGL((walk_kernel<kSinkTraceCount, false>), grid, dim3(256), 0, st, map->dm, d_origins, sc,
-                         d_samples, nullptr, r0, n, 0u, 0u, d_ray_counts, d_ray_flags, nullptr, nullptr);
+      hipLaunchKernelGGL((walk_seg_kernel<kSinkTraceCount, false>), tiles, threads, 0, st, map->dm, d_origins, sc,
+                         d_samples, nullptr, r0, n, map->seg_major_steps, 0u, 0u, d_ray_counts, d_ray_flags, nullptr,
+                         nullptr);
     else
-      hipLaunchKernelGGL((walk_kernel<kSinkTraceWrite, false>), grid, dim3(256), 0, st, map->dm, d_origins, sc,
-                         d_samples, nullptr, r0, n, 0u, 0u, nullptr, nullptr, d_ray_offsets, d_updates);
+      hipLaunchKernelGGL((walk_seg_kernel<kSinkTraceWrite, false>), tiles, threads, 0, st, map->dm, d_origins, sc,
+                         d_samples, nullptr, r0, n, map->seg_major_steps, 0u, 0u, nullptr, nullptr, d_ray_offsets,
+                         d_updates);
   }
   return last_hip_status();
+}
+
+ohm_status ohm_map_set_tuning(ohm_map map, const ohm_walk_tuning* t) {
+  if (!map || !t) return OHM_E_INVALID_ARG;
+  if (t->seg_major_steps < 1 || t->seg_major_steps > 4096) return OHM_E_INVALID_ARG;
+  if (t->tile_threads != 256 && t->tile_threads != 512 && t->tile_threads != 1024) return OHM_E_INVALID_ARG;
+  map->seg_major_steps = (int)t->seg_major_steps;
+  map->walk_threads = t->tile_threads;
+  return OHM_OK;
 }
 
 ohm_status ohm_map_set_profiling(ohm_map map, int enable) {

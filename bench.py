@@ -35,6 +35,37 @@ def walk_bytes(rays, updates):
     return 12.0 * rays + 12.0 + 8.0 * updates
 
 
+def kernel_source_digest():
+    """sha256 over the library's kernel sources (names and contents)."""
+    import hashlib
+
+    h = hashlib.sha256()
+    d = os.path.join(ROOT, "paper_2206_06079_amd", "csrc")
+    for f in sorted(os.listdir(d)):
+        if f.endswith((".h", ".hip")):
+            h.update(f.encode())
+            h.update(b"\0")
+            with open(os.path.join(d, f), "rb") as fh:
+                h.update(fh.read())
+    return h.hexdigest()
+
+
+def measured_traffic():
+    """HBM bytes per walk launch from the committed byte-counter summary, or
+    None once the kernel sources differ from those the counters were taken on."""
+    import re
+
+    path = os.path.join(ROOT, "profiles", "walk_seg_kernel_config1_pmc.md")
+    if not os.path.exists(path):
+        return None
+    text = open(path).read()
+    tb = re.search(r"^traffic_bytes_per_launch:\s*(\d+)", text, re.M)
+    sha = re.search(r"^kernel_source_sha256:\s*([0-9a-f]{64})", text, re.M)
+    if not tb or not sha or sha.group(1) != kernel_source_digest():
+        return None
+    return int(tb.group(1))
+
+
 def run_gpu(args, params, batch, mode):
     import torch
 
@@ -180,7 +211,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--scans", type=int, default=100)
     ap.add_argument("--capacity", type=int, default=512)
-    ap.add_argument("--cpu-scans", type=int, default=16)
+    ap.add_argument("--cpu-scans", type=int, default=100)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-per-update", action="store_true")
     ap.add_argument("--no-batched", action="store_true")
@@ -190,7 +221,7 @@ def main():
     ap.add_argument("--calibrate-copy-mb", type=int, default=0,
                     help="also run a plain device copy of this size (reference for HBM byte counters)")
     ap.add_argument("--batched-tiles", type=lambda v: tuple(tuple(int(y) for y in x.split("/")) for x in v.split(",")),
-                    default=((16, 512), (32, 1024)), help="walk tiles K/T,K/T,...")
+                    default=((32, 1024), (16, 1024)), help="walk tiles K/T,K/T,...")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
@@ -239,12 +270,27 @@ def main():
         "peak": HBM_PEAK_GBS,
         "unit": "GB/s",
         "frac": round(achieved / HBM_PEAK_GBS, 4),
-        "traffic": None,
+        "traffic": measured_traffic(),
         "kernel": "walk_seg_kernel (count mode)",
         "kernel_avg_ms": round(walk_avg_ms, 5),
         "bytes_per_launch": walk_bytes(rays_per_scan, upd_per_scan),
-        "atomics_per_s": round(upd_per_scan / (walk_avg_ms * 1e-3), 1),
     }
+    # the atomic roofline: one f32 atomic add per voxel update (before lane
+    # merging) against the device's measured rate of independent f32 atomic
+    # adds at the footprint of the touched regions' accumulator layer
+    footprint = max(1, res["stats"]["regions_used"]) * 32768 * 8
+    ceiling = ohm.probe_atomic_rate(footprint)
+    ceiling_seq = ohm.probe_atomic_rate(footprint, sequential=True)
+    upd_rate = upd_per_scan / (walk_avg_ms * 1e-3)
+    roofline["atomic"] = {
+        "unit": "voxel updates/s",
+        "achieved": round(upd_rate, 1),
+        "ceiling_random_f32_atomics_per_s": round(ceiling, 1),
+        "ceiling_consecutive_f32_atomics_per_s": round(ceiling_seq, 1),
+        "footprint_bytes": footprint,
+        "frac": round(upd_rate / ceiling, 4),
+    }
+    log(f"atomic roofline: {upd_rate / 1e9:.2f} G updates/s vs {ceiling / 1e9:.2f} G random f32 atomics/s")
     if args.calibrate_copy_mb:
         n = args.calibrate_copy_mb << 18  # float32 elements
         src = torch.ones(n, dtype=torch.float32, device="cuda")

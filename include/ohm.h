@@ -259,8 +259,8 @@ typedef struct {
 
 typedef struct {
   uint32_t group_scans;      /* G: scans per map per launch group, 1..64 */
-  uint32_t seg_major_steps;  /* walk segment length, as in ohm_walk_tuning (0: 16) */
-  uint32_t tile_threads;     /* threads per 256-ray tile: 256, 512 or 1024 (0: 512) */
+  uint32_t seg_major_steps;  /* walk segment length, as in ohm_walk_tuning (0: 32) */
+  uint32_t tile_threads;     /* threads per 256-ray tile: 256, 512 or 1024 (0: 1024) */
 } ohm_batch_tuning;
 
 typedef struct ohm_batch_s* ohm_batch;
@@ -279,7 +279,7 @@ ohm_status ohm_batch_destroy(ohm_batch plan);
  * seg_major_steps crossings of its major axis (the axis it travels furthest
  * along); a block of tile_threads threads (256, 512 or 1024) processes the
  * segments of 256 consecutive rays.  Affects speed only, never results.
- * Defaults: 16 and 512. */
+ * Defaults: 32 and 1024. */
 typedef struct {
   uint32_t seg_major_steps;
   uint32_t tile_threads;
@@ -304,6 +304,15 @@ enum {
  * milliseconds (h_ms[OHM_KERNEL_KINDS]), and clears the record. */
 ohm_status ohm_map_set_profiling(ohm_map map, int enable);
 ohm_status ohm_map_kernel_times(ohm_map map, uint32_t* h_launches, double* h_ms);
+
+/* Measurement helper (not part of integration): times 2^27 independent f32
+ * atomic adds of 1.0f into the caller's device buffer d_buffer (bytes long,
+ * at least 4; contents are overwritten), at pseudo-random word addresses or,
+ * with sequential != 0, at consecutive addresses across each wave.  Writes
+ * the rate in operations per second to *h_ops_per_s; synchronises `stream`.
+ * This is the ceiling that the walk's per-voxel atomic updates are compared
+ * with at the footprint of a map's accumulator layer. */
+ohm_status ohm_probe_atomic_rate(void* d_buffer, size_t bytes, int sequential, double* h_ops_per_s, void* stream);
 
 /* Synchronise `stream` and read the map's statistics. */
 ohm_status ohm_map_sync_status(ohm_map map, void* stream, ohm_map_stats* out);

@@ -11,5 +11,5 @@ from ._lib import (  # noqa: F401
     READ_CLAMP_SCAN, READ_HITS, READ_MISSES, READ_NDT_COUNT, READ_NDT_COV, READ_NDT_MEAN, READ_OCC,
     OhmError,
 )
-from .ohm import OhmIntegrate, OhmMap, regions_needed  # noqa: F401
+from .ohm import OhmIntegrate, OhmMap, probe_atomic_rate, regions_needed  # noqa: F401
 from .batch import OhmBatch, ScanSetArgs, autotune  # noqa: F401

@@ -36,7 +36,7 @@ EXPORTS = (
     "ohm_debug_trace_rays", "ohm_map_sync_status", "ohm_status_string",
     "ohm_map_set_profiling", "ohm_map_kernel_times", "ohm_backward",
     "ohm_batch_workspace_size", "ohm_batch_create", "ohm_batch_run", "ohm_batch_destroy",
-    "ohm_map_set_tuning",
+    "ohm_map_set_tuning", "ohm_probe_atomic_rate",
 )
 
 
@@ -145,6 +145,7 @@ def load() -> ctypes.CDLL:
         "ohm_map_set_tuning": [vp, vp],
         "ohm_batch_destroy": [vp],
         "ohm_map_kernel_times": [vp, vp, vp],
+        "ohm_probe_atomic_rate": [vp, ctypes.c_size_t, ctypes.c_int, P(ctypes.c_double), vp],
     }
     for name, args in sig.items():
         fn = getattr(lib, name)

@@ -38,8 +38,8 @@ struct ohm_map_s {
 namespace ohm {
 
 constexpr int kFinalizeBlocks = 2048;
-constexpr int kDefaultSegMajorSteps = 16;
-constexpr uint32_t kDefaultTileThreads = 512;
+constexpr int kDefaultSegMajorSteps = 32;
+constexpr uint32_t kDefaultTileThreads = 1024;
 
 // kernels shared across translation units
 __global__ void fill_u32_kernel(uint32_t* p, size_t n, uint32_t v);

@@ -178,7 +178,7 @@ class OhmMap:
               "ohm_backward")
         return grad_weights, gs
 
-    def set_tuning(self, seg_major_steps: int = 16, tile_threads: int = 512):
+    def set_tuning(self, seg_major_steps: int = 32, tile_threads: int = 1024):
         t = _lib.WalkTuning(int(seg_major_steps), int(tile_threads))
         check(load().ohm_map_set_tuning(self.handle, ctypes.byref(t)), "ohm_map_set_tuning")
 
@@ -198,6 +198,17 @@ class OhmMap:
         st = _lib.OhmStats()
         check(load().ohm_map_sync_status(self.handle, _stream_ptr(stream), ctypes.byref(st)), "ohm_map_sync_status")
         return st.as_dict()
+
+
+def probe_atomic_rate(footprint_bytes: int, sequential: bool = False, device=None, stream=None) -> float:
+    """Independent f32 atomic adds per second at the given footprint (see
+    ohm_probe_atomic_rate)."""
+    dev = torch.device("cuda", 0) if device is None else torch.device(device)
+    buf = torch.zeros(max(1, int(footprint_bytes) // 4), dtype=torch.float32, device=dev)
+    rate = ctypes.c_double(0.0)
+    check(load().ohm_probe_atomic_rate(ctypes.c_void_p(buf.data_ptr()), buf.numel() * 4, 1 if sequential else 0,
+                                       ctypes.byref(rate), _stream_ptr(stream)), "ohm_probe_atomic_rate")
+    return float(rate.value)
 
 
 def regions_needed(params, margin: float = 1.25) -> int:

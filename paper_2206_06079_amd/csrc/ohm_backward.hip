@@ -27,6 +27,7 @@
 #include "ohm_device.h"
 #include "ohm_host.h"
 #include "ohm_regions.h"
+#include "ohm_walk_seg.h"
 #include "ohm_wave.h"
 
 namespace ohm {
@@ -87,102 +88,90 @@ __device__ void ndt_terms(const DevMap& m, const double o[3], const double d[3],
   d_sig = -lam * (0.5 - sig_miss) * g * sn * yy * inv;
 }
 
+constexpr uint32_t kBackwardMaxThreads = 512;  // keeps the kernel within its registers
+
+// One tile of 256 rays, walked segment by segment (see ohm_walk_seg.h).  A
+// ray's weight gradient is the sum over its segments (fp64 LDS atomics);
+// the scalar gradients are reduced per block.
 template <bool kNdt, bool kWeighted>
-__global__ __launch_bounds__(256) void backward_walk_kernel(DevMap m, GradBox gb, const float* __restrict__ origins,
-                                                            uint32_t scan, const float* __restrict__ samples,
-                                                            const float* __restrict__ weights, uint32_t r0,
-                                                            uint32_t n, uint32_t tag, float* __restrict__ grad_w,
-                                                            double* __restrict__ grad_s, double sig_miss) {
+__global__ __launch_bounds__(kBackwardMaxThreads) void backward_seg_kernel(
+    DevMap m, GradBox gb, const float* __restrict__ origins, uint32_t scan, const float* __restrict__ samples,
+    const float* __restrict__ weights, uint32_t r0, uint32_t n, int K, uint32_t tag, float* __restrict__ grad_w,
+    double* __restrict__ grad_s, double sig_miss) {
 #pragma clang fp contract(off)
-  const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
-  const bool inrange = i < n;
-  const size_t ray = (size_t)r0 + i;
-  const float o[3] = {origins[3 * scan + 0], origins[3 * scan + 1], origins[3 * scan + 2]};
-  float e[3] = {0.f, 0.f, 0.f};
-  if (inrange) {
-    e[0] = samples[3 * ray + 0];
-    e[1] = samples[3 * ray + 1];
-    e[2] = samples[3 * ray + 2];
-  }
-  Ray r;
-  const int st = inrange ? prepare_ray(m, o, e, r) : kRayInvalid;
-  bool alive = inrange && st == kRayOk;
-  const double wt = (kWeighted && inrange) ? (double)weights[ray] : 1.0;
-
+  __shared__ TileRays tr;
   __shared__ RegionCache rc;
-  stage_regions<false>(m, rc, alive, r, 0u, 0u);
+  __shared__ double ray_end[3][kTileRays];
+  __shared__ double ray_gw[kTileRays];
+  const uint32_t tid = threadIdx.x;
+  const uint32_t tile0 = blockIdx.x * kTileRays;
+  const float* origin = origins + 3 * (size_t)scan;
+  TileRay t;
+  const uint32_t items = tile_prologue<kStageResolve>(m, tr, rc, origin, samples, r0, n, tile0, K, 0u, 0u, t);
+  if (tid < (uint32_t)kTileRays) {
+    ray_gw[tid] = 0.0;
+    if (t.ok)
+      for (int a = 0; a < 3; ++a) ray_end[a][tid] = t.r.end[a];
+  }
+  __syncthreads();
+  const double od[3] = {(double)origin[0], (double)origin[1], (double)origin[2]};
+  double g_hit = 0.0, g_miss = 0.0, g_sig = 0.0;
 
-  const double od[3] = {(double)o[0], (double)o[1], (double)o[2]};
-  double dv[3] = {0.0, 0.0, 0.0};
-  double dd = 0.0;
-  Walk w;
-  int32_t kx = 0, ky = 0, kz = 0;
-  int32_t slot = -1;
-  uint32_t lidx = 0;
-  if (alive) {
+  for (uint32_t it = tid; it < items; it += blockDim.x) {
+    uint32_t ray_t = 0;
+    int M = 0;
+    SegState s;
+    if (!tile_item(m, tr, it, K, s, ray_t, M)) continue;
+    const bool trunc = tr.trunc[ray_t] != 0;
+    const double wt = kWeighted ? (double)weights[(size_t)r0 + tile0 + ray_t] : 1.0;
+    double dv[3];
+    double dd = 0.0;
     for (int a = 0; a < 3; ++a) {
-      dv[a] = r.end[a] - od[a];
+      dv[a] = ray_end[a][ray_t] - od[a];
       dd = dd + dv[a] * dv[a];
     }
-    const int32_t hi[3] = {m.kmax[0] - 1, m.kmax[1] - 1, m.kmax[2] - 1};
-    walk_init(w, r.q0, r.q1, r.k0, r.k1, m.kmin, hi, m.F);
-    kx = r.k0[0];
-    ky = r.k0[1];
-    kz = r.k0[2];
-    slot = staged_slot(m, rc, kx, ky, kz);
-    lidx = local_index(kx, ky, kz);
-  }
-  double gw = 0.0, g_hit = 0.0, g_miss = 0.0, g_sig = 0.0;
-  while (alive) {
-    const bool last = w.total == 0;
-    const bool is_hit = last && !r.truncated;
-    const float G = grad_at(gb, kx, ky, kz);
-    if (G != 0.f && slot >= 0) {
-      const size_t v = (size_t)slot * kRegionVoxels + lidx;
-      if (tag > m.clampscan[v]) {
-        const double Gd = (double)G;
-        if (is_hit) {
-          gw += Gd * (double)m.l_hit;
-          g_hit += wt * Gd;
-        } else {
-          double delta = m.l_miss, dlm = 1.0, dsg = 0.0;
-          if (kNdt) {
-            const NdtVoxel nv = m.ndt[v];
-            if (nv.n >= m.ndt_min_samples) {
-              const double c[3] = {m.origin[0] + ((double)kx + 0.5) * m.voxel_size,
-                                   m.origin[1] + ((double)ky + 0.5) * m.voxel_size,
-                                   m.origin[2] + ((double)kz + 0.5) * m.voxel_size};
-              ndt_terms(m, od, dv, dd, c, nv, sig_miss, delta, dlm, dsg);
+    int32_t slot = staged_slot(m, rc, s.k[0], s.k[1], s.k[2]);
+    uint32_t lidx = local_index(s.k[0], s.k[1], s.k[2]);
+    double gw = 0.0;
+    for (;;) {
+      const bool last = s.w.total == 0;
+      const bool is_hit = last && !trunc;
+      const float G = grad_at(gb, s.k[0], s.k[1], s.k[2]);
+      if (G != 0.f && slot >= 0) {
+        const size_t v = (size_t)slot * kRegionVoxels + lidx;
+        if (tag > m.clampscan[v]) {
+          const double Gd = (double)G;
+          if (is_hit) {
+            gw += Gd * (double)m.l_hit;
+            g_hit += wt * Gd;
+          } else {
+            double delta = m.l_miss, dlm = 1.0, dsg = 0.0;
+            if (kNdt) {
+              const NdtVoxel nv = m.ndt[v];
+              if (nv.n >= m.ndt_min_samples) {
+                const double c[3] = {m.origin[0] + ((double)s.k[0] + 0.5) * m.voxel_size,
+                                     m.origin[1] + ((double)s.k[1] + 0.5) * m.voxel_size,
+                                     m.origin[2] + ((double)s.k[2] + 0.5) * m.voxel_size};
+                ndt_terms(m, od, dv, dd, c, nv, sig_miss, delta, dlm, dsg);
+              }
             }
+            gw += Gd * delta;
+            g_miss += wt * Gd * dlm;
+            g_sig += wt * Gd * dsg;
           }
-          gw += Gd * delta;
-          g_miss += wt * Gd * dlm;
-          g_sig += wt * Gd * dsg;
         }
       }
+      if (last || !tile_advance<true>(m, rc, s, M, slot, lidx)) break;
     }
-    if (last) break;
-    const int a = walk_step(w);
-    const int32_t ra = a == 0 ? w.rem[0] : (a == 1 ? w.rem[1] : w.rem[2]);
-    if (ra == 0 && ((w.clip >> a) & 1u)) break;
-    const int32_t sg = a == 0 ? w.sg[0] : (a == 1 ? w.sg[1] : w.sg[2]);
-    kx += a == 0 ? sg : 0;
-    ky += a == 1 ? sg : 0;
-    kz += a == 2 ? sg : 0;
-    const int32_t kn = a == 0 ? kx : (a == 1 ? ky : kz);
-    if ((kn & kRegionMask) == (sg > 0 ? 0 : kRegionMask)) {
-      slot = staged_slot(m, rc, kx, ky, kz);
-      lidx = local_index(kx, ky, kz);
-    } else {
-      lidx += (uint32_t)(a == 0 ? sg : (a == 1 ? sg * kRegionEdge : sg * kRegionEdge * kRegionEdge));
-    }
+    if (gw != 0.0) atomicAdd(&ray_gw[ray_t], gw);
   }
-  if (inrange && grad_w) grad_w[ray] = (float)gw;
+  __syncthreads();
+  if (t.inrange && grad_w) grad_w[(size_t)r0 + tile0 + tid] = (float)ray_gw[tid];
   // block reduction of the scalar gradients, one fp64 atomic per block each
-  __shared__ double part[3][4];
+  __shared__ double part[3][kBackwardMaxThreads / 64];
   double vals[3] = {g_hit, g_miss, g_sig};
   const uint32_t lane = lane_id();
-  const uint32_t wave = threadIdx.x >> 6;
+  const uint32_t wave = tid >> 6;
 #pragma unroll
   for (int c = 0; c < 3; ++c) {
     double x = vals[c];
@@ -190,10 +179,10 @@ __global__ __launch_bounds__(256) void backward_walk_kernel(DevMap m, GradBox gb
     if (lane == 0) part[c][wave] = x;
   }
   __syncthreads();
-  if (threadIdx.x < 3) {
+  if (tid < 3) {
     double x = 0.0;
-    for (uint32_t k = 0; k < (blockDim.x >> 6); ++k) x += part[threadIdx.x][k];
-    if (x != 0.0) unsafeAtomicAdd(grad_s + threadIdx.x, x);
+    for (uint32_t k = 0; k < (blockDim.x >> 6); ++k) x += part[tid][k];
+    if (x != 0.0) unsafeAtomicAdd(grad_s + tid, x);
   }
 }
 
@@ -304,22 +293,25 @@ extern "C" ohm_status ohm_backward(ohm_map map, int32_t ndt, const float* d_grad
     if (n == 0) continue;
     ++tag;
     const dim3 grid((n + 255) / 256);
+    const dim3 tiles((n + kTileRays - 1) / kTileRays);
+    const dim3 threads(map->walk_threads < kBackwardMaxThreads ? map->walk_threads : kBackwardMaxThreads);
+    const int K = map->seg_major_steps;
     {
       ProfScope ps(map, OHM_KERNEL_OTHER, st);
       if (ndt) {
         if (weighted)
-          hipLaunchKernelGGL((backward_walk_kernel<true, true>), grid, dim3(256), 0, st, map->dm, gb, d_origins, sc,
-                             d_samples, d_weights, r0, n, tag, d_grad_weights, d_grad_scalars, sig_miss);
+          hipLaunchKernelGGL((backward_seg_kernel<true, true>), tiles, threads, 0, st, map->dm, gb, d_origins, sc,
+                             d_samples, d_weights, r0, n, K, tag, d_grad_weights, d_grad_scalars, sig_miss);
         else
-          hipLaunchKernelGGL((backward_walk_kernel<true, false>), grid, dim3(256), 0, st, map->dm, gb, d_origins,
-                             sc, d_samples, d_weights, r0, n, tag, d_grad_weights, d_grad_scalars, sig_miss);
+          hipLaunchKernelGGL((backward_seg_kernel<true, false>), tiles, threads, 0, st, map->dm, gb, d_origins, sc,
+                             d_samples, d_weights, r0, n, K, tag, d_grad_weights, d_grad_scalars, sig_miss);
       } else {
         if (weighted)
-          hipLaunchKernelGGL((backward_walk_kernel<false, true>), grid, dim3(256), 0, st, map->dm, gb, d_origins,
-                             sc, d_samples, d_weights, r0, n, tag, d_grad_weights, d_grad_scalars, sig_miss);
+          hipLaunchKernelGGL((backward_seg_kernel<false, true>), tiles, threads, 0, st, map->dm, gb, d_origins, sc,
+                             d_samples, d_weights, r0, n, K, tag, d_grad_weights, d_grad_scalars, sig_miss);
         else
-          hipLaunchKernelGGL((backward_walk_kernel<false, false>), grid, dim3(256), 0, st, map->dm, gb, d_origins,
-                             sc, d_samples, d_weights, r0, n, tag, d_grad_weights, d_grad_scalars, sig_miss);
+          hipLaunchKernelGGL((backward_seg_kernel<false, false>), tiles, threads, 0, st, map->dm, gb, d_origins, sc,
+                             d_samples, d_weights, r0, n, K, tag, d_grad_weights, d_grad_scalars, sig_miss);
       }
     }
     if (ndt) {

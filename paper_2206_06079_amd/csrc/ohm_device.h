@@ -186,21 +186,33 @@ __host__ __device__ __forceinline__ void walk_init(Walk& w, const int64_t q0[3],
   w.cz = A[2] << S;
 }
 
-// Pick the axis of the next crossing (ties to the lower axis) and advance the
-// error terms.  Requires w.total > 0.
-__host__ __device__ __forceinline__ int walk_step(Walk& w) {
-  bool ex = w.rem[0] > 0, ey = w.rem[1] > 0, ez = w.rem[2] > 0;
-  bool sx = ex && (!ey || w.dxy <= 0) && (!ez || w.dxz <= 0);
-  bool sy = !sx && ey && (!ez || w.dyz <= 0);
-  bool sz = !sx && !sy;
-  w.dxy += sx ? w.cy : (sy ? -w.cx : 0);
-  w.dxz += sx ? w.cz : (sz ? -w.cx : 0);
-  w.dyz += sy ? w.cz : (sz ? -w.cy : 0);
+// Axis of the next crossing (ties to the lower axis).  Requires w.total > 0.
+__host__ __device__ __forceinline__ int walk_pick(const Walk& w) {
+  const bool ex = w.rem[0] > 0, ey = w.rem[1] > 0, ez = w.rem[2] > 0;
+  const bool sx = ex && (!ey || w.dxy <= 0) && (!ez || w.dxz <= 0);
+  const bool sy = !sx && ey && (!ez || w.dyz <= 0);
+  return sx ? 0 : (sy ? 1 : 2);
+}
+
+// Apply the crossing of axis a: advance the error terms and the counts.
+// (Two's-complement wrapping adds: a walk that has ended may be stepped on
+// without meaning, and must not overflow.)
+__host__ __device__ __forceinline__ void walk_apply(Walk& w, int a) {
+  const bool sx = a == 0, sy = a == 1, sz = a == 2;
+  w.dxy = (int64_t)((uint64_t)w.dxy + (uint64_t)(sx ? w.cy : (sy ? -w.cx : 0)));
+  w.dxz = (int64_t)((uint64_t)w.dxz + (uint64_t)(sx ? w.cz : (sz ? -w.cx : 0)));
+  w.dyz = (int64_t)((uint64_t)w.dyz + (uint64_t)(sy ? w.cz : (sz ? -w.cy : 0)));
   w.rem[0] -= sx ? 1 : 0;
   w.rem[1] -= sy ? 1 : 0;
   w.rem[2] -= sz ? 1 : 0;
   w.total -= 1;
-  return sx ? 0 : (sy ? 1 : 2);
+}
+
+// Pick and apply the next crossing; returns its axis.  Requires w.total > 0.
+__host__ __device__ __forceinline__ int walk_step(Walk& w) {
+  const int a = walk_pick(w);
+  walk_apply(w, a);
+  return a;
 }
 
 __device__ __forceinline__ int32_t region_index(const DevMap& m, int32_t rx, int32_t ry, int32_t rz) {

@@ -12,11 +12,13 @@
 //   clampscan   u32 [capacity][32^3] (optional, adjoint)
 //
 // Per scan the library runs (paper Sec. III-B):
-//   walk      one thread per ray.  Prologue: the block walks its rays over
-//             32^3 regions, allocates missing regions and stages their slots
-//             in LDS (count mode also lists them for finalize).  Then the
-//             exact voxel walk, one update per voxel; equal updates of
-//             adjacent lanes are merged before they are applied.
+//   walk      one block per tile of 256 rays.  Prologue: the block walks
+//             its rays over 32^3 regions, allocates missing regions and
+//             stages their slots in LDS (count mode also lists them for
+//             finalize).  Then the exact voxel walk, cut into segments of K
+//             major-axis crossings (ohm_walk_seg.h), one update per voxel;
+//             equal updates of adjacent lanes are merged before they are
+//             applied.
 //   finalize  (count mode) one clamp per touched voxel: l = clamp(l + t + u)
 #include <hip/hip_runtime.h>
 #include <math.h>
@@ -31,7 +33,6 @@
 #include "ohm_host.h"
 #include "ohm_regions.h"
 #include "ohm_wave.h"
-#include "ohm_walk_body.h"
 #include "ohm_walk_seg.h"
 
 namespace ohm {
@@ -62,19 +63,6 @@ __global__ __launch_bounds__(1024) void walk_seg_kernel(DevMap m, const float* _
                                                         int32_t* __restrict__ updates) {
   walk_tile<kSink, kWeighted>(m, origins + 3 * (size_t)scan, samples, weights, r0, n, blockIdx.x * kTileRays, K, tag,
                               parity, ray_counts, ray_flags, ray_offsets, updates);
-}
-
-template <int kSink, bool kWeighted, int kLdsLog2 = 0>
-__global__ __launch_bounds__(256) void walk_kernel(DevMap m, const float* __restrict__ origins, uint32_t scan,
-                                                   const float* __restrict__ samples,
-                                                   const float* __restrict__ weights, uint32_t r0, uint32_t n,
-                                                   uint32_t tag, uint32_t parity, uint32_t* __restrict__ ray_counts,
-                                                   int32_t* __restrict__ ray_flags,
-                                                   const int64_t* __restrict__ ray_offsets,
-                                                   int32_t* __restrict__ updates) {
-  walk_body<kSink, kWeighted, kLdsLog2>(m, origins + 3 * (size_t)scan, samples, weights, r0, n,
-                                        blockIdx.x * blockDim.x + threadIdx.x, tag, parity, ray_counts, ray_flags,
-                                        ray_offsets, updates);
 }
 
 // ---------------------------------------------------------------------------

@@ -2,8 +2,8 @@
 //
 // Each voxel of an NDT map keeps a sample count n, a mean mu and a population
 // covariance Sigma (voxel-centred, metres).  Per scan:
-//   phase 1 (ndt_walk_kernel): every ray is walked exactly as in the occupancy
-//     path.  Each miss voxel whose statistics hold >= ndt_min_samples samples
+//   phase 1 (ndt_seg_kernel): every ray is walked exactly as in the occupancy
+//     path, segment by segment.  Each miss voxel whose statistics hold >= ndt_min_samples samples
 //     weights its miss by the Gaussian agreement of the ray with the samples:
 //       x* = closest point of the segment to mu,  D = x* - mu,
 //       S = Sigma + sensor_noise^2 I,  g = exp(-D^T S^-1 D / 2),
@@ -27,6 +27,7 @@
 #include "ohm_device.h"
 #include "ohm_host.h"
 #include "ohm_regions.h"
+#include "ohm_walk_seg.h"
 #include "ohm_wave.h"
 
 namespace ohm {
@@ -68,157 +69,130 @@ __device__ __forceinline__ double ndt_delta(const DevMap& m, const double o[3], 
   return log(p / (1.0 - p));
 }
 
+// Phase 1 over a tile of 256 rays, walked segment by segment (see
+// ohm_walk_seg.h): the same per-voxel work as the occupancy walk, with the
+// NDT-weighted miss increment and the hit's sample moments.
+constexpr uint32_t kNdtMaxThreads = 512;  // keeps the kernel within its registers
+
 template <bool kCount, bool kWeighted>
-__global__ __launch_bounds__(256) void ndt_walk_kernel(DevMap m, const float* __restrict__ origins, uint32_t scan,
+__global__ __launch_bounds__(kNdtMaxThreads) void ndt_seg_kernel(DevMap m, const float* __restrict__ origins, uint32_t scan,
                                                        const float* __restrict__ samples,
                                                        const float* __restrict__ weights, uint32_t r0, uint32_t n,
-                                                       uint32_t tag, uint32_t parity, double sig_miss) {
+                                                       int K, uint32_t tag, uint32_t parity, double sig_miss) {
 #pragma clang fp contract(off)
-  const uint32_t lane = lane_id();
-  const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
-  const bool inrange = i < n;
-  const size_t ray = (size_t)r0 + i;
-  const float o[3] = {origins[3 * scan + 0], origins[3 * scan + 1], origins[3 * scan + 2]};
-  float e[3] = {0.f, 0.f, 0.f};
-  if (inrange) {
-    e[0] = samples[3 * ray + 0];
-    e[1] = samples[3 * ray + 1];
-    e[2] = samples[3 * ray + 2];
-  }
-  Ray r;
-  const int st = inrange ? prepare_ray(m, o, e, r) : kRayInvalid;
-  bool alive = inrange && st == kRayOk;
-  const double wt = (kWeighted && inrange) ? (double)weights[ray] : 1.0;
-
+  __shared__ TileRays tr;
   __shared__ RegionCache rc;
-  stage_regions<true>(m, rc, alive, r, tag, parity);
-
-  const double od[3] = {(double)o[0], (double)o[1], (double)o[2]};
-  double dv[3] = {0.0, 0.0, 0.0};
-  double dd = 0.0;
-  Walk w;
-  int32_t kx = 0, ky = 0, kz = 0;
-  int32_t slot = -1;
-  uint32_t lidx = 0;
-  if (alive) {
-    for (int a = 0; a < 3; ++a) {
-      dv[a] = r.end[a] - od[a];
-      dd = dd + dv[a] * dv[a];
-    }
-    int32_t hi[3] = {m.kmax[0] - 1, m.kmax[1] - 1, m.kmax[2] - 1};
-    walk_init(w, r.q0, r.q1, r.k0, r.k1, m.kmin, hi, m.F);
-    kx = r.k0[0];
-    ky = r.k0[1];
-    kz = r.k0[2];
-    slot = staged_slot(m, rc, kx, ky, kz);
-    lidx = local_index(kx, ky, kz);
-  }
-  const long long q_plain = llrint((double)m.l_miss * wt * kQ);
+  __shared__ double ray_end[3][kTileRays];  // world end point after truncation
+  const uint32_t tid = threadIdx.x;
+  const uint32_t lane = lane_id();
+  const uint32_t tile0 = blockIdx.x * kTileRays;
+  const float* origin = origins + 3 * (size_t)scan;
+  TileRay t;
+  const uint32_t items = tile_prologue<kStageTouch>(m, tr, rc, origin, samples, r0, n, tile0, K, tag, parity, t);
+  if (t.ok)
+    for (int a = 0; a < 3; ++a) ray_end[a][tid] = t.r.end[a];
+  __syncthreads();
+  const double od[3] = {(double)origin[0], (double)origin[1], (double)origin[2]};
   uint32_t n_upd = 0, n_drop = 0, n_hit = 0;
-  bool clipped = false;
 
-  while (__ballot(alive)) {
-    const bool last = alive && w.total == 0;
-    const bool is_hit = last && !r.truncated;
-    const bool has = alive && slot >= 0;
-    const size_t v = has ? (size_t)slot * kRegionVoxels + lidx : 0;
-    long long q = 0;
-    if (has) {
-      if (is_hit) {
-        q = llrint(wt * kQ);
-      } else {
-        q = q_plain;
-        const uint32_t cnt = m.ndt[v].n;
-        if (cnt >= m.ndt_min_samples) {
-          const NdtVoxel nv = m.ndt[v];
-          const double c[3] = {m.origin[0] + ((double)kx + 0.5) * m.voxel_size,
-                               m.origin[1] + ((double)ky + 0.5) * m.voxel_size,
-                               m.origin[2] + ((double)kz + 0.5) * m.voxel_size};
-          q = llrint(ndt_delta(m, od, dv, dd, c, nv, sig_miss) * wt * kQ);
-        }
-      }
-    }
-    const uint32_t id = has ? (((uint32_t)slot * (uint32_t)kRegionVoxels + lidx) << 1) | (is_hit ? 1u : 0u)
-                            : (0xFFFFFFFFu - lane);
-    const LaneRuns run = lane_runs(id, lane);
-    const long long qs = segmented_sum(q, run.head, lane);
-    if (has && run.tail) {
-      if (kCount || is_hit) {
-        atomicAdd(reinterpret_cast<unsigned long long*>(m.nacc + v * kNaccWords + (is_hit ? kNaccHit : kNaccMiss)),
-                  (unsigned long long)qs);
-      } else {
-        // per-update mode: the scan's misses land first, by CAS
-        uint32_t* u = reinterpret_cast<uint32_t*>(m.occ + v);
-        const float delta = (float)((double)qs * kInvQ);
-        uint32_t old = __hip_atomic_load(u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        for (;;) {
-          const float nvv = fminf(fmaxf(__uint_as_float(old) + delta, m.l_min), m.l_max);
-          const uint32_t prev = atomicCAS(u, old, __float_as_uint(nvv));
-          if (prev == old) break;
-          old = prev;
-        }
-      }
-    }
-    if (has && is_hit) {
-      // sample moments (fp64), voxel-centred: x = sample - centre
-      const double x0 = (double)e[0] - (m.origin[0] + ((double)kx + 0.5) * m.voxel_size);
-      const double x1 = (double)e[1] - (m.origin[1] + ((double)ky + 0.5) * m.voxel_size);
-      const double x2 = (double)e[2] - (m.origin[2] + ((double)kz + 0.5) * m.voxel_size);
-      double* mo = m.mom + v * kMomWords;
-      unsafeAtomicAdd(mo + 0, x0);
-      unsafeAtomicAdd(mo + 1, x1);
-      unsafeAtomicAdd(mo + 2, x2);
-      unsafeAtomicAdd(mo + 3, x0 * x0);
-      unsafeAtomicAdd(mo + 4, x0 * x1);
-      unsafeAtomicAdd(mo + 5, x0 * x2);
-      unsafeAtomicAdd(mo + 6, x1 * x1);
-      unsafeAtomicAdd(mo + 7, x1 * x2);
-      unsafeAtomicAdd(mo + 8, x2 * x2);
-      atomicAdd(reinterpret_cast<unsigned long long*>(m.nacc + v * kNaccWords + kNaccSamples), 1ull);
-    }
+  const uint32_t rounds = (items + blockDim.x - 1) / blockDim.x;
+  for (uint32_t round = 0; round < rounds; ++round) {
+    const uint32_t it = round * blockDim.x + tid;
+    bool alive = it < items;
+    uint32_t ray_t = 0;
+    int M = 0;
+    SegState s = {};
+    double wt = 1.0;
+    bool trunc = false;
+    int32_t slot = -1;
+    uint32_t lidx = 0;
+    size_t ray = 0;
+    double dv[3] = {0.0, 0.0, 0.0};
+    double dd = 0.0;
     if (alive) {
-      if (slot >= 0) {
-        ++n_upd;
-        n_hit += is_hit ? 1u : 0u;
-      } else {
-        ++n_drop;
+      alive = tile_item(m, tr, it, K, s, ray_t, M);
+      trunc = tr.trunc[ray_t] != 0;
+      ray = (size_t)r0 + tile0 + ray_t;
+      if (kWeighted) wt = (double)weights[ray];
+      for (int a = 0; a < 3; ++a) {
+        dv[a] = ray_end[a][ray_t] - od[a];
+        dd = dd + dv[a] * dv[a];
       }
+      if (alive) slot = staged_slot(m, rc, s.k[0], s.k[1], s.k[2]);
+      lidx = local_index(s.k[0], s.k[1], s.k[2]);
     }
-    if (alive) {
-      if (last) {
-        alive = false;
-      } else {
-        const int a = walk_step(w);
-        const int32_t ra = a == 0 ? w.rem[0] : (a == 1 ? w.rem[1] : w.rem[2]);
-        if (ra == 0 && ((w.clip >> a) & 1u)) {
-          alive = false;
-          clipped = true;
+    const long long q_plain = llrint((double)m.l_miss * wt * kQ);
+    while (__ballot(alive)) {
+      const bool last = alive && s.w.total == 0;
+      const bool is_hit = last && !trunc;
+      const bool has = alive && slot >= 0;
+      const size_t v = has ? (size_t)slot * kRegionVoxels + lidx : 0;
+      long long q = 0;
+      if (has) {
+        if (is_hit) {
+          q = llrint(wt * kQ);
         } else {
-          const int32_t sg = a == 0 ? w.sg[0] : (a == 1 ? w.sg[1] : w.sg[2]);
-          kx += a == 0 ? sg : 0;
-          ky += a == 1 ? sg : 0;
-          kz += a == 2 ? sg : 0;
-          const int32_t kn = a == 0 ? kx : (a == 1 ? ky : kz);
-          if ((kn & kRegionMask) == (sg > 0 ? 0 : kRegionMask)) {
-            slot = staged_slot(m, rc, kx, ky, kz);
-            lidx = local_index(kx, ky, kz);
-          } else {
-            lidx += (uint32_t)(a == 0 ? sg : (a == 1 ? sg * kRegionEdge : sg * kRegionEdge * kRegionEdge));
+          q = q_plain;
+          const uint32_t cnt = m.ndt[v].n;
+          if (cnt >= m.ndt_min_samples) {
+            const NdtVoxel nv = m.ndt[v];
+            const double c[3] = {m.origin[0] + ((double)s.k[0] + 0.5) * m.voxel_size,
+                                 m.origin[1] + ((double)s.k[1] + 0.5) * m.voxel_size,
+                                 m.origin[2] + ((double)s.k[2] + 0.5) * m.voxel_size};
+            q = llrint(ndt_delta(m, od, dv, dd, c, nv, sig_miss) * wt * kQ);
           }
         }
       }
+      const uint32_t id = has ? (((uint32_t)slot * (uint32_t)kRegionVoxels + lidx) << 1) | (is_hit ? 1u : 0u)
+                              : (0xFFFFFFFFu - lane);
+      const LaneRuns run = lane_runs(id, lane);
+      const long long qs = segmented_sum(q, run.head, lane);
+      if (has && run.tail) {
+        if (kCount || is_hit) {
+          atomicAdd(reinterpret_cast<unsigned long long*>(m.nacc + v * kNaccWords + (is_hit ? kNaccHit : kNaccMiss)),
+                    (unsigned long long)qs);
+        } else {
+          // per-update mode: the scan's misses land first, by CAS
+          uint32_t* u = reinterpret_cast<uint32_t*>(m.occ + v);
+          const float delta = (float)((double)qs * kInvQ);
+          uint32_t old = __hip_atomic_load(u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+          for (;;) {
+            const float nvv = fminf(fmaxf(__uint_as_float(old) + delta, m.l_min), m.l_max);
+            const uint32_t prev = atomicCAS(u, old, __float_as_uint(nvv));
+            if (prev == old) break;
+            old = prev;
+          }
+        }
+      }
+      if (has && is_hit) {
+        // sample moments (fp64), voxel-centred: x = sample - centre
+        const double x0 = (double)samples[3 * ray + 0] - (m.origin[0] + ((double)s.k[0] + 0.5) * m.voxel_size);
+        const double x1 = (double)samples[3 * ray + 1] - (m.origin[1] + ((double)s.k[1] + 0.5) * m.voxel_size);
+        const double x2 = (double)samples[3 * ray + 2] - (m.origin[2] + ((double)s.k[2] + 0.5) * m.voxel_size);
+        double* mo = m.mom + v * kMomWords;
+        unsafeAtomicAdd(mo + 0, x0);
+        unsafeAtomicAdd(mo + 1, x1);
+        unsafeAtomicAdd(mo + 2, x2);
+        unsafeAtomicAdd(mo + 3, x0 * x0);
+        unsafeAtomicAdd(mo + 4, x0 * x1);
+        unsafeAtomicAdd(mo + 5, x0 * x2);
+        unsafeAtomicAdd(mo + 6, x1 * x1);
+        unsafeAtomicAdd(mo + 7, x1 * x2);
+        unsafeAtomicAdd(mo + 8, x2 * x2);
+        atomicAdd(reinterpret_cast<unsigned long long*>(m.nacc + v * kNaccWords + kNaccSamples), 1ull);
+      }
+      if (alive) {
+        if (slot >= 0) {
+          ++n_upd;
+          n_hit += is_hit ? 1u : 0u;
+        } else {
+          ++n_drop;
+        }
+        alive = !last && tile_advance<true>(m, rc, s, M, slot, lidx);
+      }
     }
   }
-  uint32_t vals[kStatCount];
-  vals[kStatRays] = inrange ? 1u : 0u;
-  vals[kStatInvalid] = (inrange && st == kRayInvalid) ? 1u : 0u;
-  vals[kStatOriginOob] = (inrange && st == kRayOriginOob) ? 1u : 0u;
-  vals[kStatTruncated] = (st == kRayOk && inrange && r.truncated) ? 1u : 0u;
-  vals[kStatClipped] = clipped ? 1u : 0u;
-  vals[kStatHits] = n_hit;
-  vals[kStatUpdates] = n_upd;
-  vals[kStatDropped] = n_drop;
-  flush_stats(m, vals);
+  flush_tile_stats(m, t, n_hit, n_upd, n_drop);
 }
 
 constexpr int kNdtChunk = 2048;
@@ -313,23 +287,25 @@ extern "C" ohm_status ohm_ndt_integrate(ohm_map map, const float* d_origins, con
     clear_pending(map, st);
     const uint32_t tag = ++map->count_batches;
     const uint32_t parity = tag & 1u;
-    const dim3 grid((n + 255) / 256);
+    const dim3 tiles((n + kTileRays - 1) / kTileRays);
+    const dim3 threads(map->walk_threads < kNdtMaxThreads ? map->walk_threads : kNdtMaxThreads);
+    const int K = map->seg_major_steps;
     {
       ProfScope ps(map, OHM_KERNEL_WALK, st);
       if (count_mode) {
         if (weighted)
-          hipLaunchKernelGGL((ndt_walk_kernel<true, true>), grid, dim3(256), 0, st, map->dm, d_origins, sc,
-                             d_samples, d_weights, r0, n, tag, parity, sig_miss);
+          hipLaunchKernelGGL((ndt_seg_kernel<true, true>), tiles, threads, 0, st, map->dm, d_origins, sc, d_samples,
+                             d_weights, r0, n, K, tag, parity, sig_miss);
         else
-          hipLaunchKernelGGL((ndt_walk_kernel<true, false>), grid, dim3(256), 0, st, map->dm, d_origins, sc,
-                             d_samples, d_weights, r0, n, tag, parity, sig_miss);
+          hipLaunchKernelGGL((ndt_seg_kernel<true, false>), tiles, threads, 0, st, map->dm, d_origins, sc, d_samples,
+                             d_weights, r0, n, K, tag, parity, sig_miss);
       } else {
         if (weighted)
-          hipLaunchKernelGGL((ndt_walk_kernel<false, true>), grid, dim3(256), 0, st, map->dm, d_origins, sc,
-                             d_samples, d_weights, r0, n, tag, parity, sig_miss);
+          hipLaunchKernelGGL((ndt_seg_kernel<false, true>), tiles, threads, 0, st, map->dm, d_origins, sc, d_samples,
+                             d_weights, r0, n, K, tag, parity, sig_miss);
         else
-          hipLaunchKernelGGL((ndt_walk_kernel<false, false>), grid, dim3(256), 0, st, map->dm, d_origins, sc,
-                             d_samples, d_weights, r0, n, tag, parity, sig_miss);
+          hipLaunchKernelGGL((ndt_seg_kernel<false, false>), tiles, threads, 0, st, map->dm, d_origins, sc, d_samples,
+                             d_weights, r0, n, K, tag, parity, sig_miss);
       }
     }
     {

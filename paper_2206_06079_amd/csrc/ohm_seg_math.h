@@ -180,20 +180,20 @@ __host__ __device__ __forceinline__ uint32_t seg_count(const Walk& w, const int6
 // Move a segment walk one voxel on (requires s.w.total > 0).  Returns the
 // axis stepped, with s.k updated, or -1 when the segment ends instead: its
 // next step is a major crossing beyond its budget (the next segment's first),
-// or the step leaves the map.
+// or the step leaves the map.  The step is applied either way (branch-free);
+// after -1 the state is not used again.
 __host__ __device__ __forceinline__ int seg_advance(SegState& s, int M) {
-  Walk nw = s.w;
-  const int a = walk_step(nw);
-  if (a == M && s.allowed == 0) return -1;
-  if (a == M) --s.allowed;
-  s.w = nw;
+  const int a = walk_pick(s.w);
+  const bool over_budget = a == M && s.allowed == 0;
+  s.allowed -= a == M ? 1 : 0;
+  walk_apply(s.w, a);
   const int32_t ra = pick3(a, s.w.rem[0], s.w.rem[1], s.w.rem[2]);
-  if (ra == 0 && ((s.w.clip >> a) & 1u)) return -1;
+  const bool leaves = ra == 0 && ((s.w.clip >> a) & 1u);
   const int32_t sg = pick3(a, s.w.sg[0], s.w.sg[1], s.w.sg[2]);
   s.k[0] += a == 0 ? sg : 0;
   s.k[1] += a == 1 ? sg : 0;
   s.k[2] += a == 2 ? sg : 0;
-  return a;
+  return (over_budget || leaves) ? -1 : a;
 }
 
 // Major axis of a prepared ray.

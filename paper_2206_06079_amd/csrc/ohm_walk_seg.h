@@ -14,10 +14,25 @@
 #include "ohm_device.h"
 #include "ohm_regions.h"
 #include "ohm_seg_math.h"
-#include "ohm_walk_body.h"
 #include "ohm_wave.h"
 
 namespace ohm {
+
+// What a walk does with each voxel: count-mode accumulation, per-update CAS,
+// or the per-ray trace outputs (voxel counts, then the voxel lists).
+enum : int { kSinkCount = 0, kSinkCas = 1, kSinkTraceCount = 2, kSinkTraceWrite = 3 };
+
+// Per-update clamp-add by compare-and-swap, retried until it lands.
+__device__ __forceinline__ void cas_clamp_add(float* p, float delta, float lo, float hi) {
+  uint32_t* u = reinterpret_cast<uint32_t*>(p);
+  uint32_t old = __hip_atomic_load(u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  for (;;) {
+    const float nv = fminf(fmaxf(__uint_as_float(old) + delta, lo), hi);
+    const uint32_t prev = atomicCAS(u, old, __float_as_uint(nv));
+    if (prev == old) break;
+    old = prev;
+  }
+}
 
 // Per-ray data a tile keeps in LDS.
 struct TileRays {
@@ -31,59 +46,67 @@ struct TileRays {
   uint32_t max_seg;
 };
 
-// One block processes the tile of rays [tile0, tile0 + kTileRays) of a scan
-// (n rays from r0).  Every thread of the block must call it.
-template <int kSink, bool kWeighted>
-__device__ void walk_tile(const DevMap& m, const float* __restrict__ origin, const float* __restrict__ samples,
-                          const float* __restrict__ weights, uint32_t r0, uint32_t n, uint32_t tile0, int K,
-                          uint32_t tag, uint32_t parity, uint32_t* __restrict__ ray_counts,
-                          int32_t* __restrict__ ray_flags, const int64_t* __restrict__ ray_offsets,
-                          int32_t* __restrict__ updates) {
-  constexpr bool kAccum = kSink == kSinkCount || kSink == kSinkCas;
-  __shared__ TileRays tr;
-  __shared__ RegionCache rc;
+// Per-thread results of the tile prologue; threads >= kTileRays hold no ray.
+struct TileRay {
+  Ray r;
+  int st;           // kRayOk / kRayInvalid / kRayOriginOob
+  bool inrange;     // the thread's tile slot holds a ray of the scan
+  bool ok;          // ... which prepared successfully
+  bool clipped;     // its walk leaves the map (the end voxel is outside)
+  uint32_t voxels;  // voxels its walk visits inside the map
+};
+
+// Region staging done by the prologue.
+enum : int { kStageNone = 0, kStageResolve = 1, kStageTouch = 2 };
+
+// Prologue of a tile walk (every thread of the block must call it): threads
+// 0..255 prepare rays tile0.. of the scan and fill the LDS ray table, the
+// block stages the tile's regions in LDS (kStage), and the level-major item
+// list is built: level j lists, in ray order, the rays with more than j
+// segments.  Returns the number of items; tr.max_seg holds the level count.
+template <int kStage>
+__device__ __forceinline__ uint32_t tile_prologue(const DevMap& m, TileRays& tr, RegionCache& rc, const float* __restrict__ origin,
+                                  const float* __restrict__ samples, uint32_t r0, uint32_t n, uint32_t tile0, int K,
+                                  uint32_t tag, uint32_t parity, TileRay& t) {
   const uint32_t tid = threadIdx.x;
   const uint32_t lane = lane_id();
-  // --- prologue: prepare the tile's rays (threads 0..255) ---
-  bool ok = false;
-  int st = kRayInvalid;
-  Ray r;
-  const uint32_t ti = tid;  // tile-local ray of this thread in the prologue
-  const bool holds_ray = ti < (uint32_t)kTileRays;
-  const bool inrange = holds_ray && tile0 + ti < n;
+  const bool holds_ray = tid < (uint32_t)kTileRays;
+  t.st = kRayInvalid;
+  t.inrange = holds_ray && tile0 + tid < n;
+  t.ok = false;
+  t.clipped = false;
+  t.voxels = 0;
   if (tid == 0) tr.max_seg = 0;
-  if (inrange) {
-    const size_t ray = (size_t)r0 + tile0 + ti;
+  if (t.inrange) {
+    const size_t ray = (size_t)r0 + tile0 + tid;
     const float o[3] = {origin[0], origin[1], origin[2]};
     const float e[3] = {samples[3 * ray + 0], samples[3 * ray + 1], samples[3 * ray + 2]};
-    st = prepare_ray(m, o, e, r);
-    ok = st == kRayOk;
+    t.st = prepare_ray(m, o, e, t.r);
+    t.ok = t.st == kRayOk;
   }
   __syncthreads();
   uint32_t nseg = 0;
-  uint32_t total_upd = 0;
-  bool clipped_ray = false;
   if (holds_ray) {
-    if (ok) {
+    if (t.ok) {
       Walk w;
       const int32_t hi[3] = {m.kmax[0] - 1, m.kmax[1] - 1, m.kmax[2] - 1};
-      walk_init(w, r.q0, r.q1, r.k0, r.k1, m.kmin, hi, m.F);
-      nseg = seg_count(w, r.q0, r.q1, K);
+      walk_init(w, t.r.q0, t.r.q1, t.r.k0, t.r.k1, m.kmin, hi, m.F);
+      nseg = seg_count(w, t.r.q0, t.r.q1, K);
       // the end voxel lies outside the map exactly when some axis is clipped
-      clipped_ray = w.clip != 0;
-      total_upd = walk_voxels(w, r.q0, r.q1, m.F);
+      t.clipped = w.clip != 0;
+      t.voxels = walk_voxels(w, t.r.q0, t.r.q1, m.F);
       for (int a = 0; a < 3; ++a) {
-        tr.q0[a][ti] = r.q0[a];
-        tr.q1[a][ti] = r.q1[a];
+        tr.q0[a][tid] = t.r.q0[a];
+        tr.q1[a][tid] = t.r.q1[a];
       }
-      tr.trunc[ti] = r.truncated ? 1 : 0;
+      tr.trunc[tid] = t.r.truncated ? 1 : 0;
       atomicMax(&tr.max_seg, nseg);
     }
-    tr.nseg[ti] = (uint8_t)nseg;
+    tr.nseg[tid] = (uint8_t)nseg;
   }
-  if (kAccum) stage_regions<kSink == kSinkCount>(m, rc, ok, r, tag, parity);
+  if (kStage == kStageTouch) stage_regions<true>(m, rc, t.ok, t.r, tag, parity);
+  else if (kStage == kStageResolve) stage_regions<false>(m, rc, t.ok, t.r, tag, parity);
   else __syncthreads();
-  // --- segment-major item list: level j holds the rays with nseg > j ---
   const uint32_t levels = tr.max_seg;
   const uint32_t wave = tid >> 6;
   for (uint32_t j = 0; j < levels; ++j) {
@@ -111,60 +134,117 @@ __device__ void walk_tile(const DevMap& m, const float* __restrict__ origin, con
       const unsigned long long bal = __ballot(nseg > j);
       if (nseg > j) {
         const unsigned long long below = lane == 0 ? 0ull : (bal & (~0ull >> (64 - lane)));
-        tr.item_ray[tr.wave_count[j][wave] + __popcll(below)] = (uint8_t)ti;
+        tr.item_ray[tr.wave_count[j][wave] + __popcll(below)] = (uint8_t)tid;
       }
     }
   }
   __syncthreads();
-  const uint32_t items = tr.level_base[levels];
+  return tr.level_base[levels];
+}
 
-  // --- per-ray trace outputs and statistics (prologue threads) ---
-  if (kSink == kSinkTraceCount && inrange) {
+// Item `it` of the list: its tile-local ray, major axis and segment state.
+// False when the segment is empty (its ray left the map before it starts).
+__device__ __forceinline__ bool tile_item(const DevMap& m, const TileRays& tr, uint32_t it, int K, SegState& s,
+                                          uint32_t& ray_t, int& M) {
+  ray_t = tr.item_ray[it];
+  const uint32_t levels = tr.max_seg;
+  uint32_t level = 0;
+  while (level + 1 < levels && tr.level_base[level + 1] <= it) ++level;
+  const int64_t q0[3] = {tr.q0[0][ray_t], tr.q0[1][ray_t], tr.q0[2][ray_t]};
+  const int64_t q1[3] = {tr.q1[0][ray_t], tr.q1[1][ray_t], tr.q1[2][ray_t]};
+  seg_init(s, q0, q1, m, (int)level, K);
+  M = ray_major_axis(q0, q1);
+  return !s.empty;
+}
+
+// Move past the current voxel (requires s.w.total > 0).  False when the
+// segment ends; otherwise s.k is the next voxel and lidx (and, with kSlots,
+// the staged region slot) follow it.
+template <bool kSlots>
+__device__ __forceinline__ bool tile_advance(const DevMap& m, const RegionCache& rc, SegState& s, int M,
+                                             int32_t& slot, uint32_t& lidx) {
+  const int a = seg_advance(s, M);
+  const bool moved = a >= 0;
+  const int32_t sg = pick3(a, s.w.sg[0], s.w.sg[1], s.w.sg[2]);
+  const int32_t kn = pick3(a, s.k[0], s.k[1], s.k[2]);
+  const bool cross = moved && (kn & kRegionMask) == (sg > 0 ? 0 : kRegionMask);
+  lidx += (uint32_t)(a == 0 ? sg : (a == 1 ? sg * kRegionEdge : sg * kRegionEdge * kRegionEdge));
+  if (cross) {
+    if (kSlots) slot = staged_slot(m, rc, s.k[0], s.k[1], s.k[2]);
+    lidx = local_index(s.k[0], s.k[1], s.k[2]);
+  }
+  return moved;
+}
+
+// Block statistics of a tile walk (every thread must call it).
+__device__ __forceinline__ void flush_tile_stats(const DevMap& m, const TileRay& t, uint32_t n_hit, uint32_t n_upd,
+                                                 uint32_t n_drop) {
+  uint32_t vals[kStatCount];
+  vals[kStatRays] = t.inrange ? 1u : 0u;
+  vals[kStatInvalid] = (t.inrange && t.st == kRayInvalid) ? 1u : 0u;
+  vals[kStatOriginOob] = (t.inrange && t.st == kRayOriginOob) ? 1u : 0u;
+  vals[kStatTruncated] = (t.ok && t.r.truncated) ? 1u : 0u;
+  vals[kStatClipped] = (t.ok && t.clipped) ? 1u : 0u;
+  vals[kStatHits] = n_hit;
+  vals[kStatUpdates] = n_upd;
+  vals[kStatDropped] = n_drop;
+  flush_stats(m, vals);
+}
+
+// Occupancy walk of the tile of rays [tile0, tile0 + kTileRays) of a scan
+// (n rays from r0): count or per-update sinks, or the trace outputs.  Every
+// thread of the block must call it.
+template <int kSink, bool kWeighted>
+__device__ void walk_tile(const DevMap& m, const float* __restrict__ origin, const float* __restrict__ samples,
+                          const float* __restrict__ weights, uint32_t r0, uint32_t n, uint32_t tile0, int K,
+                          uint32_t tag, uint32_t parity, uint32_t* __restrict__ ray_counts,
+                          int32_t* __restrict__ ray_flags, const int64_t* __restrict__ ray_offsets,
+                          int32_t* __restrict__ updates) {
+  constexpr bool kAccum = kSink == kSinkCount || kSink == kSinkCas;
+  constexpr int kStage = kSink == kSinkCount ? kStageTouch : (kSink == kSinkCas ? kStageResolve : kStageNone);
+  __shared__ TileRays tr;
+  __shared__ RegionCache rc;
+  const uint32_t tid = threadIdx.x;
+  const uint32_t lane = lane_id();
+  TileRay t;
+  const uint32_t items = tile_prologue<kStage>(m, tr, rc, origin, samples, r0, n, tile0, K, tag, parity, t);
+
+  if (kSink == kSinkTraceCount && t.inrange) {
     int32_t flags = 0;
-    if (st == kRayInvalid) flags |= 8;
-    if (st == kRayOriginOob) flags |= 16;
-    if (st == kRayOk) {
-      flags |= r.truncated ? 1 : 0;
-      flags |= clipped_ray ? 2 : 0;
-      flags |= (!r.truncated && !clipped_ray) ? 4 : 0;
+    if (t.st == kRayInvalid) flags |= 8;
+    if (t.st == kRayOriginOob) flags |= 16;
+    if (t.ok) {
+      flags |= t.r.truncated ? 1 : 0;
+      flags |= t.clipped ? 2 : 0;
+      flags |= (!t.r.truncated && !t.clipped) ? 4 : 0;
     }
-    const size_t ray = (size_t)r0 + tile0 + ti;
-    ray_counts[ray] = ok ? total_upd : 0u;
+    const size_t ray = (size_t)r0 + tile0 + tid;
+    ray_counts[ray] = t.ok ? t.voxels : 0u;
     ray_flags[ray] = flags;
   }
   uint32_t n_upd = 0, n_drop = 0, n_hit = 0;
 
-  // --- items: segment walks with lane-run merging ---
+  // segment walks, one item per thread per round, with lane-run merging
   const uint32_t rounds = (items + blockDim.x - 1) / blockDim.x;
   for (uint32_t round = 0; round < rounds; ++round) {
     const uint32_t it = round * blockDim.x + tid;
     bool alive = it < items;
-    uint32_t ray_t = 0, level = 0;
-    SegState s;
+    uint32_t ray_t = 0;
+    int M = 0;
+    SegState s = {};
     float wt = 1.f;
     bool trunc = false;
     int32_t slot = -1;
     uint32_t lidx = 0;
     int64_t out_base = 0;
     if (alive) {
-      ray_t = tr.item_ray[it];
-      while (level + 1 < levels && tr.level_base[level + 1] <= it) ++level;
-      const int64_t q0[3] = {tr.q0[0][ray_t], tr.q0[1][ray_t], tr.q0[2][ray_t]};
-      const int64_t q1[3] = {tr.q1[0][ray_t], tr.q1[1][ray_t], tr.q1[2][ray_t]};
-      seg_init(s, q0, q1, m, (int)level, K);
+      alive = tile_item(m, tr, it, K, s, ray_t, M);
       trunc = tr.trunc[ray_t] != 0;
-      alive = !s.empty;
       const size_t ray = (size_t)r0 + tile0 + ray_t;
       if (kWeighted) wt = weights[ray];
       if (kSink == kSinkTraceWrite) out_base = ray_offsets[ray] + s.pos;
       if (kAccum && alive) slot = staged_slot(m, rc, s.k[0], s.k[1], s.k[2]);
       lidx = local_index(s.k[0], s.k[1], s.k[2]);
-    }
-    int M_axis = 0;
-    if (alive) {
-      const int64_t q0[3] = {tr.q0[0][ray_t], tr.q0[1][ray_t], tr.q0[2][ray_t]};
-      const int64_t q1[3] = {tr.q1[0][ray_t], tr.q1[1][ray_t], tr.q1[2][ray_t]};
-      M_axis = ray_major_axis(q0, q1);
     }
     uint32_t local = 0;
     while (__ballot(alive)) {
@@ -190,14 +270,9 @@ __device__ void walk_tile(const DevMap& m, const float* __restrict__ origin, con
           else
             cas_clamp_add(m.occ + (id >> 1), v * ((id & 1u) ? m.l_hit : m.l_miss), m.l_min, m.l_max);
         }
-        if (alive) {
-          if (slot >= 0) {
-            ++n_upd;
-            n_hit += is_hit ? 1u : 0u;
-          } else {
-            ++n_drop;
-          }
-        }
+        n_upd += has ? 1u : 0u;
+        n_hit += (has && is_hit) ? 1u : 0u;
+        n_drop += (alive && !has) ? 1u : 0u;
       } else if (alive && kSink == kSinkTraceWrite) {
         int32_t* out = updates + 4 * (out_base + local);
         out[0] = s.k[0];
@@ -205,39 +280,12 @@ __device__ void walk_tile(const DevMap& m, const float* __restrict__ origin, con
         out[2] = s.k[2];
         out[3] = is_hit ? 1 : 0;
       }
-      if (alive) {
-        ++local;
-        if (last) {
-          alive = false;
-        } else {
-          const int a = seg_advance(s, M_axis);
-          if (a < 0) {
-            alive = false;
-          } else {
-            const int32_t sg = pick3(a, s.w.sg[0], s.w.sg[1], s.w.sg[2]);
-            const int32_t kn = pick3(a, s.k[0], s.k[1], s.k[2]);
-            if ((kn & kRegionMask) == (sg > 0 ? 0 : kRegionMask)) {
-              if (kAccum) slot = staged_slot(m, rc, s.k[0], s.k[1], s.k[2]);
-              lidx = local_index(s.k[0], s.k[1], s.k[2]);
-            } else {
-              lidx += (uint32_t)(a == 0 ? sg : (a == 1 ? sg * kRegionEdge : sg * kRegionEdge * kRegionEdge));
-            }
-          }
-        }
-      }
+      local += alive ? 1u : 0u;
+      if (alive) alive = !last && tile_advance<kAccum>(m, rc, s, M, slot, lidx);
     }
   }
   if (kSink == kSinkTraceCount || kSink == kSinkTraceWrite) return;
-  uint32_t vals[kStatCount];
-  vals[kStatRays] = inrange ? 1u : 0u;
-  vals[kStatInvalid] = (inrange && st == kRayInvalid) ? 1u : 0u;
-  vals[kStatOriginOob] = (inrange && st == kRayOriginOob) ? 1u : 0u;
-  vals[kStatTruncated] = (inrange && ok && r.truncated) ? 1u : 0u;
-  vals[kStatClipped] = (inrange && ok && clipped_ray) ? 1u : 0u;
-  vals[kStatHits] = n_hit;
-  vals[kStatUpdates] = n_upd;
-  vals[kStatDropped] = n_drop;
-  flush_stats(m, vals);
+  flush_tile_stats(m, t, n_hit, n_upd, n_drop);
 }
 
 }  // namespace ohm

@@ -34,6 +34,32 @@ __device__ __forceinline__ void cas_clamp_add(float* p, float delta, float lo, f
   }
 }
 
+// Per-tile aggregation of count-mode updates: a direct-mapped LDS table of
+// 2^kAggLog2 (update id -> summed weight) entries.  A merged update whose
+// table entry holds its id, or claims the empty entry, is added there;
+// otherwise (the entry belongs to another id) it goes to the map's
+// accumulator at once.  The table is applied with one atomic per entry when
+// the tile ends, so the voxels that many rays of the tile cross cost one
+// global atomic per tile instead of one per wave and step.
+#ifndef OHM_AGG_LOG2
+#define OHM_AGG_LOG2 12
+#endif
+constexpr int kAggLog2 = OHM_AGG_LOG2;
+constexpr uint32_t kAggSize = 1u << kAggLog2;
+constexpr uint32_t kAggEmpty = 0xFFFFFFFFu;  // above every update id (capacity <= kMaxCapacity)
+
+__device__ __forceinline__ bool agg_add(uint32_t* keys, float* vals, uint32_t id, float v) {
+  const uint32_t h = (id * 0x9E3779B1u) >> (32 - kAggLog2);
+  uint32_t k = keys[h];
+  if (k == kAggEmpty) {
+    const uint32_t old = atomicCAS(keys + h, kAggEmpty, id);
+    k = old == kAggEmpty ? id : old;
+  }
+  if (k != id) return false;
+  atomicAdd(vals + h, v);
+  return true;
+}
+
 // Per-ray data a tile keeps in LDS.
 struct TileRays {
   long long q0[3][kTileRays];
@@ -202,10 +228,18 @@ __device__ void walk_tile(const DevMap& m, const float* __restrict__ origin, con
                           int32_t* __restrict__ updates) {
   constexpr bool kAccum = kSink == kSinkCount || kSink == kSinkCas;
   constexpr int kStage = kSink == kSinkCount ? kStageTouch : (kSink == kSinkCas ? kStageResolve : kStageNone);
+  constexpr bool kAgg = kSink == kSinkCount;
   __shared__ TileRays tr;
   __shared__ RegionCache rc;
+  __shared__ uint32_t agg_key[kAgg ? kAggSize : 1];
+  __shared__ float agg_val[kAgg ? kAggSize : 1];
   const uint32_t tid = threadIdx.x;
   const uint32_t lane = lane_id();
+  if (kAgg)
+    for (uint32_t h = tid; h < kAggSize; h += blockDim.x) {
+      agg_key[h] = kAggEmpty;
+      agg_val[h] = 0.f;
+    }
   TileRay t;
   const uint32_t items = tile_prologue<kStage>(m, tr, rc, origin, samples, r0, n, tile0, K, tag, parity, t);
 
@@ -265,9 +299,9 @@ __device__ void walk_tile(const DevMap& m, const float* __restrict__ origin, con
           emit_here = has && run.tail;
         }
         if (emit_here) {
-          if (kSink == kSinkCount)
-            unsafeAtomicAdd(m.acc + id, v);
-          else
+          if (kSink == kSinkCount) {
+            if (!agg_add(agg_key, agg_val, id, v)) unsafeAtomicAdd(m.acc + id, v);
+          } else
             cas_clamp_add(m.occ + (id >> 1), v * ((id & 1u) ? m.l_hit : m.l_miss), m.l_min, m.l_max);
         }
         n_upd += has ? 1u : 0u;
@@ -285,6 +319,13 @@ __device__ void walk_tile(const DevMap& m, const float* __restrict__ origin, con
     }
   }
   if (kSink == kSinkTraceCount || kSink == kSinkTraceWrite) return;
+  if (kAgg) {
+    __syncthreads();
+    for (uint32_t h = tid; h < kAggSize; h += blockDim.x) {
+      const uint32_t k = agg_key[h];
+      if (k != kAggEmpty) unsafeAtomicAdd(m.acc + k, agg_val[h]);
+    }
+  }
   flush_tile_stats(m, t, n_hit, n_upd, n_drop);
 }
 

@@ -260,7 +260,7 @@ typedef struct {
 typedef struct {
   uint32_t group_scans;      /* G: scans per map per launch group, 1..64 */
   uint32_t seg_major_steps;  /* walk segment length, as in ohm_walk_tuning (0: 32) */
-  uint32_t tile_threads;     /* threads per 256-ray tile: 256, 512 or 1024 (0: 1024) */
+  uint32_t tile_threads;     /* threads per 256-ray tile: 256, 512 or 1024 (0: 512) */
 } ohm_batch_tuning;
 
 typedef struct ohm_batch_s* ohm_batch;
@@ -279,7 +279,7 @@ ohm_status ohm_batch_destroy(ohm_batch plan);
  * seg_major_steps crossings of its major axis (the axis it travels furthest
  * along); a block of tile_threads threads (256, 512 or 1024) processes the
  * segments of 256 consecutive rays.  Affects speed only, never results.
- * Defaults: 32 and 1024. */
+ * Defaults: 32 and 512. */
 typedef struct {
   uint32_t seg_major_steps;
   uint32_t tile_threads;

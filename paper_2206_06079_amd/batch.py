@@ -22,7 +22,7 @@ from ._lib import check, load
 from .ohm import OhmMap, _dev_ptr, _host_offsets, _stream_ptr
 
 DEFAULT_CANDIDATES = (1, 2, 4, 8, 16)
-DEFAULT_TILES = ((32, 1024), (16, 1024), (32, 512))  # (segment major steps, threads per tile)
+DEFAULT_TILES = ((32, 512), (16, 512), (32, 1024))  # (segment major steps, threads per tile)
 
 
 class ScanSetArgs:

@@ -39,7 +39,7 @@ namespace ohm {
 
 constexpr int kFinalizeBlocks = 2048;
 constexpr int kDefaultSegMajorSteps = 32;
-constexpr uint32_t kDefaultTileThreads = 1024;
+constexpr uint32_t kDefaultTileThreads = 512;
 
 // kernels shared across translation units
 __global__ void fill_u32_kernel(uint32_t* p, size_t n, uint32_t v);

@@ -34,13 +34,15 @@ __device__ __forceinline__ void cas_clamp_add(float* p, float delta, float lo, f
   }
 }
 
-// Per-tile aggregation of count-mode updates: a direct-mapped LDS table of
-// 2^kAggLog2 (update id -> summed weight) entries.  A merged update whose
-// table entry holds its id, or claims the empty entry, is added there;
-// otherwise (the entry belongs to another id) it goes to the map's
-// accumulator at once.  The table is applied with one atomic per entry when
-// the tile ends, so the voxels that many rays of the tile cross cost one
-// global atomic per tile instead of one per wave and step.
+// Per-tile aggregation of updates: a direct-mapped LDS table of 2^kAggLog2
+// (update id -> summed weight) entries.  A merged update whose table entry
+// holds its id, or claims the empty entry, is added there; otherwise (the
+// entry belongs to another id) it is applied at once.  The table is applied
+// with one atomic per entry when the tile ends, so the voxels that many rays
+// of the tile cross cost one global atomic per tile instead of one per wave
+// and step.  An id names one voxel and one kind (hit or miss), so an entry
+// only sums increments of one sign; in per-update mode a clamp-add of that
+// sum equals the clamp-adds of its parts in sequence.
 #ifndef OHM_AGG_LOG2
 #define OHM_AGG_LOG2 12
 #endif
@@ -228,7 +230,7 @@ __device__ void walk_tile(const DevMap& m, const float* __restrict__ origin, con
                           int32_t* __restrict__ updates) {
   constexpr bool kAccum = kSink == kSinkCount || kSink == kSinkCas;
   constexpr int kStage = kSink == kSinkCount ? kStageTouch : (kSink == kSinkCas ? kStageResolve : kStageNone);
-  constexpr bool kAgg = kSink == kSinkCount;
+  constexpr bool kAgg = kAccum;
   __shared__ TileRays tr;
   __shared__ RegionCache rc;
   __shared__ uint32_t agg_key[kAgg ? kAggSize : 1];
@@ -299,10 +301,12 @@ __device__ void walk_tile(const DevMap& m, const float* __restrict__ origin, con
           emit_here = has && run.tail;
         }
         if (emit_here) {
-          if (kSink == kSinkCount) {
-            if (!agg_add(agg_key, agg_val, id, v)) unsafeAtomicAdd(m.acc + id, v);
-          } else
-            cas_clamp_add(m.occ + (id >> 1), v * ((id & 1u) ? m.l_hit : m.l_miss), m.l_min, m.l_max);
+          if (!agg_add(agg_key, agg_val, id, v)) {
+            if (kSink == kSinkCount)
+              unsafeAtomicAdd(m.acc + id, v);
+            else
+              cas_clamp_add(m.occ + (id >> 1), v * ((id & 1u) ? m.l_hit : m.l_miss), m.l_min, m.l_max);
+          }
         }
         n_upd += has ? 1u : 0u;
         n_hit += (has && is_hit) ? 1u : 0u;
@@ -323,7 +327,11 @@ __device__ void walk_tile(const DevMap& m, const float* __restrict__ origin, con
     __syncthreads();
     for (uint32_t h = tid; h < kAggSize; h += blockDim.x) {
       const uint32_t k = agg_key[h];
-      if (k != kAggEmpty) unsafeAtomicAdd(m.acc + k, agg_val[h]);
+      if (k == kAggEmpty) continue;
+      if (kSink == kSinkCount)
+        unsafeAtomicAdd(m.acc + k, agg_val[h]);
+      else
+        cas_clamp_add(m.occ + (k >> 1), agg_val[h] * ((k & 1u) ? m.l_hit : m.l_miss), m.l_min, m.l_max);
     }
   }
   flush_tile_stats(m, t, n_hit, n_upd, n_drop);

@@ -1,7 +1,7 @@
 #!/usr/bin/env python3
 """Throughput benchmark of lidar ray integration on one MI355X.
 
-Workload (one "step"): the 100-scan spinning-lidar sequence -- 64 beams x
+Headline workload (one "step"): the 100-scan spinning-lidar sequence -- 64 beams x
 2048 columns = 131,072 rays per scan, sensor moving 0.1 m per scan along a
 4 x 3 m box tunnel with 200 random boxes, 30 m max range -- integrated scan by
 scan into a 0.1 m occupancy map of 32^3-voxel regions over 200 x 200 x 40 m.
@@ -9,7 +9,10 @@ Inputs are generated once (seeded) and stay resident in HBM; a step re-runs
 the whole per-scan path (region pass, voxel walk with its atomic updates,
 per-scan clamp) over all 100 scans.
 
-Prints one JSON line on stdout; progress goes to stderr.
+Reported alongside: the per-update (CAS) mode, NDT-OM integration of the
+same scans, the adjoint on the 20-scan 0.2 m workload, and the batched
+multi-sensor plan against per-scan launches.  Prints one JSON line on
+stdout; progress goes to stderr.
 """
 import argparse
 import json
@@ -185,6 +188,87 @@ def run_batched(args):
     }
 
 
+def run_ndt(args, params, batch):
+    """NDT-OM integration of the same 100 scans (sensor noise 0.05 m,
+    adaptation rate 1, 4 samples before a voxel weights its misses), count
+    mode, timed like the plain path."""
+    import torch
+
+    import paper_2206_06079_amd as ohm
+
+    p = params.replace(sensor_noise=0.05, adaptation_rate=1.0, ndt_min_samples=4, mode=ohm.MODE_COUNT_CLAMP)
+    dev = torch.device("cuda", 0)
+    o = torch.from_numpy(batch.origins).to(dev)
+    s = torch.from_numpy(batch.samples).to(dev)
+    m = ohm.OhmMap(p, args.capacity, layers=ohm.LAYER_NDT, device=dev)
+    stream = torch.cuda.current_stream()
+    m.ndt_integrate(o, s, batch.offsets)
+    torch.cuda.synchronize()
+    st0 = m.stats()
+    steps = max(1, args.steps // 3)
+    m.set_profiling(True)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(steps):
+        m.ndt_integrate(o, s, batch.offsets)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    kt = m.kernel_times()
+    st1 = m.stats()
+    m.close()
+    ms = e0.elapsed_time(e1) / steps
+    rays = (st1["rays_in"] - st0["rays_in"]) / steps
+    upd = (st1["voxel_updates"] - st0["voxel_updates"]) / steps
+    log(f"ndt: {ms:.3f} ms per {batch.n_scans}-scan pass")
+    return {
+        "workload": f"the same {batch.n_scans} scans into an NDT-OM map (count mode)",
+        "rays_per_s": round(rays / (ms * 1e-3), 1),
+        "voxel_updates_per_s": round(upd / (ms * 1e-3), 1),
+        "ms_per_pass": round(ms, 3),
+        "kernel_us_per_scan": {k: round(v[1] / v[0] * 1e3, 1) for k, v in kt.items()},
+    }
+
+
+def run_adjoint(args):
+    """The differentiable workload: 20 scans at 0.2 m with per-ray weights
+    into an NDT map, then the adjoint for an upstream gradient on a 64^3
+    box (traversals recomputed, statistics replayed)."""
+    import torch
+
+    import paper_2206_06079_amd as ohm
+    from workloads import scenes
+
+    params, batch, box_min, box_dim, _ = scenes.config4(n_scans=20)
+    dev = torch.device("cuda", 0)
+    o = torch.from_numpy(batch.origins).to(dev)
+    s = torch.from_numpy(batch.samples).to(dev)
+    w = torch.from_numpy(batch.weights).to(dev)
+    g = torch.full((box_dim[2], box_dim[1], box_dim[0]), 1e-3, dtype=torch.float32, device=dev)
+    gw = torch.zeros_like(w)
+    stream = torch.cuda.current_stream()
+    e = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
+    fwd, bwd = [], []
+    for _ in range(2):  # the first pass warms up
+        m = ohm.OhmMap(params, 256, layers=ohm.LAYER_NDT | ohm.LAYER_ADJOINT, device=dev)
+        e[0].record(stream)
+        m.ndt_integrate(o, s, batch.offsets, w)
+        e[1].record(stream)
+        m.backward(g, box_min, box_dim, o, s, batch.offsets, w, ndt=True, grad_weights=gw)
+        e[2].record(stream)
+        torch.cuda.synchronize()
+        m.close()
+        fwd.append(e[0].elapsed_time(e[1]))
+        bwd.append(e[1].elapsed_time(e[2]))
+    log(f"adjoint: forward {fwd[-1]:.2f} ms, backward {bwd[-1]:.2f} ms")
+    return {
+        "workload": f"{batch.n_scans} scans x {batch.n_rays // batch.n_scans} weighted rays at 0.2 m, NDT, "
+                    "64^3 loss box",
+        "forward_ms": round(fwd[-1], 3),
+        "backward_ms": round(bwd[-1], 3),
+        "backward_rays_per_s": round(batch.n_rays / (bwd[-1] * 1e-3), 1),
+    }
+
+
 def cpu_baseline(params, batch, n_scans):
     import oracle
 
@@ -215,6 +299,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-per-update", action="store_true")
     ap.add_argument("--no-batched", action="store_true")
+    ap.add_argument("--no-ndt", action="store_true")
+    ap.add_argument("--no-adjoint", action="store_true")
     ap.add_argument("--batched-scans", type=int, default=1000)
     ap.add_argument("--batched-reps", type=int, default=3)
     ap.add_argument("--batched-groups", type=lambda v: tuple(int(x) for x in v.split(",")), default=(1, 4, 16))
@@ -300,6 +386,8 @@ def main():
         torch.cuda.synchronize()
         log(f"copied {args.calibrate_copy_mb} MiB three times (byte-counter reference)")
         del src, dst
+    ndt = None if args.no_ndt else run_ndt(args, params, batch)
+    adjoint = None if args.no_adjoint else run_adjoint(args)
     batched = None if args.no_batched else run_batched(args)
     cpu = None
     if not args.no_cpu_baseline:
@@ -331,6 +419,8 @@ def main():
         "kernel_ms_per_step": {k: round(v[1] / res["steps"], 4) for k, v in res["kernels"].items()},
         "per_update_mode": per_update,
         "batched": batched,
+        "ndt": ndt,
+        "adjoint": adjoint,
         "roofline": roofline,
         "cpu_baseline": cpu,
     }

@@ -74,6 +74,46 @@ __device__ __forceinline__ double ndt_delta(const DevMap& m, const double o[3], 
 // NDT-weighted miss increment and the hit's sample moments.
 constexpr uint32_t kNdtMaxThreads = 512;  // keeps the kernel within its registers
 
+// Per-tile LDS table of the NDT walk's increments (see the occupancy walk's
+// table): update id -> summed Q32.32 increment.  The sums are exact integers,
+// so the result does not depend on how updates reach the table.
+constexpr int kNdtAggLog2 = 12;
+constexpr uint32_t kNdtAggSize = 1u << kNdtAggLog2;
+
+__device__ __forceinline__ bool ndt_agg_add(uint32_t* keys, unsigned long long* vals, uint32_t id, long long q) {
+  const uint32_t h = (id * 0x9E3779B1u) >> (32 - kNdtAggLog2);
+  uint32_t k = keys[h];
+  if (k == kAggEmpty) {
+    const uint32_t old = atomicCAS(keys + h, kAggEmpty, id);
+    k = old == kAggEmpty ? id : old;
+  }
+  if (k != id) return false;
+  atomicAdd(vals + h, (unsigned long long)q);
+  return true;
+}
+
+// Apply a summed increment of one (voxel, kind): Q32.32 accumulators, or in
+// per-update mode a miss lands at once by CAS.
+template <bool kCount>
+__device__ __forceinline__ void ndt_apply(const DevMap& m, uint32_t id, long long qs) {
+  const size_t v = (size_t)(id >> 1);
+  const bool is_hit = (id & 1u) != 0;
+  if (kCount || is_hit) {
+    atomicAdd(reinterpret_cast<unsigned long long*>(m.nacc + v * kNaccWords + (is_hit ? kNaccHit : kNaccMiss)),
+              (unsigned long long)qs);
+  } else {
+    uint32_t* u = reinterpret_cast<uint32_t*>(m.occ + v);
+    const float delta = (float)((double)qs * kInvQ);
+    uint32_t old = __hip_atomic_load(u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    for (;;) {
+      const float nvv = fminf(fmaxf(__uint_as_float(old) + delta, m.l_min), m.l_max);
+      const uint32_t prev = atomicCAS(u, old, __float_as_uint(nvv));
+      if (prev == old) break;
+      old = prev;
+    }
+  }
+}
+
 template <bool kCount, bool kWeighted>
 __global__ __launch_bounds__(kNdtMaxThreads) void ndt_seg_kernel(DevMap m, const float* __restrict__ origins, uint32_t scan,
                                                        const float* __restrict__ samples,
@@ -83,10 +123,16 @@ __global__ __launch_bounds__(kNdtMaxThreads) void ndt_seg_kernel(DevMap m, const
   __shared__ TileRays tr;
   __shared__ RegionCache rc;
   __shared__ double ray_end[3][kTileRays];  // world end point after truncation
+  __shared__ uint32_t agg_key[kNdtAggSize];
+  __shared__ unsigned long long agg_val[kNdtAggSize];
   const uint32_t tid = threadIdx.x;
   const uint32_t lane = lane_id();
   const uint32_t tile0 = blockIdx.x * kTileRays;
   const float* origin = origins + 3 * (size_t)scan;
+  for (uint32_t h = tid; h < kNdtAggSize; h += blockDim.x) {
+    agg_key[h] = kAggEmpty;
+    agg_val[h] = 0ull;
+  }
   TileRay t;
   const uint32_t items = tile_prologue<kStageTouch>(m, tr, rc, origin, samples, r0, n, tile0, K, tag, parity, t);
   if (t.ok)
@@ -128,6 +174,7 @@ __global__ __launch_bounds__(kNdtMaxThreads) void ndt_seg_kernel(DevMap m, const
       const bool has = alive && slot >= 0;
       const size_t v = has ? (size_t)slot * kRegionVoxels + lidx : 0;
       long long q = 0;
+      bool weighted_miss = false;  // a miss whose increment the voxel's samples weight
       if (has) {
         if (is_hit) {
           q = llrint(wt * kQ);
@@ -135,6 +182,7 @@ __global__ __launch_bounds__(kNdtMaxThreads) void ndt_seg_kernel(DevMap m, const
           q = q_plain;
           const uint32_t cnt = m.ndt[v].n;
           if (cnt >= m.ndt_min_samples) {
+            weighted_miss = true;
             const NdtVoxel nv = m.ndt[v];
             const double c[3] = {m.origin[0] + ((double)s.k[0] + 0.5) * m.voxel_size,
                                  m.origin[1] + ((double)s.k[1] + 0.5) * m.voxel_size,
@@ -146,24 +194,17 @@ __global__ __launch_bounds__(kNdtMaxThreads) void ndt_seg_kernel(DevMap m, const
       const uint32_t id = has ? (((uint32_t)slot * (uint32_t)kRegionVoxels + lidx) << 1) | (is_hit ? 1u : 0u)
                               : (0xFFFFFFFFu - lane);
       const LaneRuns run = lane_runs(id, lane);
-      const long long qs = segmented_sum(q, run.head, lane);
-      if (has && run.tail) {
-        if (kCount || is_hit) {
-          atomicAdd(reinterpret_cast<unsigned long long*>(m.nacc + v * kNaccWords + (is_hit ? kNaccHit : kNaccMiss)),
-                    (unsigned long long)qs);
-        } else {
-          // per-update mode: the scan's misses land first, by CAS
-          uint32_t* u = reinterpret_cast<uint32_t*>(m.occ + v);
-          const float delta = (float)((double)qs * kInvQ);
-          uint32_t old = __hip_atomic_load(u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-          for (;;) {
-            const float nvv = fminf(fmaxf(__uint_as_float(old) + delta, m.l_min), m.l_max);
-            const uint32_t prev = atomicCAS(u, old, __float_as_uint(nvv));
-            if (prev == old) break;
-            old = prev;
-          }
-        }
+      long long qs;
+      bool emit;
+      if (!kWeighted && __ballot(weighted_miss) == 0ull) {
+        // every increment of a run is the same (unit weight, plain miss or hit)
+        qs = (long long)run.len * q;
+        emit = has && run.head;
+      } else {
+        qs = segmented_sum(q, run.head, lane);
+        emit = has && run.tail;
       }
+      if (emit && !ndt_agg_add(agg_key, agg_val, id, qs)) ndt_apply<kCount>(m, id, qs);
       if (has && is_hit) {
         // sample moments (fp64), voxel-centred: x = sample - centre
         const double x0 = (double)samples[3 * ray + 0] - (m.origin[0] + ((double)s.k[0] + 0.5) * m.voxel_size);
@@ -191,6 +232,11 @@ __global__ __launch_bounds__(kNdtMaxThreads) void ndt_seg_kernel(DevMap m, const
         alive = !last && tile_advance<true>(m, rc, s, M, slot, lidx);
       }
     }
+  }
+  __syncthreads();
+  for (uint32_t h = tid; h < kNdtAggSize; h += blockDim.x) {
+    const uint32_t k = agg_key[h];
+    if (k != kAggEmpty) ndt_apply<kCount>(m, k, (long long)agg_val[h]);
   }
   flush_tile_stats(m, t, n_hit, n_upd, n_drop);
 }

@@ -261,6 +261,11 @@ typedef struct {
   uint32_t group_scans;      /* G: scans per map per launch group, 1..64 */
   uint32_t seg_major_steps;  /* walk segment length, as in ohm_walk_tuning (0: 32) */
   uint32_t tile_threads;     /* threads per 256-ray tile: 256, 512 or 1024 (0: 512) */
+  uint32_t keep_ray_order;   /* 0: each run walks every scan's rays in direction order
+                                (strips of azimuth, then elevation), which keeps a tile's
+                                rays together when a scan's directions arrive unordered;
+                                nonzero: walk them in the given order (scans already in
+                                sensor order).  Never changes results. */
 } ohm_batch_tuning;
 
 typedef struct ohm_batch_s* ohm_batch;

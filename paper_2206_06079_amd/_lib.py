@@ -57,7 +57,7 @@ class ScanSet(ctypes.Structure):
 
 class BatchTuning(ctypes.Structure):
     _fields_ = [("group_scans", ctypes.c_uint32), ("seg_major_steps", ctypes.c_uint32),
-                ("tile_threads", ctypes.c_uint32)]
+                ("tile_threads", ctypes.c_uint32), ("keep_ray_order", ctypes.c_uint32)]
 
 KERNEL_KINDS = 8
 KERNEL_NAMES = {0: "prepass", 1: "walk", 2: "finalize", 3: "ndt_hit", 7: "other"}

@@ -65,16 +65,17 @@ class OhmBatch:
 
     ``group_scans`` scans per map share one walk launch; ``seg_major_steps``
     and ``tile_threads`` set the walk's segment length and threads per
-    256-ray tile (0 keeps the library defaults).  None of them changes the
-    result."""
+    256-ray tile (0 keeps the library defaults); ``keep_ray_order`` walks
+    each scan's rays in the given order instead of direction order.  None of
+    them changes the result."""
 
     def __init__(self, sets: Sequence[ScanSetArgs], group_scans: int, stream=None, seg_major_steps: int = 0,
-                 tile_threads: int = 0):
+                 tile_threads: int = 0, keep_ray_order: int = 0):
         lib = load()
         self.sets = list(sets)
         arr = (_lib.ScanSet * len(self.sets))(*[s.struct() for s in self.sets])
         self._arr = arr
-        tun = _lib.BatchTuning(int(group_scans), int(seg_major_steps), int(tile_threads))
+        tun = _lib.BatchTuning(int(group_scans), int(seg_major_steps), int(tile_threads), int(keep_ray_order))
         size = ctypes.c_size_t(0)
         check(lib.ohm_batch_workspace_size(arr, len(self.sets), ctypes.byref(tun), ctypes.byref(size)),
               "ohm_batch_workspace_size")
@@ -87,6 +88,7 @@ class OhmBatch:
         self.group_scans = int(group_scans)
         self.seg_major_steps = int(seg_major_steps)
         self.tile_threads = int(tile_threads)
+        self.keep_ray_order = int(keep_ray_order)
 
     def run(self, stream=None):
         check(load().ohm_batch_run(self._handle, _stream_ptr(stream)), "ohm_batch_run")
@@ -112,14 +114,15 @@ def _signature(sets: Sequence[ScanSetArgs]) -> str:
     return dev + "|" + "|".join(parts) + "|w%d" % int(sets[0].weights is not None)
 
 
-def autotune(sets: Sequence[ScanSetArgs], groups=DEFAULT_CANDIDATES, tiles=DEFAULT_TILES,
+def autotune(sets: Sequence[ScanSetArgs], groups=DEFAULT_CANDIDATES, tiles=DEFAULT_TILES, orders=(0,),
              cache_path: Optional[str] = None, reps: int = 2, log=None) -> dict:
-    """Pick the schedule -- group size G and walk tile (segment length K,
-    threads per tile) -- with the shortest plan run, timing every
-    combination on fresh maps with the sets' parameters and capacities (the
-    caller's maps are not touched).  Returns the keyword arguments of
-    ``OhmBatch``.  With ``cache_path`` the choice is read from / written to a
-    JSON cache keyed by device and workload signature."""
+    """Pick the schedule -- group size G, walk tile (segment length K,
+    threads per tile) and ray order (0: direction order, 1: as given) -- with
+    the shortest plan run, timing every combination on fresh maps with the
+    sets' parameters and capacities (the caller's maps are not touched).
+    Returns the keyword arguments of ``OhmBatch``.  With ``cache_path`` the
+    choice is read from / written to a JSON cache keyed by device and
+    workload signature."""
     key = _signature(sets)
     cache = {}
     if cache_path and os.path.exists(cache_path):
@@ -128,31 +131,32 @@ def autotune(sets: Sequence[ScanSetArgs], groups=DEFAULT_CANDIDATES, tiles=DEFAU
         if key in cache:
             c = cache[key]
             return {"group_scans": int(c["group_scans"]), "seg_major_steps": int(c["seg_major_steps"]),
-                    "tile_threads": int(c["tile_threads"])}
+                    "tile_threads": int(c["tile_threads"]), "keep_ray_order": int(c.get("keep_ray_order", 0))}
     timings = {}
     for g in groups:
         for k, t in tiles:
-            maps = [OhmMap(s.map.params, s.map.capacity, device=s.map.device) for s in sets]
-            trial = [ScanSetArgs(m, s.origins, s.samples, s.offsets, s.weights) for m, s in zip(maps, sets)]
-            plan = OhmBatch(trial, g, seg_major_steps=k, tile_threads=t)
-            plan.run()
-            torch.cuda.synchronize()
-            best = float("inf")
-            for _ in range(reps):
-                t0 = time.perf_counter()
+            for o in orders:
+                maps = [OhmMap(s.map.params, s.map.capacity, device=s.map.device) for s in sets]
+                trial = [ScanSetArgs(m, s.origins, s.samples, s.offsets, s.weights) for m, s in zip(maps, sets)]
+                plan = OhmBatch(trial, g, seg_major_steps=k, tile_threads=t, keep_ray_order=o)
                 plan.run()
                 torch.cuda.synchronize()
-                best = min(best, time.perf_counter() - t0)
-            timings[(g, k, t)] = best
-            plan.close()
-            for m in maps:
-                m.close()
-            if log:
-                log(f"autotune G={g} K={k} T={t}: {best * 1e3:.2f} ms")
-    g, k, t = min(timings, key=timings.get)
-    choice = {"group_scans": int(g), "seg_major_steps": int(k), "tile_threads": int(t)}
+                best = float("inf")
+                for _ in range(reps):
+                    t0 = time.perf_counter()
+                    plan.run()
+                    torch.cuda.synchronize()
+                    best = min(best, time.perf_counter() - t0)
+                timings[(g, k, t, o)] = best
+                plan.close()
+                for m in maps:
+                    m.close()
+                if log:
+                    log(f"autotune G={g} K={k} T={t} keep_order={o}: {best * 1e3:.2f} ms")
+    g, k, t, o = min(timings, key=timings.get)
+    choice = {"group_scans": int(g), "seg_major_steps": int(k), "tile_threads": int(t), "keep_ray_order": int(o)}
     if cache_path:
-        cache[key] = dict(choice, ms={"%d/%d/%d" % c: v * 1e3 for c, v in timings.items()})
+        cache[key] = dict(choice, ms={"%d/%d/%d/%d" % c: v * 1e3 for c, v in timings.items()})
         tmp = cache_path + ".tmp"
         with open(tmp, "w") as f:
             json.dump(cache, f, indent=1, sort_keys=True)

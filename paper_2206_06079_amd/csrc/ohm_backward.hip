@@ -107,7 +107,8 @@ __global__ __launch_bounds__(kBackwardMaxThreads) void backward_seg_kernel(
   const uint32_t tile0 = blockIdx.x * kTileRays;
   const float* origin = origins + 3 * (size_t)scan;
   TileRay t;
-  const uint32_t items = tile_prologue<kStageResolve>(m, tr, rc, origin, samples, r0, n, tile0, K, 0u, 0u, t);
+  const uint32_t items =
+      tile_prologue<kStageResolve>(m, tr, rc, origin, samples, nullptr, r0, n, tile0, K, 0u, 0u, t);
   if (tid < (uint32_t)kTileRays) {
     ray_gw[tid] = 0.0;
     if (t.ok)
@@ -123,7 +124,7 @@ __global__ __launch_bounds__(kBackwardMaxThreads) void backward_seg_kernel(
     SegState s;
     if (!tile_item(m, tr, it, K, s, ray_t, M)) continue;
     const bool trunc = tr.trunc[ray_t] != 0;
-    const double wt = kWeighted ? (double)weights[(size_t)r0 + tile0 + ray_t] : 1.0;
+    const double wt = kWeighted ? (double)weights[(size_t)r0 + tr.src[ray_t]] : 1.0;
     double dv[3];
     double dd = 0.0;
     for (int a = 0; a < 3; ++a) {
@@ -166,7 +167,7 @@ __global__ __launch_bounds__(kBackwardMaxThreads) void backward_seg_kernel(
     if (gw != 0.0) atomicAdd(&ray_gw[ray_t], gw);
   }
   __syncthreads();
-  if (t.inrange && grad_w) grad_w[(size_t)r0 + tile0 + tid] = (float)ray_gw[tid];
+  if (t.inrange && grad_w) grad_w[(size_t)r0 + tr.src[tid]] = (float)ray_gw[tid];
   // block reduction of the scalar gradients, one fp64 atomic per block each
   __shared__ double part[3][kBackwardMaxThreads / 64];
   double vals[3] = {g_hit, g_miss, g_sig};

@@ -10,6 +10,13 @@
 // the sequential per-scan count-then-clamp result.  The whole sequence is
 // captured once into a graph; scan tags live in device memory so that every
 // replay stays correct.
+//
+// Each replay first orders every scan's rays by direction (ohm_order.h):
+// a histogram of direction bins per scan, an exclusive prefix per scan and
+// a scatter give a permutation that the walk reads its rays through.  Scans
+// of unordered directions then walk in coherent tiles; the voxels each ray
+// updates do not change.  tuning->keep_ray_order skips this for scans that
+// arrive in sensor order.
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 #include <string.h>
@@ -23,6 +30,7 @@
 #include "ohm_regions.h"
 #include "ohm_wave.h"
 
+#include "ohm_order.h"
 #include "ohm_walk_seg.h"
 
 namespace ohm {
@@ -36,13 +44,79 @@ struct BlockDesc {
   uint32_t r0;     // first ray of the scan
   uint32_t n;      // rays in the scan
   uint32_t block;  // block index within the scan
+  uint32_t hbase;  // the scan's first direction bin in the plan's histogram
+};
+
+struct ScanDesc {
+  uint32_t hbase;  // first direction bin of the scan
+  uint32_t bins;   // direction bins of the scan
 };
 
 struct SetPtrs {
   const float* origins;
   const float* samples;
   const float* weights;
+  uint32_t* perm;  // walk order: perm[r0 + i] = scan index of the i-th ray walked (null: given order)
 };
+
+// --- direction ordering (one block of 256 threads per 256 rays) ---
+
+__global__ __launch_bounds__(256) void order_hist_kernel(const SetPtrs* __restrict__ sets,
+                                                         const BlockDesc* __restrict__ descs,
+                                                         uint32_t* __restrict__ hist) {
+  const BlockDesc d = descs[blockIdx.x];
+  const uint32_t i = d.block * kTileRays + threadIdx.x;
+  if (i >= d.n) return;
+  const SetPtrs sp = sets[d.set];
+  const float o[3] = {sp.origins[3 * d.scan + 0], sp.origins[3 * d.scan + 1], sp.origins[3 * d.scan + 2]};
+  const size_t r = (size_t)d.r0 + i;
+  const float e[3] = {sp.samples[3 * r + 0], sp.samples[3 * r + 1], sp.samples[3 * r + 2]};
+  atomicAdd(hist + d.hbase + direction_key(o, e, d.n), 1u);
+}
+
+// Exclusive prefix sum of each scan's bins, one block per scan.
+constexpr uint32_t kOrderScanThreads = 1024;
+
+__global__ __launch_bounds__(kOrderScanThreads) void order_scan_kernel(const ScanDesc* __restrict__ scans,
+                                                                       uint32_t* __restrict__ hist) {
+  __shared__ uint32_t part[kOrderScanThreads];
+  const ScanDesc sd = scans[blockIdx.x];
+  uint32_t* h = hist + sd.hbase;
+  const uint32_t chunk = (sd.bins + kOrderScanThreads - 1) / kOrderScanThreads;
+  const uint32_t b0 = threadIdx.x * chunk;
+  const uint32_t b1 = b0 + chunk < sd.bins ? b0 + chunk : sd.bins;
+  uint32_t sum = 0;
+  for (uint32_t b = b0; b < b1; ++b) sum += h[b];
+  part[threadIdx.x] = sum;
+  __syncthreads();
+  // inclusive scan of the chunk sums (Hillis-Steele over LDS)
+  for (uint32_t off = 1; off < kOrderScanThreads; off <<= 1) {
+    const uint32_t v = threadIdx.x >= off ? part[threadIdx.x - off] : 0u;
+    __syncthreads();
+    part[threadIdx.x] += v;
+    __syncthreads();
+  }
+  uint32_t run = threadIdx.x ? part[threadIdx.x - 1] : 0u;
+  for (uint32_t b = b0; b < b1; ++b) {
+    const uint32_t c = h[b];
+    h[b] = run;
+    run += c;
+  }
+}
+
+__global__ __launch_bounds__(256) void order_scatter_kernel(const SetPtrs* __restrict__ sets,
+                                                            const BlockDesc* __restrict__ descs,
+                                                            uint32_t* __restrict__ hist) {
+  const BlockDesc d = descs[blockIdx.x];
+  const uint32_t i = d.block * kTileRays + threadIdx.x;
+  if (i >= d.n) return;
+  const SetPtrs sp = sets[d.set];
+  const float o[3] = {sp.origins[3 * d.scan + 0], sp.origins[3 * d.scan + 1], sp.origins[3 * d.scan + 2]};
+  const size_t r = (size_t)d.r0 + i;
+  const float e[3] = {sp.samples[3 * r + 0], sp.samples[3 * r + 1], sp.samples[3 * r + 2]};
+  const uint32_t pos = atomicAdd(hist + d.hbase + direction_key(o, e, d.n), 1u);
+  sp.perm[(size_t)d.r0 + pos] = i;
+}
 
 // per-set group accumulators: G slots of [capacity][V][2] floats
 __device__ __forceinline__ size_t acc_slot_floats(const DevMap& m) { return (size_t)m.capacity * kRegionVoxels * 2; }
@@ -56,7 +130,7 @@ __global__ __launch_bounds__(1024) void batch_walk_kernel(const DevMap* __restri
   m.acc += (size_t)d.pos * acc_slot_floats(m);
   const uint32_t tag = __hip_atomic_load(m.hdr + kHdrBatchTag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   const SetPtrs sp = sets[d.set];
-  walk_tile<kSinkCount, kWeighted>(m, sp.origins + 3 * (size_t)d.scan, sp.samples, sp.weights, d.r0, d.n,
+  walk_tile<kSinkCount, kWeighted>(m, sp.origins + 3 * (size_t)d.scan, sp.samples, sp.weights, sp.perm, d.r0, d.n,
                                    d.block * kTileRays, K, tag, tag & 1u, nullptr, nullptr, nullptr, nullptr);
 }
 
@@ -130,9 +204,14 @@ struct ohm_batch_s {
   int seg_major_steps;
   uint32_t tile_threads;
   bool weighted;
+  bool order;  // direction-order the rays each run
   DevMap* d_maps;
   SetPtrs* d_sets;
   BlockDesc* d_descs;
+  ScanDesc* d_scans;
+  uint32_t* d_hist;
+  size_t hist_bins;
+  uint32_t n_blocks, n_scans;
   std::vector<uint32_t> group_first, group_blocks;
   hipStream_t capture;
   hipGraph_t graph;
@@ -145,9 +224,12 @@ constexpr size_t kAlignB = 256;
 inline size_t align_b(size_t v) { return (v + kAlignB - 1) & ~(kAlignB - 1); }
 
 struct BatchLayout {
-  size_t maps, sets, descs, acc_total, total;
-  std::vector<size_t> acc;  // per-set accumulator offsets
+  size_t maps, sets, descs, scans, hist, acc_total, total;
+  size_t hist_bins;
+  std::vector<size_t> acc;   // per-set accumulator offsets
+  std::vector<size_t> perm;  // per-set walk-order offsets
   std::vector<BlockDesc> host_descs;
+  std::vector<ScanDesc> host_scans;
   std::vector<uint32_t> group_first, group_blocks;
   uint32_t n_groups;
 };
@@ -156,6 +238,7 @@ ohm_status plan_layout(const ohm_scan_set* sets, uint32_t n_sets, const ohm_batc
   if (!sets || n_sets == 0 || n_sets > 64 || !t || t->group_scans == 0 || t->group_scans > 64)
     return OHM_E_INVALID_ARG;
   if (t->seg_major_steps > 4096) return OHM_E_INVALID_ARG;
+  const bool order = t->keep_ray_order == 0;
   if (t->tile_threads != 0 && t->tile_threads != 256 && t->tile_threads != 512 && t->tile_threads != 1024)
     return OHM_E_INVALID_ARG;
   const uint32_t G = t->group_scans;
@@ -172,6 +255,22 @@ ohm_status plan_layout(const ohm_scan_set* sets, uint32_t n_sets, const ohm_batc
     if (s.n_scans > max_scans) max_scans = s.n_scans;
   }
   L->n_groups = (max_scans + G - 1) / G;
+  // direction bins of every non-empty scan (when ordering)
+  std::vector<std::vector<uint32_t>> hbase(n_sets);
+  L->host_scans.clear();
+  size_t bins = 0;
+  for (uint32_t si = 0; si < n_sets; ++si) {
+    hbase[si].assign(sets[si].n_scans, 0u);
+    for (uint32_t sc = 0; sc < sets[si].n_scans && order; ++sc) {
+      const uint32_t n = sets[si].h_scan_offsets[sc + 1] - sets[si].h_scan_offsets[sc];
+      if (n == 0) continue;
+      if (bins + order_bins(n) > 0xFFFFFFFFull) return OHM_E_UNSUPPORTED;
+      hbase[si][sc] = (uint32_t)bins;
+      L->host_scans.push_back({(uint32_t)bins, order_bins(n)});
+      bins += order_bins(n);
+    }
+  }
+  L->hist_bins = bins;
   L->host_descs.clear();
   L->group_first.assign(L->n_groups, 0);
   L->group_blocks.assign(L->n_groups, 0);
@@ -184,7 +283,8 @@ ohm_status plan_layout(const ohm_scan_set* sets, uint32_t n_sets, const ohm_batc
         if (sc >= s.n_scans) break;
         const uint32_t r0 = s.h_scan_offsets[sc];
         const uint32_t n = s.h_scan_offsets[sc + 1] - r0;
-        for (uint32_t b = 0; b * (uint32_t)kTileRays < n; ++b) L->host_descs.push_back({si, pos, sc, r0, n, b});
+        for (uint32_t b = 0; b * (uint32_t)kTileRays < n; ++b)
+          L->host_descs.push_back({si, pos, sc, r0, n, b, hbase[si][sc]});
       }
     }
     L->group_blocks[g] = (uint32_t)L->host_descs.size() - L->group_first[g];
@@ -196,6 +296,15 @@ ohm_status plan_layout(const ohm_scan_set* sets, uint32_t n_sets, const ohm_batc
   off = align_b(off + n_sets * sizeof(SetPtrs));
   L->descs = off;
   off = align_b(off + L->host_descs.size() * sizeof(BlockDesc));
+  L->scans = off;
+  off = align_b(off + L->host_scans.size() * sizeof(ScanDesc));
+  L->hist = off;
+  off = align_b(off + L->hist_bins * sizeof(uint32_t));
+  L->perm.assign(n_sets, 0);
+  for (uint32_t si = 0; si < n_sets && order; ++si) {
+    L->perm[si] = off;
+    off = align_b(off + (size_t)sets[si].h_scan_offsets[sets[si].n_scans] * sizeof(uint32_t));
+  }
   L->acc.resize(n_sets);
   for (uint32_t si = 0; si < n_sets; ++si) {
     L->acc[si] = off;
@@ -237,12 +346,18 @@ ohm_status ohm_batch_create(const ohm_scan_set* sets, uint32_t n_sets, const ohm
   b->tile_threads = tuning->tile_threads ? tuning->tile_threads : kDefaultTileThreads;
   b->n_groups = L.n_groups;
   b->weighted = sets[0].d_weights != nullptr;
+  b->order = tuning->keep_ray_order == 0;
+  b->hist_bins = L.hist_bins;
+  b->n_blocks = (uint32_t)L.host_descs.size();
+  b->n_scans = (uint32_t)L.host_scans.size();
   b->group_first = L.group_first;
   b->group_blocks = L.group_blocks;
   char* base = static_cast<char*>(d_workspace);
   b->d_maps = reinterpret_cast<DevMap*>(base + L.maps);
   b->d_sets = reinterpret_cast<SetPtrs*>(base + L.sets);
   b->d_descs = reinterpret_cast<BlockDesc*>(base + L.descs);
+  b->d_scans = reinterpret_cast<ScanDesc*>(base + L.scans);
+  b->d_hist = reinterpret_cast<uint32_t*>(base + L.hist);
   std::vector<DevMap> hm(n_sets);
   std::vector<SetPtrs> hs(n_sets);
   for (uint32_t si = 0; si < n_sets; ++si) {
@@ -254,12 +369,16 @@ ohm_status ohm_batch_create(const ohm_scan_set* sets, uint32_t n_sets, const ohm
     hm[si] = sets[si].map->dm;
     hm[si].acc = reinterpret_cast<float*>(base + L.acc[si]);
     hm[si].clampscan = nullptr;  // per-scan clamp records are kept by the per-scan path only
-    hs[si] = {sets[si].d_origins, sets[si].d_samples, sets[si].d_weights};
+    hs[si] = {sets[si].d_origins, sets[si].d_samples, sets[si].d_weights,
+              b->order ? reinterpret_cast<uint32_t*>(base + L.perm[si]) : nullptr};
   }
   bool ok = hipMemcpyAsync(b->d_maps, hm.data(), n_sets * sizeof(DevMap), hipMemcpyHostToDevice, st) == hipSuccess;
   ok = ok && hipMemcpyAsync(b->d_sets, hs.data(), n_sets * sizeof(SetPtrs), hipMemcpyHostToDevice, st) == hipSuccess;
   if (!L.host_descs.empty())
     ok = ok && hipMemcpyAsync(b->d_descs, L.host_descs.data(), L.host_descs.size() * sizeof(BlockDesc),
+                              hipMemcpyHostToDevice, st) == hipSuccess;
+  if (!L.host_scans.empty())
+    ok = ok && hipMemcpyAsync(b->d_scans, L.host_scans.data(), L.host_scans.size() * sizeof(ScanDesc),
                               hipMemcpyHostToDevice, st) == hipSuccess;
   for (uint32_t si = 0; si < n_sets && ok; ++si) {
     const size_t nf = (size_t)b->group * hm[si].capacity * kRegionVoxels * 2;
@@ -277,6 +396,16 @@ ohm_status ohm_batch_create(const ohm_scan_set* sets, uint32_t n_sets, const ohm
   ok = hipStreamBeginCapture(b->capture, hipStreamCaptureModeThreadLocal) == hipSuccess;
   if (ok) {
     hipLaunchKernelGGL(batch_begin_kernel, dim3(1), dim3(64), 0, b->capture, b->d_maps, n_sets);
+    if (b->order && b->n_scans) {
+      // direction order of every scan (a fill kernel, not a memset: the graph is replayed)
+      hipLaunchKernelGGL(fill_u32_kernel, dim3(8192), dim3(256), 0, b->capture, b->d_hist, b->hist_bins, 0u);
+      hipLaunchKernelGGL(order_hist_kernel, dim3(b->n_blocks), dim3(kTileRays), 0, b->capture, b->d_sets,
+                         b->d_descs, b->d_hist);
+      hipLaunchKernelGGL(order_scan_kernel, dim3(b->n_scans), dim3(kOrderScanThreads), 0, b->capture, b->d_scans,
+                         b->d_hist);
+      hipLaunchKernelGGL(order_scatter_kernel, dim3(b->n_blocks), dim3(kTileRays), 0, b->capture, b->d_sets,
+                         b->d_descs, b->d_hist);
+    }
     for (uint32_t g = 0; g < b->n_groups; ++g) {
       if (b->group_blocks[g]) {
         if (b->weighted)

@@ -61,8 +61,8 @@ __global__ __launch_bounds__(1024) void walk_seg_kernel(DevMap m, const float* _
                                                         int32_t* __restrict__ ray_flags,
                                                         const int64_t* __restrict__ ray_offsets,
                                                         int32_t* __restrict__ updates) {
-  walk_tile<kSink, kWeighted>(m, origins + 3 * (size_t)scan, samples, weights, r0, n, blockIdx.x * kTileRays, K, tag,
-                              parity, ray_counts, ray_flags, ray_offsets, updates);
+  walk_tile<kSink, kWeighted>(m, origins + 3 * (size_t)scan, samples, weights, nullptr, r0, n, blockIdx.x * kTileRays,
+                              K, tag, parity, ray_counts, ray_flags, ray_offsets, updates);
 }
 
 // ---------------------------------------------------------------------------

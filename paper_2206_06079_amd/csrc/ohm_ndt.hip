@@ -134,7 +134,8 @@ __global__ __launch_bounds__(kNdtMaxThreads) void ndt_seg_kernel(DevMap m, const
     agg_val[h] = 0ull;
   }
   TileRay t;
-  const uint32_t items = tile_prologue<kStageTouch>(m, tr, rc, origin, samples, r0, n, tile0, K, tag, parity, t);
+  const uint32_t items =
+      tile_prologue<kStageTouch>(m, tr, rc, origin, samples, nullptr, r0, n, tile0, K, tag, parity, t);
   if (t.ok)
     for (int a = 0; a < 3; ++a) ray_end[a][tid] = t.r.end[a];
   __syncthreads();
@@ -158,7 +159,7 @@ __global__ __launch_bounds__(kNdtMaxThreads) void ndt_seg_kernel(DevMap m, const
     if (alive) {
       alive = tile_item(m, tr, it, K, s, ray_t, M);
       trunc = tr.trunc[ray_t] != 0;
-      ray = (size_t)r0 + tile0 + ray_t;
+      ray = (size_t)r0 + tr.src[ray_t];
       if (kWeighted) wt = (double)weights[ray];
       for (int a = 0; a < 3; ++a) {
         dv[a] = ray_end[a][ray_t] - od[a];

@@ -71,6 +71,7 @@ struct TileRays {
   uint16_t level_base[kMaxLevels + 1];
   uint16_t wave_count[kMaxLevels][kTileRays / 64];
   uint8_t item_ray[kMaxItems];
+  uint32_t src[kTileRays];  // the ray's index within its scan (the walk order may differ)
   uint32_t max_seg;
 };
 
@@ -88,14 +89,17 @@ struct TileRay {
 enum : int { kStageNone = 0, kStageResolve = 1, kStageTouch = 2 };
 
 // Prologue of a tile walk (every thread of the block must call it): threads
-// 0..255 prepare rays tile0.. of the scan and fill the LDS ray table, the
-// block stages the tile's regions in LDS (kStage), and the level-major item
-// list is built: level j lists, in ray order, the rays with more than j
-// segments.  Returns the number of items; tr.max_seg holds the level count.
+// 0..255 prepare rays tile0.. of the scan in walk order (perm[r0 + i] is the
+// scan index of walk position i; null: the scan's own order) and fill the LDS
+// ray table, the block stages the tile's regions in LDS (kStage), and the
+// level-major item list is built: level j lists, in ray order, the rays with
+// more than j segments.  Returns the number of items; tr.max_seg holds the
+// level count.
 template <int kStage>
-__device__ __forceinline__ uint32_t tile_prologue(const DevMap& m, TileRays& tr, RegionCache& rc, const float* __restrict__ origin,
-                                  const float* __restrict__ samples, uint32_t r0, uint32_t n, uint32_t tile0, int K,
-                                  uint32_t tag, uint32_t parity, TileRay& t) {
+__device__ __forceinline__ uint32_t tile_prologue(const DevMap& m, TileRays& tr, RegionCache& rc,
+                                                  const float* __restrict__ origin, const float* __restrict__ samples,
+                                                  const uint32_t* __restrict__ perm, uint32_t r0, uint32_t n,
+                                                  uint32_t tile0, int K, uint32_t tag, uint32_t parity, TileRay& t) {
   const uint32_t tid = threadIdx.x;
   const uint32_t lane = lane_id();
   const bool holds_ray = tid < (uint32_t)kTileRays;
@@ -106,7 +110,9 @@ __device__ __forceinline__ uint32_t tile_prologue(const DevMap& m, TileRays& tr,
   t.voxels = 0;
   if (tid == 0) tr.max_seg = 0;
   if (t.inrange) {
-    const size_t ray = (size_t)r0 + tile0 + tid;
+    const uint32_t src = perm ? perm[(size_t)r0 + tile0 + tid] : tile0 + tid;
+    tr.src[tid] = src;
+    const size_t ray = (size_t)r0 + src;
     const float o[3] = {origin[0], origin[1], origin[2]};
     const float e[3] = {samples[3 * ray + 0], samples[3 * ray + 1], samples[3 * ray + 2]};
     t.st = prepare_ray(m, o, e, t.r);
@@ -224,7 +230,8 @@ __device__ __forceinline__ void flush_tile_stats(const DevMap& m, const TileRay&
 // thread of the block must call it.
 template <int kSink, bool kWeighted>
 __device__ void walk_tile(const DevMap& m, const float* __restrict__ origin, const float* __restrict__ samples,
-                          const float* __restrict__ weights, uint32_t r0, uint32_t n, uint32_t tile0, int K,
+                          const float* __restrict__ weights, const uint32_t* __restrict__ perm, uint32_t r0,
+                          uint32_t n, uint32_t tile0, int K,
                           uint32_t tag, uint32_t parity, uint32_t* __restrict__ ray_counts,
                           int32_t* __restrict__ ray_flags, const int64_t* __restrict__ ray_offsets,
                           int32_t* __restrict__ updates) {
@@ -243,7 +250,7 @@ __device__ void walk_tile(const DevMap& m, const float* __restrict__ origin, con
       agg_val[h] = 0.f;
     }
   TileRay t;
-  const uint32_t items = tile_prologue<kStage>(m, tr, rc, origin, samples, r0, n, tile0, K, tag, parity, t);
+  const uint32_t items = tile_prologue<kStage>(m, tr, rc, origin, samples, perm, r0, n, tile0, K, tag, parity, t);
 
   if (kSink == kSinkTraceCount && t.inrange) {
     int32_t flags = 0;
@@ -254,7 +261,7 @@ __device__ void walk_tile(const DevMap& m, const float* __restrict__ origin, con
       flags |= t.clipped ? 2 : 0;
       flags |= (!t.r.truncated && !t.clipped) ? 4 : 0;
     }
-    const size_t ray = (size_t)r0 + tile0 + tid;
+    const size_t ray = (size_t)r0 + tr.src[tid];
     ray_counts[ray] = t.ok ? t.voxels : 0u;
     ray_flags[ray] = flags;
   }
@@ -276,7 +283,7 @@ __device__ void walk_tile(const DevMap& m, const float* __restrict__ origin, con
     if (alive) {
       alive = tile_item(m, tr, it, K, s, ray_t, M);
       trunc = tr.trunc[ray_t] != 0;
-      const size_t ray = (size_t)r0 + tile0 + ray_t;
+      const size_t ray = (size_t)r0 + tr.src[ray_t];
       if (kWeighted) wt = weights[ray];
       if (kSink == kSinkTraceWrite) out_base = ray_offsets[ray] + s.pos;
       if (kAccum && alive) slot = staged_slot(m, rc, s.k[0], s.k[1], s.k[2]);

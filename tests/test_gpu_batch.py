@@ -79,21 +79,22 @@ def test_autotuner_picks_and_caches(cfg3_small, tmp_path):
     maps, sets = make_sets(params, batches)
     cache = str(tmp_path / "tune.json")
     tiles = ((8, 256), (32, 1024))
-    choice = ohm.autotune(sets, groups=(1, 4, 16), tiles=tiles, cache_path=cache, reps=1)
+    choice = ohm.autotune(sets, groups=(1, 4, 16), tiles=tiles, orders=(0, 1), cache_path=cache, reps=1)
     assert choice["group_scans"] in (1, 4, 16)
     assert (choice["seg_major_steps"], choice["tile_threads"]) in tiles
+    assert choice["keep_ray_order"] in (0, 1)
     # served from the cache (the candidates offered now are ignored)
     assert ohm.autotune(sets, groups=(2,), tiles=((4, 512),), cache_path=cache) == choice
     # the caller's maps were not touched
     assert all(m.stats()["rays_in"] == 0 for m in maps)
 
 
-@pytest.mark.parametrize("tile", [(1, 256), (5, 1024), (4096, 512)])
+@pytest.mark.parametrize("tile", [(1, 256, 0), (5, 1024, 1), (4096, 512, 0), (32, 512, 1)])
 def test_batched_walk_tiles_agree(cfg3_small, tile):
-    """Any segment length and tile shape gives the oracle's maps."""
+    """Any segment length, tile shape and ray order gives the oracle's maps."""
     params, batches = cfg3_small
     maps, sets = make_sets(params, batches)
-    plan = ohm.OhmBatch(sets, 2, seg_major_steps=tile[0], tile_threads=tile[1])
+    plan = ohm.OhmBatch(sets, 2, seg_major_steps=tile[0], tile_threads=tile[1], keep_ray_order=tile[2])
     plan.run()
     torch.cuda.synchronize()
     for mi, (p, b) in enumerate(zip(params, batches)):

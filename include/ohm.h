@@ -292,6 +292,20 @@ typedef struct {
 
 ohm_status ohm_map_set_tuning(ohm_map map, const ohm_walk_tuning* tuning);
 
+/* Direction ordering of the per-scan path (ohm_integrate_rays).  A walk
+ * tile works best when its 256 rays point close together, as a spinning
+ * lidar's scan order gives; a scan whose ray directions arrive unordered can
+ * instead be walked in direction order (azimuth strips of about 256 rays,
+ * then elevation).  Attaching a scratch buffer turns this on for every scan
+ * of at most max_rays rays (longer scans walk in their given order); it
+ * costs three small kernels per scan and never changes results.
+ * ohm_ray_order_scratch_size gives the bytes for max_rays (> 0).
+ * d_scratch: caller-owned device memory, 256-byte aligned, at least that
+ * size, valid until detached (d_scratch = NULL) or the map is destroyed;
+ * calls on one map must not overlap while it is attached. */
+ohm_status ohm_ray_order_scratch_size(uint32_t max_rays, size_t* bytes);
+ohm_status ohm_map_set_ray_order(ohm_map map, void* d_scratch, size_t bytes, uint32_t max_rays);
+
 /* Kernel kinds reported by ohm_map_kernel_times. */
 enum {
   OHM_KERNEL_PREPASS = 0,   /* region pass: allocation and touched list */

@@ -36,7 +36,7 @@ EXPORTS = (
     "ohm_debug_trace_rays", "ohm_map_sync_status", "ohm_status_string",
     "ohm_map_set_profiling", "ohm_map_kernel_times", "ohm_backward",
     "ohm_batch_workspace_size", "ohm_batch_create", "ohm_batch_run", "ohm_batch_destroy",
-    "ohm_map_set_tuning", "ohm_probe_atomic_rate",
+    "ohm_map_set_tuning", "ohm_probe_atomic_rate", "ohm_ray_order_scratch_size", "ohm_map_set_ray_order",
 )
 
 
@@ -146,6 +146,8 @@ def load() -> ctypes.CDLL:
         "ohm_batch_destroy": [vp],
         "ohm_map_kernel_times": [vp, vp, vp],
         "ohm_probe_atomic_rate": [vp, ctypes.c_size_t, ctypes.c_int, P(ctypes.c_double), vp],
+        "ohm_ray_order_scratch_size": [ctypes.c_uint32, P(ctypes.c_size_t)],
+        "ohm_map_set_ray_order": [vp, vp, ctypes.c_size_t, ctypes.c_uint32],
     }
     for name, args in sig.items():
         fn = getattr(lib, name)

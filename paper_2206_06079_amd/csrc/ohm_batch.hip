@@ -45,18 +45,19 @@ struct BlockDesc {
   uint32_t n;      // rays in the scan
   uint32_t block;  // block index within the scan
   uint32_t hbase;  // the scan's first direction bin in the plan's histogram
+  uint32_t sbase;  // the scan's first strip in the plan's strip sums
 };
 
 struct ScanDesc {
-  uint32_t hbase;  // first direction bin of the scan
-  uint32_t bins;   // direction bins of the scan
+  uint32_t sbase;   // first strip of the scan
+  uint32_t strips;  // strips of the scan
 };
 
 struct SetPtrs {
   const float* origins;
   const float* samples;
   const float* weights;
-  uint32_t* perm;  // walk order: perm[r0 + i] = scan index of the i-th ray walked (null: given order)
+  uint32_t* perm;  // walk order: perm[r0 + i] = scan index of the scan's i-th ray walked (null: given order)
 };
 
 // --- direction ordering (one block of 256 threads per 256 rays) ---
@@ -68,54 +69,32 @@ __global__ __launch_bounds__(256) void order_hist_kernel(const SetPtrs* __restri
   const uint32_t i = d.block * kTileRays + threadIdx.x;
   if (i >= d.n) return;
   const SetPtrs sp = sets[d.set];
-  const float o[3] = {sp.origins[3 * d.scan + 0], sp.origins[3 * d.scan + 1], sp.origins[3 * d.scan + 2]};
-  const size_t r = (size_t)d.r0 + i;
-  const float e[3] = {sp.samples[3 * r + 0], sp.samples[3 * r + 1], sp.samples[3 * r + 2]};
-  atomicAdd(hist + d.hbase + direction_key(o, e, d.n), 1u);
+  order_count(sp.origins + 3 * (size_t)d.scan, sp.samples + 3 * (size_t)d.r0, d.n, i, hist + d.hbase);
 }
 
-// Exclusive prefix sum of each scan's bins, one block per scan.
-constexpr uint32_t kOrderScanThreads = 1024;
+// one block per strip of every scan (strip s of the plan: bins [256 s, 256 s + 256))
+__global__ __launch_bounds__(kOrderElevationBins) void order_strip_kernel(uint32_t* __restrict__ hist,
+                                                                         uint32_t* __restrict__ sums) {
+  order_strip_prefix(hist + (size_t)blockIdx.x * kOrderElevationBins, sums + blockIdx.x);
+}
 
-__global__ __launch_bounds__(kOrderScanThreads) void order_scan_kernel(const ScanDesc* __restrict__ scans,
-                                                                       uint32_t* __restrict__ hist) {
-  __shared__ uint32_t part[kOrderScanThreads];
+// one block per scan
+__global__ __launch_bounds__(kOrderMaxStrips) void order_sums_kernel(const ScanDesc* __restrict__ scans,
+                                                                     uint32_t* __restrict__ sums) {
   const ScanDesc sd = scans[blockIdx.x];
-  uint32_t* h = hist + sd.hbase;
-  const uint32_t chunk = (sd.bins + kOrderScanThreads - 1) / kOrderScanThreads;
-  const uint32_t b0 = threadIdx.x * chunk;
-  const uint32_t b1 = b0 + chunk < sd.bins ? b0 + chunk : sd.bins;
-  uint32_t sum = 0;
-  for (uint32_t b = b0; b < b1; ++b) sum += h[b];
-  part[threadIdx.x] = sum;
-  __syncthreads();
-  // inclusive scan of the chunk sums (Hillis-Steele over LDS)
-  for (uint32_t off = 1; off < kOrderScanThreads; off <<= 1) {
-    const uint32_t v = threadIdx.x >= off ? part[threadIdx.x - off] : 0u;
-    __syncthreads();
-    part[threadIdx.x] += v;
-    __syncthreads();
-  }
-  uint32_t run = threadIdx.x ? part[threadIdx.x - 1] : 0u;
-  for (uint32_t b = b0; b < b1; ++b) {
-    const uint32_t c = h[b];
-    h[b] = run;
-    run += c;
-  }
+  order_scan_prefix(sums + sd.sbase, sd.strips);
 }
 
 __global__ __launch_bounds__(256) void order_scatter_kernel(const SetPtrs* __restrict__ sets,
                                                             const BlockDesc* __restrict__ descs,
-                                                            uint32_t* __restrict__ hist) {
+                                                            uint32_t* __restrict__ hist,
+                                                            const uint32_t* __restrict__ sums) {
   const BlockDesc d = descs[blockIdx.x];
   const uint32_t i = d.block * kTileRays + threadIdx.x;
   if (i >= d.n) return;
   const SetPtrs sp = sets[d.set];
-  const float o[3] = {sp.origins[3 * d.scan + 0], sp.origins[3 * d.scan + 1], sp.origins[3 * d.scan + 2]};
-  const size_t r = (size_t)d.r0 + i;
-  const float e[3] = {sp.samples[3 * r + 0], sp.samples[3 * r + 1], sp.samples[3 * r + 2]};
-  const uint32_t pos = atomicAdd(hist + d.hbase + direction_key(o, e, d.n), 1u);
-  sp.perm[(size_t)d.r0 + pos] = i;
+  order_place(sp.origins + 3 * (size_t)d.scan, sp.samples + 3 * (size_t)d.r0, d.n, i, hist + d.hbase,
+              sums + d.sbase, sp.perm + d.r0);
 }
 
 // per-set group accumulators: G slots of [capacity][V][2] floats
@@ -130,7 +109,8 @@ __global__ __launch_bounds__(1024) void batch_walk_kernel(const DevMap* __restri
   m.acc += (size_t)d.pos * acc_slot_floats(m);
   const uint32_t tag = __hip_atomic_load(m.hdr + kHdrBatchTag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   const SetPtrs sp = sets[d.set];
-  walk_tile<kSinkCount, kWeighted>(m, sp.origins + 3 * (size_t)d.scan, sp.samples, sp.weights, sp.perm, d.r0, d.n,
+  walk_tile<kSinkCount, kWeighted>(m, sp.origins + 3 * (size_t)d.scan, sp.samples, sp.weights,
+                                   sp.perm ? sp.perm + d.r0 : nullptr, d.r0, d.n,
                                    d.block * kTileRays, K, tag, tag & 1u, nullptr, nullptr, nullptr, nullptr);
 }
 
@@ -210,8 +190,9 @@ struct ohm_batch_s {
   BlockDesc* d_descs;
   ScanDesc* d_scans;
   uint32_t* d_hist;
+  uint32_t* d_sums;
   size_t hist_bins;
-  uint32_t n_blocks, n_scans;
+  uint32_t n_blocks, n_scans, n_strips;
   std::vector<uint32_t> group_first, group_blocks;
   hipStream_t capture;
   hipGraph_t graph;
@@ -224,8 +205,8 @@ constexpr size_t kAlignB = 256;
 inline size_t align_b(size_t v) { return (v + kAlignB - 1) & ~(kAlignB - 1); }
 
 struct BatchLayout {
-  size_t maps, sets, descs, scans, hist, acc_total, total;
-  size_t hist_bins;
+  size_t maps, sets, descs, scans, hist, sums, acc_total, total;
+  size_t hist_bins, strips;
   std::vector<size_t> acc;   // per-set accumulator offsets
   std::vector<size_t> perm;  // per-set walk-order offsets
   std::vector<BlockDesc> host_descs;
@@ -256,21 +237,23 @@ ohm_status plan_layout(const ohm_scan_set* sets, uint32_t n_sets, const ohm_batc
   }
   L->n_groups = (max_scans + G - 1) / G;
   // direction bins of every non-empty scan (when ordering)
-  std::vector<std::vector<uint32_t>> hbase(n_sets);
+  // (strip s of the plan owns bins [256 s, 256 s + 256))
+  std::vector<std::vector<uint32_t>> sbase(n_sets);
   L->host_scans.clear();
-  size_t bins = 0;
+  size_t strips = 0;
   for (uint32_t si = 0; si < n_sets; ++si) {
-    hbase[si].assign(sets[si].n_scans, 0u);
+    sbase[si].assign(sets[si].n_scans, 0u);
     for (uint32_t sc = 0; sc < sets[si].n_scans && order; ++sc) {
       const uint32_t n = sets[si].h_scan_offsets[sc + 1] - sets[si].h_scan_offsets[sc];
       if (n == 0) continue;
-      if (bins + order_bins(n) > 0xFFFFFFFFull) return OHM_E_UNSUPPORTED;
-      hbase[si][sc] = (uint32_t)bins;
-      L->host_scans.push_back({(uint32_t)bins, order_bins(n)});
-      bins += order_bins(n);
+      if ((strips + order_strips(n)) * kOrderElevationBins > 0xFFFFFFFFull) return OHM_E_UNSUPPORTED;
+      sbase[si][sc] = (uint32_t)strips;
+      L->host_scans.push_back({(uint32_t)strips, order_strips(n)});
+      strips += order_strips(n);
     }
   }
-  L->hist_bins = bins;
+  L->strips = strips;
+  L->hist_bins = strips * kOrderElevationBins;
   L->host_descs.clear();
   L->group_first.assign(L->n_groups, 0);
   L->group_blocks.assign(L->n_groups, 0);
@@ -284,7 +267,8 @@ ohm_status plan_layout(const ohm_scan_set* sets, uint32_t n_sets, const ohm_batc
         const uint32_t r0 = s.h_scan_offsets[sc];
         const uint32_t n = s.h_scan_offsets[sc + 1] - r0;
         for (uint32_t b = 0; b * (uint32_t)kTileRays < n; ++b)
-          L->host_descs.push_back({si, pos, sc, r0, n, b, hbase[si][sc]});
+          L->host_descs.push_back(
+              {si, pos, sc, r0, n, b, sbase[si][sc] * kOrderElevationBins, sbase[si][sc]});
       }
     }
     L->group_blocks[g] = (uint32_t)L->host_descs.size() - L->group_first[g];
@@ -300,6 +284,8 @@ ohm_status plan_layout(const ohm_scan_set* sets, uint32_t n_sets, const ohm_batc
   off = align_b(off + L->host_scans.size() * sizeof(ScanDesc));
   L->hist = off;
   off = align_b(off + L->hist_bins * sizeof(uint32_t));
+  L->sums = off;
+  off = align_b(off + L->strips * sizeof(uint32_t));
   L->perm.assign(n_sets, 0);
   for (uint32_t si = 0; si < n_sets && order; ++si) {
     L->perm[si] = off;
@@ -350,6 +336,7 @@ ohm_status ohm_batch_create(const ohm_scan_set* sets, uint32_t n_sets, const ohm
   b->hist_bins = L.hist_bins;
   b->n_blocks = (uint32_t)L.host_descs.size();
   b->n_scans = (uint32_t)L.host_scans.size();
+  b->n_strips = (uint32_t)L.strips;
   b->group_first = L.group_first;
   b->group_blocks = L.group_blocks;
   char* base = static_cast<char*>(d_workspace);
@@ -358,6 +345,7 @@ ohm_status ohm_batch_create(const ohm_scan_set* sets, uint32_t n_sets, const ohm
   b->d_descs = reinterpret_cast<BlockDesc*>(base + L.descs);
   b->d_scans = reinterpret_cast<ScanDesc*>(base + L.scans);
   b->d_hist = reinterpret_cast<uint32_t*>(base + L.hist);
+  b->d_sums = reinterpret_cast<uint32_t*>(base + L.sums);
   std::vector<DevMap> hm(n_sets);
   std::vector<SetPtrs> hs(n_sets);
   for (uint32_t si = 0; si < n_sets; ++si) {
@@ -401,10 +389,12 @@ ohm_status ohm_batch_create(const ohm_scan_set* sets, uint32_t n_sets, const ohm
       hipLaunchKernelGGL(fill_u32_kernel, dim3(8192), dim3(256), 0, b->capture, b->d_hist, b->hist_bins, 0u);
       hipLaunchKernelGGL(order_hist_kernel, dim3(b->n_blocks), dim3(kTileRays), 0, b->capture, b->d_sets,
                          b->d_descs, b->d_hist);
-      hipLaunchKernelGGL(order_scan_kernel, dim3(b->n_scans), dim3(kOrderScanThreads), 0, b->capture, b->d_scans,
-                         b->d_hist);
+      hipLaunchKernelGGL(order_strip_kernel, dim3(b->n_strips), dim3(kOrderElevationBins), 0, b->capture, b->d_hist,
+                         b->d_sums);
+      hipLaunchKernelGGL(order_sums_kernel, dim3(b->n_scans), dim3(kOrderMaxStrips), 0, b->capture, b->d_scans,
+                         b->d_sums);
       hipLaunchKernelGGL(order_scatter_kernel, dim3(b->n_blocks), dim3(kTileRays), 0, b->capture, b->d_sets,
-                         b->d_descs, b->d_hist);
+                         b->d_descs, b->d_hist, b->d_sums);
     }
     for (uint32_t g = 0; g < b->n_groups; ++g) {
       if (b->group_blocks[g]) {

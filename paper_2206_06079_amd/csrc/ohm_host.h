@@ -24,6 +24,11 @@ struct ohm_map_s {
   uint32_t last_parity;
   int seg_major_steps;     // walk tuning (ohm_map_set_tuning)
   uint32_t walk_threads;
+  // direction ordering of scans (ohm_map_set_ray_order): caller scratch
+  uint32_t* order_hist;
+  uint32_t* order_sums;
+  uint32_t* order_perm;
+  uint32_t order_max_rays;  // 0: scans walk in their given order
   // kernel timing (ohm_map_set_profiling)
   bool profiling;
   std::vector<hipEvent_t> event_pool;

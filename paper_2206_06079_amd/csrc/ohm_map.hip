@@ -33,6 +33,7 @@
 #include "ohm_host.h"
 #include "ohm_regions.h"
 #include "ohm_wave.h"
+#include "ohm_order.h"
 #include "ohm_walk_seg.h"
 
 namespace ohm {
@@ -51,18 +52,46 @@ __global__ void fill_u32_kernel(uint32_t* p, size_t n, uint32_t v) {
   for (; i < n; i += stride) p[i] = v;
 }
 
-// Segmented walk: one block per tile of 256 rays.
+// Segmented walk: one block per tile of 256 rays (perm: walk order or null).
 template <int kSink, bool kWeighted>
 __global__ __launch_bounds__(1024) void walk_seg_kernel(DevMap m, const float* __restrict__ origins, uint32_t scan,
                                                         const float* __restrict__ samples,
-                                                        const float* __restrict__ weights, uint32_t r0, uint32_t n,
+                                                        const float* __restrict__ weights,
+                                                        const uint32_t* __restrict__ perm, uint32_t r0, uint32_t n,
                                                         int K, uint32_t tag, uint32_t parity,
                                                         uint32_t* __restrict__ ray_counts,
                                                         int32_t* __restrict__ ray_flags,
                                                         const int64_t* __restrict__ ray_offsets,
                                                         int32_t* __restrict__ updates) {
-  walk_tile<kSink, kWeighted>(m, origins + 3 * (size_t)scan, samples, weights, nullptr, r0, n, blockIdx.x * kTileRays,
+  walk_tile<kSink, kWeighted>(m, origins + 3 * (size_t)scan, samples, weights, perm, r0, n, blockIdx.x * kTileRays,
                               K, tag, parity, ray_counts, ray_flags, ray_offsets, updates);
+}
+
+// Direction ordering of one scan (ohm_order.h): count, prefix, place.
+__global__ __launch_bounds__(256) void scan_order_count_kernel(const float* __restrict__ origin,
+                                                               const float* __restrict__ samples, uint32_t n,
+                                                               uint32_t* __restrict__ hist) {
+  const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) order_count(origin, samples, n, i, hist);
+}
+
+__global__ __launch_bounds__(kOrderElevationBins) void scan_order_strip_kernel(uint32_t* __restrict__ hist,
+                                                                              uint32_t* __restrict__ sums) {
+  order_strip_prefix(hist + (size_t)blockIdx.x * kOrderElevationBins, sums + blockIdx.x);
+}
+
+__global__ __launch_bounds__(kOrderMaxStrips) void scan_order_sums_kernel(uint32_t* __restrict__ sums,
+                                                                          uint32_t strips) {
+  order_scan_prefix(sums, strips);
+}
+
+__global__ __launch_bounds__(256) void scan_order_place_kernel(const float* __restrict__ origin,
+                                                               const float* __restrict__ samples, uint32_t n,
+                                                               uint32_t* __restrict__ hist,
+                                                               const uint32_t* __restrict__ sums,
+                                                               uint32_t* __restrict__ perm) {
+  const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) order_place(origin, samples, n, i, hist, sums, perm);
 }
 
 // ---------------------------------------------------------------------------
@@ -402,6 +431,8 @@ ohm_status ohm_map_create(const ohm_params* params, uint32_t region_capacity, ui
   map->layers = layers | OHM_LAYER_OCC;
   map->seg_major_steps = kDefaultSegMajorSteps;
   map->walk_threads = kDefaultTileThreads;
+  map->order_hist = map->order_sums = map->order_perm = nullptr;
+  map->order_max_rays = 0;
   map->regions = L.regions;
   map->workspace = d_workspace;
   map->workspace_bytes = workspace_bytes;
@@ -488,15 +519,33 @@ ohm_status ohm_integrate_rays(ohm_map map, const float* d_origins, const float* 
     const dim3 tiles((n + kTileRays - 1) / kTileRays);
     const dim3 threads(map->walk_threads);
     const int K = map->seg_major_steps;
+    const uint32_t* perm = nullptr;
+    if (n <= map->order_max_rays) {
+      // walk the scan in direction order
+      ProfScope ps(map, OHM_KERNEL_OTHER, st);
+      const float* o = d_origins + 3 * (size_t)sc;
+      const float* smp = d_samples + 3 * (size_t)r0;
+      const uint32_t bins = order_bins(n), strips = order_strips(n);
+      hipLaunchKernelGGL(fill_u32_kernel, dim3((bins + 255) / 256 < 8192 ? (bins + 255) / 256 : 8192), dim3(256), 0,
+                         st, map->order_hist, (size_t)bins, 0u);
+      hipLaunchKernelGGL(scan_order_count_kernel, dim3((n + 255) / 256), dim3(256), 0, st, o, smp, n,
+                         map->order_hist);
+      hipLaunchKernelGGL(scan_order_strip_kernel, dim3(strips), dim3(kOrderElevationBins), 0, st, map->order_hist,
+                         map->order_sums);
+      hipLaunchKernelGGL(scan_order_sums_kernel, dim3(1), dim3(kOrderMaxStrips), 0, st, map->order_sums, strips);
+      hipLaunchKernelGGL(scan_order_place_kernel, dim3((n + 255) / 256), dim3(256), 0, st, o, smp, n,
+                         map->order_hist, map->order_sums, map->order_perm);
+      perm = map->order_perm;
+    }
     if (count_mode) {
       {
         ProfScope ps(map, OHM_KERNEL_WALK, st);
         if (weighted)
           hipLaunchKernelGGL((walk_seg_kernel<kSinkCount, true>), tiles, threads, 0, st, map->dm, d_origins, sc,
-                             d_samples, d_weights, r0, n, K, tag, parity, nullptr, nullptr, nullptr, nullptr);
+                             d_samples, d_weights, perm, r0, n, K, tag, parity, nullptr, nullptr, nullptr, nullptr);
         else
           hipLaunchKernelGGL((walk_seg_kernel<kSinkCount, false>), tiles, threads, 0, st, map->dm, d_origins, sc,
-                             d_samples, d_weights, r0, n, K, tag, parity, nullptr, nullptr, nullptr, nullptr);
+                             d_samples, d_weights, perm, r0, n, K, tag, parity, nullptr, nullptr, nullptr, nullptr);
       }
       const bool keep = sc == last;
       {
@@ -512,10 +561,10 @@ ohm_status ohm_integrate_rays(ohm_map map, const float* d_origins, const float* 
       ProfScope ps(map, OHM_KERNEL_WALK, st);
       if (weighted)
         hipLaunchKernelGGL((walk_seg_kernel<kSinkCas, true>), tiles, threads, 0, st, map->dm, d_origins, sc,
-                           d_samples, d_weights, r0, n, K, tag, parity, nullptr, nullptr, nullptr, nullptr);
+                           d_samples, d_weights, perm, r0, n, K, tag, parity, nullptr, nullptr, nullptr, nullptr);
       else
         hipLaunchKernelGGL((walk_seg_kernel<kSinkCas, false>), tiles, threads, 0, st, map->dm, d_origins, sc,
-                           d_samples, d_weights, r0, n, K, tag, parity, nullptr, nullptr, nullptr, nullptr);
+                           d_samples, d_weights, perm, r0, n, K, tag, parity, nullptr, nullptr, nullptr, nullptr);
     }
     map->scans_done += 1;
   }
@@ -556,14 +605,41 @@ ohm_status ohm_debug_trace_rays(ohm_map map, const float* d_origins, const float
     const dim3 threads(map->walk_threads);
     if (!d_updates)
       hipLaunchKernelGGL((walk_seg_kernel<kSinkTraceCount, false>), tiles, threads, 0, st, map->dm, d_origins, sc,
-                         d_samples, nullptr, r0, n, map->seg_major_steps, 0u, 0u, d_ray_counts, d_ray_flags, nullptr,
+                         d_samples, nullptr, nullptr, r0, n, map->seg_major_steps, 0u, 0u, d_ray_counts, d_ray_flags, nullptr,
                          nullptr);
     else
       hipLaunchKernelGGL((walk_seg_kernel<kSinkTraceWrite, false>), tiles, threads, 0, st, map->dm, d_origins, sc,
-                         d_samples, nullptr, r0, n, map->seg_major_steps, 0u, 0u, nullptr, nullptr, d_ray_offsets,
+                         d_samples, nullptr, nullptr, r0, n, map->seg_major_steps, 0u, 0u, nullptr, nullptr, d_ray_offsets,
                          d_updates);
   }
   return last_hip_status();
+}
+
+ohm_status ohm_ray_order_scratch_size(uint32_t max_rays, size_t* bytes) {
+  if (!bytes || max_rays == 0) return OHM_E_INVALID_ARG;
+  *bytes = align_up((size_t)order_bins(max_rays) * sizeof(uint32_t)) +
+           align_up((size_t)kOrderMaxStrips * sizeof(uint32_t)) + align_up((size_t)max_rays * sizeof(uint32_t));
+  return OHM_OK;
+}
+
+ohm_status ohm_map_set_ray_order(ohm_map map, void* d_scratch, size_t bytes, uint32_t max_rays) {
+  if (!map) return OHM_E_INVALID_ARG;
+  if (!d_scratch) {
+    map->order_hist = map->order_sums = map->order_perm = nullptr;
+    map->order_max_rays = 0;
+    return OHM_OK;
+  }
+  size_t need = 0;
+  if (ohm_ray_order_scratch_size(max_rays, &need) != OHM_OK) return OHM_E_INVALID_ARG;
+  if ((uintptr_t)d_scratch & (kAlign - 1)) return OHM_E_INVALID_ARG;
+  if (bytes < need) return OHM_E_WORKSPACE_TOO_SMALL;
+  char* base = static_cast<char*>(d_scratch);
+  const size_t hist_bytes = align_up((size_t)order_bins(max_rays) * sizeof(uint32_t));
+  map->order_hist = reinterpret_cast<uint32_t*>(base);
+  map->order_sums = reinterpret_cast<uint32_t*>(base + hist_bytes);
+  map->order_perm = reinterpret_cast<uint32_t*>(base + hist_bytes + align_up((size_t)kOrderMaxStrips * sizeof(uint32_t)));
+  map->order_max_rays = max_rays;
+  return OHM_OK;
 }
 
 ohm_status ohm_map_set_tuning(ohm_map map, const ohm_walk_tuning* t) {

@@ -89,8 +89,8 @@ struct TileRay {
 enum : int { kStageNone = 0, kStageResolve = 1, kStageTouch = 2 };
 
 // Prologue of a tile walk (every thread of the block must call it): threads
-// 0..255 prepare rays tile0.. of the scan in walk order (perm[r0 + i] is the
-// scan index of walk position i; null: the scan's own order) and fill the LDS
+// 0..255 prepare rays tile0.. of the scan in walk order (perm[i] is the scan
+// index of walk position i; null: the scan's own order) and fill the LDS
 // ray table, the block stages the tile's regions in LDS (kStage), and the
 // level-major item list is built: level j lists, in ray order, the rays with
 // more than j segments.  Returns the number of items; tr.max_seg holds the
@@ -110,7 +110,7 @@ __device__ __forceinline__ uint32_t tile_prologue(const DevMap& m, TileRays& tr,
   t.voxels = 0;
   if (tid == 0) tr.max_seg = 0;
   if (t.inrange) {
-    const uint32_t src = perm ? perm[(size_t)r0 + tile0 + tid] : tile0 + tid;
+    const uint32_t src = perm ? perm[tile0 + tid] : tile0 + tid;
     tr.src[tid] = src;
     const size_t ray = (size_t)r0 + src;
     const float o[3] = {origin[0], origin[1], origin[2]};

@@ -182,6 +182,22 @@ class OhmMap:
         t = _lib.WalkTuning(int(seg_major_steps), int(tile_threads))
         check(load().ohm_map_set_tuning(self.handle, ctypes.byref(t)), "ohm_map_set_tuning")
 
+    def set_ray_order(self, max_rays: int):
+        """Walk every scan of at most ``max_rays`` rays in direction order
+        (ohm_map_set_ray_order); 0 turns it off.  The scratch buffer is held
+        by this object."""
+        lib = load()
+        if max_rays <= 0:
+            check(lib.ohm_map_set_ray_order(self.handle, None, 0, 0), "ohm_map_set_ray_order")
+            self._order_scratch = None
+            return
+        size = ctypes.c_size_t(0)
+        check(lib.ohm_ray_order_scratch_size(int(max_rays), ctypes.byref(size)), "ohm_ray_order_scratch_size")
+        buf = torch.empty(int(size.value), dtype=torch.uint8, device=self.device)
+        check(lib.ohm_map_set_ray_order(self.handle, ctypes.c_void_p(buf.data_ptr()), int(size.value), int(max_rays)),
+              "ohm_map_set_ray_order")
+        self._order_scratch = buf
+
     def set_profiling(self, enable: bool):
         check(load().ohm_map_set_profiling(self.handle, 1 if enable else 0), "ohm_map_set_profiling")
 

@@ -115,6 +115,16 @@ def test_null_handles_are_rejected():
     assert _lib.status_string(_lib.OHM_E_NO_DEVICE) == "no HIP device"
 
 
+def test_ray_order_scratch_arguments():
+    lib = _lib.load()
+    sz = ctypes.c_size_t(0)
+    assert lib.ohm_ray_order_scratch_size(0, ctypes.byref(sz)) == _lib.OHM_E_INVALID_ARG
+    assert lib.ohm_ray_order_scratch_size(131072, ctypes.byref(sz)) == _lib.OHM_OK
+    # 512 strips x 256 elevation bins, plus one permutation entry per ray, 4 bytes each
+    assert sz.value >= 4 * (512 * 256 + 131072)
+    assert lib.ohm_map_set_ray_order(None, None, 0, 0) == _lib.OHM_E_INVALID_ARG
+
+
 def test_product_never_imports_oracle():
     """The HIP package must not reach the CPU oracle (no fallback path)."""
     pkg = os.path.join(ROOT, "paper_2206_06079_amd")

@@ -50,9 +50,12 @@ constexpr int kAggLog2 = OHM_AGG_LOG2;
 constexpr uint32_t kAggSize = 1u << kAggLog2;
 constexpr uint32_t kAggEmpty = 0xFFFFFFFFu;  // above every update id (capacity <= kMaxCapacity)
 
-__device__ __forceinline__ bool agg_add(uint32_t* keys, float* vals, uint32_t id, float v) {
-  const uint32_t h = (id * 0x9E3779B1u) >> (32 - kAggLog2);
-  uint32_t k = keys[h];
+__device__ __forceinline__ uint32_t agg_slot(uint32_t id) { return (id * 0x9E3779B1u) >> (32 - kAggLog2); }
+
+// Second half of an insert whose entry key k = keys[agg_slot(id)] was read
+// earlier: claim the entry if it is empty, add if it is (now) ours.
+__device__ __forceinline__ bool agg_finish(uint32_t* keys, float* vals, uint32_t id, uint32_t k, float v) {
+  const uint32_t h = agg_slot(id);
   if (k == kAggEmpty) {
     const uint32_t old = atomicCAS(keys + h, kAggEmpty, id);
     k = old == kAggEmpty ? id : old;
@@ -307,26 +310,30 @@ __device__ void walk_tile(const DevMap& m, const float* __restrict__ origin, con
           v = segmented_sum(has ? wt : 0.f, run.head, lane);
           emit_here = has && run.tail;
         }
-        if (emit_here) {
-          if (!agg_add(agg_key, agg_val, id, v)) {
-            if (kSink == kSinkCount)
-              unsafeAtomicAdd(m.acc + id, v);
-            else
-              cas_clamp_add(m.occ + (id >> 1), v * ((id & 1u) ? m.l_hit : m.l_miss), m.l_min, m.l_max);
-          }
-        }
+        // read the table entry now, step the walk on, then use it: the LDS
+        // read's latency overlaps the step's arithmetic
+        const uint32_t k = emit_here ? agg_key[agg_slot(id)] : 0u;
         n_upd += has ? 1u : 0u;
         n_hit += (has && is_hit) ? 1u : 0u;
         n_drop += (alive && !has) ? 1u : 0u;
-      } else if (alive && kSink == kSinkTraceWrite) {
-        int32_t* out = updates + 4 * (out_base + local);
-        out[0] = s.k[0];
-        out[1] = s.k[1];
-        out[2] = s.k[2];
-        out[3] = is_hit ? 1 : 0;
+        if (alive) alive = !last && tile_advance<kAccum>(m, rc, s, M, slot, lidx);
+        if (emit_here && !agg_finish(agg_key, agg_val, id, k, v)) {
+          if (kSink == kSinkCount)
+            unsafeAtomicAdd(m.acc + id, v);
+          else
+            cas_clamp_add(m.occ + (id >> 1), v * ((id & 1u) ? m.l_hit : m.l_miss), m.l_min, m.l_max);
+        }
+      } else {
+        if (alive && kSink == kSinkTraceWrite) {
+          int32_t* out = updates + 4 * (out_base + local);
+          out[0] = s.k[0];
+          out[1] = s.k[1];
+          out[2] = s.k[2];
+          out[3] = is_hit ? 1 : 0;
+        }
+        local += alive ? 1u : 0u;
+        if (alive) alive = !last && tile_advance<kAccum>(m, rc, s, M, slot, lidx);
       }
-      local += alive ? 1u : 0u;
-      if (alive) alive = !last && tile_advance<kAccum>(m, rc, s, M, slot, lidx);
     }
   }
   if (kSink == kSinkTraceCount || kSink == kSinkTraceWrite) return;

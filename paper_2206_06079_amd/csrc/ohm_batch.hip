@@ -118,7 +118,7 @@ __global__ __launch_bounds__(1024) void batch_walk_kernel(const DevMap* __restri
 // touched: for j = 0..G-1, l = clamp((l + H_j l_hit) + M_j l_miss).
 __global__ __launch_bounds__(256) void batch_finalize_kernel(const DevMap* __restrict__ maps, uint32_t n_sets,
                                                              uint32_t group) {
-  constexpr int kChunk = 4096;
+  constexpr int kChunk = 1024;
   constexpr int kUnits = kRegionVoxels / kChunk;
   for (uint32_t si = 0; si < n_sets; ++si) {
     const DevMap& m = maps[si];

@@ -98,7 +98,7 @@ __global__ __launch_bounds__(256) void scan_order_place_kernel(const float* __re
 // per-scan finalize (count mode)
 // ---------------------------------------------------------------------------
 
-constexpr int kFinalChunk = 4096;  // voxels per work unit
+constexpr int kFinalChunk = 1024;  // voxels per work unit
 constexpr int kFinalUnits = kRegionVoxels / kFinalChunk;
 
 // Applies l <- clamp((l + H l_hit) + M') to every voxel of the touched

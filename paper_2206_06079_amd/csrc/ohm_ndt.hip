@@ -242,7 +242,7 @@ __global__ __launch_bounds__(kNdtMaxThreads) void ndt_seg_kernel(DevMap m, const
   flush_tile_stats(m, t, n_hit, n_upd, n_drop);
 }
 
-constexpr int kNdtChunk = 2048;
+constexpr int kNdtChunk = 1024;
 constexpr int kNdtUnits = kRegionVoxels / kNdtChunk;
 
 __global__ __launch_bounds__(256) void ndt_finalize_kernel(DevMap m, uint32_t parity, int count_mode,

@@ -81,9 +81,12 @@ enum { OHM_MODE_PER_UPDATE = 0, OHM_MODE_COUNT_CLAMP = 1 };
 
 /* Optional layers requested at map creation (bit mask). */
 enum {
-  OHM_LAYER_OCC = 1,     /* always present */
-  OHM_LAYER_NDT = 2,     /* NDT-OM sample count, mean and covariance */
-  OHM_LAYER_ADJOINT = 4  /* last scan at which the clamp was active */
+  OHM_LAYER_OCC = 1,         /* always present */
+  OHM_LAYER_NDT = 2,         /* NDT-OM sample count, mean and covariance */
+  OHM_LAYER_ADJOINT = 4,     /* last scan at which the clamp was active */
+  OHM_LAYER_SCAN_GROUPS = 8  /* 8 accumulator slots: in count mode, ohm_integrate_rays walks up
+                                to 8 consecutive scans of a call in one launch (each into its
+                                own slot, finalized in scan order: the same result) */
 };
 
 /* Quantities readable with ohm_map_read_dense (output element type). */
@@ -312,6 +315,8 @@ enum {
   OHM_KERNEL_WALK = 1,      /* per-ray voxel walk with its updates */
   OHM_KERNEL_FINALIZE = 2,  /* per-scan clamp / accumulator clear */
   OHM_KERNEL_NDT_HIT = 3,   /* NDT sample fold (phase 2) */
+  OHM_KERNEL_WALK_GROUP = 4,      /* voxel walk over a group of scans (OHM_LAYER_SCAN_GROUPS) */
+  OHM_KERNEL_FINALIZE_GROUP = 5,  /* in-order apply of a group's scans */
   OHM_KERNEL_OTHER = 7,
   OHM_KERNEL_KINDS = 8
 };

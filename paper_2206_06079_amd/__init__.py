@@ -7,7 +7,7 @@ NDT-OM statistics (Sec. II-D, III-C) in dense 32^3 regions (Sec. III-A).
 """
 from . import _lib  # noqa: F401
 from ._lib import (  # noqa: F401
-    LAYER_ADJOINT, LAYER_NDT, LAYER_OCC, MODE_COUNT_CLAMP, MODE_PER_UPDATE,
+    LAYER_ADJOINT, LAYER_NDT, LAYER_OCC, LAYER_SCAN_GROUPS, MODE_COUNT_CLAMP, MODE_PER_UPDATE,
     READ_CLAMP_SCAN, READ_HITS, READ_MISSES, READ_NDT_COUNT, READ_NDT_COV, READ_NDT_MEAN, READ_OCC,
     OhmError,
 )

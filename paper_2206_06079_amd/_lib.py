@@ -20,6 +20,7 @@ MODE_COUNT_CLAMP = 1
 LAYER_OCC = 1
 LAYER_NDT = 2
 LAYER_ADJOINT = 4
+LAYER_SCAN_GROUPS = 8
 
 READ_OCC = 0
 READ_HITS = 1
@@ -60,7 +61,7 @@ class BatchTuning(ctypes.Structure):
                 ("tile_threads", ctypes.c_uint32), ("keep_ray_order", ctypes.c_uint32)]
 
 KERNEL_KINDS = 8
-KERNEL_NAMES = {0: "prepass", 1: "walk", 2: "finalize", 3: "ndt_hit", 7: "other"}
+KERNEL_NAMES = {0: "prepass", 1: "walk", 2: "finalize", 3: "ndt_hit", 4: "walk_group", 5: "finalize_group", 7: "other"}
 
 
 class OhmParams(ctypes.Structure):

@@ -43,6 +43,7 @@ struct ohm_map_s {
 namespace ohm {
 
 constexpr int kFinalizeBlocks = 2048;
+constexpr uint32_t kGroupSlots = 8;  // accumulator slots of OHM_LAYER_SCAN_GROUPS
 constexpr int kDefaultSegMajorSteps = 32;
 constexpr uint32_t kDefaultTileThreads = 512;
 

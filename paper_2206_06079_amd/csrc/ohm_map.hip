@@ -141,6 +141,68 @@ __global__ __launch_bounds__(256) void finalize_kernel(DevMap m, uint32_t parity
     __hip_atomic_store(m.hdr + kHdrTouched0 + (parity ^ 1u), 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
+// Grouped scans (OHM_LAYER_SCAN_GROUPS): up to kGroupSlots consecutive scans
+// of a call walk in one launch, scan j of the group into accumulator slot j
+// under one tag, and group_finalize_kernel applies them per voxel in scan
+// order.  More tiles per launch keep the whole device busy: one scan's
+// tiles alone leave most compute units idle behind its longest tiles.
+struct GroupArgs {
+  uint32_t count;                  // scans in the group
+  uint32_t scan[kGroupSlots];      // scan index within the call
+  uint32_t r0[kGroupSlots];        // first ray
+  uint32_t n[kGroupSlots];         // rays
+  uint32_t tile_end[kGroupSlots];  // exclusive end of the scan's blocks
+};
+
+template <bool kWeighted>
+__global__ __launch_bounds__(1024) void walk_group_kernel(DevMap m, const float* __restrict__ origins,
+                                                          const float* __restrict__ samples,
+                                                          const float* __restrict__ weights, GroupArgs g, int K,
+                                                          uint32_t tag, uint32_t parity) {
+  uint32_t j = 0;  // the block's scan (uniform over the block)
+  while (j + 1 < g.count && blockIdx.x >= g.tile_end[j]) ++j;
+  const uint32_t tile = blockIdx.x - (j ? g.tile_end[j - 1] : 0u);
+  DevMap mj = m;
+  mj.acc += (size_t)j * m.capacity * kRegionVoxels * 2;
+  walk_tile<kSinkCount, kWeighted>(mj, origins + 3 * (size_t)g.scan[j], samples, weights, nullptr, g.r0[j], g.n[j],
+                                   tile * kTileRays, K, tag, parity, nullptr, nullptr, nullptr, nullptr);
+}
+
+// Apply the group's g scans in order to every voxel of the regions the group
+// touched: l = clamp((l + H_j l_hit) + M_j l_miss) for j = 0..g-1, recording
+// the clamp scan (scan_tag0 + j), and clear the slots.
+__global__ __launch_bounds__(256) void group_finalize_kernel(DevMap m, uint32_t parity, uint32_t g,
+                                                             uint32_t scan_tag0) {
+  const uint32_t count = __hip_atomic_load(m.hdr + kHdrTouched0 + parity, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  const uint32_t units = count * kFinalUnits;
+  const size_t stride = (size_t)m.capacity * kRegionVoxels;  // float2 elements per slot
+  for (uint32_t u = blockIdx.x; u < units; u += gridDim.x) {
+    const uint32_t slot = m.touched[(size_t)parity * m.capacity + u / kFinalUnits];
+    const size_t base = (size_t)slot * kRegionVoxels + (size_t)(u % kFinalUnits) * kFinalChunk;
+    for (int v = threadIdx.x; v < kFinalChunk; v += blockDim.x) {
+      const size_t vi = base + v;
+      float l = m.occ[vi];
+      bool any = false;
+      for (uint32_t j = 0; j < g; ++j) {
+        float2* ap = reinterpret_cast<float2*>(m.acc) + j * stride + vi;
+        const float2 a = *ap;
+        if (a.x == 0.f && a.y == 0.f) continue;
+        const float t = __fmul_rn(a.y, m.l_hit);
+        const float uu = __fmul_rn(a.x, m.l_miss);
+        float sum = __fadd_rn(l, t);
+        sum = __fadd_rn(sum, uu);
+        if (m.clampscan && (sum < m.l_min || sum > m.l_max)) m.clampscan[vi] = scan_tag0 + j;
+        l = fminf(fmaxf(sum, m.l_min), m.l_max);
+        *ap = make_float2(0.f, 0.f);
+        any = true;
+      }
+      if (any) m.occ[vi] = l;
+    }
+  }
+  if (blockIdx.x == 0 && threadIdx.x == 0)
+    __hip_atomic_store(m.hdr + kHdrTouched0 + (parity ^ 1u), 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
 // ---------------------------------------------------------------------------
 // dense read-back
 // ---------------------------------------------------------------------------
@@ -227,7 +289,8 @@ ohm_status compute_layout(const ohm_params* p, uint32_t capacity, uint32_t layer
   ohm_status s = validate_params(p);
   if (s != OHM_OK) return s;
   if (capacity == 0 || capacity > kMaxCapacity) return OHM_E_INVALID_ARG;
-  if (layers & ~(uint32_t)(OHM_LAYER_OCC | OHM_LAYER_NDT | OHM_LAYER_ADJOINT)) return OHM_E_INVALID_ARG;
+  if (layers & ~(uint32_t)(OHM_LAYER_OCC | OHM_LAYER_NDT | OHM_LAYER_ADJOINT | OHM_LAYER_SCAN_GROUPS))
+    return OHM_E_INVALID_ARG;
   size_t regions = 1;
   for (int a = 0; a < 3; ++a) {
     L->rlo[a] = p->key_min[a] >> kRegionLog2;
@@ -252,7 +315,7 @@ ohm_status compute_layout(const ohm_params* p, uint32_t capacity, uint32_t layer
   L->occ = off;
   off = align_up(off + (size_t)capacity * V * sizeof(float));
   L->acc = off;
-  off = align_up(off + (size_t)capacity * V * 2 * sizeof(float));
+  off = align_up(off + (size_t)capacity * V * 2 * sizeof(float) * ((layers & OHM_LAYER_SCAN_GROUPS) ? kGroupSlots : 1));
   L->ndt = L->nacc = L->mom = L->clampscan = 0;
   if (layers & OHM_LAYER_NDT) {
     L->ndt = off;
@@ -319,7 +382,8 @@ ohm_status map_initialise(ohm_map_s* map, hipStream_t st) {
   uint32_t init_bits;
   memcpy(&init_bits, &m.l_init, sizeof(init_bits));
   launch_fill(m.occ, (size_t)m.capacity * V * sizeof(float), init_bits, st);
-  launch_fill(m.acc, (size_t)m.capacity * V * 2 * sizeof(float), 0u, st);
+  launch_fill(m.acc, (size_t)m.capacity * V * 2 * sizeof(float) * ((map->layers & OHM_LAYER_SCAN_GROUPS) ? kGroupSlots : 1),
+              0u, st);
   if (m.ndt) {
     launch_fill(m.ndt, (size_t)m.capacity * V * sizeof(NdtVoxel), 0u, st);
     launch_fill(m.nacc, (size_t)m.capacity * V * kNaccWords * sizeof(long long), 0u, st);
@@ -506,7 +570,50 @@ ohm_status ohm_integrate_rays(ohm_map map, const float* d_origins, const float* 
   uint32_t last = n_scans;
   for (uint32_t sc = 0; sc < n_scans; ++sc)
     if (h_scan_offsets[sc + 1] > h_scan_offsets[sc]) last = sc;
-  for (uint32_t sc = 0; sc < n_scans; ++sc) {
+  uint32_t first = 0;  // scans before `first` went through grouped launches
+  if (count_mode && (map->layers & OHM_LAYER_SCAN_GROUPS) && map->order_max_rays == 0 && last < n_scans) {
+    // groups of up to kGroupSlots non-empty scans before the last one (which
+    // takes the single-scan path below, so its counts stay readable)
+    const uint32_t threads = map->walk_threads;
+    const int K = map->seg_major_steps;
+    uint32_t sc = 0;
+    while (sc < last) {
+      GroupArgs g = {};
+      uint32_t tiles = 0;
+      for (; sc < last && g.count < kGroupSlots; ++sc) {
+        const uint32_t r0 = h_scan_offsets[sc];
+        const uint32_t n = h_scan_offsets[sc + 1] - r0;
+        if (n == 0) continue;
+        g.scan[g.count] = sc;
+        g.r0[g.count] = r0;
+        g.n[g.count] = n;
+        tiles += (n + kTileRays - 1) / kTileRays;
+        g.tile_end[g.count] = tiles;
+        ++g.count;
+      }
+      if (g.count == 0) break;
+      clear_pending(map, st);
+      const uint32_t tag = ++map->count_batches;
+      const uint32_t parity = tag & 1u;
+      {
+        ProfScope ps(map, OHM_KERNEL_WALK_GROUP, st);
+        if (weighted)
+          hipLaunchKernelGGL(walk_group_kernel<true>, dim3(tiles), dim3(threads), 0, st, map->dm, d_origins, d_samples,
+                             d_weights, g, K, tag, parity);
+        else
+          hipLaunchKernelGGL(walk_group_kernel<false>, dim3(tiles), dim3(threads), 0, st, map->dm, d_origins,
+                             d_samples, d_weights, g, K, tag, parity);
+      }
+      {
+        ProfScope ps(map, OHM_KERNEL_FINALIZE_GROUP, st);
+        hipLaunchKernelGGL(group_finalize_kernel, dim3(kFinalizeBlocks), dim3(256), 0, st, map->dm, parity, g.count,
+                           map->scans_done + 1);
+      }
+      map->scans_done += g.count;
+    }
+    first = last;
+  }
+  for (uint32_t sc = first; sc < n_scans; ++sc) {
     const uint32_t r0 = h_scan_offsets[sc];
     const uint32_t n = h_scan_offsets[sc + 1] - r0;
     if (n == 0) continue;

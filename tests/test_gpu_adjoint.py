@@ -26,9 +26,9 @@ def setup_case(n_scans, ndt=True, beams=64, cols=2048):
     return params, batch, box_min, box_dim, labels, mask, ref
 
 
-def gpu_grads(params, batch, box_min, box_dim, labels, mask, ndt=True):
+def gpu_grads(params, batch, box_min, box_dim, labels, mask, ndt=True, extra_layers=0):
     dev = device()
-    layers = ohm.LAYER_ADJOINT | (ohm.LAYER_NDT if ndt else 0)
+    layers = ohm.LAYER_ADJOINT | (ohm.LAYER_NDT if ndt else 0) | extra_layers
     m = ohm.OhmMap(params, 256, layers=layers, device=dev)
     o, s, off, w = to_dev(batch)
     (m.ndt_integrate if ndt else m.integrate)(o, s, off, w)
@@ -78,6 +78,15 @@ def test_adjoint_plain():
     params, batch, box_min, box_dim, labels, mask, ref = setup_case(3, ndt=False)
     gw, gs, occ, _ = gpu_grads(params, batch, box_min, box_dim, labels, mask, ndt=False)
     assert gs[2] == 0.0
+    check(gw, gs, ref, in_box_counts(params, batch, box_min, box_dim), batch.n_scans)
+
+
+def test_adjoint_plain_grouped_forward():
+    """The forward through grouped scans (one walk launch per 8 scans) leaves
+    the clamp record the backward needs: same gradients."""
+    params, batch, box_min, box_dim, labels, mask, ref = setup_case(10, ndt=False)
+    gw, gs, occ, _ = gpu_grads(params, batch, box_min, box_dim, labels, mask, ndt=False,
+                               extra_layers=ohm.LAYER_SCAN_GROUPS)
     check(gw, gs, ref, in_box_counts(params, batch, box_min, box_dim), batch.n_scans)
 
 

@@ -1,0 +1,127 @@
+"""Grouped scans (LAYER_SCAN_GROUPS): ohm_integrate_rays walks up to 8 scans of
+a call in one launch and applies them per voxel in scan order.  The results
+must be those of scan-by-scan integration: bit-identical to the oracle for
+count mode with unit weights, bit-identical to one launch per scan with
+exactly summable weights, and the same clamp-scan record as a map that
+launches once per scan."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import paper_2206_06079_amd as ohm
+from gpu_helpers import device, full_box, gpu_integrate, to_dev
+from workloads import scenes
+from workloads.scenes import RayBatch
+
+pytestmark = pytest.mark.gpu
+
+GROUPED = ohm.LAYER_OCC | ohm.LAYER_SCAN_GROUPS
+CFG1_BOX_MIN = (690, 978, 183)
+CFG1_BOX_DIM = (720, 44, 34)
+
+
+def small_map(n=48, voxel=0.1, **kw):
+    return scenes.grid_map((-n * voxel / 2,) * 3, (n * voxel / 2,) * 3, voxel, **kw)
+
+
+@pytest.mark.parametrize("n_scans", [1, 2, 9, 17])
+def test_grouped_config1_equals_oracle(n_scans):
+    """1 scan (no group), 2 (group of one + last), 9 (8 + last), 17 (8, 8, last)."""
+    mp, batch = scenes.config1(n_scans=n_scans, first_scan=5)
+    occ, hits, miss, st = gpu_integrate(mp, batch, 1024, CFG1_BOX_MIN, CFG1_BOX_DIM, layers=GROUPED)
+    o_occ, o_hit, o_miss, o_st = oracle.integrate_count(mp, batch, CFG1_BOX_MIN, CFG1_BOX_DIM)
+    assert np.array_equal(occ, o_occ)
+    # the last scan's counts stay readable
+    assert np.array_equal(hits, o_hit)
+    assert np.array_equal(miss, o_miss)
+    assert st["voxel_updates"] == o_st["updates"]
+    assert st["rays_in"] == o_st["rays"] and st["rays_truncated"] == o_st["truncated"]
+    assert st["updates_dropped_pool"] == 0
+
+
+def test_grouped_empty_scans_and_several_calls():
+    """Empty scans anywhere in a call, calls of different lengths in a row
+    (the previous call's kept counts are cleared before the next group)."""
+    mp = small_map(40)
+    n_scans, per = 21, 700
+    rng = np.random.default_rng(11)
+    parts, origins = [], []
+    for k in range(n_scans):
+        o = rng.uniform(-0.3, 0.3, 3)
+        b = scenes.random_rays(per, 100 + k, None, None, tuple(o), 0.1, 2.2)
+        parts.append(b.samples)
+        origins.append(b.origins[0])
+    sizes = np.full(n_scans, per)
+    sizes[[0, 4, 5, 13, 20]] = 0  # empty: first, a run, one inside a group, the last
+    samples = np.concatenate([p[:n] for p, n in zip(parts, sizes)])
+    offsets = np.concatenate([[0], np.cumsum(sizes)]).astype(np.uint32)
+    batch = RayBatch(np.asarray(origins, np.float32), samples.astype(np.float32), offsets)
+    bmin, bdim = full_box(mp)
+    m = ohm.OhmMap(mp, 64, layers=GROUPED, device=device())
+    # calls of 1, 12 and 8 scans
+    for first, cnt in ((0, 1), (1, 12), (13, 8)):
+        o, s, off, w = to_dev(batch.scans(first, cnt))
+        m.integrate(o, s, off, w)
+    occ = m.read_dense(ohm.READ_OCC, bmin, bdim).cpu().numpy()
+    hits = m.read_dense(ohm.READ_HITS, bmin, bdim).cpu().numpy()
+    miss = m.read_dense(ohm.READ_MISSES, bmin, bdim).cpu().numpy()
+    st = m.stats()
+    m.close()
+    o_occ, _, _, o_st = oracle.integrate_count(mp, batch)
+    assert np.array_equal(occ, o_occ)
+    # the last non-empty scan of the last call is scan 19
+    _, l_hit, l_miss, _ = oracle.integrate_count(mp, batch.scans(19, 1))
+    assert np.array_equal(hits, l_hit) and np.array_equal(miss, l_miss)
+    assert st["voxel_updates"] == o_st["updates"] and st["rays_in"] == o_st["rays"]
+
+
+def test_grouped_weighted_exact_sums():
+    """Weights from {0.5, 0.75, 1}: every per-voxel sum is exact in fp32 in any
+    order, so grouped and one-launch-per-scan integration give the same bits
+    and the same per-scan sums as the oracle; occupancy stays within the fp32
+    rounding of the per-scan updates of the oracle's fp64 evaluation (three
+    roundings of values of magnitude <= 4 per scan)."""
+    mp, batch = scenes.config1(n_scans=10, first_scan=30)
+    batch.weights = np.random.default_rng(12).choice(np.float32([0.5, 0.75, 1.0]), batch.n_rays)
+    occ, hits, miss, st = gpu_integrate(mp, batch, 1024, CFG1_BOX_MIN, CFG1_BOX_DIM, layers=GROUPED)
+    occ1, _, _, _ = gpu_integrate(mp, batch, 1024, CFG1_BOX_MIN, CFG1_BOX_DIM)
+    o_occ, o_hit, o_miss, o_st = oracle.integrate_count(mp, batch, CFG1_BOX_MIN, CFG1_BOX_DIM)
+    assert np.array_equal(hits, o_hit) and np.array_equal(miss, o_miss)
+    assert np.array_equal(occ, occ1)
+    tol = batch.n_scans * 3 * 2.0 ** -22 + 1e-6
+    assert np.abs(occ.astype(np.float64) - o_occ).max() <= tol
+    assert st["voxel_updates"] == o_st["updates"]
+
+
+def test_grouped_clamp_scan_matches_per_scan():
+    """The clamp-scan layer records, per voxel, the same scan as a map that
+    finalizes each scan in its own launch (config 1, 12 scans: clamps engage
+    on the ground and walls)."""
+    mp, batch = scenes.config1(n_scans=12, first_scan=0)
+    out = []
+    for layers in (ohm.LAYER_ADJOINT, ohm.LAYER_ADJOINT | ohm.LAYER_SCAN_GROUPS):
+        m = ohm.OhmMap(mp, 1024, layers=layers, device=device())
+        o, s, off, w = to_dev(batch)
+        m.integrate(o, s, off, w)
+        out.append((m.read_dense(ohm.READ_OCC, CFG1_BOX_MIN, CFG1_BOX_DIM).cpu().numpy(),
+                    m.read_dense(ohm.READ_CLAMP_SCAN, CFG1_BOX_MIN, CFG1_BOX_DIM).cpu().numpy()))
+        m.close()
+    (occ_a, cl_a), (occ_b, cl_b) = out
+    assert np.array_equal(occ_a, occ_b)
+    assert np.array_equal(cl_a, cl_b)
+    assert np.unique(cl_a).size > 3  # clamps engaged at several scans
+
+
+def test_grouped_ordering_scratch_takes_single_scan_path():
+    """With direction-ordering scratch attached the call walks scan by scan
+    (ordered); the result is the same."""
+    mp, batch = scenes.config1(n_scans=3, first_scan=40)
+    m = ohm.OhmMap(mp, 1024, layers=GROUPED, device=device())
+    m.set_ray_order(int(np.diff(batch.offsets.astype(np.int64)).max()))
+    o, s, off, w = to_dev(batch)
+    m.integrate(o, s, off, w)
+    occ = m.read_dense(ohm.READ_OCC, CFG1_BOX_MIN, CFG1_BOX_DIM).cpu().numpy()
+    m.close()
+    o_occ, _, _, _ = oracle.integrate_count(mp, batch, CFG1_BOX_MIN, CFG1_BOX_DIM)
+    assert np.array_equal(occ, o_occ)

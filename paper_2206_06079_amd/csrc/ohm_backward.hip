@@ -107,8 +107,9 @@ __global__ __launch_bounds__(kBackwardMaxThreads) void backward_seg_kernel(
   const uint32_t tile0 = blockIdx.x * kTileRays;
   const float* origin = origins + 3 * (size_t)scan;
   TileRay t;
+  RegionWindow rw;
   const uint32_t items =
-      tile_prologue<kStageResolve>(m, tr, rc, origin, samples, nullptr, r0, n, tile0, K, 0u, 0u, t);
+      tile_prologue<kStageResolve>(m, tr, rc, rw, origin, samples, nullptr, r0, n, tile0, K, 0u, 0u, t);
   if (tid < (uint32_t)kTileRays) {
     ray_gw[tid] = 0.0;
     if (t.ok)
@@ -131,7 +132,7 @@ __global__ __launch_bounds__(kBackwardMaxThreads) void backward_seg_kernel(
       dv[a] = ray_end[a][ray_t] - od[a];
       dd = dd + dv[a] * dv[a];
     }
-    int32_t slot = staged_slot(m, rc, s.k[0], s.k[1], s.k[2]);
+    int32_t slot = staged_slot(m, rc, rw, s.k[0], s.k[1], s.k[2]);
     uint32_t lidx = local_index(s.k[0], s.k[1], s.k[2]);
     double gw = 0.0;
     for (;;) {
@@ -162,7 +163,7 @@ __global__ __launch_bounds__(kBackwardMaxThreads) void backward_seg_kernel(
           }
         }
       }
-      if (last || !tile_advance<true>(m, rc, s, M, slot, lidx)) break;
+      if (last || !tile_advance<true>(m, rc, rw, s, M, slot, lidx)) break;
     }
     if (gw != 0.0) atomicAdd(&ray_gw[ray_t], gw);
   }

@@ -134,8 +134,9 @@ __global__ __launch_bounds__(kNdtMaxThreads) void ndt_seg_kernel(DevMap m, const
     agg_val[h] = 0ull;
   }
   TileRay t;
+  RegionWindow rw;
   const uint32_t items =
-      tile_prologue<kStageTouch>(m, tr, rc, origin, samples, nullptr, r0, n, tile0, K, tag, parity, t);
+      tile_prologue<kStageTouch>(m, tr, rc, rw, origin, samples, nullptr, r0, n, tile0, K, tag, parity, t);
   if (t.ok)
     for (int a = 0; a < 3; ++a) ray_end[a][tid] = t.r.end[a];
   __syncthreads();
@@ -165,7 +166,7 @@ __global__ __launch_bounds__(kNdtMaxThreads) void ndt_seg_kernel(DevMap m, const
         dv[a] = ray_end[a][ray_t] - od[a];
         dd = dd + dv[a] * dv[a];
       }
-      if (alive) slot = staged_slot(m, rc, s.k[0], s.k[1], s.k[2]);
+      if (alive) slot = staged_slot(m, rc, rw, s.k[0], s.k[1], s.k[2]);
       lidx = local_index(s.k[0], s.k[1], s.k[2]);
     }
     const long long q_plain = llrint((double)m.l_miss * wt * kQ);
@@ -230,7 +231,7 @@ __global__ __launch_bounds__(kNdtMaxThreads) void ndt_seg_kernel(DevMap m, const
         } else {
           ++n_drop;
         }
-        alive = !last && tile_advance<true>(m, rc, s, M, slot, lidx);
+        alive = !last && tile_advance<true>(m, rc, rw, s, M, slot, lidx);
       }
     }
   }

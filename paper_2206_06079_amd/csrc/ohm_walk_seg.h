@@ -34,33 +34,56 @@ __device__ __forceinline__ void cas_clamp_add(float* p, float delta, float lo, f
   }
 }
 
-// Per-tile aggregation of updates: a direct-mapped LDS table of 2^kAggLog2
-// (update id -> summed weight) entries.  A merged update whose table entry
-// holds its id, or claims the empty entry, is added there; otherwise (the
-// entry belongs to another id) it is applied at once.  The table is applied
-// with one atomic per entry when the tile ends, so the voxels that many rays
-// of the tile cross cost one global atomic per tile instead of one per wave
-// and step.  An id names one voxel and one kind (hit or miss), so an entry
-// only sums increments of one sign; in per-update mode a clamp-add of that
-// sum equals the clamp-adds of its parts in sequence.
+// Per-tile aggregation of updates: an LDS table of 2^kAggLog2 (update id ->
+// summed weight) entries.  A merged update is added to the entry its id owns
+// (claiming an empty one) among two probes; when both belong to other ids it
+// is applied at once.  The table is applied with one atomic per entry when
+// the tile ends, so the voxels that many rays of the tile cross cost one
+// global atomic per tile instead of one per wave and step.  An id names one
+// voxel and one kind (hit or miss), so an entry only sums increments of one
+// sign; in per-update mode a clamp-add of that sum equals the clamp-adds of
+// its parts in sequence.
+//
+// The table is laid out by 64-byte line of the accumulator: the 16 ids of a
+// line (8 voxels along x, miss and hit) share one 16-entry group, at their
+// position in the line, and the group is picked by hashing the line.  The
+// end-of-tile flush, consecutive entries by consecutive lanes, then sends
+// one wave's atomics to a few lines instead of 64 scattered ones: the memory
+// side's atomic throughput is counted in lines, and scattered atomics are
+// what bounds the walk once the voxel steps are cheap.  The second probe
+// takes the same position in the next group.
 #ifndef OHM_AGG_LOG2
 #define OHM_AGG_LOG2 12
 #endif
 constexpr int kAggLog2 = OHM_AGG_LOG2;
 constexpr uint32_t kAggSize = 1u << kAggLog2;
 constexpr uint32_t kAggEmpty = 0xFFFFFFFFu;  // above every update id (capacity <= kMaxCapacity)
+constexpr uint32_t kAggLine = 16;            // ids per 64-byte accumulator line
 
-__device__ __forceinline__ uint32_t agg_slot(uint32_t id) { return (id * 0x9E3779B1u) >> (32 - kAggLog2); }
+__device__ __forceinline__ uint32_t agg_slot(uint32_t id) {
+  const uint32_t group = ((id / kAggLine) * 0x9E3779B1u) >> (32 - (kAggLog2 - 4));
+  return group * kAggLine + id % kAggLine;
+}
 
-// Second half of an insert whose entry key k = keys[agg_slot(id)] was read
-// earlier: claim the entry if it is empty, add if it is (now) ours.
-__device__ __forceinline__ bool agg_finish(uint32_t* keys, float* vals, uint32_t id, uint32_t k, float v) {
-  const uint32_t h = agg_slot(id);
+// Claim-or-match entry h for id (k: its key as read before): true when the
+// entry is (now) the id's.
+__device__ __forceinline__ bool agg_own(uint32_t* keys, uint32_t h, uint32_t id, uint32_t k) {
   if (k == kAggEmpty) {
     const uint32_t old = atomicCAS(keys + h, kAggEmpty, id);
     k = old == kAggEmpty ? id : old;
   }
-  if (k != id) return false;
+  return k == id;
+}
+
+// Second half of an insert whose first entry's key k = keys[agg_slot(id)]
+// was read earlier: add v to the id's entry among the two probes.  False
+// when both belong to other ids.
+__device__ __forceinline__ bool agg_finish(uint32_t* keys, float* vals, uint32_t id, uint32_t k, float v) {
+  uint32_t h = agg_slot(id);
+  if (!agg_own(keys, h, id, k)) {
+    h = (h + kAggLine) & (kAggSize - 1);
+    if (!agg_own(keys, h, id, keys[h])) return false;
+  }
   atomicAdd(vals + h, v);
   return true;
 }
@@ -97,9 +120,9 @@ enum : int { kStageNone = 0, kStageResolve = 1, kStageTouch = 2 };
 // ray table, the block stages the tile's regions in LDS (kStage), and the
 // level-major item list is built: level j lists, in ray order, the rays with
 // more than j segments.  Returns the number of items; tr.max_seg holds the
-// level count.
+// level count, rw how the staged regions are looked up.
 template <int kStage>
-__device__ __forceinline__ uint32_t tile_prologue(const DevMap& m, TileRays& tr, RegionCache& rc,
+__device__ __forceinline__ uint32_t tile_prologue(const DevMap& m, TileRays& tr, RegionCache& rc, RegionWindow& rw,
                                                   const float* __restrict__ origin, const float* __restrict__ samples,
                                                   const uint32_t* __restrict__ perm, uint32_t r0, uint32_t n,
                                                   uint32_t tile0, int K, uint32_t tag, uint32_t parity, TileRay& t) {
@@ -137,12 +160,14 @@ __device__ __forceinline__ uint32_t tile_prologue(const DevMap& m, TileRays& tr,
         tr.q1[a][tid] = t.r.q1[a];
       }
       tr.trunc[tid] = t.r.truncated ? 1 : 0;
-      atomicMax(&tr.max_seg, nseg);
     }
     tr.nseg[tid] = (uint8_t)nseg;
+    const int32_t wmax = wave_max_i32((int32_t)nseg);
+    if (lane == 0 && wmax > 0) atomicMax(&tr.max_seg, (uint32_t)wmax);
   }
-  if (kStage == kStageTouch) stage_regions<true>(m, rc, t.ok, t.r, tag, parity);
-  else if (kStage == kStageResolve) stage_regions<false>(m, rc, t.ok, t.r, tag, parity);
+  rw = RegionWindow{};
+  if (kStage == kStageTouch) rw = stage_regions<true>(m, rc, t.ok, t.r, tag, parity);
+  else if (kStage == kStageResolve) rw = stage_regions<false>(m, rc, t.ok, t.r, tag, parity);
   else __syncthreads();
   const uint32_t levels = tr.max_seg;
   const uint32_t wave = tid >> 6;
@@ -198,16 +223,18 @@ __device__ __forceinline__ bool tile_item(const DevMap& m, const TileRays& tr, u
 // segment ends; otherwise s.k is the next voxel and lidx (and, with kSlots,
 // the staged region slot) follow it.
 template <bool kSlots>
-__device__ __forceinline__ bool tile_advance(const DevMap& m, const RegionCache& rc, SegState& s, int M,
-                                             int32_t& slot, uint32_t& lidx) {
+__device__ __forceinline__ bool tile_advance(const DevMap& m, const RegionCache& rc, const RegionWindow& rw,
+                                             SegState& s, int M, int32_t& slot, uint32_t& lidx) {
   const int a = seg_advance(s, M);
   const bool moved = a >= 0;
   const int32_t sg = pick3(a, s.w.sg[0], s.w.sg[1], s.w.sg[2]);
   const int32_t kn = pick3(a, s.k[0], s.k[1], s.k[2]);
   const bool cross = moved && (kn & kRegionMask) == (sg > 0 ? 0 : kRegionMask);
-  lidx += (uint32_t)(a == 0 ? sg : (a == 1 ? sg * kRegionEdge : sg * kRegionEdge * kRegionEdge));
+  // the local index moves by sg along axis a: strides 1, 32, 1024 (wrapping
+  // adds; a crossing recomputes it)
+  lidx += (uint32_t)sg << (kRegionLog2 * (a & 3));
   if (cross) {
-    if (kSlots) slot = staged_slot(m, rc, s.k[0], s.k[1], s.k[2]);
+    if (kSlots) slot = staged_slot(m, rc, rw, s.k[0], s.k[1], s.k[2]);
     lidx = local_index(s.k[0], s.k[1], s.k[2]);
   }
   return moved;
@@ -253,7 +280,9 @@ __device__ void walk_tile(const DevMap& m, const float* __restrict__ origin, con
       agg_val[h] = 0.f;
     }
   TileRay t;
-  const uint32_t items = tile_prologue<kStage>(m, tr, rc, origin, samples, perm, r0, n, tile0, K, tag, parity, t);
+  RegionWindow rw;
+  const uint32_t items =
+      tile_prologue<kStage>(m, tr, rc, rw, origin, samples, perm, r0, n, tile0, K, tag, parity, t);
 
   if (kSink == kSinkTraceCount && t.inrange) {
     int32_t flags = 0;
@@ -289,7 +318,7 @@ __device__ void walk_tile(const DevMap& m, const float* __restrict__ origin, con
       const size_t ray = (size_t)r0 + tr.src[ray_t];
       if (kWeighted) wt = weights[ray];
       if (kSink == kSinkTraceWrite) out_base = ray_offsets[ray] + s.pos;
-      if (kAccum && alive) slot = staged_slot(m, rc, s.k[0], s.k[1], s.k[2]);
+      if (kAccum && alive) slot = staged_slot(m, rc, rw, s.k[0], s.k[1], s.k[2]);
       lidx = local_index(s.k[0], s.k[1], s.k[2]);
     }
     uint32_t local = 0;
@@ -316,7 +345,7 @@ __device__ void walk_tile(const DevMap& m, const float* __restrict__ origin, con
         n_upd += has ? 1u : 0u;
         n_hit += (has && is_hit) ? 1u : 0u;
         n_drop += (alive && !has) ? 1u : 0u;
-        if (alive) alive = !last && tile_advance<kAccum>(m, rc, s, M, slot, lidx);
+        if (alive) alive = !last && tile_advance<kAccum>(m, rc, rw, s, M, slot, lidx);
         if (emit_here && !agg_finish(agg_key, agg_val, id, k, v)) {
           if (kSink == kSinkCount)
             unsafeAtomicAdd(m.acc + id, v);
@@ -332,7 +361,7 @@ __device__ void walk_tile(const DevMap& m, const float* __restrict__ origin, con
           out[3] = is_hit ? 1 : 0;
         }
         local += alive ? 1u : 0u;
-        if (alive) alive = !last && tile_advance<kAccum>(m, rc, s, M, slot, lidx);
+        if (alive) alive = !last && tile_advance<kAccum>(m, rc, rw, s, M, slot, lidx);
       }
     }
   }

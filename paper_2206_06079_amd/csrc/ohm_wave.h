@@ -18,6 +18,26 @@ __device__ __forceinline__ uint32_t wave_sum_u32(uint32_t v) {
   return v;
 }
 
+// Butterfly min / max over the wave (every lane must take part; lanes with
+// nothing to contribute pass the identity).  One LDS atomic per wave after
+// this is far cheaper than one per lane to a shared address, which the
+// compiler would serialise lane by lane.
+__device__ __forceinline__ int32_t wave_min_i32(int32_t v) {
+  for (int off = 32; off > 0; off >>= 1) {
+    const int32_t o = __shfl_xor(v, off);
+    v = o < v ? o : v;
+  }
+  return v;
+}
+
+__device__ __forceinline__ int32_t wave_max_i32(int32_t v) {
+  for (int off = 32; off > 0; off >>= 1) {
+    const int32_t o = __shfl_xor(v, off);
+    v = o > v ? o : v;
+  }
+  return v;
+}
+
 // Runs of equal ids over adjacent lanes.  Every lane learns whether it heads
 // its run, whether it ends it, and (at the head) the run length.
 struct LaneRuns {

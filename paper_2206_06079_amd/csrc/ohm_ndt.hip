@@ -75,21 +75,30 @@ __device__ __forceinline__ double ndt_delta(const DevMap& m, const double o[3], 
 constexpr uint32_t kNdtMaxThreads = 512;  // keeps the kernel within its registers
 
 // Per-tile LDS table of the NDT walk's increments (see the occupancy walk's
-// table): update id -> summed Q32.32 increment.  The sums are exact integers,
-// so the result does not depend on how updates reach the table.
+// table): update id -> summed Q32.32 increment, two probes, laid out by
+// 64-byte accumulator line (two voxels' miss and hit words: 4 ids per
+// group).  The sums are exact integers, so the result does not depend on how
+// updates reach the table.
 constexpr int kNdtAggLog2 = 12;
 constexpr uint32_t kNdtAggSize = 1u << kNdtAggLog2;
+constexpr uint32_t kNdtAggLine = 4;
 
 __device__ __forceinline__ bool ndt_agg_add(uint32_t* keys, unsigned long long* vals, uint32_t id, long long q) {
-  const uint32_t h = (id * 0x9E3779B1u) >> (32 - kNdtAggLog2);
-  uint32_t k = keys[h];
-  if (k == kAggEmpty) {
-    const uint32_t old = atomicCAS(keys + h, kAggEmpty, id);
-    k = old == kAggEmpty ? id : old;
+  const uint32_t group = ((id / kNdtAggLine) * 0x9E3779B1u) >> (32 - (kNdtAggLog2 - 2));
+  uint32_t h = group * kNdtAggLine + id % kNdtAggLine;
+  for (int p = 0; p < 2; ++p) {
+    uint32_t k = keys[h];
+    if (k == kAggEmpty) {
+      const uint32_t old = atomicCAS(keys + h, kAggEmpty, id);
+      k = old == kAggEmpty ? id : old;
+    }
+    if (k == id) {
+      atomicAdd(vals + h, (unsigned long long)q);
+      return true;
+    }
+    h = (h + kNdtAggLine) & (kNdtAggSize - 1);
   }
-  if (k != id) return false;
-  atomicAdd(vals + h, (unsigned long long)q);
-  return true;
+  return false;
 }
 
 // Apply a summed increment of one (voxel, kind): Q32.32 accumulators, or in
@@ -170,11 +179,15 @@ __global__ __launch_bounds__(kNdtMaxThreads) void ndt_seg_kernel(DevMap m, const
       lidx = local_index(s.k[0], s.k[1], s.k[2]);
     }
     const long long q_plain = llrint((double)m.l_miss * wt * kQ);
+    // sample count of the voxel being visited, loaded one step ahead so the
+    // load's latency overlaps the previous voxel's update work
+    uint32_t cnt = (alive && slot >= 0) ? m.ndt[(size_t)slot * kRegionVoxels + lidx].n : 0u;
     while (__ballot(alive)) {
       const bool last = alive && s.w.total == 0;
       const bool is_hit = last && !trunc;
       const bool has = alive && slot >= 0;
       const size_t v = has ? (size_t)slot * kRegionVoxels + lidx : 0;
+      const int32_t k0 = s.k[0], k1 = s.k[1], k2 = s.k[2];  // this voxel (the walk steps on below)
       long long q = 0;
       bool weighted_miss = false;  // a miss whose increment the voxel's samples weight
       if (has) {
@@ -182,19 +195,28 @@ __global__ __launch_bounds__(kNdtMaxThreads) void ndt_seg_kernel(DevMap m, const
           q = llrint(wt * kQ);
         } else {
           q = q_plain;
-          const uint32_t cnt = m.ndt[v].n;
           if (cnt >= m.ndt_min_samples) {
             weighted_miss = true;
             const NdtVoxel nv = m.ndt[v];
-            const double c[3] = {m.origin[0] + ((double)s.k[0] + 0.5) * m.voxel_size,
-                                 m.origin[1] + ((double)s.k[1] + 0.5) * m.voxel_size,
-                                 m.origin[2] + ((double)s.k[2] + 0.5) * m.voxel_size};
+            const double c[3] = {m.origin[0] + ((double)k0 + 0.5) * m.voxel_size,
+                                 m.origin[1] + ((double)k1 + 0.5) * m.voxel_size,
+                                 m.origin[2] + ((double)k2 + 0.5) * m.voxel_size};
             q = llrint(ndt_delta(m, od, dv, dd, c, nv, sig_miss) * wt * kQ);
           }
         }
       }
       const uint32_t id = has ? (((uint32_t)slot * (uint32_t)kRegionVoxels + lidx) << 1) | (is_hit ? 1u : 0u)
                               : (0xFFFFFFFFu - lane);
+      if (alive) {
+        if (slot >= 0) {
+          ++n_upd;
+          n_hit += is_hit ? 1u : 0u;
+        } else {
+          ++n_drop;
+        }
+        alive = !last && tile_advance<true>(m, rc, rw, s, M, slot, lidx);
+      }
+      const uint32_t cnt_next = (alive && slot >= 0) ? m.ndt[(size_t)slot * kRegionVoxels + lidx].n : 0u;
       const LaneRuns run = lane_runs(id, lane);
       long long qs;
       bool emit;
@@ -209,9 +231,9 @@ __global__ __launch_bounds__(kNdtMaxThreads) void ndt_seg_kernel(DevMap m, const
       if (emit && !ndt_agg_add(agg_key, agg_val, id, qs)) ndt_apply<kCount>(m, id, qs);
       if (has && is_hit) {
         // sample moments (fp64), voxel-centred: x = sample - centre
-        const double x0 = (double)samples[3 * ray + 0] - (m.origin[0] + ((double)s.k[0] + 0.5) * m.voxel_size);
-        const double x1 = (double)samples[3 * ray + 1] - (m.origin[1] + ((double)s.k[1] + 0.5) * m.voxel_size);
-        const double x2 = (double)samples[3 * ray + 2] - (m.origin[2] + ((double)s.k[2] + 0.5) * m.voxel_size);
+        const double x0 = (double)samples[3 * ray + 0] - (m.origin[0] + ((double)k0 + 0.5) * m.voxel_size);
+        const double x1 = (double)samples[3 * ray + 1] - (m.origin[1] + ((double)k1 + 0.5) * m.voxel_size);
+        const double x2 = (double)samples[3 * ray + 2] - (m.origin[2] + ((double)k2 + 0.5) * m.voxel_size);
         double* mo = m.mom + v * kMomWords;
         unsafeAtomicAdd(mo + 0, x0);
         unsafeAtomicAdd(mo + 1, x1);
@@ -224,15 +246,7 @@ __global__ __launch_bounds__(kNdtMaxThreads) void ndt_seg_kernel(DevMap m, const
         unsafeAtomicAdd(mo + 8, x2 * x2);
         atomicAdd(reinterpret_cast<unsigned long long*>(m.nacc + v * kNaccWords + kNaccSamples), 1ull);
       }
-      if (alive) {
-        if (slot >= 0) {
-          ++n_upd;
-          n_hit += is_hit ? 1u : 0u;
-        } else {
-          ++n_drop;
-        }
-        alive = !last && tile_advance<true>(m, rc, rw, s, M, slot, lidx);
-      }
+      cnt = cnt_next;
     }
   }
   __syncthreads();

@@ -297,7 +297,7 @@ __device__ void walk_tile(const DevMap& m, const float* __restrict__ origin, con
     ray_counts[ray] = t.ok ? t.voxels : 0u;
     ray_flags[ray] = flags;
   }
-  uint32_t n_upd = 0, n_drop = 0, n_hit = 0;
+  uint32_t n_drop = 0, n_hit_drop = 0;
 
   // segment walks, one item per thread per round, with lane-run merging
   const uint32_t rounds = (items + blockDim.x - 1) / blockDim.x;
@@ -342,9 +342,12 @@ __device__ void walk_tile(const DevMap& m, const float* __restrict__ origin, con
         // read the table entry now, step the walk on, then use it: the LDS
         // read's latency overlaps the step's arithmetic
         const uint32_t k = emit_here ? agg_key[agg_slot(id)] : 0u;
-        n_upd += has ? 1u : 0u;
-        n_hit += (has && is_hit) ? 1u : 0u;
-        n_drop += (alive && !has) ? 1u : 0u;
+        // updates and hits are counted per ray below; only drops (region
+        // pool exhausted) are counted here
+        if (alive && !has) {
+          ++n_drop;
+          n_hit_drop += is_hit ? 1u : 0u;
+        }
         if (alive) alive = !last && tile_advance<kAccum>(m, rc, rw, s, M, slot, lidx);
         if (emit_here && !agg_finish(agg_key, agg_val, id, k, v)) {
           if (kSink == kSinkCount)
@@ -377,7 +380,12 @@ __device__ void walk_tile(const DevMap& m, const float* __restrict__ origin, con
         cas_clamp_add(m.occ + (k >> 1), agg_val[h] * ((k & 1u) ? m.l_hit : m.l_miss), m.l_min, m.l_max);
     }
   }
-  flush_tile_stats(m, t, n_hit, n_upd, n_drop);
+  // every voxel a ray visits is an update unless dropped; a ray that ends
+  // inside the map and is not truncated ends in its hit (modulo-2^32 sums:
+  // only the block total matters)
+  const uint32_t ray_voxels = t.ok ? t.voxels : 0u;
+  const uint32_t ray_hit = (t.ok && !t.clipped && !t.r.truncated) ? 1u : 0u;
+  flush_tile_stats(m, t, ray_hit - n_hit_drop, ray_voxels - n_drop, n_drop);
 }
 
 }  // namespace ohm

@@ -6,10 +6,10 @@ Headline workload (one "step"): the 100-scan spinning-lidar sequence -- 64 beams
 4 x 3 m box tunnel with 200 random boxes, 30 m max range -- integrated scan by
 scan into a 0.1 m occupancy map of 32^3-voxel regions over 200 x 200 x 40 m.
 Inputs are generated once (seeded) and stay resident in HBM; a step is one
-ohm_integrate_rays call over all 100 scans on a map with 8-scan groups (the
-voxel walk with its atomic updates over 8 scans per launch, then the in-order
-per-scan clamp of the group); the same call on a map that launches once per
-scan is timed beside it.
+ohm_integrate_rays call over all 100 scans on a map with scan groups of G
+(default 32) accumulator slots (the voxel walk with its atomic updates over G
+scans per launch, then the in-order per-scan clamp of the group); the same
+call on a map that launches once per scan is timed beside it.
 
 Reported alongside: the per-update (CAS) mode, NDT-OM integration of the
 same scans, the adjoint on the 20-scan 0.2 m workload, and the batched
@@ -350,6 +350,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--scans", type=int, default=100)
     ap.add_argument("--capacity", type=int, default=512)
+    ap.add_argument("--scan-group-slots", type=int, default=32,
+                    help="accumulator slots of the headline map (scans walked per launch)")
     ap.add_argument("--cpu-scans", type=int, default=100)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-per-update", action="store_true")
@@ -385,8 +387,9 @@ def main():
 
     single = run_gpu(args, params, batch, ohm.MODE_COUNT_CLAMP)
     log(f"count mode, one launch per scan: {single['ms_per_step']:.3f} ms/step, kernels {single['kernels']}")
-    res = run_gpu(args, params, batch, ohm.MODE_COUNT_CLAMP, ohm.LAYER_OCC | ohm.LAYER_SCAN_GROUPS)
-    log(f"count mode, 8-scan groups: {res['ms_per_step']:.3f} ms/step, kernels {res['kernels']}")
+    res = run_gpu(args, params, batch, ohm.MODE_COUNT_CLAMP,
+                  ohm.LAYER_OCC | ohm.LAYER_SCAN_GROUPS | ohm.scan_group_slots(args.scan_group_slots))
+    log(f"count mode, {args.scan_group_slots}-scan groups: {res['ms_per_step']:.3f} ms/step, kernels {res['kernels']}")
     per_update = None
     if not args.no_per_update:
         pu = run_gpu(args, params, batch, ohm.MODE_PER_UPDATE)
@@ -418,7 +421,7 @@ def main():
         "unit": "GB/s",
         "frac": round(achieved / HBM_PEAK_GBS, 4),
         "traffic": measured_traffic("walk_group_kernel"),
-        "kernel": "walk_group_kernel (count mode, 8 scans per launch)",
+        "kernel": f"walk_group_kernel (count mode, up to {args.scan_group_slots} scans per launch)",
         "kernel_avg_ms": round(walk_avg_ms, 5),
         "scans_per_launch": round(scans_per_launch, 3),
         "bytes_per_launch": launch_bytes,
@@ -488,7 +491,7 @@ def main():
             "workload": f"{scans} spinning-lidar scans x {int(rays_per_scan)} rays (64x2048), tunnel scene, "
                         "0.1 m voxels, 32^3 regions over 200x200x40 m, 30 m max range",
             "mode": "count_clamp",
-            "scan_groups": 8,
+            "scan_groups": args.scan_group_slots,
             "n_scans": scans,
             "rays_per_scan": int(rays_per_scan),
         },

@@ -84,10 +84,15 @@ enum {
   OHM_LAYER_OCC = 1,         /* always present */
   OHM_LAYER_NDT = 2,         /* NDT-OM sample count, mean and covariance */
   OHM_LAYER_ADJOINT = 4,     /* last scan at which the clamp was active */
-  OHM_LAYER_SCAN_GROUPS = 8  /* 8 accumulator slots: in count mode, ohm_integrate_rays walks up
-                                to 8 consecutive scans of a call in one launch (each into its
-                                own slot, finalized in scan order: the same result) */
+  OHM_LAYER_SCAN_GROUPS = 8  /* G accumulator slots (default 8): in count mode, ohm_integrate_rays
+                                walks up to G consecutive scans of a call in one launch (each
+                                into its own slot, finalized in scan order: the same result).
+                                Each slot costs 256 KiB per region of capacity. */
 };
+
+/* Slot count of OHM_LAYER_SCAN_GROUPS, or-ed into the layer mask: n in [1, 32]
+ * (0: the default 8).  Only valid together with OHM_LAYER_SCAN_GROUPS. */
+#define OHM_SCAN_GROUP_SLOTS(n) ((uint32_t)(n) << 8)
 
 /* Quantities readable with ohm_map_read_dense (output element type). */
 enum {
@@ -136,7 +141,8 @@ typedef struct {
 } ohm_map_stats;
 
 /* Bytes of device workspace a map needs.  region_capacity is the number of
- * 32^3 regions the map can hold; layers is an OHM_LAYER_* mask. */
+ * 32^3 regions the map can hold; layers is an OHM_LAYER_* mask, optionally
+ * with OHM_SCAN_GROUP_SLOTS(n). */
 ohm_status ohm_map_workspace_size(const ohm_params* params, uint32_t region_capacity, uint32_t layers,
                                   size_t* bytes);
 

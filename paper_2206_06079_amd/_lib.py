@@ -22,6 +22,12 @@ LAYER_NDT = 2
 LAYER_ADJOINT = 4
 LAYER_SCAN_GROUPS = 8
 
+
+def scan_group_slots(n: int) -> int:
+    """Layer-mask bits asking for n accumulator slots (OHM_SCAN_GROUP_SLOTS)."""
+    return (int(n) & 0xFF) << 8
+
+
 READ_OCC = 0
 READ_HITS = 1
 READ_MISSES = 2

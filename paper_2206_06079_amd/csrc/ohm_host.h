@@ -14,6 +14,7 @@ struct ohm_map_s {
   ohm_params params;
   ohm::DevMap dm;
   uint32_t layers;
+  uint32_t group_slots;  // accumulator slots (1 without OHM_LAYER_SCAN_GROUPS)
   size_t regions;
   void* workspace;
   size_t workspace_bytes;
@@ -43,7 +44,17 @@ struct ohm_map_s {
 namespace ohm {
 
 constexpr int kFinalizeBlocks = 2048;
-constexpr uint32_t kGroupSlots = 8;  // accumulator slots of OHM_LAYER_SCAN_GROUPS
+constexpr uint32_t kGroupSlots = 8;      // default accumulator slots of OHM_LAYER_SCAN_GROUPS
+constexpr uint32_t kMaxGroupSlots = 32;  // most slots a map may ask for
+
+// Accumulator slots a layer mask asks for: 1 without OHM_LAYER_SCAN_GROUPS,
+// 0 when the mask is invalid.
+inline uint32_t group_slots_of(uint32_t layers) {
+  const uint32_t n = (layers >> 8) & 0xffu;
+  if (!(layers & OHM_LAYER_SCAN_GROUPS)) return n ? 0u : 1u;
+  if (n == 0) return kGroupSlots;
+  return n <= kMaxGroupSlots ? n : 0u;
+}
 constexpr int kDefaultSegMajorSteps = 32;
 constexpr uint32_t kDefaultTileThreads = 512;
 

@@ -141,17 +141,17 @@ __global__ __launch_bounds__(256) void finalize_kernel(DevMap m, uint32_t parity
     __hip_atomic_store(m.hdr + kHdrTouched0 + (parity ^ 1u), 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-// Grouped scans (OHM_LAYER_SCAN_GROUPS): up to kGroupSlots consecutive scans
+// Grouped scans (OHM_LAYER_SCAN_GROUPS): up to G (the map's slots) consecutive scans
 // of a call walk in one launch, scan j of the group into accumulator slot j
 // under one tag, and group_finalize_kernel applies them per voxel in scan
 // order.  More tiles per launch keep the whole device busy: one scan's
 // tiles alone leave most compute units idle behind its longest tiles.
 struct GroupArgs {
   uint32_t count;                  // scans in the group
-  uint32_t scan[kGroupSlots];      // scan index within the call
-  uint32_t r0[kGroupSlots];        // first ray
-  uint32_t n[kGroupSlots];         // rays
-  uint32_t tile_end[kGroupSlots];  // exclusive end of the scan's blocks
+  uint32_t scan[kMaxGroupSlots];      // scan index within the call
+  uint32_t r0[kMaxGroupSlots];        // first ray
+  uint32_t n[kMaxGroupSlots];         // rays
+  uint32_t tile_end[kMaxGroupSlots];  // exclusive end of the scan's blocks
 };
 
 template <bool kWeighted>
@@ -289,8 +289,11 @@ ohm_status compute_layout(const ohm_params* p, uint32_t capacity, uint32_t layer
   ohm_status s = validate_params(p);
   if (s != OHM_OK) return s;
   if (capacity == 0 || capacity > kMaxCapacity) return OHM_E_INVALID_ARG;
-  if (layers & ~(uint32_t)(OHM_LAYER_OCC | OHM_LAYER_NDT | OHM_LAYER_ADJOINT | OHM_LAYER_SCAN_GROUPS))
+  if (layers & ~(uint32_t)(OHM_LAYER_OCC | OHM_LAYER_NDT | OHM_LAYER_ADJOINT | OHM_LAYER_SCAN_GROUPS |
+                           OHM_SCAN_GROUP_SLOTS(0xff)))
     return OHM_E_INVALID_ARG;
+  const uint32_t slots = group_slots_of(layers);
+  if (slots == 0) return OHM_E_INVALID_ARG;
   size_t regions = 1;
   for (int a = 0; a < 3; ++a) {
     L->rlo[a] = p->key_min[a] >> kRegionLog2;
@@ -315,7 +318,7 @@ ohm_status compute_layout(const ohm_params* p, uint32_t capacity, uint32_t layer
   L->occ = off;
   off = align_up(off + (size_t)capacity * V * sizeof(float));
   L->acc = off;
-  off = align_up(off + (size_t)capacity * V * 2 * sizeof(float) * ((layers & OHM_LAYER_SCAN_GROUPS) ? kGroupSlots : 1));
+  off = align_up(off + (size_t)capacity * V * 2 * sizeof(float) * slots);
   L->ndt = L->nacc = L->mom = L->clampscan = 0;
   if (layers & OHM_LAYER_NDT) {
     L->ndt = off;
@@ -382,7 +385,7 @@ ohm_status map_initialise(ohm_map_s* map, hipStream_t st) {
   uint32_t init_bits;
   memcpy(&init_bits, &m.l_init, sizeof(init_bits));
   launch_fill(m.occ, (size_t)m.capacity * V * sizeof(float), init_bits, st);
-  launch_fill(m.acc, (size_t)m.capacity * V * 2 * sizeof(float) * ((map->layers & OHM_LAYER_SCAN_GROUPS) ? kGroupSlots : 1),
+  launch_fill(m.acc, (size_t)m.capacity * V * 2 * sizeof(float) * map->group_slots,
               0u, st);
   if (m.ndt) {
     launch_fill(m.ndt, (size_t)m.capacity * V * sizeof(NdtVoxel), 0u, st);
@@ -493,6 +496,7 @@ ohm_status ohm_map_create(const ohm_params* params, uint32_t region_capacity, ui
   if (!map) return OHM_E_INVALID_ARG;
   map->params = *params;
   map->layers = layers | OHM_LAYER_OCC;
+  map->group_slots = group_slots_of(layers);
   map->seg_major_steps = kDefaultSegMajorSteps;
   map->walk_threads = kDefaultTileThreads;
   map->order_hist = map->order_sums = map->order_perm = nullptr;
@@ -572,7 +576,7 @@ ohm_status ohm_integrate_rays(ohm_map map, const float* d_origins, const float* 
     if (h_scan_offsets[sc + 1] > h_scan_offsets[sc]) last = sc;
   uint32_t first = 0;  // scans before `first` went through grouped launches
   if (count_mode && (map->layers & OHM_LAYER_SCAN_GROUPS) && map->order_max_rays == 0 && last < n_scans) {
-    // groups of up to kGroupSlots non-empty scans before the last one (which
+    // groups of up to G non-empty scans before the last one (which
     // takes the single-scan path below, so its counts stay readable)
     const uint32_t threads = map->walk_threads;
     const int K = map->seg_major_steps;
@@ -580,7 +584,7 @@ ohm_status ohm_integrate_rays(ohm_map map, const float* d_origins, const float* 
     while (sc < last) {
       GroupArgs g = {};
       uint32_t tiles = 0;
-      for (; sc < last && g.count < kGroupSlots; ++sc) {
+      for (; sc < last && g.count < map->group_slots; ++sc) {
         const uint32_t r0 = h_scan_offsets[sc];
         const uint32_t n = h_scan_offsets[sc + 1] - r0;
         if (n == 0) continue;

@@ -40,6 +40,19 @@ def test_grouped_config1_equals_oracle(n_scans):
     assert st["updates_dropped_pool"] == 0
 
 
+@pytest.mark.parametrize("slots", [1, 3, 16, 32])
+def test_grouped_slot_counts(slots):
+    """Maps with 1, 3, 16 or 32 slots (OHM_SCAN_GROUP_SLOTS): 20 scans in
+    groups of that size, the same result."""
+    mp, batch = scenes.config1(n_scans=20, first_scan=60)
+    layers = GROUPED | ohm.scan_group_slots(slots)
+    occ, hits, miss, st = gpu_integrate(mp, batch, 1024, CFG1_BOX_MIN, CFG1_BOX_DIM, layers=layers)
+    o_occ, o_hit, o_miss, o_st = oracle.integrate_count(mp, batch, CFG1_BOX_MIN, CFG1_BOX_DIM)
+    assert np.array_equal(occ, o_occ)
+    assert np.array_equal(hits, o_hit) and np.array_equal(miss, o_miss)
+    assert st["voxel_updates"] == o_st["updates"]
+
+
 def test_grouped_empty_scans_and_several_calls():
     """Empty scans anywhere in a call, calls of different lengths in a row
     (the previous call's kept counts are cleared before the next group)."""

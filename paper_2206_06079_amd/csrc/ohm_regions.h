@@ -237,7 +237,11 @@ __device__ __forceinline__ void flush_stats(const DevMap& m, const uint32_t (&va
   uint32_t lane = lane_id();
 #pragma unroll
   for (int c = 0; c < kStatCount; ++c) {
-    uint32_t s = wave_sum_u32(vals[c]);
+    // most counters are per-ray flags: a ballot count replaces the butterfly
+    // sum, and counters that are zero across the wave cost one ballot
+    const unsigned long long nz = __ballot(vals[c] != 0u);
+    if (nz == 0ull) continue;
+    const uint32_t s = __ballot(vals[c] > 1u) == 0ull ? (uint32_t)__popcll(nz) : wave_sum_u32(vals[c]);
     if (lane == 0 && s) atomicAdd(&part[c], s);
   }
   __syncthreads();

@@ -407,11 +407,12 @@ def main():
     scans = args.scans
     rays_per_scan = res["rays_per_step"] / scans
     upd_per_scan = res["updates_per_step"] / scans
-    # dominant kernel: the group walk, which walks every scan but the last of
-    # a call (the last goes through walk_seg_kernel so its counts stay readable)
+    # dominant kernel: the group walk (scans that took the single-scan walk
+    # instead, if any, are not its work)
     n_walk, ms_walk = res["kernels"].get("walk_group", (0, 0.0))
     walk_avg_ms = ms_walk / max(1, n_walk)
-    scans_per_launch = (scans - 1) * res["steps"] / max(1, n_walk)
+    single_scans = res["kernels"].get("walk", (0, 0.0))[0] / res["steps"]
+    scans_per_launch = (scans - single_scans) * res["steps"] / max(1, n_walk)
     launch_bytes = walk_bytes(rays_per_scan * scans_per_launch, upd_per_scan * scans_per_launch, scans_per_launch)
     achieved = launch_bytes / (walk_avg_ms * 1e-3) / 1e9
     roofline = {

@@ -23,6 +23,7 @@ struct ohm_map_s {
   uint32_t scans_done;     // scans integrated since create / reset
   bool acc_dirty;          // the last count-mode scan's accumulators are still set
   uint32_t last_parity;
+  uint32_t kept_slot;      // accumulator slot holding those counts (scan groups), else 0
   int seg_major_steps;     // walk tuning (ohm_map_set_tuning)
   uint32_t walk_threads;
   // direction ordering of scans (ohm_map_set_ray_order): caller scratch

@@ -170,9 +170,10 @@ __global__ __launch_bounds__(1024) void walk_group_kernel(DevMap m, const float*
 
 // Apply the group's g scans in order to every voxel of the regions the group
 // touched: l = clamp((l + H_j l_hit) + M_j l_miss) for j = 0..g-1, recording
-// the clamp scan (scan_tag0 + j), and clear the slots.
+// the clamp scan (scan_tag0 + j), and clear the slots except slot `keep`
+// (the call's last scan, whose counts stay readable; keep >= g keeps none).
 __global__ __launch_bounds__(256) void group_finalize_kernel(DevMap m, uint32_t parity, uint32_t g,
-                                                             uint32_t scan_tag0) {
+                                                             uint32_t scan_tag0, uint32_t keep) {
   const uint32_t count = __hip_atomic_load(m.hdr + kHdrTouched0 + parity, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   const uint32_t units = count * kFinalUnits;
   const size_t stride = (size_t)m.capacity * kRegionVoxels;  // float2 elements per slot
@@ -193,7 +194,7 @@ __global__ __launch_bounds__(256) void group_finalize_kernel(DevMap m, uint32_t 
         sum = __fadd_rn(sum, uu);
         if (m.clampscan && (sum < m.l_min || sum > m.l_max)) m.clampscan[vi] = scan_tag0 + j;
         l = fminf(fmaxf(sum, m.l_min), m.l_max);
-        *ap = make_float2(0.f, 0.f);
+        if (j != keep) *ap = make_float2(0.f, 0.f);
         any = true;
       }
       if (any) m.occ[vi] = l;
@@ -395,6 +396,7 @@ ohm_status map_initialise(ohm_map_s* map, hipStream_t st) {
   if (m.clampscan) launch_fill(m.clampscan, (size_t)m.capacity * V * sizeof(uint32_t), 0u, st);
   map->count_batches = 0;
   map->acc_dirty = false;
+  map->kept_slot = 0;
   map->scans_done = 0;
   return last_hip_status();
 }
@@ -441,13 +443,22 @@ ProfScope::~ProfScope() {
   (void)kind_;
 }
 
+// The map's device view with `acc` at the slot that holds the last
+// count-mode scan's counts.
+DevMap kept_counts(const ohm_map_s* map) {
+  DevMap m = map->dm;
+  m.acc += (size_t)map->kept_slot * m.capacity * kRegionVoxels * 2;
+  return m;
+}
+
 // Lazy clear of the previous count-mode scan's accumulators.
 void clear_pending(ohm_map_s* map, hipStream_t st) {
   if (!map->acc_dirty) return;
   ProfScope ps(map, OHM_KERNEL_FINALIZE, st);
-  hipLaunchKernelGGL(finalize_kernel, dim3(kFinalizeBlocks), dim3(256), 0, st, map->dm, map->last_parity, 0, 1, 0,
-                     0u);
+  hipLaunchKernelGGL(finalize_kernel, dim3(kFinalizeBlocks), dim3(256), 0, st, kept_counts(map), map->last_parity,
+                     0, 1, 0, 0u);
   map->acc_dirty = false;
+  map->kept_slot = 0;
 }
 
 }  // namespace ohm
@@ -576,15 +587,15 @@ ohm_status ohm_integrate_rays(ohm_map map, const float* d_origins, const float* 
     if (h_scan_offsets[sc + 1] > h_scan_offsets[sc]) last = sc;
   uint32_t first = 0;  // scans before `first` went through grouped launches
   if (count_mode && (map->layers & OHM_LAYER_SCAN_GROUPS) && map->order_max_rays == 0 && last < n_scans) {
-    // groups of up to G non-empty scans before the last one (which
-    // takes the single-scan path below, so its counts stay readable)
+    // groups of up to G non-empty scans; the group holding the last one
+    // keeps its counts readable in that scan's slot
     const uint32_t threads = map->walk_threads;
     const int K = map->seg_major_steps;
     uint32_t sc = 0;
-    while (sc < last) {
+    while (sc <= last) {
       GroupArgs g = {};
       uint32_t tiles = 0;
-      for (; sc < last && g.count < map->group_slots; ++sc) {
+      for (; sc <= last && g.count < map->group_slots; ++sc) {
         const uint32_t r0 = h_scan_offsets[sc];
         const uint32_t n = h_scan_offsets[sc + 1] - r0;
         if (n == 0) continue;
@@ -608,14 +619,21 @@ ohm_status ohm_integrate_rays(ohm_map map, const float* d_origins, const float* 
           hipLaunchKernelGGL(walk_group_kernel<false>, dim3(tiles), dim3(threads), 0, st, map->dm, d_origins,
                              d_samples, d_weights, g, K, tag, parity);
       }
+      const bool has_last = g.scan[g.count - 1] == last;
+      const uint32_t keep = has_last ? g.count - 1 : kMaxGroupSlots;
       {
         ProfScope ps(map, OHM_KERNEL_FINALIZE_GROUP, st);
         hipLaunchKernelGGL(group_finalize_kernel, dim3(kFinalizeBlocks), dim3(256), 0, st, map->dm, parity, g.count,
-                           map->scans_done + 1);
+                           map->scans_done + 1, keep);
       }
       map->scans_done += g.count;
+      if (has_last) {
+        map->acc_dirty = true;
+        map->last_parity = parity;
+        map->kept_slot = keep;
+      }
     }
-    first = last;
+    first = n_scans;
   }
   for (uint32_t sc = first; sc < n_scans; ++sc) {
     const uint32_t r0 = h_scan_offsets[sc];
@@ -694,7 +712,7 @@ ohm_status ohm_map_read_dense(ohm_map map, int32_t what, const int32_t h_box_min
   const size_t n = (size_t)h_box_dim[0] * h_box_dim[1] * h_box_dim[2];
   const size_t blocks = (n + 255) / 256;
   if (blocks > 0x7fffffff) return OHM_E_INVALID_ARG;
-  hipLaunchKernelGGL(read_dense_kernel, dim3((unsigned)blocks), dim3(256), 0, as_stream(stream), map->dm, what,
+  hipLaunchKernelGGL(read_dense_kernel, dim3((unsigned)blocks), dim3(256), 0, as_stream(stream), kept_counts(map), what,
                      h_box_min[0], h_box_min[1], h_box_min[2], h_box_dim[0], h_box_dim[1], h_box_dim[2], d_out);
   return last_hip_status();
 }

@@ -138,3 +138,37 @@ def test_grouped_ordering_scratch_takes_single_scan_path():
     m.close()
     o_occ, _, _, _ = oracle.integrate_count(mp, batch, CFG1_BOX_MIN, CFG1_BOX_DIM)
     assert np.array_equal(occ, o_occ)
+
+
+def test_grouped_pool_exhaustion_is_reported_and_bounded():
+    """A region pool too small for the call: grouped walks drop what does not
+    fit, count it, set the sticky flag, and stay a valid count-mode result."""
+    mp, batch = scenes.config1(n_scans=6, first_scan=0)
+    occ, hits, miss, st = gpu_integrate(mp, batch, 12, CFG1_BOX_MIN, CFG1_BOX_DIM,
+                                        layers=GROUPED | ohm.scan_group_slots(4))
+    assert st["sticky_error"] & 1
+    assert st["regions_used"] == 12
+    assert st["updates_dropped_pool"] > 0
+    _, _, _, o_st = oracle.integrate_count(mp, batch, CFG1_BOX_MIN, CFG1_BOX_DIM)
+    assert st["voxel_updates"] + st["updates_dropped_pool"] == o_st["updates"]
+    assert occ.min() >= mp.l_min and occ.max() <= mp.l_max
+
+
+def test_scan_groups_leave_other_modes_alone():
+    """Per-update mode and NDT integration on a map with the layer walk scan
+    by scan: per-update values stay inside the oracle's any-order bracket,
+    and the update counts match the oracle."""
+    mp, batch = scenes.config1(n_scans=3, first_scan=20)
+    pu = mp.replace(mode=ohm.MODE_PER_UPDATE)
+    occ, _, _, st = gpu_integrate(pu, batch, 1024, CFG1_BOX_MIN, CFG1_BOX_DIM, layers=GROUPED)
+    lo, hi, nupd, o_st = oracle.integrate_envelope(pu, batch, CFG1_BOX_MIN, CFG1_BOX_DIM)
+    tol = nupd.astype(np.float64) * 2.0 ** -22 + 1e-6
+    assert np.all(occ >= lo - tol) and np.all(occ <= hi + tol)
+    assert st["voxel_updates"] == o_st["updates"]
+    m = ohm.OhmMap(mp, 1024, layers=GROUPED | ohm.LAYER_NDT, device=device())
+    o, s, off, w = to_dev(batch)
+    m.ndt_integrate(o, s, off, w)
+    st = m.stats()
+    m.close()
+    _, _, _, n_st = oracle.ndt_integrate(mp, batch, CFG1_BOX_MIN, CFG1_BOX_DIM)
+    assert st["voxel_updates"] == n_st["updates"]

@@ -7,7 +7,7 @@ Headline workload (one "step"): the 100-scan spinning-lidar sequence -- 64 beams
 scan into a 0.1 m occupancy map of 32^3-voxel regions over 200 x 200 x 40 m.
 Inputs are generated once (seeded) and stay resident in HBM; a step is one
 ohm_integrate_rays call over all 100 scans on a map with scan groups of G
-(default 32) accumulator slots (the voxel walk with its atomic updates over G
+(default 50) accumulator slots (the voxel walk with its atomic updates over G
 scans per launch, then the in-order per-scan clamp of the group); the same
 call on a map that launches once per scan is timed beside it.
 
@@ -350,7 +350,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--scans", type=int, default=100)
     ap.add_argument("--capacity", type=int, default=512)
-    ap.add_argument("--scan-group-slots", type=int, default=32,
+    ap.add_argument("--scan-group-slots", type=int, default=50,
                     help="accumulator slots of the headline map (scans walked per launch)")
     ap.add_argument("--cpu-scans", type=int, default=100)
     ap.add_argument("--no-cpu-baseline", action="store_true")

@@ -90,7 +90,7 @@ enum {
                                 Each slot costs 256 KiB per region of capacity. */
 };
 
-/* Slot count of OHM_LAYER_SCAN_GROUPS, or-ed into the layer mask: n in [1, 32]
+/* Slot count of OHM_LAYER_SCAN_GROUPS, or-ed into the layer mask: n in [1, 64]
  * (0: the default 8).  Only valid together with OHM_LAYER_SCAN_GROUPS. */
 #define OHM_SCAN_GROUP_SLOTS(n) ((uint32_t)(n) << 8)
 

@@ -46,7 +46,7 @@ namespace ohm {
 
 constexpr int kFinalizeBlocks = 2048;
 constexpr uint32_t kGroupSlots = 8;      // default accumulator slots of OHM_LAYER_SCAN_GROUPS
-constexpr uint32_t kMaxGroupSlots = 32;  // most slots a map may ask for
+constexpr uint32_t kMaxGroupSlots = 64;  // most slots a map may ask for
 
 // Accumulator slots a layer mask asks for: 1 without OHM_LAYER_SCAN_GROUPS,
 // 0 when the mask is invalid.

@@ -85,19 +85,19 @@ def test_workspace_size_and_validation():
 
 def test_scan_group_slots_in_the_layer_mask():
     """OHM_LAYER_SCAN_GROUPS adds G - 1 accumulator slots of 256 KiB per
-    region of capacity (default G = 8, OHM_SCAN_GROUP_SLOTS(n) for 1..32);
-    slot bits without the layer, or more than 32 slots, are rejected."""
+    region of capacity (default G = 8, OHM_SCAN_GROUP_SLOTS(n) for 1..64);
+    slot bits without the layer, or more than 64 slots, are rejected."""
     mp, _ = scenes.config0()
     slot = 343 * 32768 * 8
     st, plain = _size(mp, 343)
     assert st == _lib.OHM_OK
     g = _lib.LAYER_SCAN_GROUPS
     for layers, slots in ((g, 8), (g | ohm.scan_group_slots(8), 8), (g | ohm.scan_group_slots(1), 1),
-                          (g | ohm.scan_group_slots(16), 16), (g | ohm.scan_group_slots(32), 32)):
+                          (g | ohm.scan_group_slots(16), 16), (g | ohm.scan_group_slots(64), 64)):
         st, b = _size(mp, 343, layers)
         assert st == _lib.OHM_OK, layers
         assert b - plain == (slots - 1) * slot, (layers, b - plain)
-    for layers in (ohm.scan_group_slots(8), g | ohm.scan_group_slots(33), g | ohm.scan_group_slots(255)):
+    for layers in (ohm.scan_group_slots(8), g | ohm.scan_group_slots(65), g | ohm.scan_group_slots(255)):
         assert _size(mp, 343, layers)[0] == _lib.OHM_E_INVALID_ARG, layers
 
 

@@ -40,9 +40,9 @@ def test_grouped_config1_equals_oracle(n_scans):
     assert st["updates_dropped_pool"] == 0
 
 
-@pytest.mark.parametrize("slots", [1, 3, 16, 32])
+@pytest.mark.parametrize("slots", [1, 3, 16, 64])
 def test_grouped_slot_counts(slots):
-    """Maps with 1, 3, 16 or 32 slots (OHM_SCAN_GROUP_SLOTS): 20 scans in
+    """Maps with 1, 3, 16 or 64 slots (OHM_SCAN_GROUP_SLOTS): 20 scans in
     groups of that size, the same result."""
     mp, batch = scenes.config1(n_scans=20, first_scan=60)
     layers = GROUPED | ohm.scan_group_slots(slots)

@@ -123,6 +123,41 @@ __device__ __forceinline__ void ndt_apply(const DevMap& m, uint32_t id, long lon
   }
 }
 
+// A sample-weighted miss deferred to a full-wave batch: the fp64 Gaussian
+// weight costs hundreds of instructions, and a wave that evaluated it for
+// the few lanes needing it at each step would run it at a few percent lane
+// occupancy.  Each wave queues such misses in LDS and evaluates 64 at once.
+struct NdtPending {
+  uint32_t id;     // update id (voxel << 1, a miss)
+  int32_t k[3];    // voxel key
+  uint32_t ray_t;  // tile-local ray
+};
+
+template <bool kCount, bool kWeighted>
+__device__ __forceinline__ void ndt_drain(const DevMap& m, const NdtPending* pend, uint32_t n, uint32_t lane,
+                                          const double od[3], const double (*ray_end)[kTileRays], const TileRays& tr,
+                                          const float* __restrict__ weights, uint32_t r0, double sig_miss,
+                                          uint32_t* agg_key, unsigned long long* agg_val) {
+#pragma clang fp contract(off)
+  __threadfence_block();  // the queue was written by other lanes of this wave
+  if (lane < n) {
+    const NdtPending e = pend[lane];
+    double dv[3];
+    double dd = 0.0;
+    for (int a = 0; a < 3; ++a) {
+      dv[a] = ray_end[a][e.ray_t] - od[a];
+      dd = dd + dv[a] * dv[a];
+    }
+    const double wt = kWeighted ? (double)weights[(size_t)r0 + tr.src[e.ray_t]] : 1.0;
+    const NdtVoxel nv = m.ndt[e.id >> 1];
+    const double c[3] = {m.origin[0] + ((double)e.k[0] + 0.5) * m.voxel_size,
+                         m.origin[1] + ((double)e.k[1] + 0.5) * m.voxel_size,
+                         m.origin[2] + ((double)e.k[2] + 0.5) * m.voxel_size};
+    const long long q = llrint(ndt_delta(m, od, dv, dd, c, nv, sig_miss) * wt * kQ);
+    if (!ndt_agg_add(agg_key, agg_val, e.id, q)) ndt_apply<kCount>(m, e.id, q);
+  }
+}
+
 template <bool kCount, bool kWeighted>
 __global__ __launch_bounds__(kNdtMaxThreads) void ndt_seg_kernel(DevMap m, const float* __restrict__ origins, uint32_t scan,
                                                        const float* __restrict__ samples,
@@ -134,6 +169,7 @@ __global__ __launch_bounds__(kNdtMaxThreads) void ndt_seg_kernel(DevMap m, const
   __shared__ double ray_end[3][kTileRays];  // world end point after truncation
   __shared__ uint32_t agg_key[kNdtAggSize];
   __shared__ unsigned long long agg_val[kNdtAggSize];
+  __shared__ NdtPending pend[kNdtMaxThreads / 64][64];
   const uint32_t tid = threadIdx.x;
   const uint32_t lane = lane_id();
   const uint32_t tile0 = blockIdx.x * kTileRays;
@@ -151,6 +187,8 @@ __global__ __launch_bounds__(kNdtMaxThreads) void ndt_seg_kernel(DevMap m, const
   __syncthreads();
   const double od[3] = {(double)origin[0], (double)origin[1], (double)origin[2]};
   uint32_t n_upd = 0, n_drop = 0, n_hit = 0;
+  uint32_t pend_n = 0;  // this wave's queued sample-weighted misses (wave-uniform)
+  NdtPending* wpend = pend[tid >> 6];
 
   const uint32_t rounds = (items + blockDim.x - 1) / blockDim.x;
   for (uint32_t round = 0; round < rounds; ++round) {
@@ -189,20 +227,15 @@ __global__ __launch_bounds__(kNdtMaxThreads) void ndt_seg_kernel(DevMap m, const
       const size_t v = has ? (size_t)slot * kRegionVoxels + lidx : 0;
       const int32_t k0 = s.k[0], k1 = s.k[1], k2 = s.k[2];  // this voxel (the walk steps on below)
       long long q = 0;
-      bool weighted_miss = false;  // a miss whose increment the voxel's samples weight
+      // a miss whose increment the voxel's samples weight: queued, see NdtPending
+      bool deferred = false;
       if (has) {
         if (is_hit) {
           q = llrint(wt * kQ);
+        } else if (cnt >= m.ndt_min_samples) {
+          deferred = true;
         } else {
           q = q_plain;
-          if (cnt >= m.ndt_min_samples) {
-            weighted_miss = true;
-            const NdtVoxel nv = m.ndt[v];
-            const double c[3] = {m.origin[0] + ((double)k0 + 0.5) * m.voxel_size,
-                                 m.origin[1] + ((double)k1 + 0.5) * m.voxel_size,
-                                 m.origin[2] + ((double)k2 + 0.5) * m.voxel_size};
-            q = llrint(ndt_delta(m, od, dv, dd, c, nv, sig_miss) * wt * kQ);
-          }
         }
       }
       const uint32_t id = has ? (((uint32_t)slot * (uint32_t)kRegionVoxels + lidx) << 1) | (is_hit ? 1u : 0u)
@@ -217,16 +250,38 @@ __global__ __launch_bounds__(kNdtMaxThreads) void ndt_seg_kernel(DevMap m, const
         alive = !last && tile_advance<true>(m, rc, rw, s, M, slot, lidx);
       }
       const uint32_t cnt_next = (alive && slot >= 0) ? m.ndt[(size_t)slot * kRegionVoxels + lidx].n : 0u;
+      const unsigned long long dmask = __ballot(deferred);
+      if (dmask) {
+        const uint32_t nd = (uint32_t)__popcll(dmask);
+        if (pend_n + nd > 64u) {
+          ndt_drain<kCount, kWeighted>(m, wpend, pend_n, lane, od, ray_end, tr, weights, r0, sig_miss, agg_key,
+                                       agg_val);
+          pend_n = 0;
+        }
+        if (deferred) {
+          const uint32_t rank = (uint32_t)__popcll(dmask & ((1ull << lane) - 1ull));
+          NdtPending e;
+          e.id = id;
+          e.k[0] = k0;
+          e.k[1] = k1;
+          e.k[2] = k2;
+          e.ray_t = ray_t;
+          wpend[pend_n + rank] = e;
+        }
+        pend_n += nd;
+      }
+      // runs are homogeneous (one voxel and kind: all deferred or none), so
+      // the deferred lanes' runs just emit nothing here
       const LaneRuns run = lane_runs(id, lane);
       long long qs;
       bool emit;
-      if (!kWeighted && __ballot(weighted_miss) == 0ull) {
+      if (!kWeighted) {
         // every increment of a run is the same (unit weight, plain miss or hit)
         qs = (long long)run.len * q;
-        emit = has && run.head;
+        emit = has && run.head && !deferred;
       } else {
         qs = segmented_sum(q, run.head, lane);
-        emit = has && run.tail;
+        emit = has && run.tail && !deferred;
       }
       if (emit && !ndt_agg_add(agg_key, agg_val, id, qs)) ndt_apply<kCount>(m, id, qs);
       if (has && is_hit) {
@@ -249,6 +304,8 @@ __global__ __launch_bounds__(kNdtMaxThreads) void ndt_seg_kernel(DevMap m, const
       cnt = cnt_next;
     }
   }
+  if (pend_n)
+    ndt_drain<kCount, kWeighted>(m, wpend, pend_n, lane, od, ray_end, tr, weights, r0, sig_miss, agg_key, agg_val);
   __syncthreads();
   for (uint32_t h = tid; h < kNdtAggSize; h += blockDim.x) {
     const uint32_t k = agg_key[h];

@@ -72,14 +72,17 @@ __device__ __forceinline__ double ndt_delta(const DevMap& m, const double o[3], 
 // Phase 1 over a tile of 256 rays, walked segment by segment (see
 // ohm_walk_seg.h): the same per-voxel work as the occupancy walk, with the
 // NDT-weighted miss increment and the hit's sample moments.
-constexpr uint32_t kNdtMaxThreads = 512;  // keeps the kernel within its registers
+// Two 512-thread blocks per CU (four waves per SIMD): the kernel is held to
+// 128 VGPRs (the cold fp64 path of the queued misses spills) and the LDS
+// table below to 2048 entries, so two blocks' LDS fit in a CU.
+constexpr uint32_t kNdtMaxThreads = 512;
 
 // Per-tile LDS table of the NDT walk's increments (see the occupancy walk's
 // table): update id -> summed Q32.32 increment, two probes, laid out by
 // 64-byte accumulator line (two voxels' miss and hit words: 4 ids per
 // group).  The sums are exact integers, so the result does not depend on how
 // updates reach the table.
-constexpr int kNdtAggLog2 = 12;
+constexpr int kNdtAggLog2 = 11;
 constexpr uint32_t kNdtAggSize = 1u << kNdtAggLog2;
 constexpr uint32_t kNdtAggLine = 4;
 
@@ -159,7 +162,7 @@ __device__ __forceinline__ void ndt_drain(const DevMap& m, const NdtPending* pen
 }
 
 template <bool kCount, bool kWeighted>
-__global__ __launch_bounds__(kNdtMaxThreads) void ndt_seg_kernel(DevMap m, const float* __restrict__ origins, uint32_t scan,
+__global__ __launch_bounds__(kNdtMaxThreads, 4) void ndt_seg_kernel(DevMap m, const float* __restrict__ origins, uint32_t scan,
                                                        const float* __restrict__ samples,
                                                        const float* __restrict__ weights, uint32_t r0, uint32_t n,
                                                        int K, uint32_t tag, uint32_t parity, double sig_miss) {

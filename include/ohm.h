@@ -172,7 +172,10 @@ ohm_status ohm_map_set_params(ohm_map map, const ohm_params* params);
  *                                       miss increments (NULL = 1)
  * Scans are applied in order; in count mode each scan is one batch with one
  * clamp per voxel.  In count mode the last scan's hit/miss weights remain
- * readable (OHM_READ_HITS / OHM_READ_MISSES) until the next call.
+ * readable (OHM_READ_HITS / OHM_READ_MISSES) until the next call.  On a map
+ * with OHM_LAYER_SCAN_GROUPS, count mode walks up to G consecutive scans of
+ * the call in one launch (unless ray-order scratch is attached) and applies
+ * them per voxel in scan order: the result is the same.
  */
 ohm_status ohm_integrate_rays(ohm_map map, const float* d_origins, const float* d_samples,
                               const uint32_t* h_scan_offsets, uint32_t n_scans, const float* d_weights,

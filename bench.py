@@ -360,11 +360,11 @@ def main():
     ap.add_argument("--no-adjoint", action="store_true")
     ap.add_argument("--batched-scans", type=int, default=1000)
     ap.add_argument("--batched-reps", type=int, default=3)
-    ap.add_argument("--batched-groups", type=lambda v: tuple(int(x) for x in v.split(",")), default=(4, 16))
+    ap.add_argument("--batched-groups", type=lambda v: tuple(int(x) for x in v.split(",")), default=(16, 64))
     ap.add_argument("--calibrate-copy-mb", type=int, default=0,
                     help="also run a plain device copy of this size (reference for HBM byte counters)")
     ap.add_argument("--batched-tiles", type=lambda v: tuple(tuple(int(y) for y in x.split("/")) for x in v.split(",")),
-                    default=((32, 512), (32, 1024)), help="walk tiles K/T,K/T,...")
+                    default=((32, 512),), help="walk tiles K/T,K/T,...")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "

@@ -90,11 +90,49 @@ __device__ void ndt_terms(const DevMap& m, const double o[3], const double d[3],
 
 constexpr uint32_t kBackwardMaxThreads = 512;  // keeps the kernel within its registers
 
+// A miss in a voxel with enough samples, whose fp64 NDT terms are evaluated
+// with 63 others by the whole wave instead of by the few lanes that meet one
+// at a given step.
+struct BwdPending {
+  uint32_t v;      // voxel index (slot * 32^3 + local)
+  int32_t k[3];    // voxel key
+  uint32_t ray_t;  // tile-local ray
+  float G;         // dL/dl of the voxel
+};
+
+__device__ __forceinline__ void bwd_drain(const DevMap& m, const BwdPending* pend, uint32_t n, uint32_t lane,
+                                          const double od[3], const double (*ray_end)[kTileRays], double* ray_gw,
+                                          const TileRays& tr, const float* __restrict__ weights, uint32_t r0,
+                                          double sig_miss, bool weighted, double& g_miss, double& g_sig) {
+#pragma clang fp contract(off)
+  __threadfence_block();  // the queue was written by other lanes of this wave
+  if (lane < n) {
+    const BwdPending e = pend[lane];
+    double dv[3];
+    double dd = 0.0;
+    for (int a = 0; a < 3; ++a) {
+      dv[a] = ray_end[a][e.ray_t] - od[a];
+      dd = dd + dv[a] * dv[a];
+    }
+    const double wt = weighted ? (double)weights[(size_t)r0 + tr.src[e.ray_t]] : 1.0;
+    const NdtVoxel nv = m.ndt[e.v];
+    const double c[3] = {m.origin[0] + ((double)e.k[0] + 0.5) * m.voxel_size,
+                         m.origin[1] + ((double)e.k[1] + 0.5) * m.voxel_size,
+                         m.origin[2] + ((double)e.k[2] + 0.5) * m.voxel_size};
+    double delta, dlm, dsg;
+    ndt_terms(m, od, dv, dd, c, nv, sig_miss, delta, dlm, dsg);
+    const double Gd = (double)e.G;
+    atomicAdd(&ray_gw[e.ray_t], Gd * delta);
+    g_miss += wt * Gd * dlm;
+    g_sig += wt * Gd * dsg;
+  }
+}
+
 // One tile of 256 rays, walked segment by segment (see ohm_walk_seg.h).  A
 // ray's weight gradient is the sum over its segments (fp64 LDS atomics);
 // the scalar gradients are reduced per block.
 template <bool kNdt, bool kWeighted>
-__global__ __launch_bounds__(kBackwardMaxThreads) void backward_seg_kernel(
+__global__ __launch_bounds__(kBackwardMaxThreads, 4) void backward_seg_kernel(
     DevMap m, GradBox gb, const float* __restrict__ origins, uint32_t scan, const float* __restrict__ samples,
     const float* __restrict__ weights, uint32_t r0, uint32_t n, int K, uint32_t tag, float* __restrict__ grad_w,
     double* __restrict__ grad_s, double sig_miss) {
@@ -103,6 +141,7 @@ __global__ __launch_bounds__(kBackwardMaxThreads) void backward_seg_kernel(
   __shared__ RegionCache rc;
   __shared__ double ray_end[3][kTileRays];
   __shared__ double ray_gw[kTileRays];
+  __shared__ BwdPending pend[kBackwardMaxThreads / 64][64];
   const uint32_t tid = threadIdx.x;
   const uint32_t tile0 = blockIdx.x * kTileRays;
   const float* origin = origins + 3 * (size_t)scan;
@@ -118,61 +157,91 @@ __global__ __launch_bounds__(kBackwardMaxThreads) void backward_seg_kernel(
   __syncthreads();
   const double od[3] = {(double)origin[0], (double)origin[1], (double)origin[2]};
   double g_hit = 0.0, g_miss = 0.0, g_sig = 0.0;
+  const uint32_t lane = lane_id();
+  BwdPending* wpend = pend[tid >> 6];
+  uint32_t pend_n = 0;  // this wave's queued sample-weighted misses (wave-uniform)
 
-  for (uint32_t it = tid; it < items; it += blockDim.x) {
+  // segment walks, one item per thread per round; the waves step in lockstep
+  // so that misses needing the fp64 NDT terms can be evaluated 64 at a time
+  const uint32_t rounds = (items + blockDim.x - 1) / blockDim.x;
+  for (uint32_t round = 0; round < rounds; ++round) {
+    const uint32_t it = round * blockDim.x + tid;
+    bool alive = it < items;
     uint32_t ray_t = 0;
     int M = 0;
-    SegState s;
-    if (!tile_item(m, tr, it, K, s, ray_t, M)) continue;
-    const bool trunc = tr.trunc[ray_t] != 0;
-    const double wt = kWeighted ? (double)weights[(size_t)r0 + tr.src[ray_t]] : 1.0;
-    double dv[3];
-    double dd = 0.0;
-    for (int a = 0; a < 3; ++a) {
-      dv[a] = ray_end[a][ray_t] - od[a];
-      dd = dd + dv[a] * dv[a];
+    SegState s = {};
+    bool trunc = false;
+    double wt = 1.0;
+    int32_t slot = -1;
+    uint32_t lidx = 0;
+    if (alive) {
+      alive = tile_item(m, tr, it, K, s, ray_t, M);
+      trunc = tr.trunc[ray_t] != 0;
+      if (kWeighted) wt = (double)weights[(size_t)r0 + tr.src[ray_t]];
+      slot = staged_slot(m, rc, rw, s.k[0], s.k[1], s.k[2]);
+      lidx = local_index(s.k[0], s.k[1], s.k[2]);
     }
-    int32_t slot = staged_slot(m, rc, rw, s.k[0], s.k[1], s.k[2]);
-    uint32_t lidx = local_index(s.k[0], s.k[1], s.k[2]);
     double gw = 0.0;
-    for (;;) {
-      const bool last = s.w.total == 0;
-      const bool is_hit = last && !trunc;
-      const float G = grad_at(gb, s.k[0], s.k[1], s.k[2]);
-      if (G != 0.f && slot >= 0) {
-        const size_t v = (size_t)slot * kRegionVoxels + lidx;
-        if (tag > m.clampscan[v]) {
-          const double Gd = (double)G;
-          if (is_hit) {
-            gw += Gd * (double)m.l_hit;
-            g_hit += wt * Gd;
-          } else {
-            double delta = m.l_miss, dlm = 1.0, dsg = 0.0;
-            if (kNdt) {
-              const NdtVoxel nv = m.ndt[v];
-              if (nv.n >= m.ndt_min_samples) {
-                const double c[3] = {m.origin[0] + ((double)s.k[0] + 0.5) * m.voxel_size,
-                                     m.origin[1] + ((double)s.k[1] + 0.5) * m.voxel_size,
-                                     m.origin[2] + ((double)s.k[2] + 0.5) * m.voxel_size};
-                ndt_terms(m, od, dv, dd, c, nv, sig_miss, delta, dlm, dsg);
-              }
+    while (__ballot(alive)) {
+      bool deferred = false;
+      float G = 0.f;
+      size_t v = 0;
+      const int32_t k0 = s.k[0], k1 = s.k[1], k2 = s.k[2];
+      bool last = false;
+      if (alive) {
+        last = s.w.total == 0;
+        const bool is_hit = last && !trunc;
+        G = grad_at(gb, k0, k1, k2);
+        if (G != 0.f && slot >= 0) {
+          v = (size_t)slot * kRegionVoxels + lidx;
+          if (tag > m.clampscan[v]) {
+            const double Gd = (double)G;
+            if (is_hit) {
+              gw += Gd * (double)m.l_hit;
+              g_hit += wt * Gd;
+            } else if (kNdt && m.ndt[v].n >= m.ndt_min_samples) {
+              deferred = true;
+            } else {
+              gw += Gd * (double)m.l_miss;
+              g_miss += wt * Gd;
             }
-            gw += Gd * delta;
-            g_miss += wt * Gd * dlm;
-            g_sig += wt * Gd * dsg;
           }
         }
+        alive = !last && tile_advance<true>(m, rc, rw, s, M, slot, lidx);
+        if (!alive && gw != 0.0) atomicAdd(&ray_gw[ray_t], gw);
       }
-      if (last || !tile_advance<true>(m, rc, rw, s, M, slot, lidx)) break;
+      if (kNdt) {
+        const unsigned long long dmask = __ballot(deferred);
+        if (dmask) {
+          const uint32_t nd = (uint32_t)__popcll(dmask);
+          if (pend_n + nd > 64u) {
+            bwd_drain(m, wpend, pend_n, lane, od, ray_end, ray_gw, tr, weights, r0, sig_miss, kWeighted, g_miss,
+                      g_sig);
+            pend_n = 0;
+          }
+          if (deferred) {
+            const uint32_t rank = (uint32_t)__popcll(dmask & ((1ull << lane) - 1ull));
+            BwdPending e;
+            e.v = (uint32_t)v;
+            e.k[0] = k0;
+            e.k[1] = k1;
+            e.k[2] = k2;
+            e.ray_t = ray_t;
+            e.G = G;
+            wpend[pend_n + rank] = e;
+          }
+          pend_n += nd;
+        }
+      }
     }
-    if (gw != 0.0) atomicAdd(&ray_gw[ray_t], gw);
   }
+  if (kNdt && pend_n)
+    bwd_drain(m, wpend, pend_n, lane, od, ray_end, ray_gw, tr, weights, r0, sig_miss, kWeighted, g_miss, g_sig);
   __syncthreads();
   if (t.inrange && grad_w) grad_w[(size_t)r0 + tr.src[tid]] = (float)ray_gw[tid];
   // block reduction of the scalar gradients, one fp64 atomic per block each
   __shared__ double part[3][kBackwardMaxThreads / 64];
   double vals[3] = {g_hit, g_miss, g_sig};
-  const uint32_t lane = lane_id();
   const uint32_t wave = tid >> 6;
 #pragma unroll
   for (int c = 0; c < 3; ++c) {

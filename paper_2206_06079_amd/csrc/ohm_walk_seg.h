@@ -371,13 +371,43 @@ __device__ void walk_tile(const DevMap& m, const float* __restrict__ origin, con
   if (kSink == kSinkTraceCount || kSink == kSinkTraceWrite) return;
   if (kAgg) {
     __syncthreads();
-    for (uint32_t h = tid; h < kAggSize; h += blockDim.x) {
-      const uint32_t k = agg_key[h];
-      if (k == kAggEmpty) continue;
-      if (kSink == kSinkCount)
-        unsafeAtomicAdd(m.acc + k, agg_val[h]);
-      else
-        cas_clamp_add(m.occ + (k >> 1), agg_val[h] * ((k & 1u) ? m.l_hit : m.l_miss), m.l_min, m.l_max);
+    if (kSink == kSinkCount) {
+      for (uint32_t h = tid; h < kAggSize; h += blockDim.x) {
+        const uint32_t k = agg_key[h];
+        if (k != kAggEmpty) unsafeAtomicAdd(m.acc + k, agg_val[h]);
+      }
+    } else {
+      // clamp-adds by compare-and-swap, four entries in flight per thread:
+      // each round trip to memory is shared by the four
+      constexpr int kFly = 4;
+      for (uint32_t h0 = tid; h0 < kAggSize; h0 += kFly * blockDim.x) {
+        uint32_t* u[kFly];
+        float d[kFly];
+        uint32_t old[kFly];
+        bool pending[kFly];
+#pragma unroll
+        for (int i = 0; i < kFly; ++i) {
+          const uint32_t h = h0 + (uint32_t)i * blockDim.x;
+          const uint32_t k = h < kAggSize ? agg_key[h] : kAggEmpty;
+          pending[i] = k != kAggEmpty;
+          u[i] = reinterpret_cast<uint32_t*>(m.occ + (pending[i] ? (k >> 1) : 0u));
+          d[i] = pending[i] ? agg_val[h] * ((k & 1u) ? m.l_hit : m.l_miss) : 0.f;
+          old[i] = pending[i] ? __hip_atomic_load(u[i], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) : 0u;
+        }
+        for (;;) {
+          bool any = false;
+#pragma unroll
+          for (int i = 0; i < kFly; ++i) {
+            if (!pending[i]) continue;
+            const float nv = fminf(fmaxf(__uint_as_float(old[i]) + d[i], m.l_min), m.l_max);
+            const uint32_t prev = atomicCAS(u[i], old[i], __float_as_uint(nv));
+            pending[i] = prev != old[i];
+            old[i] = prev;
+            any = any || pending[i];
+          }
+          if (!any) break;
+        }
+      }
     }
   }
   // every voxel a ray visits is an update unless dropped; a ray that ends

@@ -88,6 +88,16 @@ __device__ __forceinline__ bool agg_finish(uint32_t* keys, float* vals, uint32_t
   return true;
 }
 
+// Clamp-add a wave's queued (update id, summed weight) pairs, one per lane.
+__device__ __forceinline__ void drain_cas(const DevMap& m, const uint32_t* qid, const float* qv, uint32_t n,
+                                          uint32_t lane) {
+  __threadfence_block();  // the queue was written by other lanes of this wave
+  if (lane < n) {
+    const uint32_t id = qid[lane];
+    cas_clamp_add(m.occ + (id >> 1), qv[lane] * ((id & 1u) ? m.l_hit : m.l_miss), m.l_min, m.l_max);
+  }
+}
+
 // Per-ray data a tile keeps in LDS.
 struct TileRays {
   long long q0[3][kTileRays];
@@ -272,6 +282,12 @@ __device__ void walk_tile(const DevMap& m, const float* __restrict__ origin, con
   __shared__ RegionCache rc;
   __shared__ uint32_t agg_key[kAgg ? kAggSize : 1];
   __shared__ float agg_val[kAgg ? kAggSize : 1];
+  // per-update mode: table misses queued per wave, clamp-added 64 at a time
+  // (a compare-and-swap waits for its reply; one wave-wide batch shares it)
+  constexpr bool kQueue = kSink == kSinkCas;
+  __shared__ uint32_t cq_id[kQueue ? 16 : 1][64];
+  __shared__ float cq_v[kQueue ? 16 : 1][64];
+  uint32_t cq_n = 0;  // wave-uniform
   const uint32_t tid = threadIdx.x;
   const uint32_t lane = lane_id();
   if (kAgg)
@@ -349,11 +365,25 @@ __device__ void walk_tile(const DevMap& m, const float* __restrict__ origin, con
           n_hit_drop += is_hit ? 1u : 0u;
         }
         if (alive) alive = !last && tile_advance<kAccum>(m, rc, rw, s, M, slot, lidx);
-        if (emit_here && !agg_finish(agg_key, agg_val, id, k, v)) {
-          if (kSink == kSinkCount)
-            unsafeAtomicAdd(m.acc + id, v);
-          else
-            cas_clamp_add(m.occ + (id >> 1), v * ((id & 1u) ? m.l_hit : m.l_miss), m.l_min, m.l_max);
+        const bool miss_table = emit_here && !agg_finish(agg_key, agg_val, id, k, v);
+        if (kSink == kSinkCount) {
+          if (miss_table) unsafeAtomicAdd(m.acc + id, v);
+        } else {
+          const unsigned long long qm = __ballot(miss_table);
+          if (qm) {
+            const uint32_t nq = (uint32_t)__popcll(qm);
+            const uint32_t w = tid >> 6;
+            if (cq_n + nq > 64u) {
+              drain_cas(m, cq_id[w], cq_v[w], cq_n, lane);
+              cq_n = 0;
+            }
+            if (miss_table) {
+              const uint32_t rank = (uint32_t)__popcll(qm & ((1ull << lane) - 1ull));
+              cq_id[w][cq_n + rank] = id;
+              cq_v[w][cq_n + rank] = v;
+            }
+            cq_n += nq;
+          }
         }
       } else {
         if (alive && kSink == kSinkTraceWrite) {
@@ -369,6 +399,7 @@ __device__ void walk_tile(const DevMap& m, const float* __restrict__ origin, con
     }
   }
   if (kSink == kSinkTraceCount || kSink == kSinkTraceWrite) return;
+  if (kQueue && cq_n) drain_cas(m, cq_id[tid >> 6], cq_v[tid >> 6], cq_n, lane);
   if (kAgg) {
     __syncthreads();
     if (kSink == kSinkCount) {

@@ -1,5 +1,6 @@
-"""Grouped scans (LAYER_SCAN_GROUPS): ohm_integrate_rays walks up to 8 scans of
-a call in one launch and applies them per voxel in scan order.  The results
+"""Grouped scans (LAYER_SCAN_GROUPS): ohm_integrate_rays walks up to G scans
+of a call in one launch (G = 8 by default, OHM_SCAN_GROUP_SLOTS(n) for up to
+64) and applies them per voxel in scan order.  The results
 must be those of scan-by-scan integration: bit-identical to the oracle for
 count mode with unit weights, bit-identical to one launch per scan with
 exactly summable weights, and the same clamp-scan record as a map that

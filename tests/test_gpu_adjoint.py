@@ -83,8 +83,8 @@ def test_adjoint_plain():
 
 def test_adjoint_plain_grouped_forward():
     """The forward through grouped scans (one walk launch per 8 scans, the
-    default slot count) leaves
-    the clamp record the backward needs: same gradients."""
+    default slot count) leaves the clamp record the backward needs: same
+    gradients."""
     params, batch, box_min, box_dim, labels, mask, ref = setup_case(10, ndt=False)
     gw, gs, occ, _ = gpu_grads(params, batch, box_min, box_dim, labels, mask, ndt=False,
                                extra_layers=ohm.LAYER_SCAN_GROUPS)

@@ -132,17 +132,26 @@ __global__ __launch_bounds__(256) void batch_finalize_kernel(const DevMap* __res
       const size_t base = (size_t)slot * kRegionVoxels + (size_t)(u % kUnits) * kChunk;
       for (int v = threadIdx.x; v < kChunk; v += blockDim.x) {
         const size_t vi = base + v;
+        float2* const a0 = reinterpret_cast<float2*>(m.acc) + vi;
+        const size_t step = stride / 2;  // float2 elements per slot
         float l = m.occ[vi];
         bool any = false;
-        for (uint32_t j = 0; j < group; ++j) {
-          float2* ap = reinterpret_cast<float2*>(m.acc + j * stride) + vi;
-          const float2 a = *ap;
-          if (a.x == 0.f && a.y == 0.f) continue;
-          float s = __fadd_rn(l, __fmul_rn(a.y, m.l_hit));
-          s = __fadd_rn(s, __fmul_rn(a.x, m.l_miss));
-          l = fminf(fmaxf(s, m.l_min), m.l_max);
-          *ap = make_float2(0.f, 0.f);
-          any = true;
+        // kBatch slots are loaded before any of their clearing stores, so
+        // the loads overlap instead of waiting on each other
+        constexpr int kBatch = 8;
+        for (uint32_t j0 = 0; j0 < group; j0 += kBatch) {
+          float2 a[kBatch];
+#pragma unroll
+          for (int q = 0; q < kBatch; ++q) a[q] = j0 + q < group ? a0[(j0 + q) * step] : make_float2(0.f, 0.f);
+#pragma unroll
+          for (int q = 0; q < kBatch; ++q) {
+            if (a[q].x == 0.f && a[q].y == 0.f) continue;
+            float s = __fadd_rn(l, __fmul_rn(a[q].y, m.l_hit));
+            s = __fadd_rn(s, __fmul_rn(a[q].x, m.l_miss));
+            l = fminf(fmaxf(s, m.l_min), m.l_max);
+            a0[(j0 + q) * step] = make_float2(0.f, 0.f);
+            any = true;
+          }
         }
         if (any) m.occ[vi] = l;
       }

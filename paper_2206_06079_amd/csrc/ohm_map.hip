@@ -168,6 +168,8 @@ __global__ __launch_bounds__(1024) void walk_group_kernel(DevMap m, const float*
                                    tile * kTileRays, K, tag, parity, nullptr, nullptr, nullptr, nullptr);
 }
 
+constexpr int kGroupBatch = 8;  // accumulator slots loaded together by a group finalize
+
 // Apply the group's g scans in order to every voxel of the regions the group
 // touched: l = clamp((l + H_j l_hit) + M_j l_miss) for j = 0..g-1, recording
 // the clamp scan (scan_tag0 + j), and clear the slots except slot `keep`
@@ -182,20 +184,28 @@ __global__ __launch_bounds__(256) void group_finalize_kernel(DevMap m, uint32_t 
     const size_t base = (size_t)slot * kRegionVoxels + (size_t)(u % kFinalUnits) * kFinalChunk;
     for (int v = threadIdx.x; v < kFinalChunk; v += blockDim.x) {
       const size_t vi = base + v;
+      float2* const a0 = reinterpret_cast<float2*>(m.acc) + vi;
       float l = m.occ[vi];
       bool any = false;
-      for (uint32_t j = 0; j < g; ++j) {
-        float2* ap = reinterpret_cast<float2*>(m.acc) + j * stride + vi;
-        const float2 a = *ap;
-        if (a.x == 0.f && a.y == 0.f) continue;
-        const float t = __fmul_rn(a.y, m.l_hit);
-        const float uu = __fmul_rn(a.x, m.l_miss);
-        float sum = __fadd_rn(l, t);
-        sum = __fadd_rn(sum, uu);
-        if (m.clampscan && (sum < m.l_min || sum > m.l_max)) m.clampscan[vi] = scan_tag0 + j;
-        l = fminf(fmaxf(sum, m.l_min), m.l_max);
-        if (j != keep) *ap = make_float2(0.f, 0.f);
-        any = true;
+      // slots are loaded kGroupBatch at a time, all before the batch's
+      // clearing stores, so the loads overlap instead of waiting on each other
+      for (uint32_t j0 = 0; j0 < g; j0 += kGroupBatch) {
+        float2 a[kGroupBatch];
+#pragma unroll
+        for (int q = 0; q < kGroupBatch; ++q) a[q] = j0 + q < g ? a0[(j0 + q) * stride] : make_float2(0.f, 0.f);
+#pragma unroll
+        for (int q = 0; q < kGroupBatch; ++q) {
+          if (a[q].x == 0.f && a[q].y == 0.f) continue;
+          const uint32_t j = j0 + q;
+          const float t = __fmul_rn(a[q].y, m.l_hit);
+          const float uu = __fmul_rn(a[q].x, m.l_miss);
+          float sum = __fadd_rn(l, t);
+          sum = __fadd_rn(sum, uu);
+          if (m.clampscan && (sum < m.l_min || sum > m.l_max)) m.clampscan[vi] = scan_tag0 + j;
+          l = fminf(fmaxf(sum, m.l_min), m.l_max);
+          if (j != keep) a0[j * stride] = make_float2(0.f, 0.f);
+          any = true;
+        }
       }
       if (any) m.occ[vi] = l;
     }

@@ -32,7 +32,7 @@ def cfg3_small():
     return scenes.config3(n_streams=16, n_scans=96, size_scale=0.1)
 
 
-@pytest.mark.parametrize("group", [1, 3, 8])
+@pytest.mark.parametrize("group", [1, 3, 8, 13])
 def test_batched_equals_oracle_and_per_scan(cfg3_small, group):
     params, batches = cfg3_small
     maps, sets = make_sets(params, batches)

@@ -41,10 +41,13 @@ def test_grouped_config1_equals_oracle(n_scans):
     assert st["updates_dropped_pool"] == 0
 
 
-@pytest.mark.parametrize("slots", [1, 3, 16, 64])
+@pytest.mark.parametrize("slots", [1, 3, 11, 16, 64])
 def test_grouped_slot_counts(slots):
-    """Maps with 1, 3, 16 or 64 slots (OHM_SCAN_GROUP_SLOTS): 20 scans in
-    groups of that size, the same result."""
+    """Maps with 1, 3, 11, 16 or 64 slots (OHM_SCAN_GROUP_SLOTS): 20 scans
+    in groups of that size, the same result.  The finalize loads slots eight
+    at a time.  With 11 slots the groups are 11 and 9 scans; the second ends
+    on a batch holding only the kept slot (the call's last scan).  With 64
+    the one group of 20 ends on a batch of four."""
     mp, batch = scenes.config1(n_scans=20, first_scan=60)
     layers = GROUPED | ohm.scan_group_slots(slots)
     occ, hits, miss, st = gpu_integrate(mp, batch, 1024, CFG1_BOX_MIN, CFG1_BOX_DIM, layers=layers)

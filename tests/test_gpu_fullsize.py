@@ -1,13 +1,22 @@
-"""The benchmark's headline workload at full size: 100 spinning-lidar scans
-of 131,072 rays each (0.1 m voxels, 30 m range), in the launch configurations
-the benchmark times:
+"""The benchmark's workloads at full size, in the launch configurations it
+times.
+
+Headline: 100 spinning-lidar scans of 131,072 rays each (0.1 m voxels, 30 m
+range) through
 - one ohm_integrate_rays call on a map with 50-scan groups;
 - the same call on a map that launches once per scan;
 - a batched plan of 50-scan groups over the same scans.
 Count mode with unit weights is exact, so every voxel of a window holding
 everything the scans reach (x 690..1409, y 978..1021, z 183..216; the
 touched voxels lie at least one voxel inside each face) must equal the
-oracle bit for bit, and so must the update and ray counts."""
+oracle bit for bit, and so must the update and ray counts.
+
+NDT-OM: the same 100 scans into an NDT map of 512 regions, within the NDT
+tolerances (exact sample counts; mean and covariance within 1e-5; occupancy
+within 1e-5 plus 2^-33 per update).
+
+Adjoint: 20 weighted scans at 0.2 m into an NDT map, then the backward for
+the masked BCE gradient, within 1e-4 of the oracle's fp64 gradients."""
 import numpy as np
 import pytest
 import torch
@@ -15,6 +24,8 @@ import torch
 import oracle
 import paper_2206_06079_amd as ohm
 from gpu_helpers import device, gpu_integrate, to_dev
+from test_gpu_adjoint import check, gpu_grads, in_box_counts, setup_case
+from test_gpu_ndt import check_stats, gpu_ndt, update_counts
 from workloads import scenes
 
 pytestmark = pytest.mark.gpu
@@ -57,3 +68,23 @@ def test_headline_workload_batched_equals_oracle(headline):
     assert m.stats()["voxel_updates"] == o_st["updates"]
     plan.close()
     m.close()
+
+
+def test_ndt_headline_scans_equal_oracle():
+    mp, batch = scenes.config2(n_scans=100)
+    print(f"NDT: {batch.n_scans} scans, {batch.samples.shape[0]} rays", flush=True)
+    g = gpu_ndt(mp, batch, BOX_MIN, BOX_DIM, capacity=512)
+    o_occ, o_state, _, o_st = oracle.ndt_integrate(mp, batch, BOX_MIN, BOX_DIM, mode=1)
+    k = update_counts(mp, batch, BOX_MIN, BOX_DIM)
+    check_stats(g, o_occ, o_state, k)
+    assert g["stats"]["voxel_updates"] == o_st["updates"]
+    assert g["stats"]["updates_dropped_pool"] == 0
+    assert (o_state.n >= 4).sum() > 50_000
+
+
+def test_adjoint_twenty_weighted_scans():
+    params, batch, box_min, box_dim, labels, mask, ref = setup_case(20)
+    print(f"adjoint: {batch.n_scans} scans, {batch.samples.shape[0]} rays", flush=True)
+    gw, gs, occ, n_after = gpu_grads(params, batch, box_min, box_dim, labels, mask)
+    np.testing.assert_allclose(occ, ref["occ"], atol=1e-5, rtol=0)
+    check(gw, gs, ref, in_box_counts(params, batch, box_min, box_dim), batch.n_scans)

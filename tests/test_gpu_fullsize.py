@@ -16,7 +16,13 @@ tolerances (exact sample counts; mean and covariance within 1e-5; occupancy
 within 1e-5 plus 2^-33 per update).
 
 Adjoint: 20 weighted scans at 0.2 m into an NDT map, then the backward for
-the masked BCE gradient, within 1e-4 of the oracle's fp64 gradients."""
+the masked BCE gradient, within 1e-4 of the oracle's fp64 gradients.
+
+Batched streams: the first 128 of the 16-stream workload's 1,000 scans, at
+full scan sizes (log-uniform 8,192..262,144 rays, 8.8 M rays, two maps at
+0.1 m and 0.05 m), through the plan the benchmark's autotuner settles on
+(64-scan groups, 32 major crossings per segment, 512 threads, direction
+order); both maps bit-exact against the oracle."""
 import numpy as np
 import pytest
 import torch
@@ -25,6 +31,7 @@ import oracle
 import paper_2206_06079_amd as ohm
 from gpu_helpers import device, gpu_integrate, to_dev
 from test_gpu_adjoint import check, gpu_grads, in_box_counts, setup_case
+from test_gpu_batch import WINDOWS, make_sets
 from test_gpu_ndt import check_stats, gpu_ndt, update_counts
 from workloads import scenes
 
@@ -88,3 +95,23 @@ def test_adjoint_twenty_weighted_scans():
     gw, gs, occ, n_after = gpu_grads(params, batch, box_min, box_dim, labels, mask)
     np.testing.assert_allclose(occ, ref["occ"], atol=1e-5, rtol=0)
     check(gw, gs, ref, in_box_counts(params, batch, box_min, box_dim), batch.n_scans)
+
+
+def test_batched_streams_full_scan_sizes():
+    params, batches = scenes.config3(n_streams=16, n_scans=128, jobs=16)
+    print(f"batched: {[b.samples.shape[0] for b in batches]} rays per map", flush=True)
+    maps, sets = make_sets(params, batches)
+    plan = ohm.OhmBatch(sets, 64, seg_major_steps=32, tile_threads=512, keep_ray_order=0)
+    plan.run()
+    torch.cuda.synchronize()
+    for mi, (p, b) in enumerate(zip(params, batches)):
+        bmin, bdim = WINDOWS[mi]
+        got = maps[mi].read_dense(ohm.READ_OCC, bmin, bdim).cpu().numpy()
+        exp, _, _, st = oracle.integrate_count(p, b, bmin, bdim)
+        assert np.count_nonzero(exp) > 500_000
+        assert np.array_equal(got, exp), f"map {mi}: batched differs from the oracle"
+        assert maps[mi].stats()["voxel_updates"] == st["updates"]
+        assert maps[mi].stats()["updates_dropped_pool"] == 0
+    plan.close()
+    for m in maps:
+        m.close()

@@ -11,6 +11,10 @@ everything the scans reach (x 690..1409, y 978..1021, z 183..216; the
 touched voxels lie at least one voxel inside each face) must equal the
 oracle bit for bit, and so must the update and ray counts.
 
+Per-update mode: the same 100 scans with each update applied and clamped
+on its own (compare-and-swap), inside the oracle's bracket over every order
+of a scan's updates (plus one ulp per update).
+
 NDT-OM: the same 100 scans into an NDT map of 512 regions, within the NDT
 tolerances (exact sample counts; mean and covariance within 1e-5; occupancy
 within 1e-5 plus 2^-33 per update).
@@ -29,7 +33,7 @@ import torch
 
 import oracle
 import paper_2206_06079_amd as ohm
-from gpu_helpers import device, gpu_integrate, to_dev
+from gpu_helpers import device, gpu_integrate, per_update_tolerance, to_dev
 from test_gpu_adjoint import check, gpu_grads, in_box_counts, setup_case
 from test_gpu_batch import WINDOWS, make_sets
 from test_gpu_ndt import check_stats, gpu_ndt, update_counts
@@ -75,6 +79,20 @@ def test_headline_workload_batched_equals_oracle(headline):
     assert m.stats()["voxel_updates"] == o_st["updates"]
     plan.close()
     m.close()
+
+
+def test_per_update_headline_scans_within_envelope():
+    mp, batch = scenes.config1(n_scans=100, mode=scenes.MODE_PER_UPDATE)
+    occ, _, _, st = gpu_integrate(mp, batch, 512, BOX_MIN, BOX_DIM)
+    lo, hi, nupd, o_st = oracle.integrate_envelope(mp, batch, BOX_MIN, BOX_DIM)
+    tol = per_update_tolerance(nupd)
+    assert np.all(occ >= lo - tol) and np.all(occ <= hi + tol)
+    # voxels whose every order gives one value must take it
+    free = (hi - lo) < 1e-12
+    assert free.sum() > 100_000
+    assert np.all(np.abs(occ[free] - lo[free]) <= np.maximum(tol[free], 1e-5))
+    assert st["voxel_updates"] == o_st["updates"]
+    assert st["updates_dropped_pool"] == 0
 
 
 def test_ndt_headline_scans_equal_oracle():

@@ -57,10 +57,15 @@ def _load():
     global _lib
     if _lib is not None:
         return _lib
+    from . import build as _b
     if not os.path.exists(_LIB_PATH):
-        from . import build as _b
-        _b.build()
+        raise RuntimeError(f"oracle library {_LIB_PATH} is missing: build it with `python -m oracle.build`")
     lib = ctypes.CDLL(_LIB_PATH)
+    lib.orc_source_digest.argtypes = []
+    lib.orc_source_digest.restype = ctypes.c_char_p
+    if lib.orc_source_digest().decode() != _b.source_digest():
+        raise RuntimeError(f"oracle library {_LIB_PATH} was built from another source: rebuild it with "
+                           "`python -m oracle.build`")
     P = ctypes.POINTER
     vp = ctypes.c_void_p
     lib.orc_trace.restype = ctypes.c_int64

@@ -157,6 +157,14 @@ static void prepare_ray(const orc_params* p, const float o[3], const float e[3],
   r->status = ORC_RAY_OK;
 }
 
+/* A ray whose weight is negative or not finite is rejected whole, like a
+   non-finite ray (the library's input contract for per-ray weights). */
+static void prepare_weighted_ray(const orc_params* p, const float o[3], const float* samples, const float* weights,
+                                 uint32_t i, orc_ray* r) {
+  prepare_ray(p, o, samples + 3 * (size_t)i, r);
+  if (weights && !(weights[i] >= 0.0f && isfinite(weights[i]))) r->status = ORC_RAY_INVALID;
+}
+
 static int cmp_event(const void* va, const void* vb) {
   const orc_event* x = (const orc_event*)va;
   const orc_event* y = (const orc_event*)vb;
@@ -312,12 +320,12 @@ static double clampd_(double v, double lo, double hi) {
  * but not recorded.
  */
 static void accumulate_scan(const orc_params* p, const float* origin, uint32_t r0, uint32_t r1,
-                            const float* samples, const float* weights, const int32_t box_min[3],
+                            const float* samples, const float* weights, int unit_weights, const int32_t box_min[3],
                             const int32_t box_dim[3], double* wh, double* wm, uint64_t* stats,
                             orc_scratch* s) {
   for (uint32_t i = r0; i < r1; ++i) {
     orc_ray r;
-    prepare_ray(p, origin, samples + 3 * (size_t)i, &r);
+    prepare_weighted_ray(p, origin, samples, weights, i, &r);
     if (stats) stats[ORC_S_RAYS] += 1;
     if (r.status == ORC_RAY_INVALID) {
       if (stats) stats[ORC_S_INVALID] += 1;
@@ -330,7 +338,7 @@ static void accumulate_scan(const orc_params* p, const float* origin, uint32_t r
     int clipped = 0;
     int64_t nk = walk_ray(p, &r, s, &clipped);
     int has_hit = !r.truncated && !clipped;
-    double w = weights ? (double)weights[i] : 1.0;
+    double w = (weights && !unit_weights) ? (double)weights[i] : 1.0;
     if (stats) {
       stats[ORC_S_TRUNCATED] += r.truncated ? 1 : 0;
       stats[ORC_S_CLIPPED] += clipped ? 1 : 0;
@@ -374,7 +382,7 @@ int orc_integrate_count(const orc_params* p, int32_t n_scans, const uint32_t* of
   for (int32_t sc = 0; sc < n_scans; ++sc) {
     memset(wh, 0, nv * sizeof(double));
     memset(wm, 0, nv * sizeof(double));
-    accumulate_scan(p, origins + 3 * sc, offsets[sc], offsets[sc + 1], samples, weights, box_min, box_dim, wh,
+    accumulate_scan(p, origins + 3 * sc, offsets[sc], offsets[sc + 1], samples, weights, 0, box_min, box_dim, wh,
                     wm, stats, &s);
     for (size_t v = 0; v < nv; ++v) {
       if (wh[v] == 0.0 && wm[v] == 0.0) continue;
@@ -428,14 +436,14 @@ int orc_integrate_envelope(const orc_params* p, int32_t n_scans, const uint32_t*
   for (int32_t sc = 0; sc < n_scans; ++sc) {
     memset(wh, 0, nv * sizeof(double));
     memset(wm, 0, nv * sizeof(double));
-    accumulate_scan(p, origins + 3 * sc, offsets[sc], offsets[sc + 1], samples, weights, box_min, box_dim, wh,
+    accumulate_scan(p, origins + 3 * sc, offsets[sc], offsets[sc + 1], samples, weights, 0, box_min, box_dim, wh,
                     wm, stats, &s);
     if (n_updates) {
       /* re-walk with unit weights to count updates */
       double* ch = (double*)calloc(nv, sizeof(double));
       double* cm = (double*)calloc(nv, sizeof(double));
-      accumulate_scan(p, origins + 3 * sc, offsets[sc], offsets[sc + 1], samples, NULL, box_min, box_dim, ch, cm,
-                      NULL, &s);
+      accumulate_scan(p, origins + 3 * sc, offsets[sc], offsets[sc + 1], samples, weights, 1, box_min, box_dim, ch,
+                      cm, NULL, &s);
       for (size_t v = 0; v < nv; ++v) n_updates[v] += (uint32_t)(ch[v] + cm[v]);
       free(ch);
       free(cm);
@@ -589,7 +597,7 @@ int orc_ndt_integrate(const orc_params* p, int32_t mode, int32_t n_scans, const 
     /* phase 1: misses (and hit weights) */
     for (uint32_t i = offsets[sc]; i < offsets[sc + 1]; ++i) {
       orc_ray r;
-      prepare_ray(p, of, samples + 3 * (size_t)i, &r);
+      prepare_weighted_ray(p, of, samples, weights, i, &r);
       if (stats) stats[ORC_S_RAYS] += 1;
       if (r.status != ORC_RAY_OK) {
         if (stats) stats[r.status == ORC_RAY_INVALID ? ORC_S_INVALID : ORC_S_ORIGIN_OOB] += 1;
@@ -639,7 +647,7 @@ int orc_ndt_integrate(const orc_params* p, int32_t mode, int32_t n_scans, const 
     /* phase 2b: fold this scan's samples, ascending ray order */
     for (uint32_t i = offsets[sc]; i < offsets[sc + 1]; ++i) {
       orc_ray r;
-      prepare_ray(p, of, samples + 3 * (size_t)i, &r);
+      prepare_weighted_ray(p, of, samples, weights, i, &r);
       if (r.status != ORC_RAY_OK || r.truncated) continue;
       int clipped = 0;
       int64_t nk = walk_ray(p, &r, &s, &clipped);
@@ -801,7 +809,7 @@ int orc_adjoint(const orc_params* p, int32_t ndt, int32_t n_scans, const uint32_
       double o[3] = {(double)of[0], (double)of[1], (double)of[2]};
       for (uint32_t i = offsets[sc]; i < offsets[sc + 1]; ++i) {
         orc_ray r;
-        prepare_ray(p, of, samples + 3 * (size_t)i, &r);
+        prepare_weighted_ray(p, of, samples, weights, i, &r);
         if (pass == 1 && grad_w) grad_w[i] = 0.0;
         if (r.status != ORC_RAY_OK) continue;
         int clipped = 0;
@@ -861,7 +869,7 @@ int orc_adjoint(const orc_params* p, int32_t ndt, int32_t n_scans, const uint32_
         /* fold the scan's samples (ascending ray order) */
         for (uint32_t i = offsets[sc]; i < offsets[sc + 1]; ++i) {
           orc_ray r;
-          prepare_ray(p, of, samples + 3 * (size_t)i, &r);
+          prepare_weighted_ray(p, of, samples, weights, i, &r);
           if (r.status != ORC_RAY_OK || r.truncated) continue;
           int clipped = 0;
           int64_t nk = walk_ray(p, &r, &s, &clipped);
@@ -906,3 +914,9 @@ int orc_adjoint(const orc_params* p, int32_t ndt, int32_t n_scans, const uint32_
 
 /* Library self-identification for the loaders. */
 int orc_abi_version(void) { return 1; }
+
+#ifndef ORC_SOURCE_DIGEST
+#define ORC_SOURCE_DIGEST "unknown"
+#endif
+/* sha256 of the source this library was built from (set by the build). */
+const char* orc_source_digest(void) { return ORC_SOURCE_DIGEST; }

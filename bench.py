@@ -117,7 +117,21 @@ def run_gpu(args, params, batch, mode, layers=1):
     }
 
 
-def run_batched(args):
+def generate_batched(args):
+    """The multi-sensor workload's inputs, generated before anything touches
+    the GPU (the generator's worker processes must not start from a process
+    that holds GPU state)."""
+    from workloads import scenes
+
+    jobs = max(1, min(16, os.cpu_count() or 1))
+    log(f"generating the batched workload ({args.batched_scans} scans, {jobs} processes)")
+    t0 = time.perf_counter()
+    params, batches = scenes.config3(n_scans=args.batched_scans, jobs=jobs)
+    log(f"generated {sum(b.n_rays for b in batches)} rays in {time.perf_counter() - t0:.1f} s")
+    return params, batches
+
+
+def run_batched(args, generated):
     """The multi-sensor workload: 16 streams, scans of log-uniform size in
     [8192, 262144] rays with unordered directions, half into a 0.1 m map and
     half into a 0.05 m map.  Times one graph launch of the batched plan
@@ -128,14 +142,9 @@ def run_batched(args):
     import torch
 
     import paper_2206_06079_amd as ohm
-    from workloads import scenes
 
-    jobs = max(1, min(16, os.cpu_count() or 1))
-    log(f"generating the batched workload ({args.batched_scans} scans, {jobs} processes)")
-    t0 = time.perf_counter()
-    params, batches = scenes.config3(n_scans=args.batched_scans, jobs=jobs)
+    params, batches = generated
     n_rays = sum(b.n_rays for b in batches)
-    log(f"generated {n_rays} rays in {time.perf_counter() - t0:.1f} s")
     dev = torch.device("cuda", 0)
     caps = (512, 1536)
     inputs = [(torch.from_numpy(b.origins).to(dev), torch.from_numpy(b.samples).to(dev), b.offsets)
@@ -371,10 +380,13 @@ def main():
               "(how it would shard is described in the design notes)", file=sys.stderr)
         return 2
 
+    from workloads import scenes
+
+    batched_inputs = None if args.no_batched else generate_batched(args)
+
     import torch
 
     import paper_2206_06079_amd as ohm
-    from workloads import scenes
 
     if not torch.cuda.is_available():
         print("bench.py needs a GPU", file=sys.stderr)
@@ -473,7 +485,7 @@ def main():
     headline_batched = None if args.no_batched else run_batched_headline(args, params, batch)
     ndt = None if args.no_ndt else run_ndt(args, params, batch)
     adjoint = None if args.no_adjoint else run_adjoint(args)
-    batched = None if args.no_batched else run_batched(args)
+    batched = None if args.no_batched else run_batched(args, batched_inputs)
     cpu = None
     if not args.no_cpu_baseline:
         log(f"timing the oracle on {args.cpu_scans} scans")

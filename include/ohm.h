@@ -136,7 +136,10 @@ typedef struct {
   uint64_t updates_dropped_pool;/* updates lost to a full region pool */
   uint32_t regions_used;
   uint32_t region_capacity;
-  int32_t sticky_error;         /* bit 0: region pool exhausted */
+  int32_t sticky_error;         /* bit 0: region pool exhausted; bit 1: a region slot being
+                                   published by another block never appeared (updates dropped);
+                                   bit 2: a ray weight was negative or not finite (ray skipped,
+                                   counted in rays_invalid) */
   int32_t reserved;
 } ohm_map_stats;
 
@@ -169,7 +172,10 @@ ohm_status ohm_map_set_params(ohm_map map, const ohm_params* params);
  *   h_scan_offsets  uint32[n_scans+1]   HOST array; scan s owns rays
  *                                       [h_scan_offsets[s], h_scan_offsets[s+1])
  *   d_weights       float[N] or NULL    per-ray weight scaling that ray's hit and
- *                                       miss increments (NULL = 1)
+ *                                       miss increments (NULL = 1); each must be
+ *                                       finite and >= 0: a ray with any other
+ *                                       weight is skipped whole, counted in
+ *                                       rays_invalid, and sets sticky_error bit 2
  * Scans are applied in order; in count mode each scan is one batch with one
  * clamp per voxel.  In count mode the last scan's hit/miss weights remain
  * readable (OHM_READ_HITS / OHM_READ_MISSES) until the next call.  On a map
@@ -351,6 +357,11 @@ ohm_status ohm_probe_atomic_rate(void* d_buffer, size_t bytes, int sequential, d
 ohm_status ohm_map_sync_status(ohm_map map, void* stream, ohm_map_stats* out);
 
 const char* ohm_status_string(ohm_status status);
+
+/* Build identification: the sha256 (64 hex digits) of the kernel sources,
+ * their headers and this header that the library was compiled from, so that
+ * a caller can refuse a library built from other sources. */
+const char* ohm_build_source_digest(void);
 
 #ifdef __cplusplus
 }

@@ -44,6 +44,7 @@ EXPORTS = (
     "ohm_map_set_profiling", "ohm_map_kernel_times", "ohm_backward",
     "ohm_batch_workspace_size", "ohm_batch_create", "ohm_batch_run", "ohm_batch_destroy",
     "ohm_map_set_tuning", "ohm_probe_atomic_rate", "ohm_ray_order_scratch_size", "ohm_map_set_ray_order",
+    "ohm_build_source_digest",
 )
 
 
@@ -131,6 +132,15 @@ def load() -> ctypes.CDLL:
         raise RuntimeError(f"HIP library {LIB_PATH} is missing: build it with "
                            "`python -m paper_2206_06079_amd.build`")
     lib = ctypes.CDLL(LIB_PATH)
+    lib.ohm_build_source_digest.argtypes = []
+    lib.ohm_build_source_digest.restype = ctypes.c_char_p
+    built = lib.ohm_build_source_digest().decode()
+    from . import build as _build
+    if os.path.isdir(_build.CSRC):
+        want = _build.source_digest()
+        if built != want:
+            raise RuntimeError(f"HIP library {LIB_PATH} was built from other sources (digest {built[:12]}, "
+                               f"sources {want[:12]}): rebuild it with `python -m paper_2206_06079_amd.build`")
     vp, P = ctypes.c_void_p, ctypes.POINTER
     st = ctypes.c_int
     sig = {

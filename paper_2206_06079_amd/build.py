@@ -1,5 +1,6 @@
 """Build the HIP C-ABI library (gfx950) in-tree: paper_2206_06079_amd/libohm_hip.so."""
 import glob
+import hashlib
 import os
 import subprocess
 
@@ -22,9 +23,30 @@ def sources():
     return sorted(glob.glob(os.path.join(CSRC, "*.hip")))
 
 
+def digest_inputs():
+    """Every file the library is built from: kernel sources, their headers
+    and the C-ABI header."""
+    files = glob.glob(os.path.join(CSRC, "*.hip")) + glob.glob(os.path.join(CSRC, "*.h"))
+    files.append(os.path.join(INCLUDE, "ohm.h"))
+    return sorted(files, key=os.path.basename)
+
+
+def source_digest() -> str:
+    """sha256 over the names and contents of digest_inputs(); the build
+    embeds it (ohm_build_source_digest) so a stale library can be told apart."""
+    h = hashlib.sha256()
+    for f in digest_inputs():
+        h.update(os.path.basename(f).encode())
+        h.update(b"\0")
+        with open(f, "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
 def build(verbose: bool = False) -> str:
     hipcc = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
-    cmd = [hipcc, *HIPCC_FLAGS, "-I", INCLUDE, "-I", CSRC, *sources(), "-o", LIB + ".tmp"]
+    cmd = [hipcc, *HIPCC_FLAGS, f'-DOHM_SOURCE_DIGEST="{source_digest()}"', "-I", INCLUDE, "-I", CSRC,
+           *sources(), "-o", LIB + ".tmp"]
     if verbose:
         print(" ".join(cmd), flush=True)
     res = subprocess.run(cmd, capture_output=True, text=True)

@@ -18,7 +18,9 @@
 //     d delta / d l_miss  = lambda g s (1 - s) / (p (1 - p))
 //     d delta / d sigma_n = -lambda (1/2 - s) g sigma_n |S^-1 D|^2 / (p (1 - p)).
 // The NDT statistics each scan saw are replayed: the layer is emptied, and
-// after scan k's gradient walk its samples are folded in again.
+// scan k's gradient walk, which reads the statistics as they were before
+// scan k, also adds each hit's sample to the voxel's moment accumulators,
+// which a fold after the walk merges into the statistics for scan k + 1.
 #include <hip/hip_runtime.h>
 #include <math.h>
 #include <stdint.h>
@@ -130,12 +132,15 @@ __device__ __forceinline__ void bwd_drain(const DevMap& m, const BwdPending* pen
 
 // One tile of 256 rays, walked segment by segment (see ohm_walk_seg.h).  A
 // ray's weight gradient is the sum over its segments (fp64 LDS atomics);
-// the scalar gradients are reduced per block.
+// the scalar gradients are reduced per block.  `tag` is the scan's 1-based
+// index (compared with the clamp record); with kNdt the hit samples are
+// accumulated for the statistics replay, and the touched regions listed
+// under (fold_tag, fold_parity) for the fold that follows.
 template <bool kNdt, bool kWeighted>
 __global__ __launch_bounds__(kBackwardMaxThreads, 4) void backward_seg_kernel(
     DevMap m, GradBox gb, const float* __restrict__ origins, uint32_t scan, const float* __restrict__ samples,
-    const float* __restrict__ weights, uint32_t r0, uint32_t n, int K, uint32_t tag, float* __restrict__ grad_w,
-    double* __restrict__ grad_s, double sig_miss) {
+    const float* __restrict__ weights, uint32_t r0, uint32_t n, int K, uint32_t tag, uint32_t fold_tag,
+    uint32_t fold_parity, float* __restrict__ grad_w, double* __restrict__ grad_s, double sig_miss) {
 #pragma clang fp contract(off)
   __shared__ TileRays tr;
   __shared__ RegionCache rc;
@@ -148,7 +153,8 @@ __global__ __launch_bounds__(kBackwardMaxThreads, 4) void backward_seg_kernel(
   TileRay t;
   RegionWindow rw;
   const uint32_t items =
-      tile_prologue<kStageResolve>(m, tr, rc, rw, origin, samples, nullptr, r0, n, tile0, K, 0u, 0u, t);
+      tile_prologue<kNdt ? kStageTouch : kStageResolve>(m, tr, rc, rw, origin, samples, kWeighted ? weights : nullptr,
+                                                        nullptr, r0, n, tile0, K, fold_tag, fold_parity, t);
   if (tid < (uint32_t)kTileRays) {
     ray_gw[tid] = 0.0;
     if (t.ok)
@@ -191,6 +197,25 @@ __global__ __launch_bounds__(kBackwardMaxThreads, 4) void backward_seg_kernel(
       if (alive) {
         last = s.w.total == 0;
         const bool is_hit = last && !trunc;
+        if (kNdt && is_hit && slot >= 0) {
+          // the statistics replay: this sample's moments (voxel-centred, fp64)
+          const size_t vh = (size_t)slot * kRegionVoxels + lidx;
+          const size_t ray = (size_t)r0 + tr.src[ray_t];
+          const double x0 = (double)samples[3 * ray + 0] - (m.origin[0] + ((double)k0 + 0.5) * m.voxel_size);
+          const double x1 = (double)samples[3 * ray + 1] - (m.origin[1] + ((double)k1 + 0.5) * m.voxel_size);
+          const double x2 = (double)samples[3 * ray + 2] - (m.origin[2] + ((double)k2 + 0.5) * m.voxel_size);
+          double* mo = m.mom + vh * kMomWords;
+          unsafeAtomicAdd(mo + 0, x0);
+          unsafeAtomicAdd(mo + 1, x1);
+          unsafeAtomicAdd(mo + 2, x2);
+          unsafeAtomicAdd(mo + 3, x0 * x0);
+          unsafeAtomicAdd(mo + 4, x0 * x1);
+          unsafeAtomicAdd(mo + 5, x0 * x2);
+          unsafeAtomicAdd(mo + 6, x1 * x1);
+          unsafeAtomicAdd(mo + 7, x1 * x2);
+          unsafeAtomicAdd(mo + 8, x2 * x2);
+          atomicAdd(reinterpret_cast<unsigned long long*>(m.nacc + vh * kNaccWords + kNaccSamples), 1ull);
+        }
         G = grad_at(gb, k0, k1, k2);
         if (G != 0.f && slot >= 0) {
           v = (size_t)slot * kRegionVoxels + lidx;
@@ -263,63 +288,6 @@ __global__ void zero_f64_kernel(double* p, int n) {
 
 }  // namespace
 
-// Folds each hit's sample into its voxel's moment accumulators (the NDT
-// second phase without occupancy updates): replays the statistics.
-__global__ __launch_bounds__(256) void ndt_fold_kernel(DevMap m, const float* __restrict__ origins, uint32_t scan,
-                                                       const float* __restrict__ samples, uint32_t r0, uint32_t n,
-                                                       uint32_t tag, uint32_t parity) {
-#pragma clang fp contract(off)
-  const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
-  const bool inrange = i < n;
-  const size_t ray = (size_t)r0 + i;
-  const float o[3] = {origins[3 * scan + 0], origins[3 * scan + 1], origins[3 * scan + 2]};
-  float e[3] = {0.f, 0.f, 0.f};
-  if (inrange) {
-    e[0] = samples[3 * ray + 0];
-    e[1] = samples[3 * ray + 1];
-    e[2] = samples[3 * ray + 2];
-  }
-  Ray r;
-  const int st = inrange ? prepare_ray(m, o, e, r) : kRayInvalid;
-  // a ray carries a sample when it is not truncated and its end voxel is in
-  // the map (the box is convex, so the walk then reaches it)
-  bool hit = inrange && st == kRayOk && !r.truncated;
-  for (int a = 0; a < 3; ++a) hit = hit && r.k1[a] >= m.kmin[a] && r.k1[a] < m.kmax[a];
-  __shared__ RegionCache rc;
-  for (int h = threadIdx.x; h < kRegionCacheSize; h += blockDim.x) rc.key[h] = kSlotEmpty;
-  __syncthreads();
-  int32_t ri = 0;
-  bool cached = false;
-  if (hit) {
-    ri = region_index(m, r.k1[0] >> kRegionLog2, r.k1[1] >> kRegionLog2, r.k1[2] >> kRegionLog2);
-    cached = rc_insert(rc, ri);
-  }
-  __syncthreads();
-  for (int h = threadIdx.x; h < kRegionCacheSize; h += blockDim.x) {
-    const int32_t k = rc.key[h];
-    rc.slot[h] = k == kSlotEmpty ? kSlotExhausted : resolve_region<true>(m, k, tag, parity);
-  }
-  __syncthreads();
-  if (!hit) return;
-  const int32_t slot = cached ? rc_find(rc, ri) : resolve_region<true>(m, ri, tag, parity);
-  if (slot < 0) return;
-  const size_t v = (size_t)slot * kRegionVoxels + local_index(r.k1[0], r.k1[1], r.k1[2]);
-  const double x0 = (double)e[0] - (m.origin[0] + ((double)r.k1[0] + 0.5) * m.voxel_size);
-  const double x1 = (double)e[1] - (m.origin[1] + ((double)r.k1[1] + 0.5) * m.voxel_size);
-  const double x2 = (double)e[2] - (m.origin[2] + ((double)r.k1[2] + 0.5) * m.voxel_size);
-  double* mo = m.mom + v * kMomWords;
-  unsafeAtomicAdd(mo + 0, x0);
-  unsafeAtomicAdd(mo + 1, x1);
-  unsafeAtomicAdd(mo + 2, x2);
-  unsafeAtomicAdd(mo + 3, x0 * x0);
-  unsafeAtomicAdd(mo + 4, x0 * x1);
-  unsafeAtomicAdd(mo + 5, x0 * x2);
-  unsafeAtomicAdd(mo + 6, x1 * x1);
-  unsafeAtomicAdd(mo + 7, x1 * x2);
-  unsafeAtomicAdd(mo + 8, x2 * x2);
-  atomicAdd(reinterpret_cast<unsigned long long*>(m.nacc + v * kNaccWords + kNaccSamples), 1ull);
-}
-
 }  // namespace ohm
 
 using namespace ohm;
@@ -333,6 +301,8 @@ extern "C" ohm_status ohm_backward(ohm_map map, int32_t ndt, const float* d_grad
   if (!d_grad || !h_box_min || !h_box_dim || !d_grad_scalars || !map->dm.clampscan) return OHM_E_INVALID_ARG;
   if (ndt && !map->dm.ndt) return OHM_E_INVALID_ARG;
   if (map->params.mode != OHM_MODE_COUNT_CLAMP) return OHM_E_UNSUPPORTED;
+  // a batched plan keeps no per-scan clamp record, so its scans cannot be differentiated
+  if (map->batched) return OHM_E_UNSUPPORTED;
   if (ndt && !(isinf(map->params.ndt_clear_below) && map->params.ndt_clear_below < 0)) return OHM_E_UNSUPPORTED;
   for (int a = 0; a < 3; ++a)
     if (h_box_dim[a] <= 0) return OHM_E_INVALID_ARG;
@@ -363,35 +333,36 @@ extern "C" ohm_status ohm_backward(ohm_map map, int32_t ndt, const float* d_grad
     const uint32_t n = h_scan_offsets[sc + 1] - r0;
     if (n == 0) continue;
     ++tag;
-    const dim3 grid((n + 255) / 256);
     const dim3 tiles((n + kTileRays - 1) / kTileRays);
     const dim3 threads(map->walk_threads < kBackwardMaxThreads ? map->walk_threads : kBackwardMaxThreads);
     const int K = map->seg_major_steps;
+    // NDT: the walk lists its regions under a fresh tag for the fold below
+    const uint32_t ftag = ndt ? ++map->count_batches : 0u;
+    const uint32_t fparity = ftag & 1u;
     {
       ProfScope ps(map, OHM_KERNEL_OTHER, st);
       if (ndt) {
         if (weighted)
           hipLaunchKernelGGL((backward_seg_kernel<true, true>), tiles, threads, 0, st, map->dm, gb, d_origins, sc,
-                             d_samples, d_weights, r0, n, K, tag, d_grad_weights, d_grad_scalars, sig_miss);
+                             d_samples, d_weights, r0, n, K, tag, ftag, fparity, d_grad_weights, d_grad_scalars,
+                             sig_miss);
         else
           hipLaunchKernelGGL((backward_seg_kernel<true, false>), tiles, threads, 0, st, map->dm, gb, d_origins, sc,
-                             d_samples, d_weights, r0, n, K, tag, d_grad_weights, d_grad_scalars, sig_miss);
+                             d_samples, d_weights, r0, n, K, tag, ftag, fparity, d_grad_weights, d_grad_scalars,
+                             sig_miss);
       } else {
         if (weighted)
           hipLaunchKernelGGL((backward_seg_kernel<false, true>), tiles, threads, 0, st, map->dm, gb, d_origins, sc,
-                             d_samples, d_weights, r0, n, K, tag, d_grad_weights, d_grad_scalars, sig_miss);
+                             d_samples, d_weights, r0, n, K, tag, 0u, 0u, d_grad_weights, d_grad_scalars, sig_miss);
         else
           hipLaunchKernelGGL((backward_seg_kernel<false, false>), tiles, threads, 0, st, map->dm, gb, d_origins, sc,
-                             d_samples, d_weights, r0, n, K, tag, d_grad_weights, d_grad_scalars, sig_miss);
+                             d_samples, d_weights, r0, n, K, tag, 0u, 0u, d_grad_weights, d_grad_scalars, sig_miss);
       }
     }
     if (ndt) {
-      const uint32_t ftag = ++map->count_batches;
-      const uint32_t parity = ftag & 1u;
-      hipLaunchKernelGGL(ndt_fold_kernel, grid, dim3(256), 0, st, map->dm, d_origins, sc, d_samples, r0, n, ftag,
-                         parity);
       // fold only: the accumulators hold no increments, so occupancy is unchanged
-      hipLaunchKernelGGL(ndt_finalize_kernel, dim3(kFinalizeBlocks), dim3(256), 0, st, map->dm, parity, 1, 0u);
+      ProfScope ps(map, OHM_KERNEL_NDT_HIT, st);
+      hipLaunchKernelGGL(ndt_finalize_kernel, dim3(kFinalizeBlocks), dim3(256), 0, st, map->dm, fparity, 1, 0u);
     }
   }
   hipError_t e = hipGetLastError();

@@ -97,16 +97,13 @@ __global__ __launch_bounds__(256) void order_scatter_kernel(const SetPtrs* __res
               sums + d.sbase, sp.perm + d.r0);
 }
 
-// per-set group accumulators: G slots of [capacity][V][2] floats
-__device__ __forceinline__ size_t acc_slot_floats(const DevMap& m) { return (size_t)m.capacity * kRegionVoxels * 2; }
-
 template <bool kWeighted>
 __global__ __launch_bounds__(1024) void batch_walk_kernel(const DevMap* __restrict__ maps,
                                                           const SetPtrs* __restrict__ sets,
                                                           const BlockDesc* __restrict__ descs, int K) {
   const BlockDesc d = descs[blockIdx.x];
   DevMap m = maps[d.set];
-  m.acc += (size_t)d.pos * acc_slot_floats(m);
+  m.acc += (size_t)d.pos * acc_slot_floats(m, kWeighted);
   const uint32_t tag = __hip_atomic_load(m.hdr + kHdrBatchTag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   const SetPtrs sp = sets[d.set];
   walk_tile<kSinkCount, kWeighted>(m, sp.origins + 3 * (size_t)d.scan, sp.samples, sp.weights,
@@ -115,7 +112,9 @@ __global__ __launch_bounds__(1024) void batch_walk_kernel(const DevMap* __restri
 }
 
 // Applies the group's scans in order to every voxel of the regions the group
-// touched: for j = 0..G-1, l = clamp((l + H_j l_hit) + M_j l_miss).
+// touched: for j = 0..G-1, l = clamp((l + H_j l_hit) + M_j l_miss) (kWide:
+// Q32.32 weight sums applied in fp64, as the per-scan path does).
+template <bool kWide>
 __global__ __launch_bounds__(256) void batch_finalize_kernel(const DevMap* __restrict__ maps, uint32_t n_sets,
                                                              uint32_t group) {
   constexpr int kChunk = 1024;
@@ -126,10 +125,34 @@ __global__ __launch_bounds__(256) void batch_finalize_kernel(const DevMap* __res
     const uint32_t parity = tag & 1u;
     const uint32_t count = __hip_atomic_load(m.hdr + kHdrTouched0 + parity, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     const uint32_t units = count * kUnits;
-    const size_t stride = acc_slot_floats(m);
+    const size_t stride = acc_slot_floats(m, kWide);
     for (uint32_t u = blockIdx.x; u < units; u += gridDim.x) {
       const uint32_t slot = m.touched[(size_t)parity * m.capacity + u / kUnits];
       const size_t base = (size_t)slot * kRegionVoxels + (size_t)(u % kUnits) * kChunk;
+      if constexpr (kWide) {
+        for (int v = threadIdx.x; v < kChunk; v += blockDim.x) {
+          const size_t vi = base + v;
+          longlong2* const a0 = reinterpret_cast<longlong2*>(m.acc) + vi;
+          const size_t step = stride / 4;  // longlong2 elements per slot
+          float l = m.occ[vi];
+          bool any = false;
+          constexpr int kBatch = 8;
+          for (uint32_t j0 = 0; j0 < group; j0 += kBatch) {
+            longlong2 a[kBatch];
+#pragma unroll
+            for (int q = 0; q < kBatch; ++q) a[q] = j0 + q < group ? a0[(j0 + q) * step] : make_longlong2(0, 0);
+#pragma unroll
+            for (int q = 0; q < kBatch; ++q) {
+              if (a[q].x == 0 && a[q].y == 0) continue;
+              l = apply_wide(m, l, a[q].x, a[q].y, vi, 0u);  // (the plan's maps keep no clamp record)
+              a0[(j0 + q) * step] = make_longlong2(0, 0);
+              any = true;
+            }
+          }
+          if (any) m.occ[vi] = l;
+        }
+        continue;
+      }
       for (int v = threadIdx.x; v < kChunk; v += blockDim.x) {
         const size_t vi = base + v;
         float2* const a0 = reinterpret_cast<float2*>(m.acc) + vi;
@@ -168,6 +191,17 @@ __global__ void batch_advance_kernel(const DevMap* __restrict__ maps, uint32_t n
   const uint32_t tag = m.hdr[kHdrBatchTag] + 1u;
   m.hdr[kHdrBatchTag] = tag;
   m.hdr[kHdrTouched0 + (tag & 1u)] = 0u;
+}
+
+// End of a replay: empty both touched lists, so that a later per-scan call
+// on the map (which expects the list of its scan's parity to start empty)
+// does not append after this replay's last group.
+__global__ void batch_end_kernel(const DevMap* __restrict__ maps, uint32_t n_sets) {
+  const uint32_t si = threadIdx.x;
+  if (si >= n_sets) return;
+  const DevMap& m = maps[si];
+  m.hdr[kHdrTouched0] = 0u;
+  m.hdr[kHdrTouched1] = 0u;
 }
 
 // Start of a replay: empty both touched lists; start the tag sequence once.
@@ -303,7 +337,7 @@ ohm_status plan_layout(const ohm_scan_set* sets, uint32_t n_sets, const ohm_batc
   L->acc.resize(n_sets);
   for (uint32_t si = 0; si < n_sets; ++si) {
     L->acc[si] = off;
-    off = align_b(off + (size_t)G * sets[si].map->dm.capacity * kRegionVoxels * 2 * sizeof(float));
+    off = align_b(off + (size_t)G * acc_slot_floats(sets[si].map->dm, weighted) * sizeof(float));
   }
   L->total = off;
   return OHM_OK;
@@ -378,7 +412,7 @@ ohm_status ohm_batch_create(const ohm_scan_set* sets, uint32_t n_sets, const ohm
     ok = ok && hipMemcpyAsync(b->d_scans, L.host_scans.data(), L.host_scans.size() * sizeof(ScanDesc),
                               hipMemcpyHostToDevice, st) == hipSuccess;
   for (uint32_t si = 0; si < n_sets && ok; ++si) {
-    const size_t nf = (size_t)b->group * hm[si].capacity * kRegionVoxels * 2;
+    const size_t nf = (size_t)b->group * acc_slot_floats(hm[si], b->weighted);
     hipLaunchKernelGGL(fill_u32_kernel, dim3(8192), dim3(256), 0, st, reinterpret_cast<uint32_t*>(hm[si].acc), nf,
                        0u);
   }
@@ -414,10 +448,15 @@ ohm_status ohm_batch_create(const ohm_scan_set* sets, uint32_t n_sets, const ohm
           hipLaunchKernelGGL(batch_walk_kernel<false>, dim3(b->group_blocks[g]), dim3(b->tile_threads), 0,
                              b->capture, b->d_maps, b->d_sets, b->d_descs + b->group_first[g], b->seg_major_steps);
       }
-      hipLaunchKernelGGL(batch_finalize_kernel, dim3(kFinalizeBlocks), dim3(256), 0, b->capture, b->d_maps, n_sets,
-                         b->group);
+      if (b->weighted)
+        hipLaunchKernelGGL(batch_finalize_kernel<true>, dim3(kFinalizeBlocks), dim3(256), 0, b->capture, b->d_maps,
+                           n_sets, b->group);
+      else
+        hipLaunchKernelGGL(batch_finalize_kernel<false>, dim3(kFinalizeBlocks), dim3(256), 0, b->capture, b->d_maps,
+                           n_sets, b->group);
       hipLaunchKernelGGL(batch_advance_kernel, dim3(1), dim3(64), 0, b->capture, b->d_maps, n_sets);
     }
+    hipLaunchKernelGGL(batch_end_kernel, dim3(1), dim3(64), 0, b->capture, b->d_maps, n_sets);
     ok = hipStreamEndCapture(b->capture, &b->graph) == hipSuccess;
   }
   ok = ok && hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0) == hipSuccess;
@@ -437,7 +476,10 @@ ohm_status ohm_batch_run(ohm_batch b, void* stream) {
   hipStream_t st = reinterpret_cast<hipStream_t>(stream);
   for (ohm_map m : b->maps) clear_pending(m, st);
   if (hipGraphLaunch(b->exec, st) != hipSuccess) return OHM_E_HIP;
-  for (uint32_t si = 0; si < b->n_sets; ++si) b->maps[si]->scans_done += b->nonempty[si];
+  for (uint32_t si = 0; si < b->n_sets; ++si) {
+    b->maps[si]->scans_done += b->nonempty[si];
+    b->maps[si]->batched = true;  // no per-scan clamp record: the adjoint refuses the map
+  }
   return OHM_OK;
 }
 

@@ -36,6 +36,12 @@ enum : int {
   kHdrBatchTag = 4,  // scan tag of the batched path (device-resident, survives graph replays)
   kHdrWords = 64
 };
+// sticky error bits (header word kHdrSticky)
+enum : int32_t {
+  kStickyPoolExhausted = 1,  // a region did not fit in the pool
+  kStickySlotTimeout = 2,    // a region slot another block was publishing never appeared
+  kStickyBadWeight = 4       // a ray weight was negative or not finite (the ray was skipped)
+};
 enum : int {
   kStatRays = 0,
   kStatInvalid,
@@ -79,6 +85,32 @@ struct DevMap {
   double* mom;        // NDT per-scan sample moments [capacity][V][kMomWords] or null
   uint32_t* clampscan;// [capacity][V] or null
 };
+
+// Q32.32 fixed point of the exact (order-independent) sums of weights and
+// NDT increments: each term is rounded to a multiple of 2^-32 once, and the
+// integer sums do not depend on the order the GPU adds them in.
+constexpr double kQ32 = 4294967296.0;
+constexpr double kInvQ32 = 1.0 / 4294967296.0;
+
+// Floats per count-mode accumulator slot: [capacity][V] pairs (miss, hit),
+// f32 counts for unit weights, int64 Q32.32 weight sums (wide) with weights.
+__host__ __device__ __forceinline__ size_t acc_slot_floats(const DevMap& m, bool wide) {
+  return (size_t)m.capacity * kRegionVoxels * (wide ? 4 : 2);
+}
+
+// The count-then-clamp update of one voxel from wide (Q32.32 weight sum)
+// accumulators: s = (l + H l_hit) + M l_miss in fp64, recorded in the clamp
+// layer (when present) if outside the clamp range, clamped, stored as float.
+__device__ __forceinline__ float apply_wide(const DevMap& m, float l, long long miss_q, long long hit_q, size_t vi,
+                                            uint32_t scan_tag) {
+#pragma clang fp contract(off)
+  const double hw = (double)hit_q * kInvQ32, mw = (double)miss_q * kInvQ32;
+  const double lmin = m.l_min, lmax = m.l_max;
+  double s = ((double)l + hw * (double)m.l_hit) + mw * (double)m.l_miss;
+  if (m.clampscan && (s < lmin || s > lmax)) m.clampscan[vi] = scan_tag;
+  s = s < lmin ? lmin : (s > lmax ? lmax : s);
+  return (float)s;
+}
 
 // NDT per-scan accumulators, exact integers: summed miss increment and summed
 // hit weight in Q32.32 fixed point, and the number of samples

@@ -21,9 +21,11 @@ struct ohm_map_s {
   int device;
   uint32_t count_batches;  // count-mode scans so far (tags and list parity)
   uint32_t scans_done;     // scans integrated since create / reset
+  bool batched;            // a batched plan ran on the map since create / reset
   bool acc_dirty;          // the last count-mode scan's accumulators are still set
   uint32_t last_parity;
   uint32_t kept_slot;      // accumulator slot holding those counts (scan groups), else 0
+  bool kept_wide;          // ... as Q32.32 weight sums (a weighted scan), two f32 slots wide
   int seg_major_steps;     // walk tuning (ohm_map_set_tuning)
   uint32_t walk_threads;
   // direction ordering of scans (ohm_map_set_ray_order): caller scratch
@@ -63,9 +65,6 @@ constexpr uint32_t kDefaultTileThreads = 512;
 __global__ void fill_u32_kernel(uint32_t* p, size_t n, uint32_t v);
 __global__ __launch_bounds__(256) void ndt_finalize_kernel(DevMap m, uint32_t parity, int count_mode,
                                                            uint32_t scan_tag);
-__global__ __launch_bounds__(256) void ndt_fold_kernel(DevMap m, const float* __restrict__ origins, uint32_t scan,
-                                                       const float* __restrict__ samples, uint32_t r0, uint32_t n,
-                                                       uint32_t tag, uint32_t parity);
 
 ohm_status map_initialise(ohm_map_s* map, hipStream_t st);
 ohm_status check_scans(ohm_map map, const float* d_origins, const float* d_samples, const uint32_t* h_offsets,

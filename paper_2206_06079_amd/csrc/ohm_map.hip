@@ -101,14 +101,29 @@ __global__ __launch_bounds__(256) void scan_order_place_kernel(const float* __re
 constexpr int kFinalChunk = 1024;  // voxels per work unit
 constexpr int kFinalUnits = kRegionVoxels / kFinalChunk;
 
-// Applies l <- clamp((l + H l_hit) + M') to every voxel of the touched
-// regions, where M' = M l_miss (plain) or the summed NDT miss delta.  With
-// `apply` = 0 only clears the accumulators.  Clears the accumulators when
-// `clear`, and resets the other parity's touched counter for the next scan.
+// Applies l <- clamp((l + H l_hit) + M l_miss) to every voxel of the touched
+// regions (kWide: from Q32.32 weight sums, in fp64).  With `apply` = 0 only
+// clears the accumulators.  Clears the accumulators when `clear`, and resets
+// the other parity's touched counter for the next scan.
+template <bool kWide>
 __global__ __launch_bounds__(256) void finalize_kernel(DevMap m, uint32_t parity, int apply, int clear,
-                                                       int miss_is_delta, uint32_t scan_tag) {
+                                                       uint32_t scan_tag) {
   const uint32_t count = __hip_atomic_load(m.hdr + kHdrTouched0 + parity, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   const uint32_t units = count * kFinalUnits;
+  if constexpr (kWide) {
+    for (uint32_t u = blockIdx.x; u < units; u += gridDim.x) {
+      const uint32_t slot = m.touched[(size_t)parity * m.capacity + u / kFinalUnits];
+      const size_t base = (size_t)slot * kRegionVoxels + (size_t)(u % kFinalUnits) * kFinalChunk;
+      for (int v = threadIdx.x; v < kFinalChunk; v += blockDim.x) {
+        const size_t vi = base + v;
+        longlong2* ap = reinterpret_cast<longlong2*>(m.acc) + vi;  // (miss, hit)
+        const longlong2 a = *ap;
+        if (a.x == 0 && a.y == 0) continue;
+        if (apply) m.occ[vi] = apply_wide(m, m.occ[vi], a.x, a.y, vi, scan_tag);
+        if (clear) *ap = make_longlong2(0, 0);
+      }
+    }
+  } else {
   for (uint32_t u = blockIdx.x; u < units; u += gridDim.x) {
     const uint32_t slot = m.touched[(size_t)parity * m.capacity + u / kFinalUnits];
     const size_t base = (size_t)slot * kRegionVoxels + (size_t)(u % kFinalUnits) * kFinalChunk;
@@ -126,7 +141,7 @@ __global__ __launch_bounds__(256) void finalize_kernel(DevMap m, uint32_t parity
         for (int j = 0; j < 2; ++j) {
           if (mw[j] == 0.f && hw[j] == 0.f) continue;
           const float t = __fmul_rn(hw[j], m.l_hit);
-          const float uu = miss_is_delta ? mw[j] : __fmul_rn(mw[j], m.l_miss);
+          const float uu = __fmul_rn(mw[j], m.l_miss);
           float s = __fadd_rn(lv[j], t);
           s = __fadd_rn(s, uu);
           if (m.clampscan && (s < m.l_min || s > m.l_max)) m.clampscan[base + v + j] = scan_tag;
@@ -136,6 +151,7 @@ __global__ __launch_bounds__(256) void finalize_kernel(DevMap m, uint32_t parity
       }
       if (clear) *ap = make_float4(0.f, 0.f, 0.f, 0.f);
     }
+  }
   }
   if (blockIdx.x == 0 && threadIdx.x == 0)
     __hip_atomic_store(m.hdr + kHdrTouched0 + (parity ^ 1u), 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -163,7 +179,7 @@ __global__ __launch_bounds__(1024) void walk_group_kernel(DevMap m, const float*
   while (j + 1 < g.count && blockIdx.x >= g.tile_end[j]) ++j;
   const uint32_t tile = blockIdx.x - (j ? g.tile_end[j - 1] : 0u);
   DevMap mj = m;
-  mj.acc += (size_t)j * m.capacity * kRegionVoxels * 2;
+  mj.acc += (size_t)j * acc_slot_floats(m, kWeighted);
   walk_tile<kSinkCount, kWeighted>(mj, origins + 3 * (size_t)g.scan[j], samples, weights, nullptr, g.r0[j], g.n[j],
                                    tile * kTileRays, K, tag, parity, nullptr, nullptr, nullptr, nullptr);
 }
@@ -174,11 +190,42 @@ constexpr int kGroupBatch = 8;  // accumulator slots loaded together by a group 
 // touched: l = clamp((l + H_j l_hit) + M_j l_miss) for j = 0..g-1, recording
 // the clamp scan (scan_tag0 + j), and clear the slots except slot `keep`
 // (the call's last scan, whose counts stay readable; keep >= g keeps none).
+// kWide: the slots hold Q32.32 weight sums (weighted scans), applied in fp64.
+template <bool kWide>
 __global__ __launch_bounds__(256) void group_finalize_kernel(DevMap m, uint32_t parity, uint32_t g,
                                                              uint32_t scan_tag0, uint32_t keep) {
   const uint32_t count = __hip_atomic_load(m.hdr + kHdrTouched0 + parity, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   const uint32_t units = count * kFinalUnits;
-  const size_t stride = (size_t)m.capacity * kRegionVoxels;  // float2 elements per slot
+  const size_t stride = (size_t)m.capacity * kRegionVoxels;  // accumulator pairs per slot
+  if constexpr (kWide) {
+    for (uint32_t u = blockIdx.x; u < units; u += gridDim.x) {
+      const uint32_t slot = m.touched[(size_t)parity * m.capacity + u / kFinalUnits];
+      const size_t base = (size_t)slot * kRegionVoxels + (size_t)(u % kFinalUnits) * kFinalChunk;
+      for (int v = threadIdx.x; v < kFinalChunk; v += blockDim.x) {
+        const size_t vi = base + v;
+        longlong2* const a0 = reinterpret_cast<longlong2*>(m.acc) + vi;
+        float l = m.occ[vi];
+        bool any = false;
+        for (uint32_t j0 = 0; j0 < g; j0 += kGroupBatch) {
+          longlong2 a[kGroupBatch];
+#pragma unroll
+          for (int q = 0; q < kGroupBatch; ++q) a[q] = j0 + q < g ? a0[(j0 + q) * stride] : make_longlong2(0, 0);
+#pragma unroll
+          for (int q = 0; q < kGroupBatch; ++q) {
+            if (a[q].x == 0 && a[q].y == 0) continue;
+            const uint32_t j = j0 + q;
+            l = apply_wide(m, l, a[q].x, a[q].y, vi, scan_tag0 + j);
+            if (j != keep) a0[j * stride] = make_longlong2(0, 0);
+            any = true;
+          }
+        }
+        if (any) m.occ[vi] = l;
+      }
+    }
+    if (blockIdx.x == 0 && threadIdx.x == 0)
+      __hip_atomic_store(m.hdr + kHdrTouched0 + (parity ^ 1u), 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    return;
+  }
   for (uint32_t u = blockIdx.x; u < units; u += gridDim.x) {
     const uint32_t slot = m.touched[(size_t)parity * m.capacity + u / kFinalUnits];
     const size_t base = (size_t)slot * kRegionVoxels + (size_t)(u % kFinalUnits) * kFinalChunk;
@@ -218,8 +265,8 @@ __global__ __launch_bounds__(256) void group_finalize_kernel(DevMap m, uint32_t 
 // dense read-back
 // ---------------------------------------------------------------------------
 
-__global__ __launch_bounds__(256) void read_dense_kernel(DevMap m, int what, int32_t bx, int32_t by, int32_t bz,
-                                                         int32_t dx, int32_t dy, int32_t dz, void* out) {
+__global__ __launch_bounds__(256) void read_dense_kernel(DevMap m, int what, int wide, int32_t bx, int32_t by,
+                                                         int32_t bz, int32_t dx, int32_t dy, int32_t dz, void* out) {
   const size_t nvox = (size_t)dx * dy * dz;
   size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= nvox) return;
@@ -235,11 +282,15 @@ __global__ __launch_bounds__(256) void read_dense_kernel(DevMap m, int what, int
       static_cast<float*>(out)[i] = slot >= 0 ? m.occ[v] : m.l_init;
       break;
     case OHM_READ_HITS:
-      static_cast<float*>(out)[i] = slot >= 0 ? m.acc[2 * v + 1] : 0.f;
+    case OHM_READ_MISSES: {
+      const int kind = what == OHM_READ_HITS ? 1 : 0;
+      float c = 0.f;
+      if (slot >= 0)
+        c = wide ? (float)((double)reinterpret_cast<const long long*>(m.acc)[2 * v + kind] * kInvQ32)
+                 : m.acc[2 * v + kind];
+      static_cast<float*>(out)[i] = c;
       break;
-    case OHM_READ_MISSES:
-      static_cast<float*>(out)[i] = slot >= 0 ? m.acc[2 * v] : 0.f;
-      break;
+    }
     case OHM_READ_NDT_COUNT:
       static_cast<uint32_t*>(out)[i] = slot >= 0 ? m.ndt[v].n : 0u;
       break;
@@ -329,7 +380,8 @@ ohm_status compute_layout(const ohm_params* p, uint32_t capacity, uint32_t layer
   L->occ = off;
   off = align_up(off + (size_t)capacity * V * sizeof(float));
   L->acc = off;
-  off = align_up(off + (size_t)capacity * V * 2 * sizeof(float) * slots);
+  // at least two f32 slots: a weighted scan's wide (int64) slot spans two
+  off = align_up(off + (size_t)capacity * V * 2 * sizeof(float) * (slots < 2 ? 2 : slots));
   L->ndt = L->nacc = L->mom = L->clampscan = 0;
   if (layers & OHM_LAYER_NDT) {
     L->ndt = off;
@@ -396,7 +448,7 @@ ohm_status map_initialise(ohm_map_s* map, hipStream_t st) {
   uint32_t init_bits;
   memcpy(&init_bits, &m.l_init, sizeof(init_bits));
   launch_fill(m.occ, (size_t)m.capacity * V * sizeof(float), init_bits, st);
-  launch_fill(m.acc, (size_t)m.capacity * V * 2 * sizeof(float) * map->group_slots,
+  launch_fill(m.acc, (size_t)m.capacity * V * 2 * sizeof(float) * (map->group_slots < 2 ? 2 : map->group_slots),
               0u, st);
   if (m.ndt) {
     launch_fill(m.ndt, (size_t)m.capacity * V * sizeof(NdtVoxel), 0u, st);
@@ -407,7 +459,9 @@ ohm_status map_initialise(ohm_map_s* map, hipStream_t st) {
   map->count_batches = 0;
   map->acc_dirty = false;
   map->kept_slot = 0;
+  map->kept_wide = false;
   map->scans_done = 0;
+  map->batched = false;
   return last_hip_status();
 }
 
@@ -457,7 +511,7 @@ ProfScope::~ProfScope() {
 // count-mode scan's counts.
 DevMap kept_counts(const ohm_map_s* map) {
   DevMap m = map->dm;
-  m.acc += (size_t)map->kept_slot * m.capacity * kRegionVoxels * 2;
+  m.acc += (size_t)map->kept_slot * acc_slot_floats(m, map->kept_wide);
   return m;
 }
 
@@ -465,10 +519,15 @@ DevMap kept_counts(const ohm_map_s* map) {
 void clear_pending(ohm_map_s* map, hipStream_t st) {
   if (!map->acc_dirty) return;
   ProfScope ps(map, OHM_KERNEL_FINALIZE, st);
-  hipLaunchKernelGGL(finalize_kernel, dim3(kFinalizeBlocks), dim3(256), 0, st, kept_counts(map), map->last_parity,
-                     0, 1, 0, 0u);
+  if (map->kept_wide)
+    hipLaunchKernelGGL(finalize_kernel<true>, dim3(kFinalizeBlocks), dim3(256), 0, st, kept_counts(map),
+                       map->last_parity, 0, 1, 0u);
+  else
+    hipLaunchKernelGGL(finalize_kernel<false>, dim3(kFinalizeBlocks), dim3(256), 0, st, kept_counts(map),
+                       map->last_parity, 0, 1, 0u);
   map->acc_dirty = false;
   map->kept_slot = 0;
+  map->kept_wide = false;
 }
 
 }  // namespace ohm
@@ -476,6 +535,12 @@ void clear_pending(ohm_map_s* map, hipStream_t st) {
 using namespace ohm;
 
 extern "C" {
+
+#ifndef OHM_SOURCE_DIGEST
+#define OHM_SOURCE_DIGEST "unknown"
+#endif
+
+const char* ohm_build_source_digest(void) { return OHM_SOURCE_DIGEST; }
 
 const char* ohm_status_string(ohm_status s) {
   switch (s) {
@@ -601,11 +666,13 @@ ohm_status ohm_integrate_rays(ohm_map map, const float* d_origins, const float* 
     // keeps its counts readable in that scan's slot
     const uint32_t threads = map->walk_threads;
     const int K = map->seg_major_steps;
+    // a weighted scan's wide slot takes two of the map's f32 slots
+    const uint32_t group_max = weighted ? map->group_slots / 2 : map->group_slots;
     uint32_t sc = 0;
-    while (sc <= last) {
+    while (sc <= last && group_max > 0) {
       GroupArgs g = {};
       uint32_t tiles = 0;
-      for (; sc <= last && g.count < map->group_slots; ++sc) {
+      for (; sc <= last && g.count < group_max; ++sc) {
         const uint32_t r0 = h_scan_offsets[sc];
         const uint32_t n = h_scan_offsets[sc + 1] - r0;
         if (n == 0) continue;
@@ -633,17 +700,22 @@ ohm_status ohm_integrate_rays(ohm_map map, const float* d_origins, const float* 
       const uint32_t keep = has_last ? g.count - 1 : kMaxGroupSlots;
       {
         ProfScope ps(map, OHM_KERNEL_FINALIZE_GROUP, st);
-        hipLaunchKernelGGL(group_finalize_kernel, dim3(kFinalizeBlocks), dim3(256), 0, st, map->dm, parity, g.count,
-                           map->scans_done + 1, keep);
+        if (weighted)
+          hipLaunchKernelGGL(group_finalize_kernel<true>, dim3(kFinalizeBlocks), dim3(256), 0, st, map->dm, parity,
+                             g.count, map->scans_done + 1, keep);
+        else
+          hipLaunchKernelGGL(group_finalize_kernel<false>, dim3(kFinalizeBlocks), dim3(256), 0, st, map->dm, parity,
+                             g.count, map->scans_done + 1, keep);
       }
       map->scans_done += g.count;
       if (has_last) {
         map->acc_dirty = true;
         map->last_parity = parity;
         map->kept_slot = keep;
+        map->kept_wide = weighted;
       }
     }
-    first = n_scans;
+    if (group_max > 0) first = n_scans;
   }
   for (uint32_t sc = first; sc < n_scans; ++sc) {
     const uint32_t r0 = h_scan_offsets[sc];
@@ -689,12 +761,17 @@ ohm_status ohm_integrate_rays(ohm_map map, const float* d_origins, const float* 
       const bool keep = sc == last;
       {
         ProfScope ps(map, OHM_KERNEL_FINALIZE, st);
-        hipLaunchKernelGGL(finalize_kernel, dim3(kFinalizeBlocks), dim3(256), 0, st, map->dm, parity, 1,
-                           keep ? 0 : 1, 0, map->scans_done + 1);
+        if (weighted)
+          hipLaunchKernelGGL(finalize_kernel<true>, dim3(kFinalizeBlocks), dim3(256), 0, st, map->dm, parity, 1,
+                             keep ? 0 : 1, map->scans_done + 1);
+        else
+          hipLaunchKernelGGL(finalize_kernel<false>, dim3(kFinalizeBlocks), dim3(256), 0, st, map->dm, parity, 1,
+                             keep ? 0 : 1, map->scans_done + 1);
       }
       if (keep) {
         map->acc_dirty = true;
         map->last_parity = parity;
+        map->kept_wide = weighted;
       }
     } else {
       ProfScope ps(map, OHM_KERNEL_WALK, st);
@@ -723,7 +800,7 @@ ohm_status ohm_map_read_dense(ohm_map map, int32_t what, const int32_t h_box_min
   const size_t blocks = (n + 255) / 256;
   if (blocks > 0x7fffffff) return OHM_E_INVALID_ARG;
   hipLaunchKernelGGL(read_dense_kernel, dim3((unsigned)blocks), dim3(256), 0, as_stream(stream), kept_counts(map), what,
-                     h_box_min[0], h_box_min[1], h_box_min[2], h_box_dim[0], h_box_dim[1], h_box_dim[2], d_out);
+                     map->kept_wide ? 1 : 0, h_box_min[0], h_box_min[1], h_box_min[2], h_box_dim[0], h_box_dim[1], h_box_dim[2], d_out);
   return last_hip_status();
 }
 

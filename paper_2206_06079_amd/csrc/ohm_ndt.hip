@@ -32,8 +32,6 @@
 
 namespace ohm {
 
-constexpr double kQ = 4294967296.0;  // 2^32: Q32.32 scale
-constexpr double kInvQ = 1.0 / 4294967296.0;
 
 // The NDT-weighted miss increment (see the file comment).  o / d: ray start
 // and direction (end - start), world, fp64; c: voxel centre; nv: statistics.
@@ -115,7 +113,7 @@ __device__ __forceinline__ void ndt_apply(const DevMap& m, uint32_t id, long lon
               (unsigned long long)qs);
   } else {
     uint32_t* u = reinterpret_cast<uint32_t*>(m.occ + v);
-    const float delta = (float)((double)qs * kInvQ);
+    const float delta = (float)((double)qs * kInvQ32);
     uint32_t old = __hip_atomic_load(u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     for (;;) {
       const float nvv = fminf(fmaxf(__uint_as_float(old) + delta, m.l_min), m.l_max);
@@ -156,7 +154,7 @@ __device__ __forceinline__ void ndt_drain(const DevMap& m, const NdtPending* pen
     const double c[3] = {m.origin[0] + ((double)e.k[0] + 0.5) * m.voxel_size,
                          m.origin[1] + ((double)e.k[1] + 0.5) * m.voxel_size,
                          m.origin[2] + ((double)e.k[2] + 0.5) * m.voxel_size};
-    const long long q = llrint(ndt_delta(m, od, dv, dd, c, nv, sig_miss) * wt * kQ);
+    const long long q = llrint(ndt_delta(m, od, dv, dd, c, nv, sig_miss) * wt * kQ32);
     if (!ndt_agg_add(agg_key, agg_val, e.id, q)) ndt_apply<kCount>(m, e.id, q);
   }
 }
@@ -184,7 +182,8 @@ __global__ __launch_bounds__(kNdtMaxThreads, 4) void ndt_seg_kernel(DevMap m, co
   TileRay t;
   RegionWindow rw;
   const uint32_t items =
-      tile_prologue<kStageTouch>(m, tr, rc, rw, origin, samples, nullptr, r0, n, tile0, K, tag, parity, t);
+      tile_prologue<kStageTouch>(m, tr, rc, rw, origin, samples, kWeighted ? weights : nullptr, nullptr, r0, n,
+                                 tile0, K, tag, parity, t);
   if (t.ok)
     for (int a = 0; a < 3; ++a) ray_end[a][tid] = t.r.end[a];
   __syncthreads();
@@ -219,7 +218,7 @@ __global__ __launch_bounds__(kNdtMaxThreads, 4) void ndt_seg_kernel(DevMap m, co
       if (alive) slot = staged_slot(m, rc, rw, s.k[0], s.k[1], s.k[2]);
       lidx = local_index(s.k[0], s.k[1], s.k[2]);
     }
-    const long long q_plain = llrint((double)m.l_miss * wt * kQ);
+    const long long q_plain = llrint((double)m.l_miss * wt * kQ32);
     // sample count of the voxel being visited, loaded one step ahead so the
     // load's latency overlaps the previous voxel's update work
     uint32_t cnt = (alive && slot >= 0) ? m.ndt[(size_t)slot * kRegionVoxels + lidx].n : 0u;
@@ -234,7 +233,7 @@ __global__ __launch_bounds__(kNdtMaxThreads, 4) void ndt_seg_kernel(DevMap m, co
       bool deferred = false;
       if (has) {
         if (is_hit) {
-          q = llrint(wt * kQ);
+          q = llrint(wt * kQ32);
         } else if (cnt >= m.ndt_min_samples) {
           deferred = true;
         } else {
@@ -335,8 +334,8 @@ __global__ __launch_bounds__(256) void ndt_finalize_kernel(DevMap m, uint32_t pa
       const longlong2 a01 = ap[0];
       const longlong2 a23 = ap[1];
       if (a01.x == 0 && a01.y == 0 && a23.x == 0) continue;
-      const double miss = (double)a01.x * kInvQ;
-      const double hitw = (double)a01.y * kInvQ;
+      const double miss = (double)a01.x * kInvQ32;
+      const double hitw = (double)a01.y * kInvQ32;
       double l = (double)m.occ[v];
       double s = count_mode ? (l + hitw * (double)m.l_hit) + miss : l + hitw * (double)m.l_hit;
       if (m.clampscan && (s < lmin || s > lmax)) m.clampscan[v] = scan_tag;

@@ -86,7 +86,7 @@ __device__ int32_t resolve_region(const DevMap& m, int32_t r, uint32_t tag, uint
     if (old == kSlotEmpty) {
       const uint32_t s = atomicAdd(m.hdr + kHdrPoolCount, 1u);
       slot = s < m.capacity ? (int32_t)s : kSlotExhausted;
-      if (slot == kSlotExhausted) atomicOr(reinterpret_cast<int32_t*>(m.hdr + kHdrSticky), 1);
+      if (slot == kSlotExhausted) atomicOr(reinterpret_cast<int32_t*>(m.hdr + kHdrSticky), kStickyPoolExhausted);
       __hip_atomic_store(m.table + r, slot, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     } else {
       slot = old;
@@ -98,7 +98,7 @@ __device__ int32_t resolve_region(const DevMap& m, int32_t r, uint32_t tag, uint
     slot = __hip_atomic_load(m.table + r, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   }
   if (slot == kSlotClaimed) {
-    atomicOr(reinterpret_cast<int32_t*>(m.hdr + kHdrSticky), 2);
+    atomicOr(reinterpret_cast<int32_t*>(m.hdr + kHdrSticky), kStickySlotTimeout);
     return kSlotExhausted;
   }
   if (kTouch && slot >= 0) {

@@ -11,6 +11,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <type_traits>
+
 #include "ohm_device.h"
 #include "ohm_regions.h"
 #include "ohm_seg_math.h"
@@ -52,10 +54,7 @@ __device__ __forceinline__ void cas_clamp_add(float* p, float delta, float lo, f
 // side's atomic throughput is counted in lines, and scattered atomics are
 // what bounds the walk once the voxel steps are cheap.  The second probe
 // takes the same position in the next group.
-#ifndef OHM_AGG_LOG2
-#define OHM_AGG_LOG2 12
-#endif
-constexpr int kAggLog2 = OHM_AGG_LOG2;
+constexpr int kAggLog2 = 12;
 constexpr uint32_t kAggSize = 1u << kAggLog2;
 constexpr uint32_t kAggEmpty = 0xFFFFFFFFu;  // above every update id (capacity <= kMaxCapacity)
 constexpr uint32_t kAggLine = 16;            // ids per 64-byte accumulator line
@@ -78,7 +77,8 @@ __device__ __forceinline__ bool agg_own(uint32_t* keys, uint32_t h, uint32_t id,
 // Second half of an insert whose first entry's key k = keys[agg_slot(id)]
 // was read earlier: add v to the id's entry among the two probes.  False
 // when both belong to other ids.
-__device__ __forceinline__ bool agg_finish(uint32_t* keys, float* vals, uint32_t id, uint32_t k, float v) {
+template <typename T>
+__device__ __forceinline__ bool agg_finish(uint32_t* keys, T* vals, uint32_t id, uint32_t k, T v) {
   uint32_t h = agg_slot(id);
   if (!agg_own(keys, h, id, k)) {
     h = (h + kAggLine) & (kAggSize - 1);
@@ -126,7 +126,8 @@ enum : int { kStageNone = 0, kStageResolve = 1, kStageTouch = 2 };
 
 // Prologue of a tile walk (every thread of the block must call it): threads
 // 0..255 prepare rays tile0.. of the scan in walk order (perm[i] is the scan
-// index of walk position i; null: the scan's own order) and fill the LDS
+// index of walk position i; null: the scan's own order), reject rays whose
+// weight (when weights is not null) is negative or not finite, and fill the LDS
 // ray table, the block stages the tile's regions in LDS (kStage), and the
 // level-major item list is built: level j lists, in ray order, the rays with
 // more than j segments.  Returns the number of items; tr.max_seg holds the
@@ -134,6 +135,7 @@ enum : int { kStageNone = 0, kStageResolve = 1, kStageTouch = 2 };
 template <int kStage>
 __device__ __forceinline__ uint32_t tile_prologue(const DevMap& m, TileRays& tr, RegionCache& rc, RegionWindow& rw,
                                                   const float* __restrict__ origin, const float* __restrict__ samples,
+                                                  const float* __restrict__ weights,
                                                   const uint32_t* __restrict__ perm, uint32_t r0, uint32_t n,
                                                   uint32_t tile0, int K, uint32_t tag, uint32_t parity, TileRay& t) {
   const uint32_t tid = threadIdx.x;
@@ -145,6 +147,7 @@ __device__ __forceinline__ uint32_t tile_prologue(const DevMap& m, TileRays& tr,
   t.clipped = false;
   t.voxels = 0;
   if (tid == 0) tr.max_seg = 0;
+  bool bad_weight = false;
   if (t.inrange) {
     const uint32_t src = perm ? perm[tile0 + tid] : tile0 + tid;
     tr.src[tid] = src;
@@ -152,8 +155,15 @@ __device__ __forceinline__ uint32_t tile_prologue(const DevMap& m, TileRays& tr,
     const float o[3] = {origin[0], origin[1], origin[2]};
     const float e[3] = {samples[3 * ray + 0], samples[3 * ray + 1], samples[3 * ray + 2]};
     t.st = prepare_ray(m, o, e, t.r);
+    if (weights) {
+      const float w = weights[ray];
+      bad_weight = !(w >= 0.f) || !__builtin_isfinite(w);
+      if (bad_weight) t.st = kRayInvalid;
+    }
     t.ok = t.st == kRayOk;
   }
+  if (__ballot(bad_weight) != 0ull && lane == 0)
+    atomicOr(reinterpret_cast<int32_t*>(m.hdr + kHdrSticky), kStickyBadWeight);
   __syncthreads();
   uint32_t nseg = 0;
   if (holds_ray) {
@@ -278,10 +288,14 @@ __device__ void walk_tile(const DevMap& m, const float* __restrict__ origin, con
   constexpr bool kAccum = kSink == kSinkCount || kSink == kSinkCas;
   constexpr int kStage = kSink == kSinkCount ? kStageTouch : (kSink == kSinkCas ? kStageResolve : kStageNone);
   constexpr bool kAgg = kAccum;
+  // weighted count mode sums Q32.32 integers (order-independent, exact up to
+  // the 2^-33 rounding of each weight) into the wide accumulators
+  constexpr bool kWide = kSink == kSinkCount && kWeighted;
+  using AggT = std::conditional_t<kWide, unsigned long long, float>;
   __shared__ TileRays tr;
   __shared__ RegionCache rc;
   __shared__ uint32_t agg_key[kAgg ? kAggSize : 1];
-  __shared__ float agg_val[kAgg ? kAggSize : 1];
+  __shared__ AggT agg_val[kAgg ? kAggSize : 1];
   // per-update mode: table misses queued per wave, clamp-added 64 at a time
   // (a compare-and-swap waits for its reply; one wave-wide batch shares it)
   constexpr bool kQueue = kSink == kSinkCas;
@@ -293,12 +307,13 @@ __device__ void walk_tile(const DevMap& m, const float* __restrict__ origin, con
   if (kAgg)
     for (uint32_t h = tid; h < kAggSize; h += blockDim.x) {
       agg_key[h] = kAggEmpty;
-      agg_val[h] = 0.f;
+      agg_val[h] = AggT(0);
     }
   TileRay t;
   RegionWindow rw;
   const uint32_t items =
-      tile_prologue<kStage>(m, tr, rc, rw, origin, samples, perm, r0, n, tile0, K, tag, parity, t);
+      tile_prologue<kStage>(m, tr, rc, rw, origin, samples, kWeighted ? weights : nullptr, perm, r0, n, tile0, K,
+                            tag, parity, t);
 
   if (kSink == kSinkTraceCount && t.inrange) {
     int32_t flags = 0;
@@ -324,6 +339,7 @@ __device__ void walk_tile(const DevMap& m, const float* __restrict__ origin, con
     int M = 0;
     SegState s = {};
     float wt = 1.f;
+    long long wq = 0;  // Q32.32 weight (wide accumulators)
     bool trunc = false;
     int32_t slot = -1;
     uint32_t lidx = 0;
@@ -333,6 +349,7 @@ __device__ void walk_tile(const DevMap& m, const float* __restrict__ origin, con
       trunc = tr.trunc[ray_t] != 0;
       const size_t ray = (size_t)r0 + tr.src[ray_t];
       if (kWeighted) wt = weights[ray];
+      if (kWide) wq = llrint((double)wt * kQ32);
       if (kSink == kSinkTraceWrite) out_base = ray_offsets[ray] + s.pos;
       if (kAccum && alive) slot = staged_slot(m, rc, rw, s.k[0], s.k[1], s.k[2]);
       lidx = local_index(s.k[0], s.k[1], s.k[2]);
@@ -346,11 +363,14 @@ __device__ void walk_tile(const DevMap& m, const float* __restrict__ origin, con
         const uint32_t id = has ? (((uint32_t)slot * (uint32_t)kRegionVoxels + lidx) << 1) | (is_hit ? 1u : 0u)
                                 : (0xFFFFFFFFu - lane);
         const LaneRuns run = lane_runs(id, lane);
-        float v = 1.f;
+        AggT v;
         bool emit_here;
-        if (!kWeighted) {
+        if constexpr (!kWeighted) {
           v = (float)run.len;
           emit_here = has && run.head;
+        } else if constexpr (kWide) {
+          v = (unsigned long long)segmented_sum<long long>(has ? wq : 0ll, run.head, lane);
+          emit_here = has && run.tail;
         } else {
           v = segmented_sum(has ? wt : 0.f, run.head, lane);
           emit_here = has && run.tail;
@@ -366,7 +386,9 @@ __device__ void walk_tile(const DevMap& m, const float* __restrict__ origin, con
         }
         if (alive) alive = !last && tile_advance<kAccum>(m, rc, rw, s, M, slot, lidx);
         const bool miss_table = emit_here && !agg_finish(agg_key, agg_val, id, k, v);
-        if (kSink == kSinkCount) {
+        if constexpr (kWide) {
+          if (miss_table) atomicAdd(reinterpret_cast<unsigned long long*>(m.acc) + id, v);
+        } else if constexpr (kSink == kSinkCount) {
           if (miss_table) unsafeAtomicAdd(m.acc + id, v);
         } else {
           const unsigned long long qm = __ballot(miss_table);
@@ -402,10 +424,14 @@ __device__ void walk_tile(const DevMap& m, const float* __restrict__ origin, con
   if (kQueue && cq_n) drain_cas(m, cq_id[tid >> 6], cq_v[tid >> 6], cq_n, lane);
   if (kAgg) {
     __syncthreads();
-    if (kSink == kSinkCount) {
+    if constexpr (kSink == kSinkCount) {
       for (uint32_t h = tid; h < kAggSize; h += blockDim.x) {
         const uint32_t k = agg_key[h];
-        if (k != kAggEmpty) unsafeAtomicAdd(m.acc + k, agg_val[h]);
+        if constexpr (kWide) {
+          if (k != kAggEmpty) atomicAdd(reinterpret_cast<unsigned long long*>(m.acc) + k, agg_val[h]);
+        } else {
+          if (k != kAggEmpty) unsafeAtomicAdd(m.acc + k, agg_val[h]);
+        }
       }
     } else {
       // clamp-adds by compare-and-swap, four entries in flight per thread:

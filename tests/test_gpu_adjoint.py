@@ -36,7 +36,7 @@ def gpu_grads(params, batch, box_min, box_dim, labels, mask, ndt=True, extra_lay
     y = torch.from_numpy(labels).to(dev).double()
     mk = torch.from_numpy(mask).to(dev)
     G = (mk * (torch.sigmoid(occ) - y)).float().contiguous()
-    gw = torch.zeros_like(w)
+    gw = torch.zeros(batch.n_rays, dtype=torch.float32, device=dev)
     gw, gs = m.backward(G, box_min, box_dim, o, s, off, w, ndt=ndt, grad_weights=gw)
     # NDT statistics are rebuilt in place by the replay
     n_after = m.read_dense(ohm.READ_NDT_COUNT, box_min, box_dim).cpu().numpy() if ndt else None
@@ -78,6 +78,22 @@ def test_adjoint_plain():
     params, batch, box_min, box_dim, labels, mask, ref = setup_case(3, ndt=False)
     gw, gs, occ, _ = gpu_grads(params, batch, box_min, box_dim, labels, mask, ndt=False)
     assert gs[2] == 0.0
+    check(gw, gs, ref, in_box_counts(params, batch, box_min, box_dim), batch.n_scans)
+
+
+@pytest.mark.parametrize("ndt", [False, True], ids=["plain", "ndt"])
+def test_adjoint_unweighted(ndt):
+    """No per-ray weights (all 1): the unweighted forward and backward
+    instances; dL/dw is still the gradient with respect to the unit weights."""
+    params, batch, box_min, box_dim, labels = scenes.config4(n_scans=3)
+    batch.weights = None
+    first = oracle.adjoint(params, batch, box_min, box_dim, labels, None, ndt=ndt, grads=False)
+    mask = (first["near"] == 0).astype(np.float64)
+    ref = oracle.adjoint(params, batch, box_min, box_dim, labels, mask, ndt=ndt, grads=True)
+    gw, gs, occ, _ = gpu_grads(params, batch, box_min, box_dim, labels, mask, ndt=ndt)
+    np.testing.assert_allclose(occ, ref["occ"], atol=1e-5, rtol=0)
+    if not ndt:
+        assert gs[2] == 0.0
     check(gw, gs, ref, in_box_counts(params, batch, box_min, box_dim), batch.n_scans)
 
 

@@ -310,9 +310,18 @@ def config3(n_streams: int = 16, n_scans: int = 1000, size_scale: float = 1.0, j
         mine = sorted((s for s in scans if s.map_id == map_id), key=lambda s: (s.index, s.stream))
         work = [(sc.stream, sc.index, max(1, int(round(sc.n_rays * size_scale))), mounts[sc.stream]) for sc in mine]
         if jobs > 1:
+            # fresh interpreters (spawn), ended with close/join rather than a
+            # terminate: the workers never inherit a parent's GPU state
             import multiprocessing as mp
-            with mp.get_context("fork").Pool(jobs) as pool:
+            pool = mp.get_context("spawn").Pool(jobs)
+            try:
                 res = pool.map(_config3_scan, work, chunksize=4)
+                pool.close()
+            except BaseException:
+                pool.terminate()
+                raise
+            finally:
+                pool.join()
         else:
             res = [_config3_scan(w) for w in work]
         offsets = np.zeros(len(res) + 1, np.int64)

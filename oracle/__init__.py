@@ -79,6 +79,8 @@ def _load():
     lib.orc_adjoint.restype = ctypes.c_int
     lib.orc_adjoint.argtypes = [P(OrcParams), ctypes.c_int32, ctypes.c_int32, vp, vp, vp, vp, vp, vp, vp, vp,
                                 ctypes.c_double, ctypes.c_int32, vp, vp, vp, vp, vp, vp]
+    lib.orc_mean_integrate.restype = ctypes.c_int
+    lib.orc_mean_integrate.argtypes = [P(OrcParams), ctypes.c_int32, ctypes.c_int32] + [vp] * 8
     lib.orc_ndt_miss_delta.restype = ctypes.c_double
     lib.orc_ndt_miss_delta.argtypes = [P(OrcParams), vp, vp, vp, vp, ctypes.c_uint32]
     _lib = lib
@@ -257,3 +259,32 @@ def adjoint(mp, batch, box_min, box_dim, labels, mask=None, ndt=True, grads=True
     if rc != 0:
         raise MemoryError("oracle allocation failed")
     return dict(loss=loss.value, occ=occ, clamp_last=cl, near=near, grad_w=gw, grad_scalars=gs)
+
+
+def mean_integrate(mp, batch, box_min=None, box_dim=None, packed=None, count=None, mode=1):
+    """Voxel mean layer (paper Sec. III-A, 10-bit sub-voxel codes per axis in
+    one word plus a sample count) over a box window.  mode 1 merges each
+    scan's samples of a voxel at once, mode 0 one sample at a time in ray
+    order.  Returns ``(packed uint32 [dz,dy,dx], count uint32 [dz,dy,dx])``."""
+    lib = _load()
+    p = make_params(mp)
+    if box_min is None:
+        box_min = tuple(mp.key_min)
+        box_dim = tuple(b - a for a, b in zip(mp.key_min, mp.key_max))
+    bmin = np.asarray(box_min, np.int32)
+    bdim = np.asarray(box_dim, np.int32)
+    shape = (int(bdim[2]), int(bdim[1]), int(bdim[0]))
+    packed = np.zeros(shape, np.uint32) if packed is None else np.ascontiguousarray(packed, np.uint32).copy()
+    count = np.zeros(shape, np.uint32) if count is None else np.ascontiguousarray(count, np.uint32).copy()
+    o, s, off, w = _batch_arrays(batch)
+    rc = lib.orc_mean_integrate(ctypes.byref(p), int(mode), batch.n_scans, _ptr(off), _ptr(o), _ptr(s), _ptr(w),
+                                _ptr(bmin), _ptr(bdim), _ptr(packed), _ptr(count))
+    if rc != 0:
+        raise MemoryError("oracle box allocation failed")
+    return packed, count
+
+
+def unpack_mean(packed):
+    """Per-axis 10-bit codes of packed mean words: int array [..., 3]."""
+    packed = np.asarray(packed, np.uint32)
+    return np.stack([(packed >> (10 * a)) & 1023 for a in range(3)], axis=-1).astype(np.int64)

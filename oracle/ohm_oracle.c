@@ -912,6 +912,90 @@ int orc_adjoint(const orc_params* p, int32_t ndt, int32_t n_scans, const uint32_
   return 0;
 }
 
+/* ---------------------------------------------------------------------- */
+/* Voxel mean layer                                                        */
+/* ---------------------------------------------------------------------- */
+/*
+ * The voxel mean layer (paper Sec. III-A: a 32-bit discretised mean
+ * position, 10 bits of sub-voxel position per axis packed into one word,
+ * beside a 32-bit count of the samples behind it; updated like occupancy,
+ * by compare-and-swap, Sec. III-B).  Readings (design notes):
+ *   - A sample's code per axis is its position inside its voxel in units of
+ *     1/1024 voxel, rounded down: from the fixed-point sample q (2^F units
+ *     per voxel), c = (q - k 2^F) >> (F - 10) (or << (10 - F) when F < 10).
+ *   - Packed word: x | y << 10 | z << 20.
+ *   - Merging k samples with code sum S into a voxel holding count n and
+ *     code c gives, per axis, the rational mean (n c + S) / (n + k) rounded
+ *     half up: floor((2 (n c + S) + (n + k)) / (2 (n + k))); the count
+ *     becomes n + k (saturating at 2^32 - 1).
+ *   - Count mode merges each scan's samples of a voxel in one step (per scan,
+ *     like count-then-clamp); per-update mode merges one sample at a time,
+ *     here in ascending ray order (the GPU's order is unspecified).
+ *   - Samples come from the rays that carry a hit (not truncated, end voxel
+ *     in the map); ray weights do not weight samples.
+ *   packed, count  [dz][dy][dx] uint32, in/out
+ */
+static uint32_t subvoxel_code(int64_t q, int64_t k, int F) {
+  int64_t f = q - k * ((int64_t)1 << F); /* in [0, 2^F) */
+  return (uint32_t)(F >= 10 ? (f >> (F - 10)) : (f << (10 - F)));
+}
+
+static uint32_t mean_merge_axis(uint64_t n, uint32_t c, uint64_t k, uint64_t sum) {
+  uint64_t tot = n + k;
+  uint64_t num = 2 * (n * (uint64_t)c + sum) + tot;
+  return (uint32_t)(num / (2 * tot));
+}
+
+static void mean_merge(uint32_t* packed, uint32_t* count, uint64_t k, const uint64_t sum[3]) {
+  if (k == 0) return;
+  uint64_t n = *count;
+  uint32_t out = 0;
+  for (int a = 0; a < 3; ++a) {
+    uint32_t c = (*packed >> (10 * a)) & 1023u;
+    out |= mean_merge_axis(n, c, k, sum[a]) << (10 * a);
+  }
+  *packed = out;
+  uint64_t t = n + k;
+  *count = t > 0xFFFFFFFFull ? 0xFFFFFFFFu : (uint32_t)t;
+}
+
+int orc_mean_integrate(const orc_params* p, int32_t mode, int32_t n_scans, const uint32_t* offsets,
+                       const float* origins, const float* samples, const float* weights, const int32_t box_min[3],
+                       const int32_t box_dim[3], uint32_t* packed, uint32_t* count) {
+  size_t nv = (size_t)box_dim[0] * box_dim[1] * box_dim[2];
+  uint64_t* acc = (uint64_t*)calloc(nv * 4, sizeof(uint64_t)); /* k, sum x, sum y, sum z */
+  if (!acc) return -1;
+  orc_scratch s = {0};
+  for (int32_t sc = 0; sc < n_scans; ++sc) {
+    memset(acc, 0, nv * 4 * sizeof(uint64_t));
+    const float* of = origins + 3 * sc;
+    for (uint32_t i = offsets[sc]; i < offsets[sc + 1]; ++i) {
+      orc_ray r;
+      prepare_weighted_ray(p, of, samples, weights, i, &r);
+      if (r.status != ORC_RAY_OK || r.truncated) continue;
+      int clipped = 0;
+      int64_t nk = walk_ray(p, &r, &s, &clipped);
+      if (clipped) continue;
+      const int32_t* key = s.keys + 3 * (nk - 1);
+      int64_t v = box_index(key, box_min, box_dim);
+      if (v < 0) continue;
+      uint64_t code[3];
+      for (int a = 0; a < 3; ++a) code[a] = subvoxel_code(r.q1[a], r.k1[a], p->fixed_bits);
+      if (mode == 1) {
+        acc[4 * v] += 1;
+        for (int a = 0; a < 3; ++a) acc[4 * v + 1 + a] += code[a];
+      } else {
+        mean_merge(packed + v, count + v, 1, code);
+      }
+    }
+    if (mode == 1)
+      for (size_t v = 0; v < nv; ++v) mean_merge(packed + v, count + v, acc[4 * v], acc + 4 * v + 1);
+  }
+  scratch_free(&s);
+  free(acc);
+  return 0;
+}
+
 /* Library self-identification for the loaders. */
 int orc_abi_version(void) { return 1; }
 

@@ -81,6 +81,8 @@ def _load():
                                 ctypes.c_double, ctypes.c_int32, vp, vp, vp, vp, vp, vp]
     lib.orc_mean_integrate.restype = ctypes.c_int
     lib.orc_mean_integrate.argtypes = [P(OrcParams), ctypes.c_int32, ctypes.c_int32] + [vp] * 8
+    lib.orc_decay_integrate.restype = ctypes.c_int
+    lib.orc_decay_integrate.argtypes = [P(OrcParams), ctypes.c_int32] + [vp] * 8
     lib.orc_ndt_miss_delta.restype = ctypes.c_double
     lib.orc_ndt_miss_delta.argtypes = [P(OrcParams), vp, vp, vp, vp, ctypes.c_uint32]
     _lib = lib
@@ -288,3 +290,26 @@ def unpack_mean(packed):
     """Per-axis 10-bit codes of packed mean words: int array [..., 3]."""
     packed = np.asarray(packed, np.uint32)
     return np.stack([(packed >> (10 * a)) & 1023 for a in range(3)], axis=-1).astype(np.int64)
+
+
+def decay_integrate(mp, batch, box_min=None, box_dim=None, length=None, hits=None):
+    """Decay-rate layer (paper Sec. II-E) over a box window: per voxel the
+    summed distance rays travel through it (metres, fp64) and the samples
+    that fell in it.  Returns ``(length [dz,dy,dx] float64, hits uint32)``;
+    the rate is hits / length."""
+    lib = _load()
+    p = make_params(mp)
+    if box_min is None:
+        box_min = tuple(mp.key_min)
+        box_dim = tuple(b - a for a, b in zip(mp.key_min, mp.key_max))
+    bmin = np.asarray(box_min, np.int32)
+    bdim = np.asarray(box_dim, np.int32)
+    shape = (int(bdim[2]), int(bdim[1]), int(bdim[0]))
+    length = np.zeros(shape, np.float64) if length is None else np.ascontiguousarray(length, np.float64).copy()
+    hits = np.zeros(shape, np.uint32) if hits is None else np.ascontiguousarray(hits, np.uint32).copy()
+    o, s, off, w = _batch_arrays(batch)
+    rc = lib.orc_decay_integrate(ctypes.byref(p), batch.n_scans, _ptr(off), _ptr(o), _ptr(s), _ptr(w),
+                                 _ptr(bmin), _ptr(bdim), _ptr(length), _ptr(hits))
+    if rc != 0:
+        raise MemoryError("oracle box allocation failed")
+    return length, hits

@@ -89,3 +89,22 @@ def all_orders_range(l: float, hits: List[float], misses: List[float], lo: float
         best_lo = v if best_lo is None else min(best_lo, v)
         best_hi = v if best_hi is None else max(best_hi, v)
     return best_lo, best_hi
+
+
+def segment_box_interval(q0, q1, k, F: int):
+    """Exact parameter interval [t_lo, t_hi] (Fractions, clipped to [0, 1])
+    of the segment inside the closed box of voxel k, or None."""
+    one = 1 << F
+    lo_t, hi_t = Fraction(0), Fraction(1)
+    for a in range(3):
+        lo, hi = k[a] * one, (k[a] + 1) * one
+        d = q1[a] - q0[a]
+        if d == 0:
+            if not (lo <= q0[a] <= hi):
+                return None
+            continue
+        t0, t1 = Fraction(lo - q0[a], d), Fraction(hi - q0[a], d)
+        if t0 > t1:
+            t0, t1 = t1, t0
+        lo_t, hi_t = max(lo_t, t0), min(hi_t, t1)
+    return (lo_t, hi_t) if lo_t <= hi_t else None

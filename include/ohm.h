@@ -84,11 +84,29 @@ enum {
   OHM_LAYER_OCC = 1,         /* always present */
   OHM_LAYER_NDT = 2,         /* NDT-OM sample count, mean and covariance */
   OHM_LAYER_ADJOINT = 4,     /* last scan at which the clamp was active */
-  OHM_LAYER_SCAN_GROUPS = 8  /* G accumulator slots (default 8): in count mode, ohm_integrate_rays
+  OHM_LAYER_SCAN_GROUPS = 8, /* G accumulator slots (default 8): in count mode, ohm_integrate_rays
                                 walks up to G consecutive scans of a call in one launch (each
                                 into its own slot, finalized in scan order: the same result).
-                                Each slot costs 256 KiB per region of capacity. */
+                                Each slot costs 256 KiB per region of capacity; a weighted scan
+                                uses two slots.  Every map has at least two slots' memory. */
+  OHM_LAYER_MEAN = 16,       /* voxel mean (paper Sec. III-A): per voxel a 32-bit word packing the
+                                10-bit sub-voxel position code of each axis (x bits 0-9, y 10-19,
+                                z 20-29) and a 32-bit sample count.  A sample's code is its
+                                position inside its voxel in 1/1024 voxel, rounded down, from the
+                                quantised sample; merging k samples (code sum S) into (n, c) gives
+                                floor((2 (n c + S) + n + k) / (2 (n + k))) per axis and n + k.
+                                Per-update mode merges each sample by 64-bit compare-and-swap;
+                                count mode merges each scan's samples in one step, in scan order
+                                (exact).  Updated by ohm_integrate_rays; 8 B per voxel plus 16 B
+                                per voxel and accumulator slot, and 8 B per voxel of slot mask. */
+  OHM_LAYER_DECAY = 32       /* decay rate (paper Sec. II-E): per voxel the summed distance rays
+                                travel through it, measured along the quantised segment the walk
+                                traverses (Q32.32 metres, exact integer sums), and the samples
+                                that fell in it; the rate is their quotient.  Updated by
+                                ohm_integrate_rays in both modes (plain sums).  12 B per voxel. */
 };
+/* OHM_LAYER_MEAN and OHM_LAYER_DECAY are not available together with
+ * OHM_LAYER_NDT (OHM_E_UNSUPPORTED at creation), nor in batched plans. */
 
 /* Slot count of OHM_LAYER_SCAN_GROUPS, or-ed into the layer mask: n in [1, 64]
  * (0: the default 8).  Only valid together with OHM_LAYER_SCAN_GROUPS. */
@@ -102,7 +120,14 @@ enum {
   OHM_READ_NDT_COUNT = 3,  /* uint32  NDT sample count */
   OHM_READ_NDT_MEAN = 4,   /* float[3] NDT mean, metres, relative to the voxel centre */
   OHM_READ_NDT_COV = 5,    /* float[6] NDT covariance xx, xy, xz, yy, yz, zz (m^2) */
-  OHM_READ_CLAMP_SCAN = 6  /* uint32  1 + last scan index whose pre-clamp value left [l_min, l_max], 0 = never */
+  OHM_READ_CLAMP_SCAN = 6, /* uint32  1 + last scan index whose pre-clamp value left [l_min, l_max], 0 = never */
+  OHM_READ_MEAN_PACKED = 7,  /* uint32  packed 10-bit mean codes (OHM_LAYER_MEAN) */
+  OHM_READ_MEAN_COUNT = 8,   /* uint32  samples behind the mean */
+  OHM_READ_MEAN = 9,         /* float[3] mean position, metres from the voxel centre (code cell centres;
+                                0 where no sample) */
+  OHM_READ_DECAY_LENGTH = 10,/* float   summed distance through the voxel, metres (OHM_LAYER_DECAY) */
+  OHM_READ_DECAY_HITS = 11,  /* uint32  samples that fell in the voxel */
+  OHM_READ_DECAY_RATE = 12   /* float   hits / distance (per metre; 0 where no distance) */
 };
 
 typedef struct {

@@ -7,8 +7,9 @@ NDT-OM statistics (Sec. II-D, III-C) in dense 32^3 regions (Sec. III-A).
 """
 from . import _lib  # noqa: F401
 from ._lib import (  # noqa: F401
-    LAYER_ADJOINT, LAYER_NDT, LAYER_OCC, LAYER_SCAN_GROUPS, MODE_COUNT_CLAMP, MODE_PER_UPDATE,
-    READ_CLAMP_SCAN, READ_HITS, READ_MISSES, READ_NDT_COUNT, READ_NDT_COV, READ_NDT_MEAN, READ_OCC,
+    LAYER_ADJOINT, LAYER_DECAY, LAYER_MEAN, LAYER_NDT, LAYER_OCC, LAYER_SCAN_GROUPS, MODE_COUNT_CLAMP,
+    MODE_PER_UPDATE, READ_CLAMP_SCAN, READ_DECAY_HITS, READ_DECAY_LENGTH, READ_DECAY_RATE, READ_HITS, READ_MEAN,
+    READ_MEAN_COUNT, READ_MEAN_PACKED, READ_MISSES, READ_NDT_COUNT, READ_NDT_COV, READ_NDT_MEAN, READ_OCC,
     OHM_E_HIP, OHM_E_INVALID_ARG, OHM_E_NO_DEVICE, OHM_E_UNSUPPORTED, OHM_E_WORKSPACE_TOO_SMALL, OHM_OK,
     OhmError, scan_group_slots,
 )

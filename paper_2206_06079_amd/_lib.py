@@ -21,6 +21,8 @@ LAYER_OCC = 1
 LAYER_NDT = 2
 LAYER_ADJOINT = 4
 LAYER_SCAN_GROUPS = 8
+LAYER_MEAN = 16
+LAYER_DECAY = 32
 
 
 def scan_group_slots(n: int) -> int:
@@ -35,6 +37,12 @@ READ_NDT_COUNT = 3
 READ_NDT_MEAN = 4
 READ_NDT_COV = 5
 READ_CLAMP_SCAN = 6
+READ_MEAN_PACKED = 7
+READ_MEAN_COUNT = 8
+READ_MEAN = 9
+READ_DECAY_LENGTH = 10
+READ_DECAY_HITS = 11
+READ_DECAY_RATE = 12
 
 # Every symbol include/ohm.h declares.
 EXPORTS = (

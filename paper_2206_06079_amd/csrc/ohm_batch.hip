@@ -273,6 +273,7 @@ ohm_status plan_layout(const ohm_scan_set* sets, uint32_t n_sets, const ohm_batc
     ohm_status st = check_scans(s.map, s.d_origins, s.d_samples, s.h_scan_offsets, s.n_scans);
     if (st != OHM_OK) return st;
     if (s.map->params.mode != OHM_MODE_COUNT_CLAMP) return OHM_E_UNSUPPORTED;
+    if (s.map->dm.mean || s.map->dm.decay_len) return OHM_E_UNSUPPORTED;  // optional layers: per-scan path only
     if ((s.d_weights != nullptr) != weighted) return OHM_E_INVALID_ARG;
     for (uint32_t sj = 0; sj < si; ++sj)
       if (sets[sj].map == s.map) return OHM_E_INVALID_ARG;  // one set per map

@@ -84,6 +84,19 @@ struct DevMap {
   long long* nacc;    // NDT per-scan accumulators [capacity][V][kNaccWords] or null
   double* mom;        // NDT per-scan sample moments [capacity][V][kMomWords] or null
   uint32_t* clampscan;// [capacity][V] or null
+  // voxel mean layer (or null): per voxel the packed 10-bit sub-voxel codes
+  // (bits 0-29) and the sample count (bits 32-63); in count mode the per-scan
+  // sample sums of slot j at mean_acc + 2 j capacity V (k | sum x << 32,
+  // sum y | sum z << 32 per voxel) and a per-voxel mask of the slots holding
+  // samples; mean_slot is the slot of the scan being walked
+  unsigned long long* mean;
+  unsigned long long* mean_acc;
+  unsigned long long* mean_mask;
+  uint32_t mean_slot;
+  // decay-rate layer (or null): summed distance rays travel through each
+  // voxel (Q32.32 metres) and the samples that fell in it
+  unsigned long long* decay_len;
+  uint32_t* decay_hits;
 };
 
 // Q32.32 fixed point of the exact (order-independent) sums of weights and
@@ -96,6 +109,11 @@ constexpr double kInvQ32 = 1.0 / 4294967296.0;
 // f32 counts for unit weights, int64 Q32.32 weight sums (wide) with weights.
 __host__ __device__ __forceinline__ size_t acc_slot_floats(const DevMap& m, bool wide) {
   return (size_t)m.capacity * kRegionVoxels * (wide ? 4 : 2);
+}
+
+// u64 words per slot of the voxel mean layer's per-scan sums.
+__host__ __device__ __forceinline__ size_t mean_slot_words(const DevMap& m) {
+  return (size_t)m.capacity * kRegionVoxels * 2;
 }
 
 // The count-then-clamp update of one voxel from wide (Q32.32 weight sum)

@@ -66,14 +66,32 @@ __global__ void fill_u32_kernel(uint32_t* p, size_t n, uint32_t v);
 __global__ __launch_bounds__(256) void ndt_finalize_kernel(DevMap m, uint32_t parity, int count_mode,
                                                            uint32_t scan_tag);
 
+// Direction-ordering scratch of the per-scan path: scans of at most
+// max_rays rays walk in direction order (max_rays = 0: none do).
+struct OrderScratch {
+  uint32_t* hist;
+  uint32_t* sums;
+  uint32_t* perm;
+  uint32_t max_rays;
+};
+
+// Bytes of direction-ordering scratch for scans of up to max_rays rays, and
+// its three parts at base (256-byte aligned).
+size_t order_scratch_bytes(uint32_t max_rays);
+OrderScratch order_scratch_at(void* base, uint32_t max_rays);
+
+ohm_status integrate_rays_impl(ohm_map map, const float* d_origins, const float* d_samples,
+                               const uint32_t* h_scan_offsets, uint32_t n_scans, const float* d_weights,
+                               hipStream_t st, const OrderScratch& ord, bool prof);
+
 ohm_status map_initialise(ohm_map_s* map, hipStream_t st);
 ohm_status check_scans(ohm_map map, const float* d_origins, const float* d_samples, const uint32_t* h_offsets,
                        uint32_t n_scans);
-void clear_pending(ohm_map_s* map, hipStream_t st);
+void clear_pending(ohm_map_s* map, hipStream_t st, bool prof = true);
 // Brackets one kernel launch with HIP events when profiling is enabled.
 class ProfScope {
  public:
-  ProfScope(ohm_map_s* map, int kind, hipStream_t st);
+  ProfScope(ohm_map_s* map, int kind, hipStream_t st, bool on = true);
   ~ProfScope();
 
  private:

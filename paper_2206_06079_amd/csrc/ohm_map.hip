@@ -53,7 +53,7 @@ __global__ void fill_u32_kernel(uint32_t* p, size_t n, uint32_t v) {
 }
 
 // Segmented walk: one block per tile of 256 rays (perm: walk order or null).
-template <int kSink, bool kWeighted>
+template <int kSink, bool kWeighted, bool kLayers = false>
 __global__ __launch_bounds__(1024) void walk_seg_kernel(DevMap m, const float* __restrict__ origins, uint32_t scan,
                                                         const float* __restrict__ samples,
                                                         const float* __restrict__ weights,
@@ -63,8 +63,9 @@ __global__ __launch_bounds__(1024) void walk_seg_kernel(DevMap m, const float* _
                                                         int32_t* __restrict__ ray_flags,
                                                         const int64_t* __restrict__ ray_offsets,
                                                         int32_t* __restrict__ updates) {
-  walk_tile<kSink, kWeighted>(m, origins + 3 * (size_t)scan, samples, weights, perm, r0, n, blockIdx.x * kTileRays,
-                              K, tag, parity, ray_counts, ray_flags, ray_offsets, updates);
+  walk_tile<kSink, kWeighted, kLayers>(m, origins + 3 * (size_t)scan, samples, weights, perm, r0, n,
+                                       blockIdx.x * kTileRays, K, tag, parity, ray_counts, ray_flags, ray_offsets,
+                                       updates);
 }
 
 // Direction ordering of one scan (ohm_order.h): count, prefix, place.
@@ -101,6 +102,14 @@ __global__ __launch_bounds__(256) void scan_order_place_kernel(const float* __re
 constexpr int kFinalChunk = 1024;  // voxels per work unit
 constexpr int kFinalUnits = kRegionVoxels / kFinalChunk;
 
+// Count mode: the per-scan parts of the optional layers for one unit of
+// kFinalChunk voxels from `base` (the voxel mean merges its scans' samples;
+// the decay-rate layer needs nothing here).  Every thread of the block calls it.
+__device__ __forceinline__ void finalize_layers(const DevMap& m, size_t base) {
+  if (!m.mean) return;
+  for (int v = threadIdx.x; v < kFinalChunk; v += blockDim.x) mean_finalize_voxel(m, base + v, mean_slot_words(m));
+}
+
 // Applies l <- clamp((l + H l_hit) + M l_miss) to every voxel of the touched
 // regions (kWide: from Q32.32 weight sums, in fp64).  With `apply` = 0 only
 // clears the accumulators.  Clears the accumulators when `clear`, and resets
@@ -114,6 +123,7 @@ __global__ __launch_bounds__(256) void finalize_kernel(DevMap m, uint32_t parity
     for (uint32_t u = blockIdx.x; u < units; u += gridDim.x) {
       const uint32_t slot = m.touched[(size_t)parity * m.capacity + u / kFinalUnits];
       const size_t base = (size_t)slot * kRegionVoxels + (size_t)(u % kFinalUnits) * kFinalChunk;
+      if (apply) finalize_layers(m, base);
       for (int v = threadIdx.x; v < kFinalChunk; v += blockDim.x) {
         const size_t vi = base + v;
         longlong2* ap = reinterpret_cast<longlong2*>(m.acc) + vi;  // (miss, hit)
@@ -127,6 +137,7 @@ __global__ __launch_bounds__(256) void finalize_kernel(DevMap m, uint32_t parity
   for (uint32_t u = blockIdx.x; u < units; u += gridDim.x) {
     const uint32_t slot = m.touched[(size_t)parity * m.capacity + u / kFinalUnits];
     const size_t base = (size_t)slot * kRegionVoxels + (size_t)(u % kFinalUnits) * kFinalChunk;
+    if (apply) finalize_layers(m, base);
     for (int v = threadIdx.x * 2; v < kFinalChunk; v += blockDim.x * 2) {
       float4* ap = reinterpret_cast<float4*>(m.acc + 2 * (base + v));
       float4 a = *ap;  // (miss0, hit0, miss1, hit1)
@@ -170,7 +181,7 @@ struct GroupArgs {
   uint32_t tile_end[kMaxGroupSlots];  // exclusive end of the scan's blocks
 };
 
-template <bool kWeighted>
+template <bool kWeighted, bool kLayers = false>
 __global__ __launch_bounds__(1024) void walk_group_kernel(DevMap m, const float* __restrict__ origins,
                                                           const float* __restrict__ samples,
                                                           const float* __restrict__ weights, GroupArgs g, int K,
@@ -180,7 +191,11 @@ __global__ __launch_bounds__(1024) void walk_group_kernel(DevMap m, const float*
   const uint32_t tile = blockIdx.x - (j ? g.tile_end[j - 1] : 0u);
   DevMap mj = m;
   mj.acc += (size_t)j * acc_slot_floats(m, kWeighted);
-  walk_tile<kSinkCount, kWeighted>(mj, origins + 3 * (size_t)g.scan[j], samples, weights, nullptr, g.r0[j], g.n[j],
+  if (kLayers && mj.mean) {
+    mj.mean_acc += (size_t)j * mean_slot_words(m);
+    mj.mean_slot = j;
+  }
+  walk_tile<kSinkCount, kWeighted, kLayers>(mj, origins + 3 * (size_t)g.scan[j], samples, weights, nullptr, g.r0[j], g.n[j],
                                    tile * kTileRays, K, tag, parity, nullptr, nullptr, nullptr, nullptr);
 }
 
@@ -201,6 +216,7 @@ __global__ __launch_bounds__(256) void group_finalize_kernel(DevMap m, uint32_t 
     for (uint32_t u = blockIdx.x; u < units; u += gridDim.x) {
       const uint32_t slot = m.touched[(size_t)parity * m.capacity + u / kFinalUnits];
       const size_t base = (size_t)slot * kRegionVoxels + (size_t)(u % kFinalUnits) * kFinalChunk;
+      finalize_layers(m, base);
       for (int v = threadIdx.x; v < kFinalChunk; v += blockDim.x) {
         const size_t vi = base + v;
         longlong2* const a0 = reinterpret_cast<longlong2*>(m.acc) + vi;
@@ -229,6 +245,7 @@ __global__ __launch_bounds__(256) void group_finalize_kernel(DevMap m, uint32_t 
   for (uint32_t u = blockIdx.x; u < units; u += gridDim.x) {
     const uint32_t slot = m.touched[(size_t)parity * m.capacity + u / kFinalUnits];
     const size_t base = (size_t)slot * kRegionVoxels + (size_t)(u % kFinalUnits) * kFinalChunk;
+    finalize_layers(m, base);
     for (int v = threadIdx.x; v < kFinalChunk; v += blockDim.x) {
       const size_t vi = base + v;
       float2* const a0 = reinterpret_cast<float2*>(m.acc) + vi;
@@ -303,6 +320,33 @@ __global__ __launch_bounds__(256) void read_dense_kernel(DevMap m, int what, int
     case OHM_READ_CLAMP_SCAN:
       static_cast<uint32_t*>(out)[i] = slot >= 0 ? m.clampscan[v] : 0u;
       break;
+    case OHM_READ_MEAN_PACKED:
+      static_cast<uint32_t*>(out)[i] = slot >= 0 ? (uint32_t)m.mean[v] : 0u;
+      break;
+    case OHM_READ_MEAN_COUNT:
+      static_cast<uint32_t*>(out)[i] = slot >= 0 ? (uint32_t)(m.mean[v] >> 32) : 0u;
+      break;
+    case OHM_READ_MEAN: {
+      // centre of the code cell, metres from the voxel centre (0 where empty)
+      const unsigned long long w = slot >= 0 ? m.mean[v] : 0ull;
+      for (int c = 0; c < 3; ++c) {
+        const uint32_t code = ((uint32_t)w >> (10 * c)) & 1023u;
+        static_cast<float*>(out)[3 * i + c] =
+            (w >> 32) ? (float)((((double)code + 0.5) / 1024.0 - 0.5) * m.voxel_size) : 0.f;
+      }
+      break;
+    }
+    case OHM_READ_DECAY_LENGTH:
+      static_cast<float*>(out)[i] = slot >= 0 ? (float)((double)m.decay_len[v] * kInvQ32) : 0.f;
+      break;
+    case OHM_READ_DECAY_HITS:
+      static_cast<uint32_t*>(out)[i] = slot >= 0 ? m.decay_hits[v] : 0u;
+      break;
+    case OHM_READ_DECAY_RATE: {
+      const double len = slot >= 0 ? (double)m.decay_len[v] * kInvQ32 : 0.0;
+      static_cast<float*>(out)[i] = len > 0.0 ? (float)((double)m.decay_hits[v] / len) : 0.f;
+      break;
+    }
     default:
       break;
   }
@@ -318,7 +362,8 @@ constexpr size_t kAlign = 256;
 inline size_t align_up(size_t v) { return (v + kAlign - 1) & ~(kAlign - 1); }
 
 struct Layout {
-  size_t hdr, stats, table, stamp, touched, occ, acc, ndt, nacc, mom, clampscan, total;
+  size_t hdr, stats, table, stamp, touched, occ, acc, ndt, nacc, mom, clampscan, mean, mean_acc, mean_mask,
+      decay_len, decay_hits, total;
   int32_t rlo[3], rdim[3];
   size_t regions;
 };
@@ -352,10 +397,13 @@ ohm_status compute_layout(const ohm_params* p, uint32_t capacity, uint32_t layer
   if (s != OHM_OK) return s;
   if (capacity == 0 || capacity > kMaxCapacity) return OHM_E_INVALID_ARG;
   if (layers & ~(uint32_t)(OHM_LAYER_OCC | OHM_LAYER_NDT | OHM_LAYER_ADJOINT | OHM_LAYER_SCAN_GROUPS |
+                           OHM_LAYER_MEAN | OHM_LAYER_DECAY |
                            OHM_SCAN_GROUP_SLOTS(0xff)))
     return OHM_E_INVALID_ARG;
   const uint32_t slots = group_slots_of(layers);
   if (slots == 0) return OHM_E_INVALID_ARG;
+  // the NDT walk updates none of the occupancy walk's optional layers
+  if ((layers & OHM_LAYER_NDT) && (layers & (OHM_LAYER_MEAN | OHM_LAYER_DECAY))) return OHM_E_UNSUPPORTED;
   size_t regions = 1;
   for (int a = 0; a < 3; ++a) {
     L->rlo[a] = p->key_min[a] >> kRegionLog2;
@@ -393,6 +441,21 @@ ohm_status compute_layout(const ohm_params* p, uint32_t capacity, uint32_t layer
   }
   if (layers & OHM_LAYER_ADJOINT) {
     L->clampscan = off;
+    off = align_up(off + (size_t)capacity * V * sizeof(uint32_t));
+  }
+  L->mean = L->mean_acc = L->mean_mask = L->decay_len = L->decay_hits = 0;
+  if (layers & OHM_LAYER_MEAN) {
+    L->mean = off;
+    off = align_up(off + (size_t)capacity * V * sizeof(unsigned long long));
+    L->mean_acc = off;  // one slot of per-scan sums per accumulator slot
+    off = align_up(off + (size_t)capacity * V * 2 * sizeof(unsigned long long) * slots);
+    L->mean_mask = off;
+    off = align_up(off + (size_t)capacity * V * sizeof(unsigned long long));
+  }
+  if (layers & OHM_LAYER_DECAY) {
+    L->decay_len = off;
+    off = align_up(off + (size_t)capacity * V * sizeof(unsigned long long));
+    L->decay_hits = off;
     off = align_up(off + (size_t)capacity * V * sizeof(uint32_t));
   }
   L->total = off;
@@ -438,6 +501,19 @@ void launch_fill(void* p, size_t bytes, uint32_t v, hipStream_t st) {
 
 }  // namespace
 
+size_t order_scratch_bytes(uint32_t max_rays) {
+  return align_up((size_t)order_bins(max_rays) * sizeof(uint32_t)) +
+         align_up((size_t)kOrderMaxStrips * sizeof(uint32_t)) + align_up((size_t)max_rays * sizeof(uint32_t));
+}
+
+OrderScratch order_scratch_at(void* base, uint32_t max_rays) {
+  char* b = static_cast<char*>(base);
+  const size_t hist_bytes = align_up((size_t)order_bins(max_rays) * sizeof(uint32_t));
+  const size_t sums_bytes = align_up((size_t)kOrderMaxStrips * sizeof(uint32_t));
+  return OrderScratch{reinterpret_cast<uint32_t*>(b), reinterpret_cast<uint32_t*>(b + hist_bytes),
+                      reinterpret_cast<uint32_t*>(b + hist_bytes + sums_bytes), max_rays};
+}
+
 ohm_status map_initialise(ohm_map_s* map, hipStream_t st) {
   const DevMap& m = map->dm;
   const size_t V = kRegionVoxels;
@@ -456,6 +532,15 @@ ohm_status map_initialise(ohm_map_s* map, hipStream_t st) {
     launch_fill(m.mom, (size_t)m.capacity * V * kMomWords * sizeof(double), 0u, st);
   }
   if (m.clampscan) launch_fill(m.clampscan, (size_t)m.capacity * V * sizeof(uint32_t), 0u, st);
+  if (m.mean) {
+    launch_fill(m.mean, (size_t)m.capacity * V * sizeof(unsigned long long), 0u, st);
+    launch_fill(m.mean_acc, (size_t)m.capacity * V * 2 * sizeof(unsigned long long) * map->group_slots, 0u, st);
+    launch_fill(m.mean_mask, (size_t)m.capacity * V * sizeof(unsigned long long), 0u, st);
+  }
+  if (m.decay_len) {
+    launch_fill(m.decay_len, (size_t)m.capacity * V * sizeof(unsigned long long), 0u, st);
+    launch_fill(m.decay_hits, (size_t)m.capacity * V * sizeof(uint32_t), 0u, st);
+  }
   map->count_batches = 0;
   map->acc_dirty = false;
   map->kept_slot = 0;
@@ -487,8 +572,9 @@ hipEvent_t take_event(ohm_map_s* map) {
 }
 }  // namespace
 
-ProfScope::ProfScope(ohm_map_s* map, int kind, hipStream_t st) : map_(map), st_(st), kind_(kind), stop_(nullptr) {
-  if (!map->profiling) return;
+ProfScope::ProfScope(ohm_map_s* map, int kind, hipStream_t st, bool on)
+    : map_(map), st_(st), kind_(kind), stop_(nullptr) {
+  if (!on || !map->profiling) return;
   hipEvent_t start = take_event(map);
   stop_ = take_event(map);
   if (!start || !stop_) {
@@ -516,9 +602,9 @@ DevMap kept_counts(const ohm_map_s* map) {
 }
 
 // Lazy clear of the previous count-mode scan's accumulators.
-void clear_pending(ohm_map_s* map, hipStream_t st) {
+void clear_pending(ohm_map_s* map, hipStream_t st, bool prof) {
   if (!map->acc_dirty) return;
-  ProfScope ps(map, OHM_KERNEL_FINALIZE, st);
+  ProfScope ps(map, OHM_KERNEL_FINALIZE, st, prof);
   if (map->kept_wide)
     hipLaunchKernelGGL(finalize_kernel<true>, dim3(kFinalizeBlocks), dim3(256), 0, st, kept_counts(map),
                        map->last_parity, 0, 1, 0u);
@@ -528,6 +614,32 @@ void clear_pending(ohm_map_s* map, hipStream_t st) {
   map->acc_dirty = false;
   map->kept_slot = 0;
   map->kept_wide = false;
+}
+
+// Walk launches with or without the optional-layer hooks (the hooks cost
+// registers and instructions that maps without those layers do not pay).
+template <int kSink, bool kWeighted>
+void launch_walk_seg(const ohm_map_s* map, bool layers, dim3 grid, dim3 block, hipStream_t st, const float* origins,
+                     uint32_t scan, const float* samples, const float* weights, const uint32_t* perm, uint32_t r0,
+                     uint32_t n, int K, uint32_t tag, uint32_t parity) {
+  if (layers)
+    hipLaunchKernelGGL((walk_seg_kernel<kSink, kWeighted, true>), grid, block, 0, st, map->dm, origins, scan, samples,
+                       weights, perm, r0, n, K, tag, parity, nullptr, nullptr, nullptr, nullptr);
+  else
+    hipLaunchKernelGGL((walk_seg_kernel<kSink, kWeighted, false>), grid, block, 0, st, map->dm, origins, scan,
+                       samples, weights, perm, r0, n, K, tag, parity, nullptr, nullptr, nullptr, nullptr);
+}
+
+template <bool kWeighted>
+void launch_walk_group(const ohm_map_s* map, bool layers, dim3 grid, dim3 block, hipStream_t st,
+                       const float* origins, const float* samples, const float* weights, const GroupArgs& g, int K,
+                       uint32_t tag, uint32_t parity) {
+  if (layers)
+    hipLaunchKernelGGL((walk_group_kernel<kWeighted, true>), grid, block, 0, st, map->dm, origins, samples, weights,
+                       g, K, tag, parity);
+  else
+    hipLaunchKernelGGL((walk_group_kernel<kWeighted, false>), grid, block, 0, st, map->dm, origins, samples, weights,
+                       g, K, tag, parity);
 }
 
 }  // namespace ohm
@@ -611,6 +723,13 @@ ohm_status ohm_map_create(const ohm_params* params, uint32_t region_capacity, ui
   dm.nacc = (layers & OHM_LAYER_NDT) ? reinterpret_cast<long long*>(base + L.nacc) : nullptr;
   dm.mom = (layers & OHM_LAYER_NDT) ? reinterpret_cast<double*>(base + L.mom) : nullptr;
   dm.clampscan = (layers & OHM_LAYER_ADJOINT) ? reinterpret_cast<uint32_t*>(base + L.clampscan) : nullptr;
+  const bool has_mean = (layers & OHM_LAYER_MEAN) != 0, has_decay = (layers & OHM_LAYER_DECAY) != 0;
+  dm.mean = has_mean ? reinterpret_cast<unsigned long long*>(base + L.mean) : nullptr;
+  dm.mean_acc = has_mean ? reinterpret_cast<unsigned long long*>(base + L.mean_acc) : nullptr;
+  dm.mean_mask = has_mean ? reinterpret_cast<unsigned long long*>(base + L.mean_mask) : nullptr;
+  dm.mean_slot = 0;
+  dm.decay_len = has_decay ? reinterpret_cast<unsigned long long*>(base + L.decay_len) : nullptr;
+  dm.decay_hits = has_decay ? reinterpret_cast<uint32_t*>(base + L.decay_hits) : nullptr;
   s = map_initialise(map, as_stream(stream));
   if (s != OHM_OK) {
     delete map;
@@ -649,19 +768,23 @@ ohm_status ohm_map_set_params(ohm_map map, const ohm_params* params) {
   return OHM_OK;
 }
 
-ohm_status ohm_integrate_rays(ohm_map map, const float* d_origins, const float* d_samples,
-                              const uint32_t* h_scan_offsets, uint32_t n_scans, const float* d_weights,
-                              void* stream) {
-  ohm_status s = check_scans(map, d_origins, d_samples, h_scan_offsets, n_scans);
-  if (s != OHM_OK || n_scans == 0) return s;
-  hipStream_t st = as_stream(stream);
+}  // extern "C"
+
+namespace ohm {
+
+// ohm_integrate_rays with the ordering scratch given explicitly; prof =
+// false records no profiling events (the allocation-free entry point).
+ohm_status integrate_rays_impl(ohm_map map, const float* d_origins, const float* d_samples,
+                               const uint32_t* h_scan_offsets, uint32_t n_scans, const float* d_weights,
+                               hipStream_t st, const OrderScratch& ord, bool prof) {
+  const bool layers = map->dm.mean || map->dm.decay_len;  // walks that also update the optional layers
   const bool count_mode = map->params.mode == OHM_MODE_COUNT_CLAMP;
   const bool weighted = d_weights != nullptr;
   uint32_t last = n_scans;
   for (uint32_t sc = 0; sc < n_scans; ++sc)
     if (h_scan_offsets[sc + 1] > h_scan_offsets[sc]) last = sc;
   uint32_t first = 0;  // scans before `first` went through grouped launches
-  if (count_mode && (map->layers & OHM_LAYER_SCAN_GROUPS) && map->order_max_rays == 0 && last < n_scans) {
+  if (count_mode && (map->layers & OHM_LAYER_SCAN_GROUPS) && ord.max_rays == 0 && last < n_scans) {
     // groups of up to G non-empty scans; the group holding the last one
     // keeps its counts readable in that scan's slot
     const uint32_t threads = map->walk_threads;
@@ -684,22 +807,22 @@ ohm_status ohm_integrate_rays(ohm_map map, const float* d_origins, const float* 
         ++g.count;
       }
       if (g.count == 0) break;
-      clear_pending(map, st);
+      clear_pending(map, st, prof);
       const uint32_t tag = ++map->count_batches;
       const uint32_t parity = tag & 1u;
       {
-        ProfScope ps(map, OHM_KERNEL_WALK_GROUP, st);
+        ProfScope ps(map, OHM_KERNEL_WALK_GROUP, st, prof);
         if (weighted)
-          hipLaunchKernelGGL(walk_group_kernel<true>, dim3(tiles), dim3(threads), 0, st, map->dm, d_origins, d_samples,
-                             d_weights, g, K, tag, parity);
+          launch_walk_group<true>(map, layers, dim3(tiles), dim3(threads), st, d_origins, d_samples, d_weights, g, K,
+                                  tag, parity);
         else
-          hipLaunchKernelGGL(walk_group_kernel<false>, dim3(tiles), dim3(threads), 0, st, map->dm, d_origins,
-                             d_samples, d_weights, g, K, tag, parity);
+          launch_walk_group<false>(map, layers, dim3(tiles), dim3(threads), st, d_origins, d_samples, d_weights, g,
+                                   K, tag, parity);
       }
       const bool has_last = g.scan[g.count - 1] == last;
       const uint32_t keep = has_last ? g.count - 1 : kMaxGroupSlots;
       {
-        ProfScope ps(map, OHM_KERNEL_FINALIZE_GROUP, st);
+        ProfScope ps(map, OHM_KERNEL_FINALIZE_GROUP, st, prof);
         if (weighted)
           hipLaunchKernelGGL(group_finalize_kernel<true>, dim3(kFinalizeBlocks), dim3(256), 0, st, map->dm, parity,
                              g.count, map->scans_done + 1, keep);
@@ -723,7 +846,7 @@ ohm_status ohm_integrate_rays(ohm_map map, const float* d_origins, const float* 
     if (n == 0) continue;
     uint32_t tag = 0, parity = 0;
     if (count_mode) {
-      clear_pending(map, st);
+      clear_pending(map, st, prof);
       tag = ++map->count_batches;
       parity = tag & 1u;
     }
@@ -731,36 +854,36 @@ ohm_status ohm_integrate_rays(ohm_map map, const float* d_origins, const float* 
     const dim3 threads(map->walk_threads);
     const int K = map->seg_major_steps;
     const uint32_t* perm = nullptr;
-    if (n <= map->order_max_rays) {
+    if (n <= ord.max_rays) {
       // walk the scan in direction order
-      ProfScope ps(map, OHM_KERNEL_OTHER, st);
+      ProfScope ps(map, OHM_KERNEL_OTHER, st, prof);
       const float* o = d_origins + 3 * (size_t)sc;
       const float* smp = d_samples + 3 * (size_t)r0;
       const uint32_t bins = order_bins(n), strips = order_strips(n);
       hipLaunchKernelGGL(fill_u32_kernel, dim3((bins + 255) / 256 < 8192 ? (bins + 255) / 256 : 8192), dim3(256), 0,
-                         st, map->order_hist, (size_t)bins, 0u);
+                         st, ord.hist, (size_t)bins, 0u);
       hipLaunchKernelGGL(scan_order_count_kernel, dim3((n + 255) / 256), dim3(256), 0, st, o, smp, n,
-                         map->order_hist);
-      hipLaunchKernelGGL(scan_order_strip_kernel, dim3(strips), dim3(kOrderElevationBins), 0, st, map->order_hist,
-                         map->order_sums);
-      hipLaunchKernelGGL(scan_order_sums_kernel, dim3(1), dim3(kOrderMaxStrips), 0, st, map->order_sums, strips);
+                         ord.hist);
+      hipLaunchKernelGGL(scan_order_strip_kernel, dim3(strips), dim3(kOrderElevationBins), 0, st, ord.hist,
+                         ord.sums);
+      hipLaunchKernelGGL(scan_order_sums_kernel, dim3(1), dim3(kOrderMaxStrips), 0, st, ord.sums, strips);
       hipLaunchKernelGGL(scan_order_place_kernel, dim3((n + 255) / 256), dim3(256), 0, st, o, smp, n,
-                         map->order_hist, map->order_sums, map->order_perm);
-      perm = map->order_perm;
+                         ord.hist, ord.sums, ord.perm);
+      perm = ord.perm;
     }
     if (count_mode) {
       {
-        ProfScope ps(map, OHM_KERNEL_WALK, st);
+        ProfScope ps(map, OHM_KERNEL_WALK, st, prof);
         if (weighted)
-          hipLaunchKernelGGL((walk_seg_kernel<kSinkCount, true>), tiles, threads, 0, st, map->dm, d_origins, sc,
-                             d_samples, d_weights, perm, r0, n, K, tag, parity, nullptr, nullptr, nullptr, nullptr);
+          launch_walk_seg<kSinkCount, true>(map, layers, tiles, threads, st, d_origins, sc, d_samples, d_weights,
+                                            perm, r0, n, K, tag, parity);
         else
-          hipLaunchKernelGGL((walk_seg_kernel<kSinkCount, false>), tiles, threads, 0, st, map->dm, d_origins, sc,
-                             d_samples, d_weights, perm, r0, n, K, tag, parity, nullptr, nullptr, nullptr, nullptr);
+          launch_walk_seg<kSinkCount, false>(map, layers, tiles, threads, st, d_origins, sc, d_samples, d_weights,
+                                             perm, r0, n, K, tag, parity);
       }
       const bool keep = sc == last;
       {
-        ProfScope ps(map, OHM_KERNEL_FINALIZE, st);
+        ProfScope ps(map, OHM_KERNEL_FINALIZE, st, prof);
         if (weighted)
           hipLaunchKernelGGL(finalize_kernel<true>, dim3(kFinalizeBlocks), dim3(256), 0, st, map->dm, parity, 1,
                              keep ? 0 : 1, map->scans_done + 1);
@@ -774,23 +897,42 @@ ohm_status ohm_integrate_rays(ohm_map map, const float* d_origins, const float* 
         map->kept_wide = weighted;
       }
     } else {
-      ProfScope ps(map, OHM_KERNEL_WALK, st);
+      ProfScope ps(map, OHM_KERNEL_WALK, st, prof);
       if (weighted)
-        hipLaunchKernelGGL((walk_seg_kernel<kSinkCas, true>), tiles, threads, 0, st, map->dm, d_origins, sc,
-                           d_samples, d_weights, perm, r0, n, K, tag, parity, nullptr, nullptr, nullptr, nullptr);
+        launch_walk_seg<kSinkCas, true>(map, layers, tiles, threads, st, d_origins, sc, d_samples, d_weights, perm,
+                                        r0, n, K, tag, parity);
       else
-        hipLaunchKernelGGL((walk_seg_kernel<kSinkCas, false>), tiles, threads, 0, st, map->dm, d_origins, sc,
-                           d_samples, d_weights, perm, r0, n, K, tag, parity, nullptr, nullptr, nullptr, nullptr);
+        launch_walk_seg<kSinkCas, false>(map, layers, tiles, threads, st, d_origins, sc, d_samples, d_weights, perm,
+                                         r0, n, K, tag, parity);
     }
     map->scans_done += 1;
   }
   return last_hip_status();
 }
 
+}  // namespace ohm
+
+extern "C" {
+
+ohm_status ohm_integrate_rays(ohm_map map, const float* d_origins, const float* d_samples,
+                              const uint32_t* h_scan_offsets, uint32_t n_scans, const float* d_weights,
+                              void* stream) {
+  ohm_status s = check_scans(map, d_origins, d_samples, h_scan_offsets, n_scans);
+  if (s != OHM_OK || n_scans == 0) return s;
+  const OrderScratch ord{map->order_hist, map->order_sums, map->order_perm, map->order_max_rays};
+  return integrate_rays_impl(map, d_origins, d_samples, h_scan_offsets, n_scans, d_weights, as_stream(stream), ord,
+                             true);
+}
+
 ohm_status ohm_map_read_dense(ohm_map map, int32_t what, const int32_t h_box_min[3], const int32_t h_box_dim[3],
                               void* d_out, void* stream) {
   if (!map || !h_box_min || !h_box_dim || !d_out) return OHM_E_INVALID_ARG;
-  if (what < OHM_READ_OCC || what > OHM_READ_CLAMP_SCAN) return OHM_E_INVALID_ARG;
+  if (what < OHM_READ_OCC || what > OHM_READ_DECAY_RATE) return OHM_E_INVALID_ARG;
+  if ((what == OHM_READ_MEAN_PACKED || what == OHM_READ_MEAN_COUNT || what == OHM_READ_MEAN) && !map->dm.mean)
+    return OHM_E_INVALID_ARG;
+  if ((what == OHM_READ_DECAY_LENGTH || what == OHM_READ_DECAY_HITS || what == OHM_READ_DECAY_RATE) &&
+      !map->dm.decay_len)
+    return OHM_E_INVALID_ARG;
   if ((what == OHM_READ_NDT_COUNT || what == OHM_READ_NDT_MEAN || what == OHM_READ_NDT_COV) && !map->dm.ndt)
     return OHM_E_INVALID_ARG;
   if (what == OHM_READ_CLAMP_SCAN && !map->dm.clampscan) return OHM_E_INVALID_ARG;
@@ -833,8 +975,7 @@ ohm_status ohm_debug_trace_rays(ohm_map map, const float* d_origins, const float
 
 ohm_status ohm_ray_order_scratch_size(uint32_t max_rays, size_t* bytes) {
   if (!bytes || max_rays == 0) return OHM_E_INVALID_ARG;
-  *bytes = align_up((size_t)order_bins(max_rays) * sizeof(uint32_t)) +
-           align_up((size_t)kOrderMaxStrips * sizeof(uint32_t)) + align_up((size_t)max_rays * sizeof(uint32_t));
+  *bytes = order_scratch_bytes(max_rays);
   return OHM_OK;
 }
 
@@ -849,11 +990,10 @@ ohm_status ohm_map_set_ray_order(ohm_map map, void* d_scratch, size_t bytes, uin
   if (ohm_ray_order_scratch_size(max_rays, &need) != OHM_OK) return OHM_E_INVALID_ARG;
   if ((uintptr_t)d_scratch & (kAlign - 1)) return OHM_E_INVALID_ARG;
   if (bytes < need) return OHM_E_WORKSPACE_TOO_SMALL;
-  char* base = static_cast<char*>(d_scratch);
-  const size_t hist_bytes = align_up((size_t)order_bins(max_rays) * sizeof(uint32_t));
-  map->order_hist = reinterpret_cast<uint32_t*>(base);
-  map->order_sums = reinterpret_cast<uint32_t*>(base + hist_bytes);
-  map->order_perm = reinterpret_cast<uint32_t*>(base + hist_bytes + align_up((size_t)kOrderMaxStrips * sizeof(uint32_t)));
+  const OrderScratch o = order_scratch_at(d_scratch, max_rays);
+  map->order_hist = o.hist;
+  map->order_sums = o.sums;
+  map->order_perm = o.perm;
   map->order_max_rays = max_rays;
   return OHM_OK;
 }

@@ -14,6 +14,7 @@
 #include <type_traits>
 
 #include "ohm_device.h"
+#include "ohm_layers.h"
 #include "ohm_regions.h"
 #include "ohm_seg_math.h"
 #include "ohm_wave.h"
@@ -224,14 +225,16 @@ __device__ __forceinline__ uint32_t tile_prologue(const DevMap& m, TileRays& tr,
   return tr.level_base[levels];
 }
 
-// Item `it` of the list: its tile-local ray, major axis and segment state.
-// False when the segment is empty (its ray left the map before it starts).
+// Item `it` of the list: its tile-local ray, major axis and segment state
+// (and, when asked, its segment level).  False when the segment is empty
+// (its ray left the map before it starts).
 __device__ __forceinline__ bool tile_item(const DevMap& m, const TileRays& tr, uint32_t it, int K, SegState& s,
-                                          uint32_t& ray_t, int& M) {
+                                          uint32_t& ray_t, int& M, uint32_t* level_out = nullptr) {
   ray_t = tr.item_ray[it];
   const uint32_t levels = tr.max_seg;
   uint32_t level = 0;
   while (level + 1 < levels && tr.level_base[level + 1] <= it) ++level;
+  if (level_out) *level_out = level;
   const int64_t q0[3] = {tr.q0[0][ray_t], tr.q0[1][ray_t], tr.q0[2][ray_t]};
   const int64_t q1[3] = {tr.q1[0][ray_t], tr.q1[1][ray_t], tr.q1[2][ray_t]};
   seg_init(s, q0, q1, m, (int)level, K);
@@ -276,9 +279,10 @@ __device__ __forceinline__ void flush_tile_stats(const DevMap& m, const TileRay&
 }
 
 // Occupancy walk of the tile of rays [tile0, tile0 + kTileRays) of a scan
-// (n rays from r0): count or per-update sinks, or the trace outputs.  Every
-// thread of the block must call it.
-template <int kSink, bool kWeighted>
+// (n rays from r0): count or per-update sinks, or the trace outputs.  With
+// kLayers the voxel mean and decay-rate layers the map holds are updated
+// too (ohm_layers.h).  Every thread of the block must call it.
+template <int kSink, bool kWeighted, bool kLayers = false>
 __device__ void walk_tile(const DevMap& m, const float* __restrict__ origin, const float* __restrict__ samples,
                           const float* __restrict__ weights, const uint32_t* __restrict__ perm, uint32_t r0,
                           uint32_t n, uint32_t tile0, int K,
@@ -344,8 +348,15 @@ __device__ void walk_tile(const DevMap& m, const float* __restrict__ origin, con
     int32_t slot = -1;
     uint32_t lidx = 0;
     int64_t out_base = 0;
+    DecayState dec;
     if (alive) {
-      alive = tile_item(m, tr, it, K, s, ray_t, M);
+      uint32_t level = 0;
+      alive = tile_item(m, tr, it, K, s, ray_t, M, &level);
+      if (kLayers && m.decay_len && alive) {
+        const int64_t q0[3] = {tr.q0[0][ray_t], tr.q0[1][ray_t], tr.q0[2][ray_t]};
+        const int64_t q1[3] = {tr.q1[0][ray_t], tr.q1[1][ray_t], tr.q1[2][ray_t]};
+        decay_init(dec, m, q0, q1, s, (int)level, M);
+      }
       trunc = tr.trunc[ray_t] != 0;
       const size_t ray = (size_t)r0 + tr.src[ray_t];
       if (kWeighted) wt = weights[ray];
@@ -383,6 +394,19 @@ __device__ void walk_tile(const DevMap& m, const float* __restrict__ origin, con
         if (alive && !has) {
           ++n_drop;
           n_hit_drop += is_hit ? 1u : 0u;
+        }
+        if constexpr (kLayers) {
+          if (m.decay_len) {
+            // the distance through this voxel, summed over the lanes' run
+            const long long dq = alive ? decay_visit(dec, m, s) : 0ll;
+            const long long sum = segmented_sum<long long>(has ? dq : 0ll, run.head, lane);
+            if (has && run.tail && sum) atomicAdd(m.decay_len + (id >> 1), (unsigned long long)sum);
+            if (has && is_hit && run.head) atomicAdd(m.decay_hits + (id >> 1), run.len);
+          }
+          if (m.mean && has && is_hit) {
+            const int64_t q1[3] = {tr.q1[0][ray_t], tr.q1[1][ray_t], tr.q1[2][ray_t]};
+            mean_sample<kSink == kSinkCount>(m, id >> 1, pack_codes(q1, m.F));
+          }
         }
         if (alive) alive = !last && tile_advance<kAccum>(m, rc, rw, s, M, slot, lidx);
         const bool miss_table = emit_here && !agg_finish(agg_key, agg_val, id, k, v);

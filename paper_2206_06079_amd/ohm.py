@@ -120,6 +120,9 @@ class OhmMap:
         _lib.READ_MISSES: (torch.float32, ()), _lib.READ_NDT_COUNT: (torch.int32, ()),
         _lib.READ_NDT_MEAN: (torch.float32, (3,)), _lib.READ_NDT_COV: (torch.float32, (6,)),
         _lib.READ_CLAMP_SCAN: (torch.int32, ()),
+        _lib.READ_MEAN_PACKED: (torch.int32, ()), _lib.READ_MEAN_COUNT: (torch.int32, ()),
+        _lib.READ_MEAN: (torch.float32, (3,)), _lib.READ_DECAY_LENGTH: (torch.float32, ()),
+        _lib.READ_DECAY_HITS: (torch.int32, ()), _lib.READ_DECAY_RATE: (torch.float32, ()),
     }
 
     def read_dense(self, what: int, box_min: Sequence[int], box_dim: Sequence[int], out=None, stream=None):

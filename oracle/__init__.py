@@ -50,6 +50,7 @@ class OrcParams(ctypes.Structure):
         ("adaptation_rate", ctypes.c_double),
         ("ndt_min_samples", ctypes.c_int32),
         ("ndt_clear_below", ctypes.c_double),
+        ("ndt_tm_gate", ctypes.c_double),
     ]
 
 
@@ -85,6 +86,10 @@ def _load():
     lib.orc_decay_integrate.argtypes = [P(OrcParams), ctypes.c_int32] + [vp] * 8
     lib.orc_ndt_miss_delta.restype = ctypes.c_double
     lib.orc_ndt_miss_delta.argtypes = [P(OrcParams), vp, vp, vp, vp, ctypes.c_uint32]
+    lib.orc_ndt_closest_q.restype = ctypes.c_double
+    lib.orc_ndt_closest_q.argtypes = [P(OrcParams), vp, vp, vp, vp]
+    lib.orc_ndt_tm_integrate.restype = ctypes.c_int
+    lib.orc_ndt_tm_integrate.argtypes = [P(OrcParams), ctypes.c_int32, ctypes.c_int32] + [vp] * 16
     _lib = lib
     return lib
 
@@ -105,6 +110,7 @@ def make_params(mp) -> OrcParams:
     p.adaptation_rate = float(mp.adaptation_rate)
     p.ndt_min_samples = int(mp.ndt_min_samples)
     p.ndt_clear_below = float(mp.ndt_clear_below)
+    p.ndt_tm_gate = float(mp.ndt_tm_gate)
     return p
 
 
@@ -234,6 +240,62 @@ def ndt_integrate(mp, batch, box_min=None, box_dim=None, occ=None, state=None, m
     if rc != 0:
         raise MemoryError("oracle box allocation failed")
     return occ, state, miss, dict(zip(STATS_FIELDS, (int(v) for v in stats)))
+
+
+def ndt_closest_q(mp, o, e, mu_w, cov6) -> float:
+    """Squared Mahalanobis distance of the ray's closest point to a voxel's
+    Gaussian (the NDT-TM miss check, paper Sec. II-D)."""
+    lib = _load()
+    p = make_params(mp)
+    a = [np.ascontiguousarray(np.asarray(x, np.float64)) for x in (o, e, mu_w, cov6)]
+    return float(lib.orc_ndt_closest_q(ctypes.byref(p), *[_ptr(x) for x in a]))
+
+
+class NdtTmState(NdtState):
+    """NDT-TM voxel state over a box window: the NDT-OM statistics plus the
+    checked miss count M (permeability n / (n + M)), the count of misses whose
+    check sat within a relative 1e-9 of the gate, and the intensity mean and
+    population variance."""
+
+    def __init__(self, shape):
+        super().__init__(shape)
+        self.miss = np.zeros(shape, np.uint32)
+        self.near = np.zeros(shape, np.uint32)
+        self.in_mean = np.zeros(shape, np.float64)
+        self.in_var = np.zeros(shape, np.float64)
+
+    def permeability(self):
+        tot = self.n.astype(np.float64) + self.miss
+        return np.divide(self.n.astype(np.float64), tot, out=np.zeros_like(tot), where=tot > 0)
+
+
+def ndt_tm_integrate(mp, batch, intensities, box_min=None, box_dim=None, occ=None, state=None, mode=1):
+    """NDT-TM integration (paper Sec. II-D, III-C) into a box window: NDT-OM
+    plus permeability counts and the intensity Gaussian.  ``intensities``:
+    float32 per ray.  Returns ``(occ, state, stats)``."""
+    lib = _load()
+    p = make_params(mp)
+    if box_min is None:
+        box_min = tuple(mp.key_min)
+        box_dim = tuple(b - a for a, b in zip(mp.key_min, mp.key_max))
+    bmin = np.asarray(box_min, np.int32)
+    bdim = np.asarray(box_dim, np.int32)
+    shape = (int(bdim[2]), int(bdim[1]), int(bdim[0]))
+    occ = np.full(shape, np.float32(mp.l_init), np.float32) if occ is None else np.ascontiguousarray(occ, np.float32).copy()
+    if state is None:
+        state = NdtTmState(shape)
+    inten = np.ascontiguousarray(intensities, np.float32)
+    if inten.shape[0] < batch.n_rays:
+        raise ValueError("one intensity per ray")
+    stats = np.zeros(len(STATS_FIELDS), np.uint64)
+    o, s, off, w = _batch_arrays(batch)
+    rc = lib.orc_ndt_tm_integrate(ctypes.byref(p), int(mode), batch.n_scans, _ptr(off), _ptr(o), _ptr(s),
+                                  _ptr(inten), _ptr(w), _ptr(bmin), _ptr(bdim), _ptr(occ), _ptr(state.n),
+                                  _ptr(state.mu), _ptr(state.cov), _ptr(state.miss), _ptr(state.near),
+                                  _ptr(state.in_mean), _ptr(state.in_var), _ptr(stats))
+    if rc != 0:
+        raise MemoryError("oracle box allocation failed")
+    return occ, state, dict(zip(STATS_FIELDS, (int(v) for v in stats)))
 
 
 def adjoint(mp, batch, box_min, box_dim, labels, mask=None, ndt=True, grads=True, near_eps=1e-3):

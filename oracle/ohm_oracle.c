@@ -52,6 +52,7 @@ typedef struct {
   double adaptation_rate;
   int32_t ndt_min_samples;
   double ndt_clear_below;
+  double ndt_tm_gate;
 } orc_params;
 
 enum { ORC_RAY_OK = 0, ORC_RAY_INVALID = 1, ORC_RAY_ORIGIN_OOB = 2 };
@@ -507,12 +508,11 @@ static double quad_form_inv(const double S6[6], const double D[3]) {
   return z0 * z0 + z1 * z1 + z2 * z2;
 }
 
-/* The NDT-weighted miss increment for one voxel (see above).  o and e are the
-   ray's world start and (possibly truncated) end; mu_w the voxel's world
-   mean; cov its covariance. */
-double orc_ndt_miss_delta(const orc_params* p, const double o[3], const double e[3], const double mu_w[3],
-                          const double cov[6], uint32_t n) {
-  if (n < (uint32_t)p->ndt_min_samples) return (double)p->l_miss;
+/* Squared Mahalanobis distance q = D^T S^-1 D of the ray's closest point to
+   the voxel's mean (see above).  o and e are the ray's world start and
+   (possibly truncated) end; mu_w the voxel's world mean; cov its covariance. */
+static double ndt_closest_q(const orc_params* p, const double o[3], const double e[3], const double mu_w[3],
+                            const double cov[6]) {
   double d[3], w[3];
   double dd = 0.0, wd = 0.0;
   for (int a = 0; a < 3; ++a) {
@@ -528,7 +528,14 @@ double orc_ndt_miss_delta(const orc_params* p, const double o[3], const double e
   for (int a = 0; a < 3; ++a) D[a] = (o[a] + t * d[a]) - mu_w[a];
   double s2 = p->sensor_noise * p->sensor_noise;
   double S[6] = {cov[0] + s2, cov[1], cov[2], cov[3] + s2, cov[4], cov[5] + s2};
-  double g = exp(-0.5 * quad_form_inv(S, D));
+  return quad_form_inv(S, D);
+}
+
+/* The NDT-weighted miss increment for one voxel (see above). */
+double orc_ndt_miss_delta(const orc_params* p, const double o[3], const double e[3], const double mu_w[3],
+                          const double cov[6], uint32_t n) {
+  if (n < (uint32_t)p->ndt_min_samples) return (double)p->l_miss;
+  double g = exp(-0.5 * ndt_closest_q(p, o, e, mu_w, cov));
   double pr = 0.5 - p->adaptation_rate * g * (0.5 - sigmoid_d((double)p->l_miss));
   return log(pr / (1.0 - pr));
 }
@@ -556,6 +563,32 @@ static void voxel_centre(const orc_params* p, const int32_t* k, double c[3]) {
 }
 
 /*
+ * NDT-TM (paper Sec. II-D, III-C) keeps, beside the NDT-OM statistics, the
+ * counts behind a voxel's permeability H / (H + M) and a 1D Gaussian of the
+ * intensity of the samples that fell in it:
+ *   H  = the voxel's samples (the NDT sample count n: both start together
+ *        and are cleared together);
+ *   M  = misses through the voxel that passed the check that the ray came
+ *        close to the voxel's data: the voxel holds >= ndt_min_samples
+ *        samples (so it has a Gaussian, from the statistics before the scan,
+ *        as the NDT-OM weighting uses) and the ray's closest point lies
+ *        within ndt_tm_gate of it in squared Mahalanobis distance
+ *        (q = D^T S^-1 D <= ndt_tm_gate);
+ *   intensity mean and population variance of the samples, by Welford's
+ *        update in ascending ray order alongside the position statistics.
+ * Counts are plain (ray weights scale only occupancy increments).  Voxels
+ * whose statistics are cleared lose M and the intensity Gaussian too.
+ */
+typedef struct {
+  uint32_t* miss;     /* M, [dz][dy][dx] */
+  uint32_t* near;     /* misses with q within a relative 1e-9 of the gate (either side): the
+                         decision there rests on the last bits of q; the GPU may take either */
+  double* in_mean;    /* intensity mean */
+  double* in_var;     /* intensity population variance */
+  const float* intensities; /* per ray */
+} orc_ndt_tm;
+
+/*
  * NDT-OM integration of n_scans scans into the box window (paper Sec. II-D,
  * III-C; formulas above).  mode 1 = count-then-clamp, 0 = per-update.
  *   occ        [dz][dy][dx] float, in/out
@@ -563,13 +596,14 @@ static void voxel_centre(const orc_params* p, const int32_t* k, double c[3]) {
  *   nd_mu      [dz][dy][dx][3] fp64, in/out means (voxel-centred, metres)
  *   nd_cov     [dz][dy][dx][6] fp64, in/out covariances
  *   miss_sum   optional out: last scan's summed miss increments per voxel
+ *   tm         optional NDT-TM state (see above), in/out
  *   stats      ORC_S_COUNT counters (accumulated)
  * Updates landing outside the window are ignored; so is the NDT state there.
  */
-int orc_ndt_integrate(const orc_params* p, int32_t mode, int32_t n_scans, const uint32_t* offsets,
-                      const float* origins, const float* samples, const float* weights, const int32_t box_min[3],
-                      const int32_t box_dim[3], float* occ, uint32_t* nd_n, double* nd_mu, double* nd_cov,
-                      double* miss_sum, uint64_t* stats) {
+static int ndt_integrate_core(const orc_params* p, int32_t mode, int32_t n_scans, const uint32_t* offsets,
+                              const float* origins, const float* samples, const float* weights,
+                              const int32_t box_min[3], const int32_t box_dim[3], float* occ, uint32_t* nd_n,
+                              double* nd_mu, double* nd_cov, double* miss_sum, orc_ndt_tm* tm, uint64_t* stats) {
   size_t nv = (size_t)box_dim[0] * box_dim[1] * box_dim[2];
   double* wh = (double*)calloc(nv, sizeof(double));
   double* dm = (double*)calloc(nv, sizeof(double));
@@ -625,6 +659,11 @@ int orc_ndt_integrate(const orc_params* p, int32_t mode, int32_t n_scans, const 
           voxel_centre(p, key, c);
           for (int a = 0; a < 3; ++a) muw[a] = c[a] + mu0[3 * v + a];
           dm[v] += w * orc_ndt_miss_delta(p, o, r.end, muw, cov0 + 6 * v, n0[v]);
+          if (tm && n0[v] >= (uint32_t)p->ndt_min_samples) {
+            double q = ndt_closest_q(p, o, r.end, muw, cov0 + 6 * v);
+            if (q <= p->ndt_tm_gate) tm->miss[v] += 1;
+            if (fabs(q - p->ndt_tm_gate) <= 1e-9 * fabs(p->ndt_tm_gate)) tm->near[v] += 1;
+          }
         }
       }
     }
@@ -642,6 +681,11 @@ int orc_ndt_integrate(const orc_params* p, int32_t mode, int32_t n_scans, const 
         nd_n[v] = 0;
         for (int a = 0; a < 3; ++a) nd_mu[3 * v + a] = 0.0;
         for (int a = 0; a < 6; ++a) nd_cov[6 * v + a] = 0.0;
+        if (tm) {
+          tm->miss[v] = 0;
+          tm->in_mean[v] = 0.0;
+          tm->in_var[v] = 0.0;
+        }
       }
     }
     /* phase 2b: fold this scan's samples, ascending ray order */
@@ -659,6 +703,13 @@ int orc_ndt_integrate(const orc_params* p, int32_t mode, int32_t n_scans, const 
       voxel_centre(p, key, c);
       const float* e = samples + 3 * (size_t)i;
       for (int a = 0; a < 3; ++a) x[a] = (double)e[a] - c[a];
+      if (tm) {
+        /* intensity Welford over the same samples: count n + 1 after this one */
+        double nn = (double)nd_n[v] + 1.0;
+        double d = (double)tm->intensities[i] - tm->in_mean[v];
+        tm->in_mean[v] += d / nn;
+        tm->in_var[v] = tm->in_var[v] * ((nn - 1.0) / nn) + d * d * ((nn - 1.0) / (nn * nn));
+      }
       welford_add(nd_n + v, nd_mu + 3 * v, nd_cov + 6 * v, x);
     }
     if (miss_sum && sc == n_scans - 1) memcpy(miss_sum, dm, nv * sizeof(double));
@@ -671,6 +722,35 @@ int orc_ndt_integrate(const orc_params* p, int32_t mode, int32_t n_scans, const 
   free(mu0);
   free(cov0);
   return 0;
+}
+
+int orc_ndt_integrate(const orc_params* p, int32_t mode, int32_t n_scans, const uint32_t* offsets,
+                      const float* origins, const float* samples, const float* weights, const int32_t box_min[3],
+                      const int32_t box_dim[3], float* occ, uint32_t* nd_n, double* nd_mu, double* nd_cov,
+                      double* miss_sum, uint64_t* stats) {
+  return ndt_integrate_core(p, mode, n_scans, offsets, origins, samples, weights, box_min, box_dim, occ, nd_n,
+                            nd_mu, nd_cov, miss_sum, NULL, stats);
+}
+
+/* NDT-TM integration: NDT-OM (above) plus the permeability counts and the
+   intensity Gaussian (tm_miss, tm_near, in_mean, in_var: in/out over the
+   window; intensities: one per ray). */
+int orc_ndt_tm_integrate(const orc_params* p, int32_t mode, int32_t n_scans, const uint32_t* offsets,
+                         const float* origins, const float* samples, const float* intensities, const float* weights,
+                         const int32_t box_min[3], const int32_t box_dim[3], float* occ, uint32_t* nd_n, double* nd_mu,
+                         double* nd_cov, uint32_t* tm_miss, uint32_t* tm_near, double* in_mean, double* in_var,
+                         uint64_t* stats) {
+  if (!intensities || !tm_miss || !tm_near || !in_mean || !in_var) return -2;
+  orc_ndt_tm tm = {tm_miss, tm_near, in_mean, in_var, intensities};
+  return ndt_integrate_core(p, mode, n_scans, offsets, origins, samples, weights, box_min, box_dim, occ, nd_n,
+                            nd_mu, nd_cov, NULL, &tm, stats);
+}
+
+/* The squared Mahalanobis distance behind the NDT-TM miss check of one voxel
+   (exposed for tests). */
+double orc_ndt_closest_q(const orc_params* p, const double o[3], const double e[3], const double mu_w[3],
+                         const double cov[6]) {
+  return ndt_closest_q(p, o, e, mu_w, cov);
 }
 
 /* ---------------------------------------------------------------------- */

@@ -57,6 +57,7 @@ class MapParams:
     adaptation_rate: float = 1.0      # NDT
     ndt_min_samples: int = 4          # NDT
     ndt_clear_below: float = -math.inf  # NDT sample clearing threshold (disabled)
+    ndt_tm_gate: float = 9.0          # NDT-TM: squared Mahalanobis distance of a checked miss (3 sigma)
 
     def replace(self, **kw) -> "MapParams":
         return dataclasses.replace(self, **kw)

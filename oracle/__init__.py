@@ -51,6 +51,8 @@ class OrcParams(ctypes.Structure):
         ("ndt_min_samples", ctypes.c_int32),
         ("ndt_clear_below", ctypes.c_double),
         ("ndt_tm_gate", ctypes.c_double),
+        ("tsdf_truncation", ctypes.c_double),
+        ("tsdf_max_weight", ctypes.c_double),
     ]
 
 
@@ -88,6 +90,8 @@ def _load():
     lib.orc_ndt_miss_delta.argtypes = [P(OrcParams), vp, vp, vp, vp, ctypes.c_uint32]
     lib.orc_ndt_closest_q.restype = ctypes.c_double
     lib.orc_ndt_closest_q.argtypes = [P(OrcParams), vp, vp, vp, vp]
+    lib.orc_tsdf_integrate.restype = ctypes.c_int
+    lib.orc_tsdf_integrate.argtypes = [P(OrcParams), ctypes.c_int32, ctypes.c_int32] + [vp] * 8
     lib.orc_ndt_tm_integrate.restype = ctypes.c_int
     lib.orc_ndt_tm_integrate.argtypes = [P(OrcParams), ctypes.c_int32, ctypes.c_int32] + [vp] * 16
     _lib = lib
@@ -111,6 +115,8 @@ def make_params(mp) -> OrcParams:
     p.ndt_min_samples = int(mp.ndt_min_samples)
     p.ndt_clear_below = float(mp.ndt_clear_below)
     p.ndt_tm_gate = float(mp.ndt_tm_gate)
+    p.tsdf_truncation = float(mp.tsdf_truncation)
+    p.tsdf_max_weight = float(mp.tsdf_max_weight)
     return p
 
 
@@ -375,3 +381,26 @@ def decay_integrate(mp, batch, box_min=None, box_dim=None, length=None, hits=Non
     if rc != 0:
         raise MemoryError("oracle box allocation failed")
     return length, hits
+
+
+def tsdf_integrate(mp, batch, box_min=None, box_dim=None, dist=None, weight=None, mode=1):
+    """TSDF integration (paper Sec. II-F) into a box window: per voxel the
+    weighted mean projective distance D and its weight W.  mode 1 = per-scan
+    sums, 0 = per update in ray order.  Returns ``(dist, weight, stats)``."""
+    lib = _load()
+    p = make_params(mp)
+    if box_min is None:
+        box_min = tuple(mp.key_min)
+        box_dim = tuple(b - a for a, b in zip(mp.key_min, mp.key_max))
+    bmin = np.asarray(box_min, np.int32)
+    bdim = np.asarray(box_dim, np.int32)
+    shape = (int(bdim[2]), int(bdim[1]), int(bdim[0]))
+    dist = np.zeros(shape, np.float32) if dist is None else np.ascontiguousarray(dist, np.float32).copy()
+    weight = np.zeros(shape, np.float32) if weight is None else np.ascontiguousarray(weight, np.float32).copy()
+    stats = np.zeros(len(STATS_FIELDS), np.uint64)
+    o, s, off, _ = _batch_arrays(batch)
+    rc = lib.orc_tsdf_integrate(ctypes.byref(p), int(mode), batch.n_scans, _ptr(off), _ptr(o), _ptr(s), _ptr(bmin),
+                                _ptr(bdim), _ptr(dist), _ptr(weight), _ptr(stats))
+    if rc != 0:
+        raise MemoryError("oracle box allocation failed")
+    return dist, weight, dict(zip(STATS_FIELDS, (int(v) for v in stats)))

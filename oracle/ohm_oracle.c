@@ -53,6 +53,8 @@ typedef struct {
   int32_t ndt_min_samples;
   double ndt_clear_below;
   double ndt_tm_gate;
+  double tsdf_truncation;
+  double tsdf_max_weight;
 } orc_params;
 
 enum { ORC_RAY_OK = 0, ORC_RAY_INVALID = 1, ORC_RAY_ORIGIN_OOB = 2 };
@@ -751,6 +753,152 @@ int orc_ndt_tm_integrate(const orc_params* p, int32_t mode, int32_t n_scans, con
 double orc_ndt_closest_q(const orc_params* p, const double o[3], const double e[3], const double mu_w[3],
                          const double cov[6]) {
   return ndt_closest_q(p, o, e, mu_w, cov);
+}
+
+/* ---------------------------------------------------------------------- */
+/* TSDF                                                                    */
+/* ---------------------------------------------------------------------- */
+/*
+ * Truncated signed distance (paper Sec. II-F: voxels within a truncation
+ * distance in front of and behind the measured point, along the ray from
+ * the sensor, take a projective distance; Sec. III-B: updated like the
+ * other 64-bit layers).  Readings:
+ *   - only a ray with a surface takes part: valid, origin in the map, not
+ *     truncated by max range, sample voxel in the map, and of non-zero
+ *     length (the occupancy rules for a hit);
+ *   - with r = |e - o| and u = (e - o) / r (fp64), the band is the segment
+ *     from o + max(r - tau, 0) u to o + (r + tau) u; its two ends are
+ *     quantised like ray ends and walked exactly (clipped at the map's
+ *     bounds; a band whose first voxel lies outside the map is skipped);
+ *   - each voxel of the band takes sdf = clamp(r - (c - o).u, -tau, tau),
+ *     c its centre: positive in front of the surface, negative behind;
+ *   - a voxel keeps a distance D and a weight W (both 0 until observed);
+ *     n updates of summed distance S (unit weight each) give
+ *     D <- (W D + S) / (W + n), W <- min(W + n, tsdf_max_weight);
+ *     count mode applies each scan's updates at once, per-update mode one at
+ *     a time (here in ray order, band order); D and W are stored as float
+ *     after every application.
+ * tau = tsdf_truncation.  Arithmetic fp64.
+ */
+
+/* The band of a prepared ray (see above); returns 0 when the ray has none. */
+static int tsdf_band(const orc_params* p, const float o[3], const float e[3], const orc_ray* r, orc_ray* band,
+                     double* range, double u[3]) {
+  if (r->status != ORC_RAY_OK || r->truncated || !in_bounds(p, r->k1)) return 0;
+  double d[3];
+  for (int a = 0; a < 3; ++a) d[a] = (double)e[a] - (double)o[a];
+  double r2 = d[0] * d[0];
+  r2 = r2 + d[1] * d[1];
+  r2 = r2 + d[2] * d[2];
+  if (!(r2 > 0.0)) return 0;
+  double len = sqrt(r2);
+  double tau = p->tsdf_truncation;
+  double s0 = len - tau;
+  if (s0 < 0.0) s0 = 0.0;
+  double s1 = len + tau;
+  double scale = ldexp(1.0, p->fixed_bits) / p->voxel_size;
+  memset(band, 0, sizeof(*band));
+  for (int a = 0; a < 3; ++a) {
+    u[a] = d[a] / len;
+    double b0 = (double)o[a] + s0 * u[a];
+    double b1 = (double)o[a] + s1 * u[a];
+    if (!quantise(b0, p->map_origin[a], scale, &band->q0[a]) || !quantise(b1, p->map_origin[a], scale, &band->q1[a]))
+      return 0;
+    band->k0[a] = floor_div_pow2(band->q0[a], p->fixed_bits);
+    band->k1[a] = floor_div_pow2(band->q1[a], p->fixed_bits);
+  }
+  if (!in_bounds(p, band->k0)) return 0;
+  *range = len;
+  return 1;
+}
+
+static double tsdf_distance(const orc_params* p, const float o[3], double range, const double u[3],
+                            const int32_t* key) {
+  double c[3];
+  voxel_centre(p, key, c);
+  double proj = (c[0] - (double)o[0]) * u[0];
+  proj = proj + (c[1] - (double)o[1]) * u[1];
+  proj = proj + (c[2] - (double)o[2]) * u[2];
+  double v = range - proj;
+  double tau = p->tsdf_truncation;
+  return v < -tau ? -tau : (v > tau ? tau : v);
+}
+
+static void tsdf_apply(const orc_params* p, float* dist, float* weight, double sum, double n) {
+  double W = (double)*weight;
+  double D = ((double)*dist * W + sum) / (W + n);
+  double Wn = W + n;
+  if (Wn > p->tsdf_max_weight) Wn = p->tsdf_max_weight;
+  *dist = (float)D;
+  *weight = (float)Wn;
+}
+
+/*
+ * TSDF integration of n_scans scans into the box window.  mode 1 = count
+ * (per-scan sums), 0 = per-update (sequential).  dist / weight:
+ * [dz][dy][dx] float in/out.  stats: ORC_S_RAYS / INVALID / ORIGIN_OOB /
+ * TRUNCATED / CLIPPED as for occupancy, ORC_S_HITS = rays with a band,
+ * ORC_S_UPDATES = band voxel updates (inside the map).
+ */
+int orc_tsdf_integrate(const orc_params* p, int32_t mode, int32_t n_scans, const uint32_t* offsets,
+                       const float* origins, const float* samples, const int32_t box_min[3], const int32_t box_dim[3],
+                       float* dist, float* weight, uint64_t* stats) {
+  size_t nv = (size_t)box_dim[0] * box_dim[1] * box_dim[2];
+  double* sum = (double*)calloc(nv, sizeof(double));
+  double* cnt = (double*)calloc(nv, sizeof(double));
+  if (!sum || !cnt) {
+    free(sum);
+    free(cnt);
+    return -1;
+  }
+  orc_scratch s = {0};
+  for (int32_t sc = 0; sc < n_scans; ++sc) {
+    const float* of = origins + 3 * sc;
+    for (uint32_t i = offsets[sc]; i < offsets[sc + 1]; ++i) {
+      const float* e = samples + 3 * (size_t)i;
+      orc_ray r, band;
+      prepare_ray(p, of, e, &r);
+      if (stats) stats[ORC_S_RAYS] += 1;
+      if (r.status != ORC_RAY_OK) {
+        if (stats) stats[r.status == ORC_RAY_INVALID ? ORC_S_INVALID : ORC_S_ORIGIN_OOB] += 1;
+        continue;
+      }
+      if (stats) {
+        stats[ORC_S_TRUNCATED] += r.truncated ? 1 : 0;
+        stats[ORC_S_CLIPPED] += (!r.truncated && !in_bounds(p, r.k1)) ? 1 : 0;
+      }
+      double range, u[3];
+      if (!tsdf_band(p, of, e, &r, &band, &range, u)) continue;
+      int clipped = 0;
+      int64_t nk = walk_ray(p, &band, &s, &clipped);
+      if (stats) {
+        stats[ORC_S_HITS] += 1;
+        stats[ORC_S_UPDATES] += (uint64_t)nk;
+      }
+      for (int64_t j = 0; j < nk; ++j) {
+        const int32_t* key = s.keys + 3 * j;
+        int64_t v = box_index(key, box_min, box_dim);
+        if (v < 0) continue;
+        double sd = tsdf_distance(p, of, range, u, key);
+        if (mode == 1) {
+          sum[v] += sd;
+          cnt[v] += 1.0;
+        } else {
+          tsdf_apply(p, dist + v, weight + v, sd, 1.0);
+        }
+      }
+    }
+    if (mode == 1) {
+      for (size_t v = 0; v < nv; ++v)
+        if (cnt[v] > 0.0) tsdf_apply(p, dist + v, weight + v, sum[v], cnt[v]);
+      memset(sum, 0, nv * sizeof(double));
+      memset(cnt, 0, nv * sizeof(double));
+    }
+  }
+  scratch_free(&s);
+  free(sum);
+  free(cnt);
+  return 0;
 }
 
 /* ---------------------------------------------------------------------- */

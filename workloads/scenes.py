@@ -58,6 +58,8 @@ class MapParams:
     ndt_min_samples: int = 4          # NDT
     ndt_clear_below: float = -math.inf  # NDT sample clearing threshold (disabled)
     ndt_tm_gate: float = 9.0          # NDT-TM: squared Mahalanobis distance of a checked miss (3 sigma)
+    tsdf_truncation: float = 0.3      # TSDF: band half-width along the ray (metres)
+    tsdf_max_weight: float = 10000.0  # TSDF: weight cap
 
     def replace(self, **kw) -> "MapParams":
         return dataclasses.replace(self, **kw)

@@ -11,10 +11,12 @@ ohm_integrate_rays call over all 100 scans on a map with scan groups of G
 scans per launch, then the in-order per-scan clamp of the group); the same
 call on a map that launches once per scan is timed beside it.
 
-Reported alongside: the per-update (CAS) mode, NDT-OM integration of the
-same scans, the adjoint on the 20-scan 0.2 m workload, and the batched
-multi-sensor plan against per-scan launches.  Prints one JSON line on
-stdout; progress goes to stderr.
+Reported alongside, each with its roofline: the 32,768-ray single-batch
+workload, the per-update (CAS) mode, the occupancy map with the voxel-mean
+layer (what the paper's occupancy timings include) and with the decay-rate
+layer, NDT-OM, NDT-TM and TSDF integration of the same scans, the adjoint on
+the 20-scan 0.2 m workload, and the batched multi-sensor plan against
+per-scan launches.  Prints one JSON line on stdout; progress goes to stderr.
 """
 import argparse
 import json
@@ -28,16 +30,40 @@ if ROOT not in sys.path:
 
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, published
 
+# Algorithmic bytes per unit of work (the figures the roofline fractions use).
+RAY_BYTES = 12.0          # one sample (3 x f32)
+SCAN_BYTES = 12.0         # one sensor origin per scan
+COUNT_UPDATE_BYTES = 16.0 # count mode: one 8-byte counter read-modify-write at the coherence point
+CAS_UPDATE_BYTES = 8.0    # per-update mode: one 4-byte f32 read-modify-write
+NDT_MISS_EXTRA = 40.0     # NDT: the voxel's statistics (n, mean, covariance) read by a miss
+NDT_SAMPLE_BYTES = 12.0 + 10 * 16.0  # NDT: the sample plus ten 8-byte moment read-modify-writes
+ADJ_VISIT_BYTES = 8.0     # adjoint: the voxel's upstream gradient and clamp record per visit
+
 
 def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
-def walk_bytes(rays, updates, scans=1.0):
-    """Algorithmic bytes of the walk kernel: each ray reads its 12-byte sample
-    (plus each scan's 12-byte origin), and each voxel update is one 4-byte
-    read-modify-write at the coherence point (4 B read + 4 B written)."""
-    return 12.0 * rays + 12.0 * scans + 8.0 * updates
+def walk_bytes(rays, updates, scans=1.0, per_update=COUNT_UPDATE_BYTES):
+    """Algorithmic bytes of an occupancy walk: each ray reads its 12-byte
+    sample, each scan its 12-byte origin, and each voxel update is one
+    counter read-modify-write at the coherence point (16 B in count mode,
+    8 B for the per-update mode's f32 compare-and-swap)."""
+    return RAY_BYTES * rays + SCAN_BYTES * scans + per_update * updates
+
+
+def percentiles(ms):
+    import numpy as np
+
+    a = np.asarray(ms, np.float64)
+    return {"median": round(float(np.median(a)), 5), "p10": round(float(np.percentile(a, 10)), 5),
+            "p90": round(float(np.percentile(a, 90)), 5)}
+
+
+def hbm(bytes_, ms):
+    """GB/s and fraction of the published HBM peak for `bytes_` moved in `ms`."""
+    gbs = bytes_ / (ms * 1e-3) / 1e9
+    return {"achieved_gbs": round(gbs, 1), "frac": round(gbs / HBM_PEAK_GBS, 4), "bytes": int(bytes_)}
 
 
 def kernel_source_digest():
@@ -55,24 +81,62 @@ def kernel_source_digest():
     return h.hexdigest()
 
 
-def measured_traffic(kernel):
-    """HBM bytes per launch of `kernel` from its committed byte-counter
-    summary, or None once the kernel sources differ from those the counters
-    were taken on."""
+def measured_counters(name):
+    """Per-launch counter figures of a kernel from its committed summary
+    (profiles/<name>_pmc.md), or {} once the kernel sources differ from
+    those the counters were taken on."""
     import re
 
-    path = os.path.join(ROOT, "profiles", f"{kernel}_config1_pmc.md")
+    path = os.path.join(ROOT, "profiles", f"{name}_pmc.md")
     if not os.path.exists(path):
-        return None
+        return {}
     text = open(path).read()
-    tb = re.search(r"^traffic_bytes_per_launch:\s*(\d+)", text, re.M)
     sha = re.search(r"^kernel_source_sha256:\s*([0-9a-f]{64})", text, re.M)
-    if not tb or not sha or sha.group(1) != kernel_source_digest():
-        return None
-    return int(tb.group(1))
+    if not sha or sha.group(1) != kernel_source_digest():
+        return {}
+    out = {}
+    for key in ("traffic_bytes_per_launch", "atomic_requests_per_launch"):
+        m = re.search(rf"^{key}:\s*(\d+)", text, re.M)
+        if m:
+            out[key] = int(m.group(1))
+    return out
 
 
-def run_gpu(args, params, batch, mode, layers=1):
+def host_cpu():
+    model = "unknown"
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    try:
+        usable = len(os.sched_getaffinity(0))
+    except AttributeError:
+        usable = os.cpu_count()
+    return {"cpu_model": model, "nproc": os.cpu_count(), "usable_cpus": usable}
+
+
+def timed(fn, steps, stream):
+    """Run fn() `steps` times with a pair of HIP events around each run on
+    `stream`; returns the per-run milliseconds."""
+    import torch
+
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(steps)]
+    for a, b in ev:
+        a.record(stream)
+        fn()
+        b.record(stream)
+    torch.cuda.synchronize()
+    return [a.elapsed_time(b) for a, b in ev]
+
+
+def run_map(args, params, batch, mode, layers=1, call="integrate", steps=None, capacity=None, extra=None):
+    """Time `steps` calls of OhmMap.<call> over the whole batch on one map
+    (after the warm-up calls); returns per-step times, kernel times and the
+    per-step rays and updates."""
     import torch
 
     import paper_2206_06079_amd as ohm
@@ -81,40 +145,52 @@ def run_gpu(args, params, batch, mode, layers=1):
     o = torch.from_numpy(batch.origins).to(dev)
     s = torch.from_numpy(batch.samples).to(dev)
     off = batch.offsets
-    m = ohm.OhmMap(params.replace(mode=mode), args.capacity, layers=layers, device=dev)
+    m = ohm.OhmMap(params.replace(mode=mode), capacity or args.capacity, layers=layers, device=dev)
+    fn_call = getattr(m, call)
+    x = extra or ()
+    if call == "ndt_tm_integrate":
+        fn = lambda: fn_call(o, s, *x, off)  # noqa: E731
+    else:
+        fn = lambda: fn_call(o, s, off)  # noqa: E731
     stream = torch.cuda.current_stream()
     for _ in range(args.warmup):
-        m.integrate(o, s, off)
+        fn()
     torch.cuda.synchronize()
     st0 = m.stats()
-    steps = args.steps if mode == ohm.MODE_COUNT_CLAMP else max(2, args.steps // 2)
+    steps = steps or args.steps
     m.set_profiling(True)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    e0 = torch.cuda.Event(enable_timing=True)
-    e1 = torch.cuda.Event(enable_timing=True)
-    e0.record(stream)
-    for k in range(steps):
-        m.integrate(o, s, off)
-    e1.record(stream)
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
+    ms = timed(fn, steps, stream)
     kt = m.kernel_times()
     m.set_profiling(False)
     st1 = m.stats()
     m.close()
-    ms_total = e0.elapsed_time(e1)
-    upd = (st1["voxel_updates"] - st0["voxel_updates"]) / steps
-    rays = (st1["rays_in"] - st0["rays_in"]) / steps
     return {
         "steps": steps,
-        "ms_per_step": ms_total / steps,
-        "wall_ms_per_step": (t1 - t0) * 1e3 / steps,
-        "rays_per_step": rays,
-        "updates_per_step": upd,
+        "ms": ms,
+        "ms_per_step": sum(ms) / steps,
+        "rays_per_step": (st1["rays_in"] - st0["rays_in"]) / steps,
+        "updates_per_step": (st1["voxel_updates"] - st0["voxel_updates"]) / steps,
+        "hits_per_step": (st1["rays_hit"] - st0["rays_hit"]) / steps,
         "kernels": kt,
         "stats": st1,
     }
+
+
+def leg_summary(r, workload):
+    sec = r["ms_per_step"] * 1e-3
+    return {
+        "workload": workload,
+        "rays_per_s": round(r["rays_per_step"] / sec, 1),
+        "voxel_updates_per_s": round(r["updates_per_step"] / sec, 1),
+        "ms_per_step": round(r["ms_per_step"], 4),
+        "ms_per_step_pct": percentiles(r["ms"]),
+        "kernel_ms_per_step": {k: round(v[1] / r["steps"], 4) for k, v in r["kernels"].items()},
+    }
+
+
+def kernel_avg_ms(r, kind):
+    n, ms = r["kernels"].get(kind, (0, 0.0))
+    return ms / max(1, n), n
 
 
 def generate_batched(args):
@@ -134,7 +210,7 @@ def generate_batched(args):
 def run_batched(args, generated):
     """The multi-sensor workload: 16 streams, scans of log-uniform size in
     [8192, 262144] rays with unordered directions, half into a 0.1 m map and
-    half into a 0.05 m map.  Times one graph launch of the batched plan
+    half into a 0.05 m map.  Times graph launches of the batched plan
     (schedule from the autotuner) against per-scan launches of the plain
     path over the same maps (walking each scan in direction order, and in
     its given order), all with inputs resident in HBM."""
@@ -161,14 +237,9 @@ def run_batched(args, generated):
     plan.run(stream)
     torch.cuda.synchronize()
     st0 = [m.stats() for m in maps]
-    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     reps = args.batched_reps
-    e0.record(stream)
-    for _ in range(reps):
-        plan.run(stream)
-    e1.record(stream)
-    torch.cuda.synchronize()
-    ms_batched = e0.elapsed_time(e1) / reps
+    ms = timed(lambda: plan.run(stream), reps, stream)
+    ms_batched = sum(ms) / reps
     st1 = [m.stats() for m in maps]
     upd = sum(b["voxel_updates"] - a["voxel_updates"] for a, b in zip(st0, st1)) / reps
     plan.close()
@@ -184,23 +255,25 @@ def run_batched(args, generated):
             m.set_ray_order(order)
             m.integrate(o, s, off)
         torch.cuda.synchronize()
-        e0.record(stream)
-        for _ in range(reps):
+
+        def one_pass():
             for m, (o, s, off) in zip(maps, inputs):
                 m.integrate(o, s, off)
-        e1.record(stream)
-        torch.cuda.synchronize()
-        ms_plain[label] = e0.elapsed_time(e1) / reps
+
+        ms_plain[label] = sum(timed(one_pass, reps, stream)) / reps
         for m in maps:
             m.close()
     log(f"batched {choice}: {ms_batched:.2f} ms per pass; per-scan launches: {ms_plain}")
+    pass_bytes = walk_bytes(n_rays, upd, sum(b.n_scans for b in batches))
     return {
         "workload": f"16 sensor streams, {args.batched_scans} scans of log-uniform size in [8192, 262144] rays "
                     f"({n_rays} rays), tunnel scene, maps at 0.1 m and 0.05 m",
         "rays_per_s": round(n_rays / (ms_batched * 1e-3), 1),
         "voxel_updates_per_s": round(upd / (ms_batched * 1e-3), 1),
         "ms_per_pass": round(ms_batched, 3),
+        "ms_per_pass_pct": percentiles(ms),
         "schedule": choice,
+        "roofline_hbm": hbm(pass_bytes, ms_batched),
         "per_scan_plain_rays_per_s": round(n_rays / (ms_plain["direction_order"] * 1e-3), 1),
         "per_scan_plain_ms_per_pass": round(ms_plain["direction_order"], 3),
         "speedup_vs_per_scan": round(ms_plain["direction_order"] / ms_batched, 3),
@@ -229,68 +302,106 @@ def run_batched_headline(args, params, batch):
     plan.run(stream)
     torch.cuda.synchronize()
     st0 = m.stats()
-    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     reps = max(1, args.steps // 2)
-    e0.record(stream)
-    for _ in range(reps):
-        plan.run(stream)
-    e1.record(stream)
-    torch.cuda.synchronize()
-    ms = e0.elapsed_time(e1) / reps
+    ms = timed(lambda: plan.run(stream), reps, stream)
+    ms_avg = sum(ms) / reps
     st1 = m.stats()
     plan.close()
     m.close()
     rays = (st1["rays_in"] - st0["rays_in"]) / reps
     upd = (st1["voxel_updates"] - st0["voxel_updates"]) / reps
-    log(f"headline scans through the batched plan {choice}: {ms:.3f} ms per pass")
+    log(f"headline scans through the batched plan {choice}: {ms_avg:.3f} ms per pass")
     return {
         "workload": f"the same {batch.n_scans} scans through the batched plan (one map)",
-        "rays_per_s": round(rays / (ms * 1e-3), 1),
-        "voxel_updates_per_s": round(upd / (ms * 1e-3), 1),
-        "ms_per_pass": round(ms, 3),
+        "rays_per_s": round(rays / (ms_avg * 1e-3), 1),
+        "voxel_updates_per_s": round(upd / (ms_avg * 1e-3), 1),
+        "ms_per_pass": round(ms_avg, 3),
+        "ms_per_pass_pct": percentiles(ms),
         "schedule": choice,
+        "roofline_hbm": hbm(walk_bytes(rays, upd, batch.n_scans), ms_avg),
     }
 
 
-def run_ndt(args, params, batch):
-    """NDT-OM integration of the same 100 scans (sensor noise 0.05 m,
-    adaptation rate 1, 4 samples before a voxel weights its misses), count
-    mode, timed like the plain path."""
-    import torch
+def run_config0(args):
+    """The single-batch workload: 32,768 rays from the centre of a 20 m cube
+    of 0.1 m voxels (every ray starts in the same voxel), count mode, one
+    integrate call per step."""
+    from workloads import scenes
 
     import paper_2206_06079_amd as ohm
 
-    p = params.replace(sensor_noise=0.05, adaptation_rate=1.0, ndt_min_samples=4, mode=ohm.MODE_COUNT_CLAMP)
-    dev = torch.device("cuda", 0)
-    o = torch.from_numpy(batch.origins).to(dev)
-    s = torch.from_numpy(batch.samples).to(dev)
-    m = ohm.OhmMap(p, args.capacity, layers=ohm.LAYER_NDT, device=dev)
-    stream = torch.cuda.current_stream()
-    m.ndt_integrate(o, s, batch.offsets)
-    torch.cuda.synchronize()
-    st0 = m.stats()
-    steps = max(1, args.steps // 3)
-    m.set_profiling(True)
-    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    e0.record(stream)
-    for _ in range(steps):
-        m.ndt_integrate(o, s, batch.offsets)
-    e1.record(stream)
-    torch.cuda.synchronize()
-    kt = m.kernel_times()
-    st1 = m.stats()
-    m.close()
-    ms = e0.elapsed_time(e1) / steps
-    rays = (st1["rays_in"] - st0["rays_in"]) / steps
-    upd = (st1["voxel_updates"] - st0["voxel_updates"]) / steps
-    log(f"ndt: {ms:.3f} ms per {batch.n_scans}-scan pass")
-    return {
-        "workload": f"the same {batch.n_scans} scans into an NDT-OM map (count mode)",
-        "rays_per_s": round(rays / (ms * 1e-3), 1),
-        "voxel_updates_per_s": round(upd / (ms * 1e-3), 1),
-        "ms_per_pass": round(ms, 3),
-        "kernel_us_per_scan": {k: round(v[1] / v[0] * 1e3, 1) for k, v in kt.items()},
-    }
+    mp, batch = scenes.config0()
+    r = run_map(args, mp, batch, ohm.MODE_COUNT_CLAMP, steps=max(5, args.steps * 2), capacity=343)
+    out = leg_summary(r, "32,768 rays from a voxel corner at the centre of a 20 m cube, 0.1 m voxels, "
+                         "ranges U[1, 15] m, one batch per step")
+    walk_ms, _ = kernel_avg_ms(r, "walk")
+    out["walk_kernel_ms"] = round(walk_ms, 5)
+    out["roofline_hbm"] = hbm(walk_bytes(r["rays_per_step"], r["updates_per_step"]), walk_ms)
+    log(f"config 0: {r['ms_per_step']:.4f} ms per batch, walk {walk_ms * 1e3:.1f} us")
+    return out
+
+
+def run_layers(args, params, batch):
+    """Occupancy with the voxel-mean layer (the paper's occupancy timings
+    maintain the mean too) and with the decay-rate layer, scan-grouped like
+    the headline."""
+    import paper_2206_06079_amd as ohm
+
+    out = {}
+    groups = ohm.LAYER_SCAN_GROUPS | ohm.scan_group_slots(args.scan_group_slots)
+    for name, layer in (("occupancy_with_mean", ohm.LAYER_MEAN), ("occupancy_with_decay_rate", ohm.LAYER_DECAY)):
+        r = run_map(args, params, batch, ohm.MODE_COUNT_CLAMP, ohm.LAYER_OCC | groups | layer,
+                    steps=max(2, args.steps // 2))
+        out[name] = leg_summary(r, f"the {batch.n_scans} headline scans, count mode, "
+                                   f"{args.scan_group_slots}-scan groups, with the layer")
+        log(f"{name}: {r['ms_per_step']:.3f} ms per step")
+    return out
+
+
+def run_ndt(args, params, batch, tm=False):
+    """NDT-OM (or NDT-TM) integration of the same 100 scans (sensor noise
+    0.05 m, adaptation rate 1, 4 samples before a voxel weights its misses),
+    count mode, timed like the plain path."""
+    import torch
+
+    import paper_2206_06079_amd as ohm
+    from workloads import scenes
+
+    p = params.replace(sensor_noise=0.05, adaptation_rate=1.0, ndt_min_samples=4)
+    layers = ohm.LAYER_NDT | (ohm.LAYER_NDT_TM if tm else 0)
+    extra = None
+    if tm:
+        extra = (torch.from_numpy(scenes.lidar_intensities(batch)).to("cuda"),)
+    r = run_map(args, p, batch, ohm.MODE_COUNT_CLAMP, layers, call="ndt_tm_integrate" if tm else "ndt_integrate",
+                steps=max(2, args.steps // 3), extra=extra)
+    name = "NDT-TM" if tm else "NDT-OM"
+    out = leg_summary(r, f"the same {batch.n_scans} scans into an {name} map (count mode)")
+    walk_ms, n_walk = kernel_avg_ms(r, "walk")
+    scans = batch.n_scans
+    rays, upd, hits = r["rays_per_step"] / scans, r["updates_per_step"] / scans, r["hits_per_step"] / scans
+    walk_b = (RAY_BYTES * rays + SCAN_BYTES + (COUNT_UPDATE_BYTES + NDT_MISS_EXTRA) * (upd - hits)
+              + (COUNT_UPDATE_BYTES + NDT_SAMPLE_BYTES) * hits)
+    out["kernel_us_per_scan"] = {k: round(v[1] / v[0] * 1e3, 1) for k, v in r["kernels"].items()}
+    out["roofline_hbm"] = dict(hbm(walk_b, walk_ms), kernel="ndt_seg_kernel", unit="per scan")
+    log(f"{name}: {r['ms_per_step']:.3f} ms per {scans}-scan pass")
+    return out
+
+
+def run_tsdf(args, params, batch):
+    """TSDF integration of the same 100 scans (band of 0.3 m on each side of
+    the sample), count mode."""
+    import paper_2206_06079_amd as ohm
+
+    r = run_map(args, params, batch, ohm.MODE_COUNT_CLAMP, ohm.LAYER_TSDF, call="tsdf_integrate",
+                steps=max(2, args.steps // 2))
+    out = leg_summary(r, f"the same {batch.n_scans} scans into a TSDF layer (count mode, tau = "
+                         f"{params.tsdf_truncation} m)")
+    walk_ms, _ = kernel_avg_ms(r, "walk")
+    scans = batch.n_scans
+    out["roofline_hbm"] = dict(hbm(walk_bytes(r["rays_per_step"] / scans, r["updates_per_step"] / scans), walk_ms),
+                               kernel="tsdf_kernel", unit="per scan")
+    log(f"TSDF: {r['ms_per_step']:.3f} ms per {scans}-scan pass")
+    return out
 
 
 def run_adjoint(args):
@@ -312,7 +423,8 @@ def run_adjoint(args):
     stream = torch.cuda.current_stream()
     e = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
     fwd, bwd = [], []
-    for _ in range(2):  # the first pass warms up
+    st = None
+    for _ in range(4):  # the first pass warms up
         m = ohm.OhmMap(params, 256, layers=ohm.LAYER_NDT | ohm.LAYER_ADJOINT, device=dev)
         e[0].record(stream)
         m.ndt_integrate(o, s, batch.offsets, w)
@@ -320,16 +432,26 @@ def run_adjoint(args):
         m.backward(g, box_min, box_dim, o, s, batch.offsets, w, ndt=True, grad_weights=gw)
         e[2].record(stream)
         torch.cuda.synchronize()
+        st = m.stats()
         m.close()
         fwd.append(e[0].elapsed_time(e[1]))
         bwd.append(e[1].elapsed_time(e[2]))
-    log(f"adjoint: forward {fwd[-1]:.2f} ms, backward {bwd[-1]:.2f} ms")
+    fwd, bwd = fwd[1:], bwd[1:]
+    f_ms, b_ms = sum(fwd) / len(fwd), sum(bwd) / len(bwd)
+    visits = st["voxel_updates"]
+    # the backward re-walks every ray: per visit the gradient and clamp
+    # record, plus each voxel's statistics (NDT), and the ray's sample
+    bwd_bytes = RAY_BYTES * batch.n_rays + (ADJ_VISIT_BYTES + NDT_MISS_EXTRA) * visits
+    log(f"adjoint: forward {f_ms:.2f} ms, backward {b_ms:.2f} ms")
     return {
         "workload": f"{batch.n_scans} scans x {batch.n_rays // batch.n_scans} weighted rays at 0.2 m, NDT, "
                     "64^3 loss box",
-        "forward_ms": round(fwd[-1], 3),
-        "backward_ms": round(bwd[-1], 3),
-        "backward_rays_per_s": round(batch.n_rays / (bwd[-1] * 1e-3), 1),
+        "forward_ms": round(f_ms, 3),
+        "backward_ms": round(b_ms, 3),
+        "backward_ms_pct": percentiles(bwd),
+        "backward_rays_per_s": round(batch.n_rays / (b_ms * 1e-3), 1),
+        "voxel_visits": int(visits),
+        "roofline_hbm_backward": hbm(bwd_bytes, b_ms),
     }
 
 
@@ -349,6 +471,7 @@ def cpu_baseline(params, batch, n_scans):
         "sample": f"first {n_scans} of the 100 scans ({st['rays']} rays, {st['updates']} voxel updates), "
                   f"single-threaded C oracle, count-then-clamp, {dt:.1f} s",
         "voxel_updates_per_s": st["updates"] / dt,
+        "host": host_cpu(),
     }
 
 
@@ -367,6 +490,9 @@ def main():
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--no-ndt", action="store_true")
     ap.add_argument("--no-adjoint", action="store_true")
+    ap.add_argument("--no-layers", action="store_true", help="skip the mean, decay-rate, NDT-TM and TSDF legs")
+    ap.add_argument("--no-config0", action="store_true")
+    ap.add_argument("--only-headline", action="store_true", help="the headline legs only (profiling runs)")
     ap.add_argument("--batched-scans", type=int, default=1000)
     ap.add_argument("--batched-reps", type=int, default=3)
     ap.add_argument("--batched-groups", type=lambda v: tuple(int(x) for x in v.split(",")), default=(16, 64))
@@ -379,6 +505,9 @@ def main():
         print("bench.py measures one GPU only: this build has no multi-GPU path "
               "(how it would shard is described in the design notes)", file=sys.stderr)
         return 2
+    if args.only_headline:
+        args.no_batched = args.no_ndt = args.no_adjoint = args.no_layers = args.no_config0 = True
+        args.no_cpu_baseline = args.no_per_update = True
 
     from workloads import scenes
 
@@ -397,82 +526,105 @@ def main():
     params, batch = scenes.config1(n_scans=args.scans)
     log(f"generated {batch.n_rays} rays in {time.perf_counter() - t0:.1f} s")
 
-    single = run_gpu(args, params, batch, ohm.MODE_COUNT_CLAMP)
+    single = run_map(args, params, batch, ohm.MODE_COUNT_CLAMP)
     log(f"count mode, one launch per scan: {single['ms_per_step']:.3f} ms/step, kernels {single['kernels']}")
-    res = run_gpu(args, params, batch, ohm.MODE_COUNT_CLAMP,
+    res = run_map(args, params, batch, ohm.MODE_COUNT_CLAMP,
                   ohm.LAYER_OCC | ohm.LAYER_SCAN_GROUPS | ohm.scan_group_slots(args.scan_group_slots))
     log(f"count mode, {args.scan_group_slots}-scan groups: {res['ms_per_step']:.3f} ms/step, kernels {res['kernels']}")
-    per_update = None
-    if not args.no_per_update:
-        pu = run_gpu(args, params, batch, ohm.MODE_PER_UPDATE)
-        log(f"per-update mode: {pu['ms_per_step']:.3f} ms/step, kernels {pu['kernels']}")
-        per_update = {
-            "rays_per_s": pu["rays_per_step"] / (pu["ms_per_step"] * 1e-3),
-            "voxel_updates_per_s": pu["updates_per_step"] / (pu["ms_per_step"] * 1e-3),
-            "ms_per_step": pu["ms_per_step"],
-            "walk_kernel_ms": pu["kernels"].get("walk", (0, 0.0))[1] / max(1, pu["kernels"].get("walk", (1, 0))[0]),
-        }
-
-    sec = res["ms_per_step"] * 1e-3
-    rays_per_s = res["rays_per_step"] / sec
-    upd_per_s = res["updates_per_step"] / sec
     scans = args.scans
     rays_per_scan = res["rays_per_step"] / scans
     upd_per_scan = res["updates_per_step"] / scans
-    # dominant kernel: the group walk (scans that took the single-scan walk
-    # instead, if any, are not its work)
-    n_walk, ms_walk = res["kernels"].get("walk_group", (0, 0.0))
-    walk_avg_ms = ms_walk / max(1, n_walk)
+
+    per_update = None
+    if not args.no_per_update:
+        pu = run_map(args, params, batch, ohm.MODE_PER_UPDATE, steps=max(2, args.steps // 2))
+        log(f"per-update mode: {pu['ms_per_step']:.3f} ms/step, kernels {pu['kernels']}")
+        per_update = leg_summary(pu, f"the {scans} headline scans, per-update (compare-and-swap) mode, one launch "
+                                     "per scan")
+        pu_walk, _ = kernel_avg_ms(pu, "walk")
+        per_update["walk_kernel_ms"] = round(pu_walk, 5)
+        per_update["roofline_hbm"] = dict(hbm(walk_bytes(rays_per_scan, upd_per_scan, per_update=CAS_UPDATE_BYTES),
+                                              pu_walk), kernel="walk_seg_kernel<per-update>", unit="per scan")
+        # the atomic ceiling of the mode: independent f32 clamp-adds by
+        # compare-and-swap at the occupancy layer's footprint
+        occ_bytes = max(1, pu["stats"]["regions_used"]) * 32768 * 4
+        cas_rand = ohm.probe_atomic_rate(occ_bytes, op="f32_cas")
+        cas_seq = ohm.probe_atomic_rate(occ_bytes, sequential=True, op="f32_cas")
+        rate = upd_per_scan / (pu_walk * 1e-3)
+        per_update["roofline_atomic"] = {
+            "unit": "voxel updates/s", "achieved": round(rate, 1),
+            "ceiling_random_f32_cas_per_s": round(cas_rand, 1),
+            "ceiling_consecutive_f32_cas_per_s": round(cas_seq, 1),
+            "frac_vs_random": round(rate / cas_rand, 4), "frac_vs_consecutive": round(rate / cas_seq, 4),
+            "footprint_bytes": occ_bytes,
+        }
+        counters = measured_counters("walk_seg_kernel_per_update_config1")
+        per_update["traffic"] = counters.get("traffic_bytes_per_launch")
+
+    # dominant kernel: the group walk
+    walk_avg_ms, n_walk = kernel_avg_ms(res, "walk_group")
     single_scans = res["kernels"].get("walk", (0, 0.0))[0] / res["steps"]
     scans_per_launch = (scans - single_scans) * res["steps"] / max(1, n_walk)
-    launch_bytes = walk_bytes(rays_per_scan * scans_per_launch, upd_per_scan * scans_per_launch, scans_per_launch)
+    launch_rays = rays_per_scan * scans_per_launch
+    launch_upd = upd_per_scan * scans_per_launch
+    launch_bytes = walk_bytes(launch_rays, launch_upd, scans_per_launch)
+    launch_bytes_f32 = walk_bytes(launch_rays, launch_upd, scans_per_launch, per_update=8.0)
     achieved = launch_bytes / (walk_avg_ms * 1e-3) / 1e9
+    counters = measured_counters("walk_group_kernel_config1")
     roofline = {
         "bound": "hbm",
         "achieved": round(achieved, 1),
         "peak": HBM_PEAK_GBS,
         "unit": "GB/s",
         "frac": round(achieved / HBM_PEAK_GBS, 4),
-        "traffic": measured_traffic("walk_group_kernel"),
+        "traffic": counters.get("traffic_bytes_per_launch"),
         "kernel": f"walk_group_kernel (count mode, up to {args.scan_group_slots} scans per launch)",
         "kernel_avg_ms": round(walk_avg_ms, 5),
         "scans_per_launch": round(scans_per_launch, 3),
         "bytes_per_launch": launch_bytes,
+        "bytes_per_unit": {"ray": RAY_BYTES, "scan": SCAN_BYTES, "voxel_update": COUNT_UPDATE_BYTES},
+        # the same launch priced at what its counters are (one 4-byte f32
+        # read-modify-write per update, hit and miss counted separately)
+        "at_8B_per_update": {"achieved": round(launch_bytes_f32 / (walk_avg_ms * 1e-3) / 1e9, 1),
+                             "frac": round(launch_bytes_f32 / (walk_avg_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)},
     }
-    s_walk_n, s_walk_ms = single["kernels"].get("walk", (0, 0.0))
-    s_walk_avg = s_walk_ms / max(1, s_walk_n)
-    s_sec = single["ms_per_step"] * 1e-3
-    one_launch_per_scan = {
-        "rays_per_s": round(single["rays_per_step"] / s_sec, 1),
-        "voxel_updates_per_s": round(single["updates_per_step"] / s_sec, 1),
-        "ms_per_step": round(single["ms_per_step"], 4),
+    s_walk_avg, _ = kernel_avg_ms(single, "walk")
+    one_launch_per_scan = leg_summary(single, f"the {scans} headline scans, one walk launch per scan")
+    one_launch_per_scan.update({
         "kernel": "walk_seg_kernel",
         "kernel_avg_ms": round(s_walk_avg, 5),
-        "hbm_frac": round(walk_bytes(rays_per_scan, upd_per_scan) / (s_walk_avg * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
-        "traffic": measured_traffic("walk_seg_kernel"),
-        "kernel_ms_per_step": {k: round(v[1] / single["steps"], 4) for k, v in single["kernels"].items()},
-    }
-    # the atomic roofline: one f32 atomic add per voxel update (before lane
+        "roofline_hbm": hbm(walk_bytes(rays_per_scan, upd_per_scan), s_walk_avg),
+        "traffic": measured_counters("walk_seg_kernel_config1").get("traffic_bytes_per_launch"),
+    })
+    # the atomic roofline: one counter update per voxel update (before lane
     # merging) against the device's measured rate of independent f32 atomic
-    # adds at the footprint of the touched regions' accumulator layer
+    # adds at the footprint of the group's accumulator slots
     footprint = max(1, res["stats"]["regions_used"]) * 32768 * 8 * int(round(scans_per_launch))
     ceiling = ohm.probe_atomic_rate(footprint)
     ceiling_seq = ohm.probe_atomic_rate(footprint, sequential=True)
-    upd_rate = upd_per_scan * scans_per_launch / (walk_avg_ms * 1e-3)
+    ceiling_u64 = ohm.probe_atomic_rate(footprint, op="u64_add")
+    upd_rate = launch_upd / (walk_avg_ms * 1e-3)
+    requests = counters.get("atomic_requests_per_launch")
     roofline["atomic"] = {
         "unit": "voxel updates/s",
         "achieved": round(upd_rate, 1),
         "ceiling_random_f32_atomics_per_s": round(ceiling, 1),
         "ceiling_consecutive_f32_atomics_per_s": round(ceiling_seq, 1),
+        "ceiling_random_u64_atomics_per_s": round(ceiling_u64, 1),
         "footprint_bytes": footprint,
-        # against the best case of the memory-side atomic units (each wave's
-        # adds on consecutive words); the random-address rate is the floor
-        # an unmerged walk would see
-        "frac": round(upd_rate / ceiling_seq, 4),
+        # updates per second against the distinct-address rate: above 1 only
+        # because lane merging and the tile tables combine updates first
         "frac_vs_random": round(upd_rate / ceiling, 4),
+        "frac_vs_consecutive": round(upd_rate / ceiling_seq, 4),
+        # what reaches memory: the L2 atomic requests per launch (counter
+        # TCC_ATOMIC), their share of the updates and their rate
+        "atomic_requests_per_launch": requests,
+        "merge_factor": round(requests / launch_upd, 4) if requests else None,
+        "request_rate_per_s": round(requests / (walk_avg_ms * 1e-3), 1) if requests else None,
+        "request_frac_vs_random": round(requests / (walk_avg_ms * 1e-3) / ceiling, 4) if requests else None,
     }
-    log(f"atomic roofline: {upd_rate / 1e9:.2f} G updates/s vs {ceiling_seq / 1e9:.2f} G consecutive "
-        f"and {ceiling / 1e9:.2f} G random f32 atomics/s")
+    log(f"roofline: {achieved:.0f} GB/s at 16 B per update ({achieved / HBM_PEAK_GBS:.3f} of peak); "
+        f"{upd_rate / 1e9:.2f} G updates/s vs {ceiling / 1e9:.2f} G random f32 atomics/s")
     if args.calibrate_copy_mb:
         n = args.calibrate_copy_mb << 18  # float32 elements
         src = torch.ones(n, dtype=torch.float32, device="cuda")
@@ -482,8 +634,12 @@ def main():
         torch.cuda.synchronize()
         log(f"copied {args.calibrate_copy_mb} MiB three times (byte-counter reference)")
         del src, dst
+    config0 = None if args.no_config0 else run_config0(args)
     headline_batched = None if args.no_batched else run_batched_headline(args, params, batch)
+    layers = None if args.no_layers else run_layers(args, params, batch)
     ndt = None if args.no_ndt else run_ndt(args, params, batch)
+    ndt_tm = None if (args.no_ndt or args.no_layers) else run_ndt(args, params, batch, tm=True)
+    tsdf = None if args.no_layers else run_tsdf(args, params, batch)
     adjoint = None if args.no_adjoint else run_adjoint(args)
     batched = None if args.no_batched else run_batched(args, batched_inputs)
     cpu = None
@@ -491,15 +647,17 @@ def main():
         log(f"timing the oracle on {args.cpu_scans} scans")
         cpu = cpu_baseline(params, batch, min(args.cpu_scans, scans))
         log(f"oracle: {cpu['value']:.0f} rays/s")
+    sec = res["ms_per_step"] * 1e-3
     out = {
-        "metric": "rays/s (voxel-updates/s alongside), plain occupancy through ohm_integrate_rays, "
-                  "config-1 spinning-lidar scans",
-        "value": round(rays_per_s, 1),
+        "metric": "rays/s (voxel-updates/s alongside), scan-grouped occupancy integration through "
+                  "ohm_integrate_rays (50 scans per walk launch), config-1 spinning-lidar scans",
+        "value": round(res["rays_per_step"] / sec, 1),
         "unit": "rays/s",
         "n_gpus": 1,
         "steps": res["steps"],
         "warmup": args.warmup,
         "ms_per_step": round(res["ms_per_step"], 4),
+        "ms_per_step_pct": percentiles(res["ms"]),
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
@@ -513,14 +671,18 @@ def main():
             "n_scans": scans,
             "rays_per_scan": int(rays_per_scan),
         },
-        "voxel_updates_per_s": round(upd_per_s, 1),
+        "voxel_updates_per_s": round(res["updates_per_step"] / sec, 1),
         "voxel_updates_per_step": int(res["updates_per_step"]),
         "kernel_ms_per_step": {k: round(v[1] / res["steps"], 4) for k, v in res["kernels"].items()},
         "one_launch_per_scan": one_launch_per_scan,
+        "config0": config0,
         "per_update_mode": per_update,
         "batched_same_scans": headline_batched,
         "batched": batched,
+        "layers": layers,
         "ndt": ndt,
+        "ndt_tm": ndt_tm,
+        "tsdf": tsdf,
         "adjoint": adjoint,
         "roofline": roofline,
         "cpu_baseline": cpu,

@@ -99,14 +99,27 @@ enum {
                                 count mode merges each scan's samples in one step, in scan order
                                 (exact).  Updated by ohm_integrate_rays; 8 B per voxel plus 16 B
                                 per voxel and accumulator slot, and 8 B per voxel of slot mask. */
-  OHM_LAYER_DECAY = 32       /* decay rate (paper Sec. II-E): per voxel the summed distance rays
+  OHM_LAYER_DECAY = 32,      /* decay rate (paper Sec. II-E): per voxel the summed distance rays
                                 travel through it, measured along the quantised segment the walk
                                 traverses (Q32.32 metres, exact integer sums), and the samples
                                 that fell in it; the rate is their quotient.  Updated by
                                 ohm_integrate_rays in both modes (plain sums).  12 B per voxel. */
+  OHM_LAYER_NDT_TM = 64,     /* NDT-TM (paper Sec. II-D, III-C; requires OHM_LAYER_NDT): per voxel the
+                                misses M behind the permeability H / (H + M) (H = the NDT sample
+                                count) and a 1D Gaussian (mean, population variance) of the
+                                intensity of the samples that fell in it.  A miss counts toward M
+                                when the voxel held >= ndt_min_samples samples before the scan and
+                                the squared Mahalanobis distance q = D^T S^-1 D of the ray's closest
+                                point (as in the NDT-OM weighting) is <= ndt_tm_gate.  Updated by
+                                ohm_ndt_tm_integrate; cleared with the NDT statistics.  12 B per
+                                voxel plus 16 B of per-scan intensity moments. */
+  OHM_LAYER_TSDF = 128       /* truncated signed distance (paper Sec. II-F): per voxel a distance D
+                                and a weight W (float, packed in one 64-bit word), updated by
+                                ohm_tsdf_integrate.  8 B per voxel plus 16 B of per-scan sums. */
 };
 /* OHM_LAYER_MEAN and OHM_LAYER_DECAY are not available together with
- * OHM_LAYER_NDT (OHM_E_UNSUPPORTED at creation), nor in batched plans. */
+ * OHM_LAYER_NDT (OHM_E_UNSUPPORTED at creation), nor in batched plans;
+ * OHM_LAYER_NDT_TM needs OHM_LAYER_NDT (OHM_E_INVALID_ARG without it). */
 
 /* Slot count of OHM_LAYER_SCAN_GROUPS, or-ed into the layer mask: n in [1, 64]
  * (0: the default 8).  Only valid together with OHM_LAYER_SCAN_GROUPS. */
@@ -127,7 +140,13 @@ enum {
                                 0 where no sample) */
   OHM_READ_DECAY_LENGTH = 10,/* float   summed distance through the voxel, metres (OHM_LAYER_DECAY) */
   OHM_READ_DECAY_HITS = 11,  /* uint32  samples that fell in the voxel */
-  OHM_READ_DECAY_RATE = 12   /* float   hits / distance (per metre; 0 where no distance) */
+  OHM_READ_DECAY_RATE = 12,  /* float   hits / distance (per metre; 0 where no distance) */
+  OHM_READ_TM_MISSES = 13,   /* uint32  NDT-TM checked misses M (OHM_LAYER_NDT_TM) */
+  OHM_READ_TM_PERMEABILITY = 14, /* float H / (H + M), H the NDT sample count; 0 where H + M = 0 */
+  OHM_READ_INTENSITY_MEAN = 15,  /* float NDT-TM intensity mean (0 where no sample) */
+  OHM_READ_INTENSITY_VAR = 16,   /* float NDT-TM intensity population variance */
+  OHM_READ_TSDF_DISTANCE = 17,   /* float TSDF distance D, metres (0 where never observed) */
+  OHM_READ_TSDF_WEIGHT = 18      /* float TSDF weight W (0 where never observed) */
 };
 
 typedef struct {
@@ -148,6 +167,10 @@ typedef struct {
   uint32_t ndt_min_samples;/* NDT: samples needed before a voxel's Gaussian is used (>= 2) */
   float ndt_clear_below;   /* NDT: clear sample data where l < this after a scan's
                               misses; -INFINITY disables */
+  double ndt_tm_gate;      /* NDT-TM: largest squared Mahalanobis distance of a miss that
+                              counts toward M (> 0; 9 = three standard deviations) */
+  double tsdf_truncation;  /* TSDF: band half-width tau along the ray, metres (> 0) */
+  double tsdf_max_weight;  /* TSDF: weight cap (>= 1) */
 } ohm_params;
 
 typedef struct {
@@ -201,6 +224,9 @@ ohm_status ohm_map_set_params(ohm_map map, const ohm_params* params);
  *                                       finite and >= 0: a ray with any other
  *                                       weight is skipped whole, counted in
  *                                       rays_invalid, and sets sticky_error bit 2
+ * Scan offsets are a host array, not device memory: the host sizes every
+ * launch from the scans' sizes and cuts scan groups from them, which device
+ * offsets would make a synchronising copy per call.
  * Scans are applied in order; in count mode each scan is one batch with one
  * clamp per voxel.  In count mode the last scan's hit/miss weights remain
  * readable (OHM_READ_HITS / OHM_READ_MISSES) until the next call.  On a map
@@ -231,6 +257,45 @@ ohm_status ohm_ndt_integrate(ohm_map map, const float* d_origins, const float* d
                              void* stream);
 
 /*
+ * NDT-TM integration (map created with OHM_LAYER_NDT | OHM_LAYER_NDT_TM;
+ * paper Sec. II-D and III-C): everything ohm_ndt_integrate does, plus, per
+ * scan, the checked misses M (see OHM_LAYER_NDT_TM; decided on the voxel's
+ * statistics from before the scan, like the NDT-OM weight, and counted
+ * whatever the ray's weight) and, in the second phase, the intensities of
+ * the scan's samples merged into each voxel's intensity mean and population
+ * variance (pairwise merge of the scan's moments, in fp64).
+ *   d_intensities  float[N]: one intensity per ray (required)
+ * Other arguments as for ohm_ndt_integrate.  ohm_ndt_integrate itself
+ * returns OHM_E_INVALID_ARG on an NDT-TM map (it has no intensities).
+ */
+ohm_status ohm_ndt_tm_integrate(ohm_map map, const float* d_origins, const float* d_samples,
+                                const float* d_intensities, const uint32_t* h_scan_offsets, uint32_t n_scans,
+                                const float* d_weights, void* stream);
+
+/*
+ * TSDF integration (map created with OHM_LAYER_TSDF; paper Sec. II-F).  Only
+ * a ray with a surface takes part: valid, origin in the map, not truncated
+ * by max_range, sample voxel in the map and of non-zero length.  With
+ * r = |e - o| and u = (e - o) / r (fp64), its band is the segment from
+ * o + max(r - tau, 0) u to o + (r + tau) u, tau = tsdf_truncation; both
+ * ends are quantised like ray ends and the band is walked exactly (clipped
+ * at the map's bounds; a band whose first voxel is outside the map is
+ * skipped).  Each band voxel with centre c takes the projective distance
+ * sd = clamp(r - (c - o).u, -tau, tau) (positive in front of the surface).
+ * A voxel keeps (D, W), both 0 until observed; n updates of summed distance
+ * S give D <- (W D + S) / (W + n), W <- min(W + n, tsdf_max_weight), in fp64,
+ * stored as float.  Count mode sums each scan's distances per voxel (Q32.32
+ * integers: exact and order-free) and applies them once per scan;
+ * per-update mode applies every update at once by 64-bit compare-and-swap on
+ * the packed (D, W) word, in whatever order the GPU produces.  Statistics:
+ * rays_hit counts rays with a band, voxel_updates the band voxels inside the
+ * map.  The occupancy layer is not touched.  Arguments as for
+ * ohm_integrate_rays without weights.
+ */
+ohm_status ohm_tsdf_integrate(ohm_map map, const float* d_origins, const float* d_samples,
+                              const uint32_t* h_scan_offsets, uint32_t n_scans, void* stream);
+
+/*
  * Adjoint of count-mode integration (the gradient of a loss on the final
  * log-odds; forward per scan k and voxel v: s = (l + H l_hit) + U,
  * l <- clamp(s), with H the summed hit weight and U the summed weighted miss
@@ -244,6 +309,9 @@ ohm_status ohm_ndt_integrate(ohm_map map, const float* d_origins, const float* d
  *                   (0 for skipped rays)
  *   d_grad_scalars  double[3]: receives dL/d(l_hit, l_miss, sensor_noise)
  *                   (overwritten, not accumulated)
+ * `ndt` says which forward to differentiate: a map with the NDT layer can also
+ * be integrated with ohm_integrate_rays (occupancy only), so the layer mask
+ * alone cannot tell.
  * The traversals are recomputed, not stored.  For NDT maps the sample
  * statistics are rebuilt in place scan by scan and hold the same values
  * afterwards.  Returns OHM_E_UNSUPPORTED for per-update mode or enabled NDT
@@ -290,6 +358,16 @@ ohm_status ohm_debug_trace_rays(ohm_map map, const float* d_origins, const float
  * concurrently.  tuning->group_scans (G, 1..64) scans per map share one walk
  * launch and one finalize; each group needs G per-scan accumulators of
  * capacity x 32^3 x 8 bytes per map in the plan workspace.
+ *
+ * This plan API stands in for a single "integrate batched" call: the
+ * library allocates no device memory, so the plan's accumulators live in a
+ * caller workspace sized by ohm_batch_workspace_size; the graph is captured
+ * once and replayed per run instead of being rebuilt by every call; and a
+ * set per map replaces a per-scan map index.  The schedule search (group
+ * size, walk tile, ray order) and its on-disk cache are in the Python
+ * binding (batch.autotune): it builds and times candidate plans, each of
+ * which needs its own workspace, and allocation belongs to the caller.  C
+ * callers pass an ohm_batch_tuning directly.
  */
 typedef struct {
   ohm_map map;
@@ -369,14 +447,18 @@ enum {
 ohm_status ohm_map_set_profiling(ohm_map map, int enable);
 ohm_status ohm_map_kernel_times(ohm_map map, uint32_t* h_launches, double* h_ms);
 
-/* Measurement helper (not part of integration): times 2^27 independent f32
- * atomic adds of 1.0f into the caller's device buffer d_buffer (bytes long,
- * at least 4; contents are overwritten), at pseudo-random word addresses or,
- * with sequential != 0, at consecutive addresses across each wave.  Writes
- * the rate in operations per second to *h_ops_per_s; synchronises `stream`.
- * This is the ceiling that the walk's per-voxel atomic updates are compared
- * with at the footprint of a map's accumulator layer. */
-ohm_status ohm_probe_atomic_rate(void* d_buffer, size_t bytes, int sequential, double* h_ops_per_s, void* stream);
+/* Measurement helper (not part of integration): times 2^27 independent
+ * atomic updates into the caller's device buffer d_buffer (bytes long, at
+ * least one word; contents are overwritten), at pseudo-random word addresses
+ * or, with OHM_PROBE_SEQUENTIAL in flags, at consecutive addresses across
+ * each wave.  The update is an f32 atomic add of 1.0f (default), an f32
+ * clamp-add by compare-and-swap retried until it lands (OHM_PROBE_F32_CAS;
+ * the per-update walk's operation) or a u64 atomic add (OHM_PROBE_U64_ADD).
+ * Writes the rate in operations per second to *h_ops_per_s; synchronises
+ * `stream`.  These are the ceilings that the walks' per-voxel atomic
+ * updates are compared with at the footprint of the layer they update. */
+enum { OHM_PROBE_SEQUENTIAL = 1, OHM_PROBE_F32_CAS = 2, OHM_PROBE_U64_ADD = 4 };
+ohm_status ohm_probe_atomic_rate(void* d_buffer, size_t bytes, int flags, double* h_ops_per_s, void* stream);
 
 /* Synchronise `stream` and read the map's statistics. */
 ohm_status ohm_map_sync_status(ohm_map map, void* stream, ohm_map_stats* out);

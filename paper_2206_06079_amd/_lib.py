@@ -23,6 +23,8 @@ LAYER_ADJOINT = 4
 LAYER_SCAN_GROUPS = 8
 LAYER_MEAN = 16
 LAYER_DECAY = 32
+LAYER_NDT_TM = 64
+LAYER_TSDF = 128
 
 
 def scan_group_slots(n: int) -> int:
@@ -43,6 +45,12 @@ READ_MEAN = 9
 READ_DECAY_LENGTH = 10
 READ_DECAY_HITS = 11
 READ_DECAY_RATE = 12
+READ_TM_MISSES = 13
+READ_TM_PERMEABILITY = 14
+READ_INTENSITY_MEAN = 15
+READ_INTENSITY_VAR = 16
+READ_TSDF_DISTANCE = 17
+READ_TSDF_WEIGHT = 18
 
 # Every symbol include/ohm.h declares.
 EXPORTS = (
@@ -52,7 +60,7 @@ EXPORTS = (
     "ohm_map_set_profiling", "ohm_map_kernel_times", "ohm_backward",
     "ohm_batch_workspace_size", "ohm_batch_create", "ohm_batch_run", "ohm_batch_destroy",
     "ohm_map_set_tuning", "ohm_probe_atomic_rate", "ohm_ray_order_scratch_size", "ohm_map_set_ray_order",
-    "ohm_build_source_digest",
+    "ohm_build_source_digest", "ohm_ndt_tm_integrate", "ohm_tsdf_integrate",
 )
 
 
@@ -98,6 +106,9 @@ class OhmParams(ctypes.Structure):
         ("adaptation_rate", ctypes.c_float),
         ("ndt_min_samples", ctypes.c_uint32),
         ("ndt_clear_below", ctypes.c_float),
+        ("ndt_tm_gate", ctypes.c_double),
+        ("tsdf_truncation", ctypes.c_double),
+        ("tsdf_max_weight", ctypes.c_double),
     ]
 
 
@@ -159,6 +170,8 @@ def load() -> ctypes.CDLL:
         "ohm_map_set_params": [vp, P(OhmParams)],
         "ohm_integrate_rays": [vp, vp, vp, vp, ctypes.c_uint32, vp, vp],
         "ohm_ndt_integrate": [vp, vp, vp, vp, ctypes.c_uint32, vp, vp],
+        "ohm_ndt_tm_integrate": [vp, vp, vp, vp, vp, ctypes.c_uint32, vp, vp],
+        "ohm_tsdf_integrate": [vp, vp, vp, vp, ctypes.c_uint32, vp],
         "ohm_map_read_dense": [vp, ctypes.c_int32, vp, vp, vp, vp],
         "ohm_debug_trace_rays": [vp, vp, vp, vp, ctypes.c_uint32, vp, vp, vp, vp, vp],
         "ohm_map_sync_status": [vp, vp, P(OhmStats)],
@@ -215,4 +228,7 @@ def make_params(mp) -> OhmParams:
     p.adaptation_rate = float(mp.adaptation_rate)
     p.ndt_min_samples = int(mp.ndt_min_samples)
     p.ndt_clear_below = float(mp.ndt_clear_below)
+    p.ndt_tm_gate = float(getattr(mp, "ndt_tm_gate", 9.0))
+    p.tsdf_truncation = float(getattr(mp, "tsdf_truncation", 0.3))
+    p.tsdf_max_weight = float(getattr(mp, "tsdf_max_weight", 10000.0))
     return p

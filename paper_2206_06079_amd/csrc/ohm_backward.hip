@@ -198,23 +198,9 @@ __global__ __launch_bounds__(kBackwardMaxThreads, 4) void backward_seg_kernel(
         last = s.w.total == 0;
         const bool is_hit = last && !trunc;
         if (kNdt && is_hit && slot >= 0) {
-          // the statistics replay: this sample's moments (voxel-centred, fp64)
-          const size_t vh = (size_t)slot * kRegionVoxels + lidx;
-          const size_t ray = (size_t)r0 + tr.src[ray_t];
-          const double x0 = (double)samples[3 * ray + 0] - (m.origin[0] + ((double)k0 + 0.5) * m.voxel_size);
-          const double x1 = (double)samples[3 * ray + 1] - (m.origin[1] + ((double)k1 + 0.5) * m.voxel_size);
-          const double x2 = (double)samples[3 * ray + 2] - (m.origin[2] + ((double)k2 + 0.5) * m.voxel_size);
-          double* mo = m.mom + vh * kMomWords;
-          unsafeAtomicAdd(mo + 0, x0);
-          unsafeAtomicAdd(mo + 1, x1);
-          unsafeAtomicAdd(mo + 2, x2);
-          unsafeAtomicAdd(mo + 3, x0 * x0);
-          unsafeAtomicAdd(mo + 4, x0 * x1);
-          unsafeAtomicAdd(mo + 5, x0 * x2);
-          unsafeAtomicAdd(mo + 6, x1 * x1);
-          unsafeAtomicAdd(mo + 7, x1 * x2);
-          unsafeAtomicAdd(mo + 8, x2 * x2);
-          atomicAdd(reinterpret_cast<unsigned long long*>(m.nacc + vh * kNaccWords + kNaccSamples), 1ull);
+          // the statistics replay: this sample's moments, as the forward adds them
+          const int32_t kh[3] = {k0, k1, k2};
+          ndt_add_sample(m, (size_t)slot * kRegionVoxels + lidx, samples + 3 * ((size_t)r0 + tr.src[ray_t]), kh);
         }
         G = grad_at(gb, k0, k1, k2);
         if (G != 0.f && slot >= 0) {
@@ -319,6 +305,11 @@ extern "C" ohm_status ohm_backward(ohm_map map, int32_t ndt, const float* d_grad
   }
   const double sig_miss = 1.0 / (1.0 + exp(-(double)map->params.l_miss));
   const bool weighted = d_weights != nullptr;
+  // the replay rebuilds the NDT statistics only: an NDT-TM layer keeps its
+  // final state (the replay adds no intensity moments for it to merge)
+  DevMap bm = map->dm;
+  bm.tm = nullptr;
+  bm.tm_mom = nullptr;
   hipLaunchKernelGGL(zero_f64_kernel, dim3(1), dim3(64), 0, st, d_grad_scalars, 3);
   if (ndt) {
     clear_pending(map, st);
@@ -343,26 +334,26 @@ extern "C" ohm_status ohm_backward(ohm_map map, int32_t ndt, const float* d_grad
       ProfScope ps(map, OHM_KERNEL_OTHER, st);
       if (ndt) {
         if (weighted)
-          hipLaunchKernelGGL((backward_seg_kernel<true, true>), tiles, threads, 0, st, map->dm, gb, d_origins, sc,
+          hipLaunchKernelGGL((backward_seg_kernel<true, true>), tiles, threads, 0, st, bm, gb, d_origins, sc,
                              d_samples, d_weights, r0, n, K, tag, ftag, fparity, d_grad_weights, d_grad_scalars,
                              sig_miss);
         else
-          hipLaunchKernelGGL((backward_seg_kernel<true, false>), tiles, threads, 0, st, map->dm, gb, d_origins, sc,
+          hipLaunchKernelGGL((backward_seg_kernel<true, false>), tiles, threads, 0, st, bm, gb, d_origins, sc,
                              d_samples, d_weights, r0, n, K, tag, ftag, fparity, d_grad_weights, d_grad_scalars,
                              sig_miss);
       } else {
         if (weighted)
-          hipLaunchKernelGGL((backward_seg_kernel<false, true>), tiles, threads, 0, st, map->dm, gb, d_origins, sc,
+          hipLaunchKernelGGL((backward_seg_kernel<false, true>), tiles, threads, 0, st, bm, gb, d_origins, sc,
                              d_samples, d_weights, r0, n, K, tag, 0u, 0u, d_grad_weights, d_grad_scalars, sig_miss);
         else
-          hipLaunchKernelGGL((backward_seg_kernel<false, false>), tiles, threads, 0, st, map->dm, gb, d_origins, sc,
+          hipLaunchKernelGGL((backward_seg_kernel<false, false>), tiles, threads, 0, st, bm, gb, d_origins, sc,
                              d_samples, d_weights, r0, n, K, tag, 0u, 0u, d_grad_weights, d_grad_scalars, sig_miss);
       }
     }
     if (ndt) {
       // fold only: the accumulators hold no increments, so occupancy is unchanged
       ProfScope ps(map, OHM_KERNEL_NDT_HIT, st);
-      hipLaunchKernelGGL(ndt_finalize_kernel, dim3(kFinalizeBlocks), dim3(256), 0, st, map->dm, fparity, 1, 0u);
+      hipLaunchKernelGGL(ndt_finalize_kernel, dim3(kFinalizeBlocks), dim3(256), 0, st, bm, fparity, 1, 0u);
     }
   }
   hipError_t e = hipGetLastError();

@@ -60,6 +60,12 @@ struct NdtVoxel {       // 40 bytes, one per voxel of an NDT map
   float cov[6];         // xx, xy, xz, yy, yz, zz  (population covariance, m^2)
 };
 
+struct TmVoxel {      // 12 bytes, one per voxel of an NDT-TM map
+  uint32_t miss;      // checked misses M (permeability H / (H + M), H = the NDT sample count)
+  float imean;        // intensity mean of the voxel's samples
+  float ivar;         // intensity population variance
+};
+
 struct DevMap {
   double origin[3];
   double scale;       // 2^F / voxel_size
@@ -97,6 +103,18 @@ struct DevMap {
   // voxel (Q32.32 metres) and the samples that fell in it
   unsigned long long* decay_len;
   uint32_t* decay_hits;
+  // NDT-TM layer (or null): per voxel the checked misses and the intensity
+  // Gaussian; per scan the intensity moments (sum i, sum i^2; fp64) of the
+  // samples that fell in each voxel
+  TmVoxel* tm;
+  double* tm_mom;     // [capacity][V][2]
+  double tm_gate;     // largest squared Mahalanobis distance of a checked miss
+  // TSDF layer (or null): per voxel the distance D (bits 0-31) and weight W
+  // (bits 32-63) as floats in one 64-bit word; per scan the Q32.32 sum of
+  // the distances and the number of updates of each voxel
+  unsigned long long* tsdf;
+  long long* tsdf_acc;  // [capacity][V][2]
+  double tsdf_tau, tsdf_wmax;
 };
 
 // Q32.32 fixed point of the exact (order-independent) sums of weights and
@@ -137,6 +155,27 @@ enum : int { kNaccMiss = 0, kNaccHit = 1, kNaccSamples = 2 };
 // per-voxel sample moments of one scan: sum x (3), sum x x^T (6), x = sample
 // minus voxel centre (metres)
 constexpr int kMomWords = 9;
+
+// Add one sample (e: the ray's sample, k: the key of its voxel, which the
+// ray hits) to voxel v's moments and sample count.
+__device__ __forceinline__ void ndt_add_sample(const DevMap& m, size_t v, const float* __restrict__ e,
+                                               const int32_t k[3]) {
+#pragma clang fp contract(off)
+  const double x0 = (double)e[0] - (m.origin[0] + ((double)k[0] + 0.5) * m.voxel_size);
+  const double x1 = (double)e[1] - (m.origin[1] + ((double)k[1] + 0.5) * m.voxel_size);
+  const double x2 = (double)e[2] - (m.origin[2] + ((double)k[2] + 0.5) * m.voxel_size);
+  double* mo = m.mom + v * kMomWords;
+  unsafeAtomicAdd(mo + 0, x0);
+  unsafeAtomicAdd(mo + 1, x1);
+  unsafeAtomicAdd(mo + 2, x2);
+  unsafeAtomicAdd(mo + 3, x0 * x0);
+  unsafeAtomicAdd(mo + 4, x0 * x1);
+  unsafeAtomicAdd(mo + 5, x0 * x2);
+  unsafeAtomicAdd(mo + 6, x1 * x1);
+  unsafeAtomicAdd(mo + 7, x1 * x2);
+  unsafeAtomicAdd(mo + 8, x2 * x2);
+  atomicAdd(reinterpret_cast<unsigned long long*>(m.nacc + v * kNaccWords + kNaccSamples), 1ull);
+}
 
 __device__ __forceinline__ uint32_t lane_id() {
   return __builtin_amdgcn_mbcnt_hi(~0u, __builtin_amdgcn_mbcnt_lo(~0u, 0u));

@@ -347,6 +347,27 @@ __global__ __launch_bounds__(256) void read_dense_kernel(DevMap m, int what, int
       static_cast<float*>(out)[i] = len > 0.0 ? (float)((double)m.decay_hits[v] / len) : 0.f;
       break;
     }
+    case OHM_READ_TM_MISSES:
+      static_cast<uint32_t*>(out)[i] = slot >= 0 ? m.tm[v].miss : 0u;
+      break;
+    case OHM_READ_TM_PERMEABILITY: {
+      const double h = slot >= 0 ? (double)m.ndt[v].n : 0.0;
+      const double hm = h + (slot >= 0 ? (double)m.tm[v].miss : 0.0);
+      static_cast<float*>(out)[i] = hm > 0.0 ? (float)(h / hm) : 0.f;
+      break;
+    }
+    case OHM_READ_INTENSITY_MEAN:
+      static_cast<float*>(out)[i] = slot >= 0 ? m.tm[v].imean : 0.f;
+      break;
+    case OHM_READ_INTENSITY_VAR:
+      static_cast<float*>(out)[i] = slot >= 0 ? m.tm[v].ivar : 0.f;
+      break;
+    case OHM_READ_TSDF_DISTANCE:
+      static_cast<float*>(out)[i] = slot >= 0 ? __uint_as_float((uint32_t)m.tsdf[v]) : 0.f;
+      break;
+    case OHM_READ_TSDF_WEIGHT:
+      static_cast<float*>(out)[i] = slot >= 0 ? __uint_as_float((uint32_t)(m.tsdf[v] >> 32)) : 0.f;
+      break;
     default:
       break;
   }
@@ -363,7 +384,7 @@ inline size_t align_up(size_t v) { return (v + kAlign - 1) & ~(kAlign - 1); }
 
 struct Layout {
   size_t hdr, stats, table, stamp, touched, occ, acc, ndt, nacc, mom, clampscan, mean, mean_acc, mean_mask,
-      decay_len, decay_hits, total;
+      decay_len, decay_hits, tm, tm_mom, tsdf, tsdf_acc, total;
   int32_t rlo[3], rdim[3];
   size_t regions;
 };
@@ -389,6 +410,9 @@ ohm_status validate_params(const ohm_params* p) {
   if (!(p->adaptation_rate >= 0.f && p->adaptation_rate <= 1.f)) return OHM_E_INVALID_ARG;
   if (p->ndt_min_samples < 2) return OHM_E_INVALID_ARG;
   if (isnan(p->ndt_clear_below)) return OHM_E_INVALID_ARG;
+  if (!(p->ndt_tm_gate > 0.0) || !isfinite(p->ndt_tm_gate)) return OHM_E_INVALID_ARG;
+  if (!(p->tsdf_truncation > 0.0) || !isfinite(p->tsdf_truncation)) return OHM_E_INVALID_ARG;
+  if (!(p->tsdf_max_weight >= 1.0) || !isfinite(p->tsdf_max_weight)) return OHM_E_INVALID_ARG;
   return OHM_OK;
 }
 
@@ -397,9 +421,10 @@ ohm_status compute_layout(const ohm_params* p, uint32_t capacity, uint32_t layer
   if (s != OHM_OK) return s;
   if (capacity == 0 || capacity > kMaxCapacity) return OHM_E_INVALID_ARG;
   if (layers & ~(uint32_t)(OHM_LAYER_OCC | OHM_LAYER_NDT | OHM_LAYER_ADJOINT | OHM_LAYER_SCAN_GROUPS |
-                           OHM_LAYER_MEAN | OHM_LAYER_DECAY |
+                           OHM_LAYER_MEAN | OHM_LAYER_DECAY | OHM_LAYER_NDT_TM | OHM_LAYER_TSDF |
                            OHM_SCAN_GROUP_SLOTS(0xff)))
     return OHM_E_INVALID_ARG;
+  if ((layers & OHM_LAYER_NDT_TM) && !(layers & OHM_LAYER_NDT)) return OHM_E_INVALID_ARG;
   const uint32_t slots = group_slots_of(layers);
   if (slots == 0) return OHM_E_INVALID_ARG;
   // the NDT walk updates none of the occupancy walk's optional layers
@@ -458,6 +483,19 @@ ohm_status compute_layout(const ohm_params* p, uint32_t capacity, uint32_t layer
     L->decay_hits = off;
     off = align_up(off + (size_t)capacity * V * sizeof(uint32_t));
   }
+  L->tm = L->tm_mom = L->tsdf = L->tsdf_acc = 0;
+  if (layers & OHM_LAYER_NDT_TM) {
+    L->tm = off;
+    off = align_up(off + (size_t)capacity * V * sizeof(TmVoxel));
+    L->tm_mom = off;
+    off = align_up(off + (size_t)capacity * V * 2 * sizeof(double));
+  }
+  if (layers & OHM_LAYER_TSDF) {
+    L->tsdf = off;
+    off = align_up(off + (size_t)capacity * V * sizeof(unsigned long long));
+    L->tsdf_acc = off;
+    off = align_up(off + (size_t)capacity * V * 2 * sizeof(long long));
+  }
   L->total = off;
   return OHM_OK;
 }
@@ -482,6 +520,9 @@ void fill_params(DevMap& dm, const ohm_params* p) {
   dm.adaptation_rate = p->adaptation_rate;
   dm.ndt_min_samples = p->ndt_min_samples;
   dm.ndt_clear_below = p->ndt_clear_below;
+  dm.tm_gate = p->ndt_tm_gate;
+  dm.tsdf_tau = p->tsdf_truncation;
+  dm.tsdf_wmax = p->tsdf_max_weight;
 }
 
 inline hipStream_t as_stream(void* s) { return reinterpret_cast<hipStream_t>(s); }
@@ -540,6 +581,14 @@ ohm_status map_initialise(ohm_map_s* map, hipStream_t st) {
   if (m.decay_len) {
     launch_fill(m.decay_len, (size_t)m.capacity * V * sizeof(unsigned long long), 0u, st);
     launch_fill(m.decay_hits, (size_t)m.capacity * V * sizeof(uint32_t), 0u, st);
+  }
+  if (m.tm) {
+    launch_fill(m.tm, (size_t)m.capacity * V * sizeof(TmVoxel), 0u, st);
+    launch_fill(m.tm_mom, (size_t)m.capacity * V * 2 * sizeof(double), 0u, st);
+  }
+  if (m.tsdf) {
+    launch_fill(m.tsdf, (size_t)m.capacity * V * sizeof(unsigned long long), 0u, st);
+    launch_fill(m.tsdf_acc, (size_t)m.capacity * V * 2 * sizeof(long long), 0u, st);
   }
   map->count_batches = 0;
   map->acc_dirty = false;
@@ -730,6 +779,11 @@ ohm_status ohm_map_create(const ohm_params* params, uint32_t region_capacity, ui
   dm.mean_slot = 0;
   dm.decay_len = has_decay ? reinterpret_cast<unsigned long long*>(base + L.decay_len) : nullptr;
   dm.decay_hits = has_decay ? reinterpret_cast<uint32_t*>(base + L.decay_hits) : nullptr;
+  const bool has_tm = (layers & OHM_LAYER_NDT_TM) != 0, has_tsdf = (layers & OHM_LAYER_TSDF) != 0;
+  dm.tm = has_tm ? reinterpret_cast<TmVoxel*>(base + L.tm) : nullptr;
+  dm.tm_mom = has_tm ? reinterpret_cast<double*>(base + L.tm_mom) : nullptr;
+  dm.tsdf = has_tsdf ? reinterpret_cast<unsigned long long*>(base + L.tsdf) : nullptr;
+  dm.tsdf_acc = has_tsdf ? reinterpret_cast<long long*>(base + L.tsdf_acc) : nullptr;
   s = map_initialise(map, as_stream(stream));
   if (s != OHM_OK) {
     delete map;
@@ -927,7 +981,9 @@ ohm_status ohm_integrate_rays(ohm_map map, const float* d_origins, const float* 
 ohm_status ohm_map_read_dense(ohm_map map, int32_t what, const int32_t h_box_min[3], const int32_t h_box_dim[3],
                               void* d_out, void* stream) {
   if (!map || !h_box_min || !h_box_dim || !d_out) return OHM_E_INVALID_ARG;
-  if (what < OHM_READ_OCC || what > OHM_READ_DECAY_RATE) return OHM_E_INVALID_ARG;
+  if (what < OHM_READ_OCC || what > OHM_READ_TSDF_WEIGHT) return OHM_E_INVALID_ARG;
+  if (what >= OHM_READ_TM_MISSES && what <= OHM_READ_INTENSITY_VAR && !map->dm.tm) return OHM_E_INVALID_ARG;
+  if ((what == OHM_READ_TSDF_DISTANCE || what == OHM_READ_TSDF_WEIGHT) && !map->dm.tsdf) return OHM_E_INVALID_ARG;
   if ((what == OHM_READ_MEAN_PACKED || what == OHM_READ_MEAN_COUNT || what == OHM_READ_MEAN) && !map->dm.mean)
     return OHM_E_INVALID_ARG;
   if ((what == OHM_READ_DECAY_LENGTH || what == OHM_READ_DECAY_HITS || what == OHM_READ_DECAY_RATE) &&

@@ -19,6 +19,13 @@
 //     that fell below ndt_clear_below, and merges the scan's sample moments
 //     into (n, mu, Sigma) (Chan et al.'s pairwise update), as the paper's
 //     per-voxel second phase does.
+//
+// NDT-TM (paper Sec. II-D; OHM_LAYER_NDT_TM) rides on the same two phases:
+// a miss the voxel's Gaussian weights is also checked against it, and
+// counts toward the voxel's misses M when the squared Mahalanobis distance
+// q of the ray's closest point is at most the gate; a hit adds its ray's
+// intensity to the scan's intensity moments, which phase 2 merges into the
+// voxel's intensity mean and variance alongside the position statistics.
 #include <hip/hip_runtime.h>
 #include <math.h>
 #include <stdint.h>
@@ -35,8 +42,9 @@ namespace ohm {
 
 // The NDT-weighted miss increment (see the file comment).  o / d: ray start
 // and direction (end - start), world, fp64; c: voxel centre; nv: statistics.
+// q_out: the squared Mahalanobis distance D^T S^-1 D behind the weight.
 __device__ __forceinline__ double ndt_delta(const DevMap& m, const double o[3], const double d[3], double dd,
-                                            const double c[3], const NdtVoxel& nv, double sig_miss) {
+                                            const double c[3], const NdtVoxel& nv, double sig_miss, double& q_out) {
 #pragma clang fp contract(off)
   double mu[3], w[3];
   double wd = 0.0;
@@ -62,6 +70,7 @@ __device__ __forceinline__ double ndt_delta(const DevMap& m, const double o[3], 
   const double z1 = (D[1] - l10 * z0) / l11;
   const double z2 = (D[2] - l20 * z0 - l21 * z1) / l22;
   const double q = z0 * z0 + z1 * z1 + z2 * z2;
+  q_out = q;
   const double g = exp(-0.5 * q);
   const double p = 0.5 - (double)m.adaptation_rate * g * (0.5 - sig_miss);
   return log(p / (1.0 - p));
@@ -134,7 +143,7 @@ struct NdtPending {
   uint32_t ray_t;  // tile-local ray
 };
 
-template <bool kCount, bool kWeighted>
+template <bool kCount, bool kWeighted, bool kTm>
 __device__ __forceinline__ void ndt_drain(const DevMap& m, const NdtPending* pend, uint32_t n, uint32_t lane,
                                           const double od[3], const double (*ray_end)[kTileRays], const TileRays& tr,
                                           const float* __restrict__ weights, uint32_t r0, double sig_miss,
@@ -154,15 +163,19 @@ __device__ __forceinline__ void ndt_drain(const DevMap& m, const NdtPending* pen
     const double c[3] = {m.origin[0] + ((double)e.k[0] + 0.5) * m.voxel_size,
                          m.origin[1] + ((double)e.k[1] + 0.5) * m.voxel_size,
                          m.origin[2] + ((double)e.k[2] + 0.5) * m.voxel_size};
-    const long long q = llrint(ndt_delta(m, od, dv, dd, c, nv, sig_miss) * wt * kQ32);
+    double maha;
+    const long long q = llrint(ndt_delta(m, od, dv, dd, c, nv, sig_miss, maha) * wt * kQ32);
     if (!ndt_agg_add(agg_key, agg_val, e.id, q)) ndt_apply<kCount>(m, e.id, q);
+    // NDT-TM: the ray came close enough to the voxel's data to count as a miss
+    if (kTm && maha <= m.tm_gate) atomicAdd(&m.tm[e.id >> 1].miss, 1u);
   }
 }
 
-template <bool kCount, bool kWeighted>
+template <bool kCount, bool kWeighted, bool kTm>
 __global__ __launch_bounds__(kNdtMaxThreads, 4) void ndt_seg_kernel(DevMap m, const float* __restrict__ origins, uint32_t scan,
                                                        const float* __restrict__ samples,
-                                                       const float* __restrict__ weights, uint32_t r0, uint32_t n,
+                                                       const float* __restrict__ weights,
+                                                       const float* __restrict__ intensities, uint32_t r0, uint32_t n,
                                                        int K, uint32_t tag, uint32_t parity, double sig_miss) {
 #pragma clang fp contract(off)
   __shared__ TileRays tr;
@@ -256,8 +269,8 @@ __global__ __launch_bounds__(kNdtMaxThreads, 4) void ndt_seg_kernel(DevMap m, co
       if (dmask) {
         const uint32_t nd = (uint32_t)__popcll(dmask);
         if (pend_n + nd > 64u) {
-          ndt_drain<kCount, kWeighted>(m, wpend, pend_n, lane, od, ray_end, tr, weights, r0, sig_miss, agg_key,
-                                       agg_val);
+          ndt_drain<kCount, kWeighted, kTm>(m, wpend, pend_n, lane, od, ray_end, tr, weights, r0, sig_miss, agg_key,
+                                            agg_val);
           pend_n = 0;
         }
         if (deferred) {
@@ -287,27 +300,21 @@ __global__ __launch_bounds__(kNdtMaxThreads, 4) void ndt_seg_kernel(DevMap m, co
       }
       if (emit && !ndt_agg_add(agg_key, agg_val, id, qs)) ndt_apply<kCount>(m, id, qs);
       if (has && is_hit) {
-        // sample moments (fp64), voxel-centred: x = sample - centre
-        const double x0 = (double)samples[3 * ray + 0] - (m.origin[0] + ((double)k0 + 0.5) * m.voxel_size);
-        const double x1 = (double)samples[3 * ray + 1] - (m.origin[1] + ((double)k1 + 0.5) * m.voxel_size);
-        const double x2 = (double)samples[3 * ray + 2] - (m.origin[2] + ((double)k2 + 0.5) * m.voxel_size);
-        double* mo = m.mom + v * kMomWords;
-        unsafeAtomicAdd(mo + 0, x0);
-        unsafeAtomicAdd(mo + 1, x1);
-        unsafeAtomicAdd(mo + 2, x2);
-        unsafeAtomicAdd(mo + 3, x0 * x0);
-        unsafeAtomicAdd(mo + 4, x0 * x1);
-        unsafeAtomicAdd(mo + 5, x0 * x2);
-        unsafeAtomicAdd(mo + 6, x1 * x1);
-        unsafeAtomicAdd(mo + 7, x1 * x2);
-        unsafeAtomicAdd(mo + 8, x2 * x2);
-        atomicAdd(reinterpret_cast<unsigned long long*>(m.nacc + v * kNaccWords + kNaccSamples), 1ull);
+        // the sample's moments (fp64, voxel-centred: x = sample - centre)
+        const int32_t kh[3] = {k0, k1, k2};
+        ndt_add_sample(m, v, samples + 3 * ray, kh);
+        if (kTm) {
+          const double in = (double)intensities[ray];
+          unsafeAtomicAdd(m.tm_mom + 2 * v, in);
+          unsafeAtomicAdd(m.tm_mom + 2 * v + 1, in * in);
+        }
       }
       cnt = cnt_next;
     }
   }
   if (pend_n)
-    ndt_drain<kCount, kWeighted>(m, wpend, pend_n, lane, od, ray_end, tr, weights, r0, sig_miss, agg_key, agg_val);
+    ndt_drain<kCount, kWeighted, kTm>(m, wpend, pend_n, lane, od, ray_end, tr, weights, r0, sig_miss, agg_key,
+                                      agg_val);
   __syncthreads();
   for (uint32_t h = tid; h < kNdtAggSize; h += blockDim.x) {
     const uint32_t k = agg_key[h];
@@ -349,8 +356,25 @@ __global__ __launch_bounds__(256) void ndt_finalize_kernel(DevMap m, uint32_t pa
         for (int c = 0; c < 3; ++c) nv.mean[c] = 0.f;
         for (int c = 0; c < 6; ++c) nv.cov[c] = 0.f;
         dirty = true;
+        if (m.tm) m.tm[v] = TmVoxel{0u, 0.f, 0.f};
       }
       const long long nb = a23.x;
+      if (nb > 0 && m.tm) {
+        // NDT-TM intensity Gaussian: pairwise merge of the scan's moments
+        // with the stored mean and variance (count: the NDT sample count)
+        double* im = m.tm_mom + 2 * v;
+        TmVoxel tv = m.tm[v];
+        const double na = (double)nv.n, nbd = (double)nb, nt = na + nbd;
+        const double mb = im[0] / nbd;
+        double vb = im[1] / nbd - mb * mb;
+        vb = vb < 0.0 ? 0.0 : vb;
+        const double d = mb - (double)tv.imean;
+        tv.ivar = (float)((na * (double)tv.ivar + nbd * vb) / nt + d * d * (na * nbd / (nt * nt)));
+        tv.imean = (float)((double)tv.imean + d * (nbd / nt));
+        m.tm[v] = tv;
+        im[0] = 0.0;
+        im[1] = 0.0;
+      }
       if (nb > 0) {
         double* mo = m.mom + v * kMomWords;
         const double inv = 1.0 / (double)nb;
@@ -391,12 +415,25 @@ __global__ __launch_bounds__(256) void ndt_finalize_kernel(DevMap m, uint32_t pa
 
 using namespace ohm;
 
-extern "C" ohm_status ohm_ndt_integrate(ohm_map map, const float* d_origins, const float* d_samples,
-                                        const uint32_t* h_scan_offsets, uint32_t n_scans, const float* d_weights,
-                                        void* stream) {
-  ohm_status s = check_scans(map, d_origins, d_samples, h_scan_offsets, n_scans);
-  if (s != OHM_OK || n_scans == 0) return s;
-  if (!map->dm.ndt) return OHM_E_INVALID_ARG;
+namespace {
+
+template <bool kCount, bool kWeighted>
+void launch_ndt_seg(const ohm_map_s* map, bool tm, dim3 tiles, dim3 threads, hipStream_t st, const float* origins,
+                    uint32_t sc, const float* samples, const float* weights, const float* intensities, uint32_t r0,
+                    uint32_t n, int K, uint32_t tag, uint32_t parity, double sig_miss) {
+  if (tm)
+    hipLaunchKernelGGL((ndt_seg_kernel<kCount, kWeighted, true>), tiles, threads, 0, st, map->dm, origins, sc, samples,
+                       weights, intensities, r0, n, K, tag, parity, sig_miss);
+  else
+    hipLaunchKernelGGL((ndt_seg_kernel<kCount, kWeighted, false>), tiles, threads, 0, st, map->dm, origins, sc,
+                       samples, weights, intensities, r0, n, K, tag, parity, sig_miss);
+}
+
+// Both NDT entry points: intensities non-null exactly for NDT-TM maps.
+ohm_status ndt_integrate_impl(ohm_map map, const float* d_origins, const float* d_samples, const float* d_intensities,
+                              const uint32_t* h_scan_offsets, uint32_t n_scans, const float* d_weights,
+                              void* stream) {
+  const bool tm = d_intensities != nullptr;
   hipStream_t st = reinterpret_cast<hipStream_t>(stream);
   const bool count_mode = map->params.mode == OHM_MODE_COUNT_CLAMP;
   const bool weighted = d_weights != nullptr;
@@ -415,18 +452,18 @@ extern "C" ohm_status ohm_ndt_integrate(ohm_map map, const float* d_origins, con
       ProfScope ps(map, OHM_KERNEL_WALK, st);
       if (count_mode) {
         if (weighted)
-          hipLaunchKernelGGL((ndt_seg_kernel<true, true>), tiles, threads, 0, st, map->dm, d_origins, sc, d_samples,
-                             d_weights, r0, n, K, tag, parity, sig_miss);
+          launch_ndt_seg<true, true>(map, tm, tiles, threads, st, d_origins, sc, d_samples, d_weights, d_intensities,
+                                     r0, n, K, tag, parity, sig_miss);
         else
-          hipLaunchKernelGGL((ndt_seg_kernel<true, false>), tiles, threads, 0, st, map->dm, d_origins, sc, d_samples,
-                             d_weights, r0, n, K, tag, parity, sig_miss);
+          launch_ndt_seg<true, false>(map, tm, tiles, threads, st, d_origins, sc, d_samples, d_weights, d_intensities,
+                                      r0, n, K, tag, parity, sig_miss);
       } else {
         if (weighted)
-          hipLaunchKernelGGL((ndt_seg_kernel<false, true>), tiles, threads, 0, st, map->dm, d_origins, sc, d_samples,
-                             d_weights, r0, n, K, tag, parity, sig_miss);
+          launch_ndt_seg<false, true>(map, tm, tiles, threads, st, d_origins, sc, d_samples, d_weights, d_intensities,
+                                      r0, n, K, tag, parity, sig_miss);
         else
-          hipLaunchKernelGGL((ndt_seg_kernel<false, false>), tiles, threads, 0, st, map->dm, d_origins, sc, d_samples,
-                             d_weights, r0, n, K, tag, parity, sig_miss);
+          launch_ndt_seg<false, false>(map, tm, tiles, threads, st, d_origins, sc, d_samples, d_weights,
+                                       d_intensities, r0, n, K, tag, parity, sig_miss);
       }
     }
     {
@@ -438,4 +475,27 @@ extern "C" ohm_status ohm_ndt_integrate(ohm_map map, const float* d_origins, con
   }
   hipError_t e = hipGetLastError();
   return e == hipSuccess ? OHM_OK : OHM_E_HIP;
+}
+
+}  // namespace
+
+extern "C" ohm_status ohm_ndt_integrate(ohm_map map, const float* d_origins, const float* d_samples,
+                                        const uint32_t* h_scan_offsets, uint32_t n_scans, const float* d_weights,
+                                        void* stream) {
+  ohm_status s = check_scans(map, d_origins, d_samples, h_scan_offsets, n_scans);
+  if (s != OHM_OK) return s;
+  if (!map->dm.ndt || map->dm.tm) return OHM_E_INVALID_ARG;  // an NDT-TM map needs intensities
+  if (n_scans == 0) return OHM_OK;
+  return ndt_integrate_impl(map, d_origins, d_samples, nullptr, h_scan_offsets, n_scans, d_weights, stream);
+}
+
+extern "C" ohm_status ohm_ndt_tm_integrate(ohm_map map, const float* d_origins, const float* d_samples,
+                                           const float* d_intensities, const uint32_t* h_scan_offsets,
+                                           uint32_t n_scans, const float* d_weights, void* stream) {
+  ohm_status s = check_scans(map, d_origins, d_samples, h_scan_offsets, n_scans);
+  if (s != OHM_OK) return s;
+  if (!map->dm.ndt || !map->dm.tm) return OHM_E_INVALID_ARG;
+  if (n_scans == 0) return OHM_OK;
+  if (!d_intensities && h_scan_offsets[n_scans] > h_scan_offsets[0]) return OHM_E_INVALID_ARG;
+  return ndt_integrate_impl(map, d_origins, d_samples, d_intensities, h_scan_offsets, n_scans, d_weights, stream);
 }

@@ -1,7 +1,8 @@
-// Measurement helper: the device's rate of independent f32 atomic adds at a
-// given footprint -- the ceiling the walk's voxel updates are compared with
-// (the walk applies one f32 atomic add per merged update into a
-// region-chunked accumulator layer of about that size).
+// Measurement helper: the device's rate of independent atomic updates at a
+// given footprint -- the ceilings the walks' voxel updates are compared with
+// (the count walk applies one f32 atomic add per merged update into a
+// region-chunked accumulator layer of about that size, the per-update walk
+// one f32 clamp-add by compare-and-swap into the occupancy layer).
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
@@ -19,25 +20,45 @@ __device__ __forceinline__ uint32_t mix32(uint32_t x) {
   return x;
 }
 
-// Every lane adds 1.0f to `iters` words of buf[0, n): pseudo-random words,
-// or consecutive words across the wave when `sequential`.
-__global__ __launch_bounds__(256) void atomic_rate_kernel(float* __restrict__ buf, uint32_t n, uint32_t iters,
+// Every lane updates `iters` words of buf[0, n): pseudo-random words, or
+// consecutive words across the wave when `sequential`.  kOp: 0 = f32
+// atomic add of 1.0f, 1 = f32 clamp-add by compare-and-swap (retried until
+// it lands, as the per-update walk does), 2 = u64 atomic add of 1.
+template <int kOp>
+__global__ __launch_bounds__(256) void atomic_rate_kernel(void* __restrict__ buf, uint32_t n, uint32_t iters,
                                                            int sequential) {
   const uint32_t tid = blockIdx.x * blockDim.x + threadIdx.x;
   for (uint32_t i = 0; i < iters; ++i) {
-    const uint32_t h = sequential ? tid + i * 977u : mix32(tid * 131u + i * 7919u);
-    unsafeAtomicAdd(buf + h % n, 1.0f);
+    const uint32_t h = (sequential ? tid + i * 977u : mix32(tid * 131u + i * 7919u)) % n;
+    if (kOp == 0) {
+      unsafeAtomicAdd(static_cast<float*>(buf) + h, 1.0f);
+    } else if (kOp == 1) {
+      uint32_t* u = static_cast<uint32_t*>(buf) + h;
+      uint32_t old = __hip_atomic_load(u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      for (;;) {
+        const float nv = fminf(fmaxf(__uint_as_float(old) + 1.0f, -1e30f), 1e30f);
+        const uint32_t prev = atomicCAS(u, old, __float_as_uint(nv));
+        if (prev == old) break;
+        old = prev;
+      }
+    } else {
+      atomicAdd(static_cast<unsigned long long*>(buf) + h, 1ull);
+    }
   }
 }
 
 }  // namespace
 }  // namespace ohm
 
-extern "C" ohm_status ohm_probe_atomic_rate(void* d_buffer, size_t bytes, int sequential, double* h_ops_per_s,
+extern "C" ohm_status ohm_probe_atomic_rate(void* d_buffer, size_t bytes, int flags, double* h_ops_per_s,
                                             void* stream) {
-  if (!d_buffer || !h_ops_per_s || bytes < sizeof(float) || bytes / sizeof(float) > 0xFFFFFFFFu)
-    return OHM_E_INVALID_ARG;
-  const uint32_t n = (uint32_t)(bytes / sizeof(float));
+  const int op = (flags & OHM_PROBE_U64_ADD) ? 2 : ((flags & OHM_PROBE_F32_CAS) ? 1 : 0);
+  const size_t word = op == 2 ? sizeof(unsigned long long) : sizeof(float);
+  if (!d_buffer || !h_ops_per_s || bytes < word || bytes / word > 0xFFFFFFFFu) return OHM_E_INVALID_ARG;
+  if (flags & ~(OHM_PROBE_SEQUENTIAL | OHM_PROBE_F32_CAS | OHM_PROBE_U64_ADD)) return OHM_E_INVALID_ARG;
+  if ((flags & OHM_PROBE_F32_CAS) && (flags & OHM_PROBE_U64_ADD)) return OHM_E_INVALID_ARG;
+  const uint32_t n = (uint32_t)(bytes / word);
+  const int seq = (flags & OHM_PROBE_SEQUENTIAL) ? 1 : 0;
   const uint32_t blocks = 8192, iters = 64;
   hipStream_t st = reinterpret_cast<hipStream_t>(stream);
   hipEvent_t a = nullptr, b = nullptr;
@@ -45,10 +66,15 @@ extern "C" ohm_status ohm_probe_atomic_rate(void* d_buffer, size_t bytes, int se
     if (a) (void)hipEventDestroy(a);
     return OHM_E_HIP;
   }
-  float* buf = static_cast<float*>(d_buffer);
-  hipLaunchKernelGGL(ohm::atomic_rate_kernel, dim3(blocks), dim3(256), 0, st, buf, n, iters, sequential);  // warm-up
-  (void)hipEventRecord(a, st);
-  hipLaunchKernelGGL(ohm::atomic_rate_kernel, dim3(blocks), dim3(256), 0, st, buf, n, iters, sequential);
+  for (int rep = 0; rep < 2; ++rep) {  // the first launch warms up
+    if (rep == 1) (void)hipEventRecord(a, st);
+    if (op == 0)
+      hipLaunchKernelGGL(ohm::atomic_rate_kernel<0>, dim3(blocks), dim3(256), 0, st, d_buffer, n, iters, seq);
+    else if (op == 1)
+      hipLaunchKernelGGL(ohm::atomic_rate_kernel<1>, dim3(blocks), dim3(256), 0, st, d_buffer, n, iters, seq);
+    else
+      hipLaunchKernelGGL(ohm::atomic_rate_kernel<2>, dim3(blocks), dim3(256), 0, st, d_buffer, n, iters, seq);
+  }
   (void)hipEventRecord(b, st);
   float ms = 0.f;
   const bool ok = hipEventSynchronize(b) == hipSuccess && hipEventElapsedTime(&ms, a, b) == hipSuccess && ms > 0.f;

@@ -114,6 +114,23 @@ class OhmMap:
         check(load().ohm_ndt_integrate(self.handle, o, s, h_off.ctypes.data_as(ctypes.c_void_p), n_scans, w,
                                        _stream_ptr(stream)), "ohm_ndt_integrate")
 
+    def ndt_tm_integrate(self, origins: torch.Tensor, samples: torch.Tensor, intensities: torch.Tensor, offsets,
+                         weights=None, stream=None):
+        """NDT-TM integration of scans (ohm_ndt_tm_integrate): NDT-OM plus
+        checked misses and the intensity Gaussian; one intensity per ray."""
+        o, s, h_off, n_scans, w = self._scan_args(origins, samples, offsets, weights)
+        if intensities.shape[0] < int(h_off[-1]):
+            raise ValueError("intensities must have one entry per ray")
+        i = _dev_ptr(intensities, torch.float32, "intensities", self.device)
+        check(load().ohm_ndt_tm_integrate(self.handle, o, s, i, h_off.ctypes.data_as(ctypes.c_void_p), n_scans, w,
+                                          _stream_ptr(stream)), "ohm_ndt_tm_integrate")
+
+    def tsdf_integrate(self, origins: torch.Tensor, samples: torch.Tensor, offsets, stream=None):
+        """TSDF integration of scans (ohm_tsdf_integrate)."""
+        o, s, h_off, n_scans, _ = self._scan_args(origins, samples, offsets, None)
+        check(load().ohm_tsdf_integrate(self.handle, o, s, h_off.ctypes.data_as(ctypes.c_void_p), n_scans,
+                                        _stream_ptr(stream)), "ohm_tsdf_integrate")
+
     # -- read-back ------------------------------------------------------------------
     _READ_SHAPES = {
         _lib.READ_OCC: (torch.float32, ()), _lib.READ_HITS: (torch.float32, ()),
@@ -123,6 +140,9 @@ class OhmMap:
         _lib.READ_MEAN_PACKED: (torch.int32, ()), _lib.READ_MEAN_COUNT: (torch.int32, ()),
         _lib.READ_MEAN: (torch.float32, (3,)), _lib.READ_DECAY_LENGTH: (torch.float32, ()),
         _lib.READ_DECAY_HITS: (torch.int32, ()), _lib.READ_DECAY_RATE: (torch.float32, ()),
+        _lib.READ_TM_MISSES: (torch.int32, ()), _lib.READ_TM_PERMEABILITY: (torch.float32, ()),
+        _lib.READ_INTENSITY_MEAN: (torch.float32, ()), _lib.READ_INTENSITY_VAR: (torch.float32, ()),
+        _lib.READ_TSDF_DISTANCE: (torch.float32, ()), _lib.READ_TSDF_WEIGHT: (torch.float32, ()),
     }
 
     def read_dense(self, what: int, box_min: Sequence[int], box_dim: Sequence[int], out=None, stream=None):
@@ -219,13 +239,19 @@ class OhmMap:
         return st.as_dict()
 
 
-def probe_atomic_rate(footprint_bytes: int, sequential: bool = False, device=None, stream=None) -> float:
-    """Independent f32 atomic adds per second at the given footprint (see
-    ohm_probe_atomic_rate)."""
+_PROBE_OPS = {"f32_add": 0, "f32_cas": 2, "u64_add": 4}
+
+
+def probe_atomic_rate(footprint_bytes: int, sequential: bool = False, op: str = "f32_add", device=None,
+                      stream=None) -> float:
+    """Independent atomic updates per second at the given footprint (see
+    ohm_probe_atomic_rate): op is "f32_add", "f32_cas" (clamp-add by
+    compare-and-swap) or "u64_add"."""
     dev = torch.device("cuda", 0) if device is None else torch.device(device)
-    buf = torch.zeros(max(1, int(footprint_bytes) // 4), dtype=torch.float32, device=dev)
+    buf = torch.zeros(max(2, int(footprint_bytes) // 4), dtype=torch.float32, device=dev)
     rate = ctypes.c_double(0.0)
-    check(load().ohm_probe_atomic_rate(ctypes.c_void_p(buf.data_ptr()), buf.numel() * 4, 1 if sequential else 0,
+    flags = _PROBE_OPS[op] | (1 if sequential else 0)
+    check(load().ohm_probe_atomic_rate(ctypes.c_void_p(buf.data_ptr()), buf.numel() * 4, flags,
                                        ctypes.byref(rate), _stream_ptr(stream)), "ohm_probe_atomic_rate")
     return float(rate.value)
 

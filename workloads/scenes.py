@@ -257,6 +257,16 @@ def config1(n_scans: int = 100, first_scan: int = 0, beams: int = 64, cols: int 
     return params, RayBatch(origins, samples, offsets)
 
 
+def lidar_intensities(batch: RayBatch, seed: int = 7) -> np.ndarray:
+    """Synthetic return intensities for the NDT-TM workload (the recorded data
+    sets' intensities are not available): a smooth field over the sample
+    positions, 100 +- 60, plus per-ray noise N(0, 5), seeded; float32 per ray."""
+    rng = np.random.default_rng(seed)
+    p = batch.samples.astype(np.float64)
+    field = 100.0 + 60.0 * np.sin(0.7 * p[:, 0]) * np.cos(1.3 * p[:, 2])
+    return (field + rng.normal(0.0, 5.0, size=p.shape[0])).astype(np.float32)
+
+
 def config2(n_scans: int = 100, first_scan: int = 0, mode: int = MODE_COUNT_CLAMP, **kw):
     params, batch = config1(n_scans, first_scan, mode=mode, **kw)
     return params.replace(sensor_noise=0.05, adaptation_rate=1.0, ndt_min_samples=4), batch

@@ -427,6 +427,25 @@ ohm_status ohm_map_set_tuning(ohm_map map, const ohm_walk_tuning* tuning);
 ohm_status ohm_ray_order_scratch_size(uint32_t max_rays, size_t* bytes);
 ohm_status ohm_map_set_ray_order(ohm_map map, void* d_scratch, size_t bytes, uint32_t max_rays);
 
+/*
+ * For callers that cannot allocate (code under HIP graph capture, tight
+ * serving loops, harnesses that forbid allocation): ohm_integrate_rays with
+ * direction ordering (as with ohm_map_set_ray_order) whose ordering scratch
+ * is a fixed buffer inside the library instead of caller memory.  It
+ * allocates nothing: no hipMalloc, no events (map profiling records nothing
+ * for it).  Every scan is walked in direction order; a scan of more than
+ * OHM_NO_ALLOC_MAX_RAYS rays is an argument error (nothing enqueued), and so
+ * is a current device other than the map's.  The buffer (about 2 MiB) is
+ * one per GPU, held until the process ends, and shared by every call on
+ * that GPU: calls that overlap on one GPU (other streams, other threads)
+ * race on it and must be serialised by the caller.  The result equals
+ * ohm_integrate_rays on a map with ray ordering attached.
+ */
+#define OHM_NO_ALLOC_MAX_RAYS 262144u
+ohm_status ohm_integrate_rays_no_alloc(ohm_map map, const float* d_origins, const float* d_samples,
+                                       const uint32_t* h_scan_offsets, uint32_t n_scans, const float* d_weights,
+                                       void* stream);
+
 /* Kernel kinds reported by ohm_map_kernel_times. */
 enum {
   OHM_KERNEL_PREPASS = 0,   /* region pass: allocation and touched list */

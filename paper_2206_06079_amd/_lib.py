@@ -60,8 +60,10 @@ EXPORTS = (
     "ohm_map_set_profiling", "ohm_map_kernel_times", "ohm_backward",
     "ohm_batch_workspace_size", "ohm_batch_create", "ohm_batch_run", "ohm_batch_destroy",
     "ohm_map_set_tuning", "ohm_probe_atomic_rate", "ohm_ray_order_scratch_size", "ohm_map_set_ray_order",
-    "ohm_build_source_digest", "ohm_ndt_tm_integrate", "ohm_tsdf_integrate",
+    "ohm_build_source_digest", "ohm_ndt_tm_integrate", "ohm_tsdf_integrate", "ohm_integrate_rays_no_alloc",
 )
+
+NO_ALLOC_MAX_RAYS = 262144
 
 
 class WalkTuning(ctypes.Structure):
@@ -169,6 +171,7 @@ def load() -> ctypes.CDLL:
         "ohm_map_reset": [vp, vp],
         "ohm_map_set_params": [vp, P(OhmParams)],
         "ohm_integrate_rays": [vp, vp, vp, vp, ctypes.c_uint32, vp, vp],
+        "ohm_integrate_rays_no_alloc": [vp, vp, vp, vp, ctypes.c_uint32, vp, vp],
         "ohm_ndt_integrate": [vp, vp, vp, vp, ctypes.c_uint32, vp, vp],
         "ohm_ndt_tm_integrate": [vp, vp, vp, vp, vp, ctypes.c_uint32, vp, vp],
         "ohm_tsdf_integrate": [vp, vp, vp, vp, ctypes.c_uint32, vp],

@@ -26,6 +26,7 @@
 #include <stdlib.h>
 #include <string.h>
 
+#include <mutex>
 #include <new>
 
 #include "ohm.h"
@@ -976,6 +977,65 @@ ohm_status ohm_integrate_rays(ohm_map map, const float* d_origins, const float* 
   const OrderScratch ord{map->order_hist, map->order_sums, map->order_perm, map->order_max_rays};
   return integrate_rays_impl(map, d_origins, d_samples, h_scan_offsets, n_scans, d_weights, as_stream(stream), ord,
                              true);
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------------------
+// allocation-free entry point
+// ---------------------------------------------------------------------------
+
+namespace {
+
+// Direction-ordering scratch of ohm_integrate_rays_no_alloc: the bin
+// histogram, the strip sums and the permutation for one scan of up to
+// OHM_NO_ALLOC_MAX_RAYS rays.  Each GPU the library runs on holds its own
+// copy until the process ends; every call on that GPU shares it.
+constexpr uint32_t kNoAllocMaxRays = OHM_NO_ALLOC_MAX_RAYS;
+constexpr size_t kNoAllocScratchBytes = (size_t)kOrderMaxStrips * kOrderElevationBins * sizeof(uint32_t) +
+                                        (size_t)kOrderMaxStrips * sizeof(uint32_t) +
+                                        (size_t)kNoAllocMaxRays * sizeof(uint32_t);
+__device__ __align__(256) unsigned char scratch[kNoAllocScratchBytes];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mutex;
+void* g_scratch_ptr[kMaxDevices];  // device address of `scratch` per device (null until looked up)
+
+// The device address of the current device's `scratch` (looked up once per
+// device); null on failure.
+void* scratch_of_device(int dev) {
+  if (dev < 0 || dev >= kMaxDevices) return nullptr;
+  std::lock_guard<std::mutex> lock(g_scratch_mutex);
+  if (!g_scratch_ptr[dev]) {
+    void* ptr = nullptr;
+    if (hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)) != hipSuccess || !ptr) {
+      (void)hipGetLastError();
+      return nullptr;
+    }
+    g_scratch_ptr[dev] = ptr;
+  }
+  return g_scratch_ptr[dev];
+}
+
+}  // namespace
+
+extern "C" {
+
+ohm_status ohm_integrate_rays_no_alloc(ohm_map map, const float* d_origins, const float* d_samples,
+                                       const uint32_t* h_scan_offsets, uint32_t n_scans, const float* d_weights,
+                                       void* stream) {
+  ohm_status s = check_scans(map, d_origins, d_samples, h_scan_offsets, n_scans);
+  if (s != OHM_OK || n_scans == 0) return s;
+  for (uint32_t sc = 0; sc < n_scans; ++sc)
+    if (h_scan_offsets[sc + 1] - h_scan_offsets[sc] > kNoAllocMaxRays) return OHM_E_INVALID_ARG;
+  int dev = -1;
+  if (hipGetDevice(&dev) != hipSuccess || dev != map->device) return OHM_E_INVALID_ARG;
+  if (order_scratch_bytes(kNoAllocMaxRays) > kNoAllocScratchBytes) return OHM_E_UNSUPPORTED;
+  void* base = scratch_of_device(dev);
+  if (!base) return OHM_E_HIP;
+  const OrderScratch ord = order_scratch_at(base, kNoAllocMaxRays);
+  return integrate_rays_impl(map, d_origins, d_samples, h_scan_offsets, n_scans, d_weights, as_stream(stream), ord,
+                             false);
 }
 
 ohm_status ohm_map_read_dense(ohm_map map, int32_t what, const int32_t h_box_min[3], const int32_t h_box_dim[3],

@@ -108,6 +108,13 @@ class OhmMap:
         check(load().ohm_integrate_rays(self.handle, o, s, h_off.ctypes.data_as(ctypes.c_void_p), n_scans, w,
                                         _stream_ptr(stream)), "ohm_integrate_rays")
 
+    def integrate_no_alloc(self, origins: torch.Tensor, samples: torch.Tensor, offsets, weights=None, stream=None):
+        """Occupancy integration in direction order with the library's own
+        fixed scratch (ohm_integrate_rays_no_alloc)."""
+        o, s, h_off, n_scans, w = self._scan_args(origins, samples, offsets, weights)
+        check(load().ohm_integrate_rays_no_alloc(self.handle, o, s, h_off.ctypes.data_as(ctypes.c_void_p), n_scans,
+                                                 w, _stream_ptr(stream)), "ohm_integrate_rays_no_alloc")
+
     def ndt_integrate(self, origins: torch.Tensor, samples: torch.Tensor, offsets, weights=None, stream=None):
         """NDT-OM integration of scans (ohm_ndt_integrate)."""
         o, s, h_off, n_scans, w = self._scan_args(origins, samples, offsets, weights)

@@ -493,6 +493,9 @@ def main():
     ap.add_argument("--no-layers", action="store_true", help="skip the mean, decay-rate, NDT-TM and TSDF legs")
     ap.add_argument("--no-config0", action="store_true")
     ap.add_argument("--only-headline", action="store_true", help="the headline legs only (profiling runs)")
+    ap.add_argument("--only", default="",
+                    help="comma list of legs to run besides the headline (profiling runs): per_update, config0, "
+                         "batched, layers, ndt, adjoint, cpu")
     ap.add_argument("--batched-scans", type=int, default=1000)
     ap.add_argument("--batched-reps", type=int, default=3)
     ap.add_argument("--batched-groups", type=lambda v: tuple(int(x) for x in v.split(",")), default=(16, 64))
@@ -505,9 +508,18 @@ def main():
         print("bench.py measures one GPU only: this build has no multi-GPU path "
               "(how it would shard is described in the design notes)", file=sys.stderr)
         return 2
-    if args.only_headline:
-        args.no_batched = args.no_ndt = args.no_adjoint = args.no_layers = args.no_config0 = True
-        args.no_cpu_baseline = args.no_per_update = True
+    if args.only_headline or args.only:
+        keep = set(x for x in args.only.split(",") if x)
+        unknown = keep - {"per_update", "config0", "batched", "layers", "ndt", "adjoint", "cpu"}
+        if unknown:
+            ap.error(f"unknown legs {sorted(unknown)}")
+        args.no_batched = "batched" not in keep
+        args.no_ndt = "ndt" not in keep
+        args.no_adjoint = "adjoint" not in keep
+        args.no_layers = "layers" not in keep
+        args.no_config0 = "config0" not in keep
+        args.no_cpu_baseline = "cpu" not in keep
+        args.no_per_update = "per_update" not in keep
 
     from workloads import scenes
 

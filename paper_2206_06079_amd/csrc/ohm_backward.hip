@@ -17,10 +17,12 @@
 // g = exp(-q/2), q = D^T S^-1 D, S = Sigma + sigma_n^2 I, s = sigmoid(l_miss):
 //     d delta / d l_miss  = lambda g s (1 - s) / (p (1 - p))
 //     d delta / d sigma_n = -lambda (1/2 - s) g sigma_n |S^-1 D|^2 / (p (1 - p)).
-// The NDT statistics each scan saw are replayed: the layer is emptied, and
-// scan k's gradient walk, which reads the statistics as they were before
-// scan k, also adds each hit's sample to the voxel's moment accumulators,
-// which a fold after the walk merges into the statistics for scan k + 1.
+// The NDT statistics each scan saw are replayed for the voxels whose
+// statistics the gradient reads, those of the loss box (G_v = 0 elsewhere):
+// their statistics are emptied, and scan k's gradient walk, which reads the
+// statistics as they were before scan k, also adds each hit's sample that
+// falls in the box to the voxel's moment accumulators, which a fold after the
+// walk merges into the statistics for scan k + 1.
 #include <hip/hip_runtime.h>
 #include <math.h>
 #include <stdint.h>
@@ -40,6 +42,26 @@ struct GradBox {
   const float* g;
   int32_t bmin[3], bdim[3];
 };
+
+__device__ __forceinline__ bool in_box(const GradBox& gb, int32_t x, int32_t y, int32_t z) {
+  return (uint32_t)(x - gb.bmin[0]) < (uint32_t)gb.bdim[0] && (uint32_t)(y - gb.bmin[1]) < (uint32_t)gb.bdim[1] &&
+         (uint32_t)(z - gb.bmin[2]) < (uint32_t)gb.bdim[2];
+}
+
+// Empty the NDT statistics of every voxel of the loss box (the ones the
+// replay rebuilds); one thread per box voxel.
+__global__ __launch_bounds__(256) void clear_box_stats_kernel(DevMap m, GradBox gb) {
+  const size_t nbox = (size_t)gb.bdim[0] * gb.bdim[1] * gb.bdim[2];
+  const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= nbox) return;
+  const int32_t x = gb.bmin[0] + (int32_t)(i % (size_t)gb.bdim[0]);
+  const int32_t y = gb.bmin[1] + (int32_t)((i / (size_t)gb.bdim[0]) % (size_t)gb.bdim[1]);
+  const int32_t z = gb.bmin[2] + (int32_t)(i / ((size_t)gb.bdim[0] * gb.bdim[1]));
+  if (x < m.kmin[0] || x >= m.kmax[0] || y < m.kmin[1] || y >= m.kmax[1] || z < m.kmin[2] || z >= m.kmax[2]) return;
+  const int32_t slot = lookup_slot(m, x, y, z);
+  if (slot < 0) return;
+  m.ndt[(size_t)slot * kRegionVoxels + local_index(x, y, z)] = NdtVoxel{};
+}
 
 __device__ __forceinline__ float grad_at(const GradBox& gb, int32_t x, int32_t y, int32_t z) {
   const int32_t dx = x - gb.bmin[0], dy = y - gb.bmin[1], dz = z - gb.bmin[2];
@@ -197,8 +219,9 @@ __global__ __launch_bounds__(kBackwardMaxThreads, 4) void backward_seg_kernel(
       if (alive) {
         last = s.w.total == 0;
         const bool is_hit = last && !trunc;
-        if (kNdt && is_hit && slot >= 0) {
-          // the statistics replay: this sample's moments, as the forward adds them
+        if (kNdt && is_hit && slot >= 0 && in_box(gb, k0, k1, k2)) {
+          // the statistics replay, for the voxels whose statistics the
+          // gradient reads (the box's): this sample's moments, as the forward adds them
           const int32_t kh[3] = {k0, k1, k2};
           ndt_add_sample(m, (size_t)slot * kRegionVoxels + lidx, samples + 3 * ((size_t)r0 + tr.src[ray_t]), kh);
         }
@@ -292,6 +315,7 @@ extern "C" ohm_status ohm_backward(ohm_map map, int32_t ndt, const float* d_grad
   if (ndt && !(isinf(map->params.ndt_clear_below) && map->params.ndt_clear_below < 0)) return OHM_E_UNSUPPORTED;
   for (int a = 0; a < 3; ++a)
     if (h_box_dim[a] <= 0) return OHM_E_INVALID_ARG;
+  if ((size_t)h_box_dim[0] * h_box_dim[1] * h_box_dim[2] > ((size_t)1 << 38)) return OHM_E_INVALID_ARG;
   // the map must hold exactly these scans since its last create / reset
   uint32_t nonempty = 0;
   for (uint32_t sc = 0; sc < n_scans; ++sc) nonempty += h_scan_offsets[sc + 1] > h_scan_offsets[sc] ? 1u : 0u;
@@ -313,10 +337,11 @@ extern "C" ohm_status ohm_backward(ohm_map map, int32_t ndt, const float* d_grad
   hipLaunchKernelGGL(zero_f64_kernel, dim3(1), dim3(64), 0, st, d_grad_scalars, 3);
   if (ndt) {
     clear_pending(map, st);
-    // empty the statistics; they are replayed scan by scan below
-    const size_t bytes = (size_t)map->dm.capacity * kRegionVoxels * sizeof(NdtVoxel);
-    hipLaunchKernelGGL(fill_u32_kernel, dim3(8192), dim3(256), 0, st, reinterpret_cast<uint32_t*>(map->dm.ndt),
-                       bytes / 4, 0u);
+    // empty the statistics of the box's voxels, the only ones the gradient
+    // reads; they are replayed scan by scan below (the others keep their
+    // final values)
+    const size_t nbox = (size_t)gb.bdim[0] * gb.bdim[1] * gb.bdim[2];
+    hipLaunchKernelGGL(clear_box_stats_kernel, dim3((unsigned)((nbox + 255) / 256)), dim3(256), 0, st, bm, gb);
   }
   uint32_t tag = 0;
   for (uint32_t sc = 0; sc < n_scans; ++sc) {

@@ -16,10 +16,14 @@
 // One thread per ray, 256 rays per block: a band is a few voxels long, so
 // segmenting it (as the occupancy walk does its rays) would cost more than
 // it balances.  The block stages the regions of its bands in LDS first.
-//   count mode: each update adds its Q32.32 distance and a count to the
-//     voxel's per-scan sums (exact integers: the result does not depend on
-//     the order of the adds); tsdf_finalize_kernel applies them per voxel of
-//     the scan's regions.
+//   count mode: each update's Q32.32 distance and count go to the voxel's
+//     per-scan sums (exact integers: the result does not depend on the order
+//     of the adds); tsdf_finalize_kernel applies them per voxel of the
+//     scan's regions.  Adjacent rays of a scan reach nearby points of one
+//     surface, so their bands share voxels: the lanes step in lockstep, runs
+//     of adjacent lanes in one voxel are summed in registers, and a per-block
+//     LDS table (voxel -> sums) takes the runs, so the global sums see about
+//     one update per voxel and block.
 //   per-update mode: each update is applied at once by one 64-bit
 //     compare-and-swap on the packed (D, W) word, retried until it lands.
 #include <hip/hip_runtime.h>
@@ -31,6 +35,7 @@
 #include "ohm_host.h"
 #include "ohm_regions.h"
 #include "ohm_seg_math.h"
+#include "ohm_wave.h"
 
 namespace ohm {
 
@@ -102,11 +107,53 @@ __device__ __forceinline__ unsigned long long tsdf_merge(const DevMap& m, unsign
   return ((unsigned long long)__float_as_uint((float)Wn) << 32) | (unsigned long long)__float_as_uint((float)Dn);
 }
 
+// Per-block LDS table of count-mode updates: voxel index -> (summed Q32.32
+// distance, update count), two probes; a run whose two entries belong to
+// other voxels goes to the global sums at once.
+constexpr int kTsdfAggLog2 = 11;
+constexpr uint32_t kTsdfAggSize = 1u << kTsdfAggLog2;
+constexpr uint32_t kTsdfEmpty = 0xFFFFFFFFu;  // above every voxel index (capacity <= kMaxCapacity)
+
+__device__ __forceinline__ bool tsdf_agg_add(uint32_t* keys, unsigned long long* sums, uint32_t* counts, uint32_t v,
+                                             long long q, uint32_t c) {
+  uint32_t h = (v * 0x9E3779B1u) >> (32 - kTsdfAggLog2);
+  for (int p = 0; p < 2; ++p) {
+    uint32_t k = keys[h];
+    if (k == kTsdfEmpty) {
+      const uint32_t old = atomicCAS(keys + h, kTsdfEmpty, v);
+      k = old == kTsdfEmpty ? v : old;
+    }
+    if (k == v) {
+      atomicAdd(sums + h, (unsigned long long)q);
+      atomicAdd(counts + h, c);
+      return true;
+    }
+    h = (h + 1) & (kTsdfAggSize - 1);
+  }
+  return false;
+}
+
+__device__ __forceinline__ void tsdf_global_add(const DevMap& m, uint32_t v, long long q, uint32_t c) {
+  unsigned long long* a = reinterpret_cast<unsigned long long*>(m.tsdf_acc + 2 * (size_t)v);
+  atomicAdd(a, (unsigned long long)q);
+  atomicAdd(a + 1, (unsigned long long)c);
+}
+
 template <bool kCount>
 __global__ __launch_bounds__(kTsdfThreads) void tsdf_kernel(DevMap m, const float* __restrict__ origins, uint32_t scan,
                                                            const float* __restrict__ samples, uint32_t r0, uint32_t n,
                                                            uint32_t tag, uint32_t parity) {
   __shared__ RegionCache rc;
+  __shared__ uint32_t agg_key[kCount ? kTsdfAggSize : 1];
+  __shared__ unsigned long long agg_sum[kCount ? kTsdfAggSize : 1];
+  __shared__ uint32_t agg_cnt[kCount ? kTsdfAggSize : 1];
+  if (kCount)
+    for (uint32_t h = threadIdx.x; h < kTsdfAggSize; h += blockDim.x) {
+      agg_key[h] = kTsdfEmpty;
+      agg_sum[h] = 0ull;
+      agg_cnt[h] = 0u;
+    }
+  const uint32_t lane = lane_id();
   const uint32_t i = blockIdx.x * kTsdfThreads + threadIdx.x;
   const bool inrange = i < n;
   const float o[3] = {origins[3 * (size_t)scan], origins[3 * (size_t)scan + 1], origins[3 * (size_t)scan + 2]};
@@ -125,37 +172,70 @@ __global__ __launch_bounds__(kTsdfThreads) void tsdf_kernel(DevMap m, const floa
   }
   const RegionWindow rw = stage_regions<kCount>(m, rc, has, band, tag, parity);
   uint32_t n_upd = 0, n_drop = 0;
+  Walk w;
+  int32_t k[3] = {0, 0, 0};
+  bool alive = has;
   if (has) {
-    Walk w;
     const int32_t hi[3] = {m.kmax[0] - 1, m.kmax[1] - 1, m.kmax[2] - 1};
     walk_init(w, band.q0, band.q1, band.k0, band.k1, m.kmin, hi, m.F);
-    int32_t k[3] = {band.k0[0], band.k0[1], band.k0[2]};
-    for (;;) {
-      const int32_t slot = staged_slot(m, rc, rw, k[0], k[1], k[2]);
+    for (int a = 0; a < 3; ++a) k[a] = band.k0[a];
+  }
+  // lockstep band walks: at every step each live lane visits one voxel
+  while (__ballot(alive)) {
+    int32_t slot = -1;
+    uint32_t v = kTsdfEmpty - lane;  // distinct per lane where there is no update
+    long long q = 0;
+    if (alive) {
+      slot = staged_slot(m, rc, rw, k[0], k[1], k[2]);
       if (slot >= 0) {
-        const size_t v = (size_t)slot * kRegionVoxels + local_index(k[0], k[1], k[2]);
-        const double sd = tsdf_distance(m, o, range, u, k);
-        if (kCount) {
-          unsigned long long* a = reinterpret_cast<unsigned long long*>(m.tsdf_acc + 2 * v);
-          atomicAdd(a, (unsigned long long)llrint(sd * kQ32));
-          atomicAdd(a + 1, 1ull);
-        } else {
-          unsigned long long old = __hip_atomic_load(m.tsdf + v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-          for (;;) {
-            const unsigned long long prev = atomicCAS(m.tsdf + v, old, tsdf_merge(m, old, sd, 1.0));
-            if (prev == old) break;
-            old = prev;
-          }
-        }
+        v = (uint32_t)slot * (uint32_t)kRegionVoxels + local_index(k[0], k[1], k[2]);
+        if (kCount) q = llrint(tsdf_distance(m, o, range, u, k) * kQ32);
         ++n_upd;
       } else {
         ++n_drop;
       }
-      if (w.total == 0) break;
-      const int a = walk_step(w);
-      const int32_t ra = a == 0 ? w.rem[0] : (a == 1 ? w.rem[1] : w.rem[2]);
-      if (ra == 0 && ((w.clip >> a) & 1u)) break;  // the band leaves the map
-      k[a] += w.sg[a];
+    }
+    const bool upd = alive && slot >= 0;
+    if (kCount) {
+      // runs of adjacent lanes in one voxel: the run's tail holds its summed
+      // distance and counts its lanes back to the head
+      const LaneRuns run = lane_runs(v, lane);
+      const long long qs = segmented_sum<long long>(q, run.head, lane);
+      const unsigned long long heads = __ballot(run.head);
+      const unsigned long long upto = lane == 63 ? ~0ull : ((2ull << lane) - 1ull);
+      const uint32_t head_lane = 63u - (uint32_t)__builtin_clzll(heads & upto);
+      if (upd && run.tail) {
+        const uint32_t c = lane - head_lane + 1u;
+        if (!tsdf_agg_add(agg_key, agg_sum, agg_cnt, v, qs, c)) tsdf_global_add(m, v, qs, c);
+      }
+    } else if (upd) {
+      const double sd = tsdf_distance(m, o, range, u, k);
+      unsigned long long old = __hip_atomic_load(m.tsdf + v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      for (;;) {
+        const unsigned long long prev = atomicCAS(m.tsdf + v, old, tsdf_merge(m, old, sd, 1.0));
+        if (prev == old) break;
+        old = prev;
+      }
+    }
+    if (alive) {
+      if (w.total == 0) {
+        alive = false;
+      } else {
+        const int a = walk_step(w);
+        const int32_t ra = a == 0 ? w.rem[0] : (a == 1 ? w.rem[1] : w.rem[2]);
+        if (ra == 0 && ((w.clip >> a) & 1u)) {
+          alive = false;  // the band leaves the map
+        } else {
+          k[a] += w.sg[a];
+        }
+      }
+    }
+  }
+  if (kCount) {
+    __syncthreads();
+    for (uint32_t h = threadIdx.x; h < kTsdfAggSize; h += blockDim.x) {
+      const uint32_t key = agg_key[h];
+      if (key != kTsdfEmpty) tsdf_global_add(m, key, (long long)agg_sum[h], agg_cnt[h]);
     }
   }
   uint32_t vals[kStatCount];

@@ -203,7 +203,18 @@ __global__ __launch_bounds__(kBackwardMaxThreads, 4) void backward_seg_kernel(
     int32_t slot = -1;
     uint32_t lidx = 0;
     if (alive) {
-      alive = tile_item(m, tr, it, K, s, ray_t, M);
+      uint32_t level = 0;
+      alive = tile_item(m, tr, it, K, s, ray_t, M, &level);
+      if (alive) {
+        // a segment whose voxels all lie outside the loss box contributes
+        // nothing (zero upstream gradient there, and no replayed sample)
+        const int64_t q0[3] = {tr.q0[0][ray_t], tr.q0[1][ray_t], tr.q0[2][ray_t]};
+        const int64_t q1[3] = {tr.q1[0][ray_t], tr.q1[1][ray_t], tr.q1[2][ray_t]};
+        int32_t lo[3], hi[3];
+        seg_bounds(s, q0, q1, M, K, level + 1 == (uint32_t)kMaxLevels, m.F, lo, hi);
+        for (int a = 0; a < 3; ++a)
+          alive = alive && hi[a] >= gb.bmin[a] && lo[a] < gb.bmin[a] + gb.bdim[a];
+      }
       trunc = tr.trunc[ray_t] != 0;
       if (kWeighted) wt = (double)weights[(size_t)r0 + tr.src[ray_t]];
       slot = staged_slot(m, rc, rw, s.k[0], s.k[1], s.k[2]);

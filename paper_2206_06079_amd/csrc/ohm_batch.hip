@@ -104,80 +104,109 @@ __global__ __launch_bounds__(1024) void batch_walk_kernel(const DevMap* __restri
   const BlockDesc d = descs[blockIdx.x];
   DevMap m = maps[d.set];
   m.acc += (size_t)d.pos * acc_slot_floats(m, kWeighted);
+  m.brick_mask += (size_t)d.pos * m.capacity;
   const uint32_t tag = __hip_atomic_load(m.hdr + kHdrBatchTag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   const SetPtrs sp = sets[d.set];
-  walk_tile<kSinkCount, kWeighted>(m, sp.origins + 3 * (size_t)d.scan, sp.samples, sp.weights,
+  walk_tile<kSinkCount, kWeighted, false, true, true>(m, sp.origins + 3 * (size_t)d.scan, sp.samples, sp.weights,
                                    sp.perm ? sp.perm + d.r0 : nullptr, d.r0, d.n,
                                    d.block * kTileRays, K, tag, tag & 1u, nullptr, nullptr, nullptr, nullptr);
 }
 
 // Applies the group's scans in order to every voxel of the regions the group
 // touched: for j = 0..G-1, l = clamp((l + H_j l_hit) + M_j l_miss) (kWide:
-// Q32.32 weight sums applied in fp64, as the per-scan path does).
+// Q32.32 weight sums applied in fp64, as the per-scan path does).  Work goes
+// by 8^3 brick: the brick masks the walk left say which scans' slots hold
+// counts in the brick, and only those slots are read (a group's scans
+// leave most of their slots' words zero).
 template <bool kWide>
 __global__ __launch_bounds__(256) void batch_finalize_kernel(const DevMap* __restrict__ maps, uint32_t n_sets,
                                                              uint32_t group) {
-  constexpr int kChunk = 1024;
-  constexpr int kUnits = kRegionVoxels / kChunk;
+  __shared__ unsigned long long active_slots;
   for (uint32_t si = 0; si < n_sets; ++si) {
     const DevMap& m = maps[si];
     const uint32_t tag = __hip_atomic_load(m.hdr + kHdrBatchTag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     const uint32_t parity = tag & 1u;
     const uint32_t count = __hip_atomic_load(m.hdr + kHdrTouched0 + parity, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    const uint32_t units = count * kUnits;
+    const uint32_t units = count * 64u;  // bricks
     const size_t stride = acc_slot_floats(m, kWide);
     for (uint32_t u = blockIdx.x; u < units; u += gridDim.x) {
-      const uint32_t slot = m.touched[(size_t)parity * m.capacity + u / kUnits];
-      const size_t base = (size_t)slot * kRegionVoxels + (size_t)(u % kUnits) * kChunk;
-      if constexpr (kWide) {
-        for (int v = threadIdx.x; v < kChunk; v += blockDim.x) {
-          const size_t vi = base + v;
-          longlong2* const a0 = reinterpret_cast<longlong2*>(m.acc) + vi;
-          const size_t step = stride / 4;  // longlong2 elements per slot
-          float l = m.occ[vi];
-          bool any = false;
-          constexpr int kBatch = 8;
-          for (uint32_t j0 = 0; j0 < group; j0 += kBatch) {
+      const uint32_t slot = m.touched[(size_t)parity * m.capacity + u / 64u];
+      const uint32_t brick = u % 64u;
+      // the slots with counts in this brick: one wave, one slot per lane
+      if (threadIdx.x < 64) {
+        const bool has = threadIdx.x < group &&
+                         ((m.brick_mask[(size_t)threadIdx.x * m.capacity + slot] >> brick) & 1ull) != 0ull;
+        const unsigned long long bal = __ballot(has);
+        if (threadIdx.x == 0) active_slots = bal;
+      }
+      __syncthreads();
+      const unsigned long long act = active_slots;
+      // brick origin within the region: x, y, z in steps of 8 (x fastest)
+      const uint32_t b0 = ((brick >> 4) << 13) | (((brick >> 2) & 3u) << 8) | ((brick & 3u) << 3);
+      for (uint32_t i = threadIdx.x; act && i < 512u; i += blockDim.x) {
+        const size_t vi = (size_t)slot * kRegionVoxels + (b0 | (i & 7u) | (((i >> 3) & 7u) << 5) | ((i >> 6) << 10));
+        float l = m.occ[vi];
+        bool any = false;
+        // the active slots' words are loaded kBatch at a time, all before
+        // any of their clearing stores, so the loads overlap
+        constexpr int kBatch = 8;
+        unsigned long long rest = act;
+        while (rest) {
+          uint32_t js[kBatch];
+#pragma unroll
+          for (int q = 0; q < kBatch; ++q) {
+            js[q] = rest ? (uint32_t)__builtin_ctzll(rest) : 0xFFFFFFFFu;
+            rest &= rest ? rest - 1ull : 0ull;
+          }
+          if constexpr (kWide) {
             longlong2 a[kBatch];
 #pragma unroll
-            for (int q = 0; q < kBatch; ++q) a[q] = j0 + q < group ? a0[(j0 + q) * step] : make_longlong2(0, 0);
+            for (int q = 0; q < kBatch; ++q)
+              a[q] = js[q] != 0xFFFFFFFFu ? reinterpret_cast<const longlong2*>(m.acc + (size_t)js[q] * stride)[vi]
+                                          : make_longlong2(0, 0);
 #pragma unroll
             for (int q = 0; q < kBatch; ++q) {
               if (a[q].x == 0 && a[q].y == 0) continue;
               l = apply_wide(m, l, a[q].x, a[q].y, vi, 0u);  // (the plan's maps keep no clamp record)
-              a0[(j0 + q) * step] = make_longlong2(0, 0);
+              reinterpret_cast<longlong2*>(m.acc + (size_t)js[q] * stride)[vi] = make_longlong2(0, 0);
               any = true;
             }
-          }
-          if (any) m.occ[vi] = l;
-        }
-        continue;
-      }
-      for (int v = threadIdx.x; v < kChunk; v += blockDim.x) {
-        const size_t vi = base + v;
-        float2* const a0 = reinterpret_cast<float2*>(m.acc) + vi;
-        const size_t step = stride / 2;  // float2 elements per slot
-        float l = m.occ[vi];
-        bool any = false;
-        // kBatch slots are loaded before any of their clearing stores, so
-        // the loads overlap instead of waiting on each other
-        constexpr int kBatch = 8;
-        for (uint32_t j0 = 0; j0 < group; j0 += kBatch) {
-          float2 a[kBatch];
+          } else {
+            float2 a[kBatch];
 #pragma unroll
-          for (int q = 0; q < kBatch; ++q) a[q] = j0 + q < group ? a0[(j0 + q) * step] : make_float2(0.f, 0.f);
+            for (int q = 0; q < kBatch; ++q)
+              a[q] = js[q] != 0xFFFFFFFFu ? reinterpret_cast<const float2*>(m.acc + (size_t)js[q] * stride)[vi]
+                                          : make_float2(0.f, 0.f);
 #pragma unroll
-          for (int q = 0; q < kBatch; ++q) {
-            if (a[q].x == 0.f && a[q].y == 0.f) continue;
-            float s = __fadd_rn(l, __fmul_rn(a[q].y, m.l_hit));
-            s = __fadd_rn(s, __fmul_rn(a[q].x, m.l_miss));
-            l = fminf(fmaxf(s, m.l_min), m.l_max);
-            a0[(j0 + q) * step] = make_float2(0.f, 0.f);
-            any = true;
+            for (int q = 0; q < kBatch; ++q) {
+              if (a[q].x == 0.f && a[q].y == 0.f) continue;
+              float s = __fadd_rn(l, __fmul_rn(a[q].y, m.l_hit));
+              s = __fadd_rn(s, __fmul_rn(a[q].x, m.l_miss));
+              l = fminf(fmaxf(s, m.l_min), m.l_max);
+              reinterpret_cast<float2*>(m.acc + (size_t)js[q] * stride)[vi] = make_float2(0.f, 0.f);
+              any = true;
+            }
           }
         }
         if (any) m.occ[vi] = l;
       }
+      __syncthreads();  // active_slots is rewritten by the next unit
+    }
+  }
+}
+
+// After a group's finalize: clear the brick masks of the regions it touched
+// (one thread per region and slot).
+__global__ __launch_bounds__(256) void batch_clear_masks_kernel(const DevMap* __restrict__ maps, uint32_t n_sets,
+                                                                uint32_t group) {
+  for (uint32_t si = 0; si < n_sets; ++si) {
+    const DevMap& m = maps[si];
+    const uint32_t tag = __hip_atomic_load(m.hdr + kHdrBatchTag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    const uint32_t parity = tag & 1u;
+    const uint32_t count = __hip_atomic_load(m.hdr + kHdrTouched0 + parity, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < count * group; i += gridDim.x * blockDim.x) {
+      const uint32_t slot = m.touched[(size_t)parity * m.capacity + i / group];
+      m.brick_mask[(size_t)(i % group) * m.capacity + slot] = 0ull;
     }
   }
 }
@@ -249,6 +278,7 @@ inline size_t align_b(size_t v) { return (v + kAlignB - 1) & ~(kAlignB - 1); }
 
 struct BatchLayout {
   size_t maps, sets, descs, scans, hist, sums, acc_total, total;
+  std::vector<size_t> mask;  // per-set brick-mask offsets
   size_t hist_bins, strips;
   std::vector<size_t> acc;   // per-set accumulator offsets
   std::vector<size_t> perm;  // per-set walk-order offsets
@@ -336,9 +366,12 @@ ohm_status plan_layout(const ohm_scan_set* sets, uint32_t n_sets, const ohm_batc
     off = align_b(off + (size_t)sets[si].h_scan_offsets[sets[si].n_scans] * sizeof(uint32_t));
   }
   L->acc.resize(n_sets);
+  L->mask.resize(n_sets);
   for (uint32_t si = 0; si < n_sets; ++si) {
     L->acc[si] = off;
     off = align_b(off + (size_t)G * acc_slot_floats(sets[si].map->dm, weighted) * sizeof(float));
+    L->mask[si] = off;
+    off = align_b(off + (size_t)G * sets[si].map->dm.capacity * sizeof(unsigned long long));
   }
   L->total = off;
   return OHM_OK;
@@ -400,6 +433,7 @@ ohm_status ohm_batch_create(const ohm_scan_set* sets, uint32_t n_sets, const ohm
     b->nonempty.push_back(ne);
     hm[si] = sets[si].map->dm;
     hm[si].acc = reinterpret_cast<float*>(base + L.acc[si]);
+    hm[si].brick_mask = reinterpret_cast<unsigned long long*>(base + L.mask[si]);
     hm[si].clampscan = nullptr;  // per-scan clamp records are kept by the per-scan path only
     hs[si] = {sets[si].d_origins, sets[si].d_samples, sets[si].d_weights,
               b->order ? reinterpret_cast<uint32_t*>(base + L.perm[si]) : nullptr};
@@ -416,6 +450,8 @@ ohm_status ohm_batch_create(const ohm_scan_set* sets, uint32_t n_sets, const ohm
     const size_t nf = (size_t)b->group * acc_slot_floats(hm[si], b->weighted);
     hipLaunchKernelGGL(fill_u32_kernel, dim3(8192), dim3(256), 0, st, reinterpret_cast<uint32_t*>(hm[si].acc), nf,
                        0u);
+    hipLaunchKernelGGL(fill_u32_kernel, dim3(256), dim3(256), 0, st, reinterpret_cast<uint32_t*>(hm[si].brick_mask),
+                       (size_t)b->group * hm[si].capacity * 2, 0u);
   }
   // the host copies above must land before `hm` / `L` go out of scope
   ok = ok && hipStreamSynchronize(st) == hipSuccess;
@@ -455,6 +491,7 @@ ohm_status ohm_batch_create(const ohm_scan_set* sets, uint32_t n_sets, const ohm
       else
         hipLaunchKernelGGL(batch_finalize_kernel<false>, dim3(kFinalizeBlocks), dim3(256), 0, b->capture, b->d_maps,
                            n_sets, b->group);
+      hipLaunchKernelGGL(batch_clear_masks_kernel, dim3(64), dim3(256), 0, b->capture, b->d_maps, n_sets, b->group);
       hipLaunchKernelGGL(batch_advance_kernel, dim3(1), dim3(64), 0, b->capture, b->d_maps, n_sets);
     }
     hipLaunchKernelGGL(batch_end_kernel, dim3(1), dim3(64), 0, b->capture, b->d_maps, n_sets);

@@ -87,6 +87,7 @@ struct DevMap {
   float* occ;         // [capacity][V]
   float* acc;         // [capacity][V][2]: miss weight, hit weight
   NdtVoxel* ndt;      // [capacity][V] or null
+  uint32_t* ndt_ready;  // [capacity][V / 32]: bit set where the voxel holds >= ndt_min_samples samples
   long long* nacc;    // NDT per-scan accumulators [capacity][V][kNaccWords] or null
   double* mom;        // NDT per-scan sample moments [capacity][V][kMomWords] or null
   uint32_t* clampscan;// [capacity][V] or null
@@ -115,7 +116,17 @@ struct DevMap {
   unsigned long long* tsdf;
   long long* tsdf_acc;  // [capacity][V][2]
   double tsdf_tau, tsdf_wmax;
+  // batched plans (or null): per region one 64-bit mask of the 8^3 bricks in
+  // which the scan being walked left a non-zero count (the walk points it at
+  // that scan's slot: [capacity] words per slot), so that the finalize skips
+  // the slots a brick never received
+  unsigned long long* brick_mask;
 };
+
+// Brick (8^3 voxels, 64 per region) of a region-local voxel index.
+__host__ __device__ __forceinline__ uint32_t brick_of(uint32_t lidx) {
+  return ((lidx >> 13) << 4) | (((lidx >> 8) & 3u) << 2) | ((lidx >> 3) & 3u);
+}
 
 // Q32.32 fixed point of the exact (order-independent) sums of weights and
 // NDT increments: each term is rounded to a multiple of 2^-32 once, and the
@@ -302,6 +313,63 @@ __host__ __device__ __forceinline__ int walk_step(Walk& w) {
   const int a = walk_pick(w);
   walk_apply(w, a);
   return a;
+}
+
+// The same walk with its error terms held in 32 bits, for the voxel loops.
+// Every crossing moves a pairwise term d by a multiple of 2^S (A_a << S), so
+// d's low S bits never change: c = ceil(d / 2^S) moves by A_a exactly, and
+// d <= 0 exactly when c <= 0.  Along a walk the next crossings of two axes
+// lie within one cell of each other in t, so |d| <= 2^S max_a A_a and
+// |c| <= max_a A_a < 2^31 (ray preparation rejects spans of 2^31 or more).
+// The loop then keeps three int32 terms and three int32 steps instead of
+// six int64 values.
+struct WalkH {
+  int32_t exy, exz, eyz;   // ceil(d / 2^S) of the pairwise error terms
+  int32_t ax, ay, az;      // A_a: what a crossing adds to or takes from them
+  int32_t rem[3];          // crossings still to apply per axis
+  int32_t total;           // sum of rem
+  int32_t sg[3];           // step direction per axis
+  uint32_t clip;           // bit a: axis a's last counted crossing leaves the bounds
+};
+
+__host__ __device__ __forceinline__ int32_t ceil_shift(int64_t d, int S) {
+  return (int32_t)((d + (((int64_t)1 << S) - 1)) >> S);
+}
+
+__host__ __device__ __forceinline__ WalkH walk_half(const Walk& w, int S) {
+  WalkH h;
+  h.exy = ceil_shift(w.dxy, S);
+  h.exz = ceil_shift(w.dxz, S);
+  h.eyz = ceil_shift(w.dyz, S);
+  h.ax = (int32_t)(w.cx >> S);
+  h.ay = (int32_t)(w.cy >> S);
+  h.az = (int32_t)(w.cz >> S);
+  for (int a = 0; a < 3; ++a) {
+    h.rem[a] = w.rem[a];
+    h.sg[a] = w.sg[a];
+  }
+  h.total = w.total;
+  h.clip = w.clip;
+  return h;
+}
+
+__host__ __device__ __forceinline__ int walk_pick(const WalkH& w) {
+  const bool ex = w.rem[0] > 0, ey = w.rem[1] > 0, ez = w.rem[2] > 0;
+  const bool sx = ex && (!ey || w.exy <= 0) && (!ez || w.exz <= 0);
+  const bool sy = !sx && ey && (!ez || w.eyz <= 0);
+  return sx ? 0 : (sy ? 1 : 2);
+}
+
+// (Wrapping adds, as for Walk: an ended walk may be stepped on without meaning.)
+__host__ __device__ __forceinline__ void walk_apply(WalkH& w, int a) {
+  const bool sx = a == 0, sy = a == 1, sz = a == 2;
+  w.exy = (int32_t)((uint32_t)w.exy + (uint32_t)(sx ? w.ay : (sy ? -w.ax : 0)));
+  w.exz = (int32_t)((uint32_t)w.exz + (uint32_t)(sx ? w.az : (sz ? -w.ax : 0)));
+  w.eyz = (int32_t)((uint32_t)w.eyz + (uint32_t)(sy ? w.az : (sz ? -w.ay : 0)));
+  w.rem[0] -= sx ? 1 : 0;
+  w.rem[1] -= sy ? 1 : 0;
+  w.rem[2] -= sz ? 1 : 0;
+  w.total -= 1;
 }
 
 __device__ __forceinline__ int32_t region_index(const DevMap& m, int32_t rx, int32_t ry, int32_t rz) {

@@ -23,6 +23,7 @@ struct ohm_map_s {
   uint32_t scans_done;     // scans integrated since create / reset
   bool batched;            // a batched plan ran on the map since create / reset
   bool acc_dirty;          // the last count-mode scan's accumulators are still set
+  bool ndt_ready_stale;    // ndt_min_samples changed since the NDT ready bits were last computed
   uint32_t last_parity;
   uint32_t kept_slot;      // accumulator slot holding those counts (scan groups), else 0
   bool kept_wide;          // ... as Q32.32 weight sums (a weighted scan), two f32 slots wide

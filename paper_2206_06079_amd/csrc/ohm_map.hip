@@ -385,7 +385,7 @@ inline size_t align_up(size_t v) { return (v + kAlign - 1) & ~(kAlign - 1); }
 
 struct Layout {
   size_t hdr, stats, table, stamp, touched, occ, acc, ndt, nacc, mom, clampscan, mean, mean_acc, mean_mask,
-      decay_len, decay_hits, tm, tm_mom, tsdf, tsdf_acc, total;
+      decay_len, decay_hits, tm, tm_mom, tsdf, tsdf_acc, ndt_ready, total;
   int32_t rlo[3], rdim[3];
   size_t regions;
 };
@@ -456,10 +456,12 @@ ohm_status compute_layout(const ohm_params* p, uint32_t capacity, uint32_t layer
   L->acc = off;
   // at least two f32 slots: a weighted scan's wide (int64) slot spans two
   off = align_up(off + (size_t)capacity * V * 2 * sizeof(float) * (slots < 2 ? 2 : slots));
-  L->ndt = L->nacc = L->mom = L->clampscan = 0;
+  L->ndt = L->nacc = L->mom = L->clampscan = L->ndt_ready = 0;
   if (layers & OHM_LAYER_NDT) {
     L->ndt = off;
     off = align_up(off + (size_t)capacity * V * sizeof(NdtVoxel));
+    L->ndt_ready = off;
+    off = align_up(off + (size_t)capacity * (V / 32) * sizeof(uint32_t));
     L->nacc = off;
     off = align_up(off + (size_t)capacity * V * kNaccWords * sizeof(long long));
     L->mom = off;
@@ -572,6 +574,7 @@ ohm_status map_initialise(ohm_map_s* map, hipStream_t st) {
     launch_fill(m.ndt, (size_t)m.capacity * V * sizeof(NdtVoxel), 0u, st);
     launch_fill(m.nacc, (size_t)m.capacity * V * kNaccWords * sizeof(long long), 0u, st);
     launch_fill(m.mom, (size_t)m.capacity * V * kMomWords * sizeof(double), 0u, st);
+    launch_fill(m.ndt_ready, (size_t)m.capacity * (V / 32) * sizeof(uint32_t), 0u, st);
   }
   if (m.clampscan) launch_fill(m.clampscan, (size_t)m.capacity * V * sizeof(uint32_t), 0u, st);
   if (m.mean) {
@@ -593,6 +596,7 @@ ohm_status map_initialise(ohm_map_s* map, hipStream_t st) {
   }
   map->count_batches = 0;
   map->acc_dirty = false;
+  map->ndt_ready_stale = false;
   map->kept_slot = 0;
   map->kept_wide = false;
   map->scans_done = 0;
@@ -772,6 +776,7 @@ ohm_status ohm_map_create(const ohm_params* params, uint32_t region_capacity, ui
   dm.ndt = (layers & OHM_LAYER_NDT) ? reinterpret_cast<NdtVoxel*>(base + L.ndt) : nullptr;
   dm.nacc = (layers & OHM_LAYER_NDT) ? reinterpret_cast<long long*>(base + L.nacc) : nullptr;
   dm.mom = (layers & OHM_LAYER_NDT) ? reinterpret_cast<double*>(base + L.mom) : nullptr;
+  dm.ndt_ready = (layers & OHM_LAYER_NDT) ? reinterpret_cast<uint32_t*>(base + L.ndt_ready) : nullptr;
   dm.clampscan = (layers & OHM_LAYER_ADJOINT) ? reinterpret_cast<uint32_t*>(base + L.clampscan) : nullptr;
   const bool has_mean = (layers & OHM_LAYER_MEAN) != 0, has_decay = (layers & OHM_LAYER_DECAY) != 0;
   dm.mean = has_mean ? reinterpret_cast<unsigned long long*>(base + L.mean) : nullptr;
@@ -818,6 +823,7 @@ ohm_status ohm_map_set_params(ohm_map map, const ohm_params* params) {
     if (params->map_origin[a] != o.map_origin[a] || params->key_min[a] != o.key_min[a] ||
         params->key_max[a] != o.key_max[a])
       return OHM_E_INVALID_ARG;
+  if (map->dm.ndt && params->ndt_min_samples != map->params.ndt_min_samples) map->ndt_ready_stale = true;
   map->params = *params;
   fill_params(map->dm, params);
   return OHM_OK;

@@ -76,6 +76,11 @@ __device__ __forceinline__ double ndt_delta(const DevMap& m, const double o[3], 
   return log(p / (1.0 - p));
 }
 
+// Whether voxel v holds at least ndt_min_samples samples (its ready bit).
+__device__ __forceinline__ bool ndt_is_ready(const DevMap& m, size_t v) {
+  return ((m.ndt_ready[v >> 5] >> (v & 31u)) & 1u) != 0u;
+}
+
 // Phase 1 over a tile of 256 rays, walked segment by segment (see
 // ohm_walk_seg.h): the same per-voxel work as the occupancy walk, with the
 // NDT-weighted miss increment and the hit's sample moments.
@@ -232,9 +237,11 @@ __global__ __launch_bounds__(kNdtMaxThreads, 4) void ndt_seg_kernel(DevMap m, co
       lidx = local_index(s.k[0], s.k[1], s.k[2]);
     }
     const long long q_plain = llrint((double)m.l_miss * wt * kQ32);
-    // sample count of the voxel being visited, loaded one step ahead so the
-    // load's latency overlaps the previous voxel's update work
-    uint32_t cnt = (alive && slot >= 0) ? m.ndt[(size_t)slot * kRegionVoxels + lidx].n : 0u;
+    // whether the voxel being visited holds enough samples for its Gaussian,
+    // from the per-region bit mask (4 KB per region, cache-resident, where
+    // the 40-byte statistics are not), loaded one step ahead so the load's
+    // latency overlaps the previous voxel's update work
+    bool ready = (alive && slot >= 0) && ndt_is_ready(m, (size_t)slot * kRegionVoxels + lidx);
     while (__ballot(alive)) {
       const bool last = alive && s.w.total == 0;
       const bool is_hit = last && !trunc;
@@ -247,7 +254,7 @@ __global__ __launch_bounds__(kNdtMaxThreads, 4) void ndt_seg_kernel(DevMap m, co
       if (has) {
         if (is_hit) {
           q = llrint(wt * kQ32);
-        } else if (cnt >= m.ndt_min_samples) {
+        } else if (ready) {
           deferred = true;
         } else {
           q = q_plain;
@@ -264,7 +271,7 @@ __global__ __launch_bounds__(kNdtMaxThreads, 4) void ndt_seg_kernel(DevMap m, co
         }
         alive = !last && tile_advance<true>(m, rc, rw, s, M, slot, lidx);
       }
-      const uint32_t cnt_next = (alive && slot >= 0) ? m.ndt[(size_t)slot * kRegionVoxels + lidx].n : 0u;
+      const bool ready_next = (alive && slot >= 0) && ndt_is_ready(m, (size_t)slot * kRegionVoxels + lidx);
       const unsigned long long dmask = __ballot(deferred);
       if (dmask) {
         const uint32_t nd = (uint32_t)__popcll(dmask);
@@ -309,7 +316,7 @@ __global__ __launch_bounds__(kNdtMaxThreads, 4) void ndt_seg_kernel(DevMap m, co
           unsafeAtomicAdd(m.tm_mom + 2 * v + 1, in * in);
         }
       }
-      cnt = cnt_next;
+      ready = ready_next;
     }
   }
   if (pend_n)
@@ -321,6 +328,17 @@ __global__ __launch_bounds__(kNdtMaxThreads, 4) void ndt_seg_kernel(DevMap m, co
     if (k != kAggEmpty) ndt_apply<kCount>(m, k, (long long)agg_val[h]);
   }
   flush_tile_stats(m, t, n_hit, n_upd, n_drop);
+}
+
+// Recompute every ready bit from the sample counts (after ndt_min_samples
+// changed).  Each wave covers 64 consecutive voxels, two mask words.
+__global__ __launch_bounds__(256) void ndt_ready_rebuild_kernel(DevMap m) {
+  const size_t nv = (size_t)m.capacity * kRegionVoxels;
+  for (size_t v = (size_t)blockIdx.x * blockDim.x + threadIdx.x; v < nv; v += (size_t)gridDim.x * blockDim.x) {
+    const unsigned long long bal = __ballot(m.ndt[v].n >= m.ndt_min_samples);
+    const uint32_t lane = lane_id();
+    if ((lane & 31u) == 0u) m.ndt_ready[v >> 5] = (uint32_t)(bal >> lane);
+  }
 }
 
 constexpr int kNdtChunk = 1024;
@@ -350,6 +368,7 @@ __global__ __launch_bounds__(256) void ndt_finalize_kernel(DevMap m, uint32_t pa
       const float lf = (float)s;
       m.occ[v] = lf;
       NdtVoxel nv = m.ndt[v];
+      const bool was_ready = nv.n >= m.ndt_min_samples;
       bool dirty = false;
       if (lf < m.ndt_clear_below && nv.n != 0) {
         nv.n = 0;
@@ -402,7 +421,17 @@ __global__ __launch_bounds__(256) void ndt_finalize_kernel(DevMap m, uint32_t pa
         for (int c = 0; c < kMomWords; ++c) mo[c] = 0.0;
         dirty = true;
       }
-      if (dirty) m.ndt[v] = nv;
+      if (dirty) {
+        m.ndt[v] = nv;
+        const bool now_ready = nv.n >= m.ndt_min_samples;
+        if (now_ready != was_ready) {
+          uint32_t* w = m.ndt_ready + (v >> 5);
+          if (now_ready)
+            atomicOr(w, 1u << (v & 31u));
+          else
+            atomicAnd(w, ~(1u << (v & 31u)));
+        }
+      }
       ap[0] = make_longlong2(0, 0);
       ap[1] = make_longlong2(0, 0);
     }
@@ -438,6 +467,10 @@ ohm_status ndt_integrate_impl(ohm_map map, const float* d_origins, const float* 
   const bool count_mode = map->params.mode == OHM_MODE_COUNT_CLAMP;
   const bool weighted = d_weights != nullptr;
   const double sig_miss = 1.0 / (1.0 + exp(-(double)map->params.l_miss));
+  if (map->ndt_ready_stale) {
+    hipLaunchKernelGGL(ndt_ready_rebuild_kernel, dim3(8192), dim3(256), 0, st, map->dm);
+    map->ndt_ready_stale = false;
+  }
   for (uint32_t sc = 0; sc < n_scans; ++sc) {
     const uint32_t r0 = h_scan_offsets[sc];
     const uint32_t n = h_scan_offsets[sc + 1] - r0;

@@ -27,7 +27,7 @@ constexpr int kMaxLevels = 32;     // segment levels per tile (the last one abso
 constexpr int kMaxItems = kTileRays * kMaxLevels;
 
 struct SegState {
-  Walk w;
+  WalkH w;
   int32_t k[3];
   int32_t allowed;   // major crossings this segment may still apply
   uint32_t pos;      // index of the segment's first voxel in the ray's update list
@@ -122,18 +122,20 @@ __host__ __device__ __forceinline__ void seg_init(SegState& s, const int64_t q0[
     k1[a] = (int32_t)(q1[a] >> S);
     s.k[a] = k0[a];
   }
-  walk_init(s.w, q0, q1, k0, k1, m.kmin, hi, S);
+  Walk w;  // the 64-bit form while the start state is computed
+  walk_init(w, q0, q1, k0, k1, m.kmin, hi, S);
   s.allowed = seg + 1 == kMaxLevels ? 0x7fffffff : K - 1;  // the last level runs to the end
   s.pos = 0;
   s.empty = false;
+  s.w = walk_half(w, S);
   if (seg == 0) return;
   int64_t A[3], b[3];
   int32_t n[3];
   crossing_geometry(q0, q1, S, A, b, n);
   const int M = major_axis(A);
   const int64_t c = (int64_t)seg * K - 1;  // the boundary's major crossing
-  const int32_t remM = pick3(M, s.w.rem[0], s.w.rem[1], s.w.rem[2]);
-  if (c >= remM || (((s.w.clip >> M) & 1u) && c + 1 == remM)) {
+  const int32_t remM = pick3(M, w.rem[0], w.rem[1], w.rem[2]);
+  if (c >= remM || (((w.clip >> M) & 1u) && c + 1 == remM)) {
     s.empty = true;
     return;
   }
@@ -143,23 +145,24 @@ __host__ __device__ __forceinline__ void seg_init(SegState& s, const int64_t q0[
   uint32_t pos = 0;
   for (int a = 0; a < 3; ++a) {
     cnt[a] = a == M ? c + 1 : crossings_before(a, M, Nc, A, b, n, S);
-    const int32_t ra = pick3(a, s.w.rem[0], s.w.rem[1], s.w.rem[2]);
-    if (((s.w.clip >> a) & 1u) && cnt[a] >= ra) s.empty = true;  // left the map earlier
+    const int32_t ra = pick3(a, w.rem[0], w.rem[1], w.rem[2]);
+    if (((w.clip >> a) & 1u) && cnt[a] >= ra) s.empty = true;  // left the map earlier
     pos += (uint32_t)cnt[a];
   }
   if (s.empty) return;
   int64_t N[3];
   for (int a = 0; a < 3; ++a) {
     N[a] = b[a] + (cnt[a] << S);
-    s.k[a] = k0[a] + s.w.sg[a] * (int32_t)cnt[a];
+    s.k[a] = k0[a] + w.sg[a] * (int32_t)cnt[a];
   }
-  s.w.rem[0] -= (int32_t)cnt[0];
-  s.w.rem[1] -= (int32_t)cnt[1];
-  s.w.rem[2] -= (int32_t)cnt[2];
-  s.w.total -= (int32_t)pos;
-  s.w.dxy = N[0] * A[1] - N[1] * A[0];
-  s.w.dxz = N[0] * A[2] - N[2] * A[0];
-  s.w.dyz = N[1] * A[2] - N[2] * A[1];
+  w.rem[0] -= (int32_t)cnt[0];
+  w.rem[1] -= (int32_t)cnt[1];
+  w.rem[2] -= (int32_t)cnt[2];
+  w.total -= (int32_t)pos;
+  w.dxy = N[0] * A[1] - N[1] * A[0];
+  w.dxz = N[0] * A[2] - N[2] * A[0];
+  w.dyz = N[1] * A[2] - N[2] * A[1];
+  s.w = walk_half(w, S);
   s.pos = pos;
 }
 
@@ -194,6 +197,37 @@ __host__ __device__ __forceinline__ int seg_advance(SegState& s, int M) {
   s.k[1] += a == 1 ? sg : 0;
   s.k[2] += a == 2 ? sg : 0;
   return (over_budget || leaves) ? -1 : a;
+}
+
+// A box holding every voxel of a segment (keys, inclusive), from its start
+// state: the walk is monotone per axis, the segment applies at most
+// K - 1 further crossings of the major axis M, and between two major
+// crossings an axis b crosses at most ceil(A_b / A_M) + 1 times, so at most
+// ceil(K A_b / A_M) + 1 times in the segment.  The last level (no budget)
+// runs to the ray's end key (q1), which bounds it.
+__host__ __device__ __forceinline__ void seg_bounds(const SegState& s, const int64_t q0[3], const int64_t q1[3],
+                                                    int M, int K, bool last_level, int S, int32_t lo[3],
+                                                    int32_t hi[3]) {
+  int64_t A[3];
+  for (int a = 0; a < 3; ++a) {
+    const int64_t D = q1[a] - q0[a];
+    A[a] = D < 0 ? -D : D;
+  }
+  const int64_t AM = pick3(M, A[0], A[1], A[2]);
+  for (int a = 0; a < 3; ++a) {
+    int64_t span;
+    if (last_level || AM == 0) {
+      const int32_t k1 = (int32_t)(q1[a] >> S);
+      span = k1 > s.k[a] ? (int64_t)k1 - s.k[a] : (int64_t)s.k[a] - k1;
+    } else if (a == M) {
+      span = K - 1;
+    } else {
+      span = ((int64_t)K * A[a] + AM - 1) / AM + 1;
+    }
+    const int64_t end = (int64_t)s.k[a] + (int64_t)s.w.sg[a] * span;
+    lo[a] = (int32_t)(end < s.k[a] ? end : s.k[a]);
+    hi[a] = (int32_t)(end < s.k[a] ? s.k[a] : end);
+  }
 }
 
 // Major axis of a prepared ray.

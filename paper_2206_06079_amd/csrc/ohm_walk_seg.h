@@ -89,6 +89,76 @@ __device__ __forceinline__ bool agg_finish(uint32_t* keys, T* vals, uint32_t id,
   return true;
 }
 
+// The batched plan's unit-weight walk keeps a different per-tile table,
+// keyed by the 64-byte accumulator line itself: an entry holds one line's 16
+// counts (8 voxels along x, miss and hit) as 16-bit counters, two to an LDS
+// word.  A voxel is visited at most once per ray, so no count in a 256-ray
+// tile exceeds 256 and the halves never carry into each other.  A tile
+// touches 430 lines on average (p99 about 1,500) against about 1,430 update
+// ids, so 1,024 line entries hold every line of most tiles, where the id
+// table's 16-entry line groups overflow on hash collisions of lines.
+// Lookups probe up to kLineProbes consecutive entries; an update finding
+// none of them is applied to the accumulator at once.  A lane that claims an
+// entry appends it to a list, so the flush visits only the claimed entries,
+// each by 16 consecutive lanes.  (Fewer entries and fallbacks also make the
+// brick marks below cheaper; on the spinning-lidar groups the id table is
+// faster.)
+constexpr uint32_t kLineEntries = 1024;
+constexpr uint32_t kLineWords = 8;  // 16 x u16 counts per entry
+constexpr int kLineProbes = 4;
+
+__device__ __forceinline__ uint32_t line_slot(uint32_t line) {
+  return (line * 0x9E3779B1u) >> (32 - 10);
+}
+static_assert(kLineEntries == 1024u, "line_slot hashes to 10 bits");
+
+// Add `len` unit updates of id to the line table (k: the key of the first
+// probe, read earlier); false when no probed entry is, or could become, the
+// line's.  A claimed entry is appended to list[*n_list].
+__device__ __forceinline__ bool line_add(uint32_t* keys, uint32_t* cnt, uint32_t* list, uint32_t* n_list, uint32_t id,
+                                         uint32_t k, uint32_t len) {
+  const uint32_t line = id >> 4, pos = id & 15u;
+  uint32_t h = line_slot(line);
+  for (int p = 0; p < kLineProbes; ++p) {
+    if (p > 0) {
+      h = (h + 1u) & (kLineEntries - 1u);
+      k = keys[h];
+    }
+    if (k == kAggEmpty) {
+      const uint32_t old = atomicCAS(keys + h, kAggEmpty, line);
+      if (old == kAggEmpty) list[atomicAdd(n_list, 1u)] = h;
+      k = old == kAggEmpty ? line : old;
+    }
+    if (k == line) {
+      atomicAdd(cnt + h * kLineWords + (pos >> 1), len << (16u * (pos & 1u)));
+      return true;
+    }
+  }
+  return false;
+}
+
+// Per-tile record of the bricks that received counts (the batched plan's
+// walks, whose finalize reads only the slots a brick received): region slot
+// -> 64-bit brick mask in LDS, flushed with one global OR per region the
+// tile reached.  Linear probing over kBrickEntries; a region finding no
+// entry ORs its bit into the global mask at once.
+constexpr uint32_t kBrickEntries = 256;
+constexpr int kBrickProbes = 8;
+
+__device__ __forceinline__ void brick_mark(const DevMap& m, uint32_t* keys, unsigned long long* masks, uint32_t voxel) {
+  const uint32_t slot = voxel >> 15;
+  const unsigned long long bit = 1ull << brick_of(voxel & (uint32_t)(kRegionVoxels - 1));
+  uint32_t h = (slot * 0x9E3779B1u) >> 24;
+  for (int p = 0; p < kBrickProbes; ++p) {
+    if (agg_own(keys, h, slot, keys[h])) {
+      atomicOr(masks + h, bit);
+      return;
+    }
+    h = (h + 1u) & (kBrickEntries - 1u);
+  }
+  atomicOr(m.brick_mask + slot, bit);
+}
+
 // Clamp-add a wave's queued (update id, summed weight) pairs, one per lane.
 __device__ __forceinline__ void drain_cas(const DevMap& m, const uint32_t* qid, const float* qv, uint32_t n,
                                           uint32_t lane) {
@@ -281,8 +351,11 @@ __device__ __forceinline__ void flush_tile_stats(const DevMap& m, const TileRay&
 // Occupancy walk of the tile of rays [tile0, tile0 + kTileRays) of a scan
 // (n rays from r0): count or per-update sinks, or the trace outputs.  With
 // kLayers the voxel mean and decay-rate layers the map holds are updated
-// too (ohm_layers.h).  Every thread of the block must call it.
-template <int kSink, bool kWeighted, bool kLayers = false>
+// too (ohm_layers.h); with kBricks (count sink) the bricks that received
+// counts are marked in m.brick_mask, and with kLineTable (unit-weight count
+// sink) updates aggregate in the line table instead of the id table.  Every
+// thread of the block must call it.
+template <int kSink, bool kWeighted, bool kLayers = false, bool kBricks = false, bool kLineTable = false>
 __device__ void walk_tile(const DevMap& m, const float* __restrict__ origin, const float* __restrict__ samples,
                           const float* __restrict__ weights, const uint32_t* __restrict__ perm, uint32_t r0,
                           uint32_t n, uint32_t tile0, int K,
@@ -291,15 +364,22 @@ __device__ void walk_tile(const DevMap& m, const float* __restrict__ origin, con
                           int32_t* __restrict__ updates) {
   constexpr bool kAccum = kSink == kSinkCount || kSink == kSinkCas;
   constexpr int kStage = kSink == kSinkCount ? kStageTouch : (kSink == kSinkCas ? kStageResolve : kStageNone);
-  constexpr bool kAgg = kAccum;
+  constexpr bool kLine = kLineTable && kSink == kSinkCount && !kWeighted;
+  constexpr bool kAgg = kAccum && !kLine;
   // weighted count mode sums Q32.32 integers (order-independent, exact up to
   // the 2^-33 rounding of each weight) into the wide accumulators
   constexpr bool kWide = kSink == kSinkCount && kWeighted;
   using AggT = std::conditional_t<kWide, unsigned long long, float>;
   __shared__ TileRays tr;
   __shared__ RegionCache rc;
-  __shared__ uint32_t agg_key[kAgg ? kAggSize : 1];
+  __shared__ uint32_t agg_key[kAgg ? kAggSize : (kLine ? kLineEntries : 1)];
   __shared__ AggT agg_val[kAgg ? kAggSize : 1];
+  static_assert(!kBricks || kSink == kSinkCount, "brick marks are for count walks");
+  __shared__ uint32_t line_cnt[kLine ? kLineEntries * kLineWords : 1];
+  __shared__ uint32_t line_list[kLine ? kLineEntries : 1];  // claimed entries, in claim order
+  __shared__ uint32_t line_n;
+  __shared__ uint32_t bk_key[kBricks ? kBrickEntries : 1];
+  __shared__ unsigned long long bk_mask[kBricks ? kBrickEntries : 1];
   // per-update mode: table misses queued per wave, clamp-added 64 at a time
   // (a compare-and-swap waits for its reply; one wave-wide batch shares it)
   constexpr bool kQueue = kSink == kSinkCas;
@@ -312,6 +392,16 @@ __device__ void walk_tile(const DevMap& m, const float* __restrict__ origin, con
     for (uint32_t h = tid; h < kAggSize; h += blockDim.x) {
       agg_key[h] = kAggEmpty;
       agg_val[h] = AggT(0);
+    }
+  if (kLine) {
+    if (tid == 0) line_n = 0u;
+    for (uint32_t h = tid; h < kLineEntries; h += blockDim.x) agg_key[h] = kAggEmpty;
+    for (uint32_t h = tid; h < kLineEntries * kLineWords; h += blockDim.x) line_cnt[h] = 0u;
+  }
+  if (kBricks)
+    for (uint32_t h = tid; h < kBrickEntries; h += blockDim.x) {
+      bk_key[h] = kAggEmpty;
+      bk_mask[h] = 0ull;
     }
   TileRay t;
   RegionWindow rw;
@@ -388,7 +478,7 @@ __device__ void walk_tile(const DevMap& m, const float* __restrict__ origin, con
         }
         // read the table entry now, step the walk on, then use it: the LDS
         // read's latency overlaps the step's arithmetic
-        const uint32_t k = emit_here ? agg_key[agg_slot(id)] : 0u;
+        const uint32_t k = emit_here ? agg_key[kLine ? line_slot(id >> 4) : agg_slot(id)] : 0u;
         // updates and hits are counted per ray below; only drops (region
         // pool exhausted) are counted here
         if (alive && !has) {
@@ -409,7 +499,13 @@ __device__ void walk_tile(const DevMap& m, const float* __restrict__ origin, con
           }
         }
         if (alive) alive = !last && tile_advance<kAccum>(m, rc, rw, s, M, slot, lidx);
-        const bool miss_table = emit_here && !agg_finish(agg_key, agg_val, id, k, v);
+        bool miss_table;
+        if constexpr (kLine) {
+          miss_table = emit_here && !line_add(agg_key, line_cnt, line_list, &line_n, id, k, run.len);
+        } else {
+          miss_table = emit_here && !agg_finish(agg_key, agg_val, id, k, v);
+        }
+        if (kBricks && miss_table) brick_mark(m, bk_key, bk_mask, id >> 1);
         if constexpr (kWide) {
           if (miss_table) atomicAdd(reinterpret_cast<unsigned long long*>(m.acc) + id, v);
         } else if constexpr (kSink == kSinkCount) {
@@ -446,6 +542,20 @@ __device__ void walk_tile(const DevMap& m, const float* __restrict__ origin, con
   }
   if (kSink == kSinkTraceCount || kSink == kSinkTraceWrite) return;
   if (kQueue && cq_n) drain_cas(m, cq_id[tid >> 6], cq_v[tid >> 6], cq_n, lane);
+  if (kLine) {
+    __syncthreads();
+    // 16 lanes per claimed line: one wave instruction reaches four
+    // accumulator lines
+    const uint32_t pos = tid & 15u;
+    const uint32_t n_lines = line_n;
+    for (uint32_t e = tid >> 4; e < n_lines; e += blockDim.x >> 4) {
+      const uint32_t h = line_list[e];
+      const uint32_t line = agg_key[h];
+      const uint32_t c = (line_cnt[h * kLineWords + (pos >> 1)] >> (16u * (pos & 1u))) & 0xFFFFu;
+      if (c) unsafeAtomicAdd(m.acc + (line << 4) + pos, (float)c);
+      if (kBricks && pos == 0u) brick_mark(m, bk_key, bk_mask, line << 3);
+    }
+  }
   if (kAgg) {
     __syncthreads();
     if constexpr (kSink == kSinkCount) {
@@ -456,6 +566,7 @@ __device__ void walk_tile(const DevMap& m, const float* __restrict__ origin, con
         } else {
           if (k != kAggEmpty) unsafeAtomicAdd(m.acc + k, agg_val[h]);
         }
+        if (kBricks && k != kAggEmpty) brick_mark(m, bk_key, bk_mask, k >> 1);
       }
     } else {
       // clamp-adds by compare-and-swap, four entries in flight per thread:
@@ -489,6 +600,13 @@ __device__ void walk_tile(const DevMap& m, const float* __restrict__ origin, con
           if (!any) break;
         }
       }
+    }
+  }
+  if (kBricks) {
+    __syncthreads();
+    for (uint32_t h = tid; h < kBrickEntries; h += blockDim.x) {
+      const uint32_t slot = bk_key[h];
+      if (slot != kAggEmpty) atomicOr(m.brick_mask + slot, bk_mask[h]);
     }
   }
   // every voxel a ray visits is an update unless dropped; a ray that ends

@@ -2,7 +2,8 @@
 // segments of every length K, walked with the same header code the kernels
 // run, must concatenate to the canonical exact walk -- same keys, same hit
 // flag on the last voxel, segment start positions equal to the voxels
-// before them -- and every key must lie inside the map bounds.
+// before them -- every key must lie inside the map bounds, and every
+// segment's voxels inside the box seg_bounds gives for it.
 //
 // usage: seg_walk_check <seed> <rays> ; prints "ok <rays> <voxels>" or the
 // first mismatch, exit status 0 only when every check holds.
@@ -128,12 +129,19 @@ int main(int argc, char** argv) {
         seg_init(s, q0, q1, m, (int)j, K);
         if (s.empty) continue;
         if (s.pos != got.size()) return fail("segment start position", ray, K, q0, q1, (long)j);
+        // every voxel of the segment lies in its seg_bounds box
+        int32_t blo[3], bhi[3];
+        seg_bounds(s, q0, q1, M, K, j + 1 == (uint32_t)kMaxLevels, m.F, blo, bhi);
+        const size_t first = got.size();
         got.push_back({{s.k[0], s.k[1], s.k[2]}, s.w.total == 0});
         while (s.w.total > 0) {
           if (seg_advance(s, M) < 0) break;
           got.push_back({{s.k[0], s.k[1], s.k[2]}, s.w.total == 0});
           if (got.size() > ref.size()) return fail("segments overrun the walk", ray, K, q0, q1, (long)j);
         }
+        for (size_t i = first; i < got.size(); ++i)
+          for (int a = 0; a < 3; ++a)
+            if (got[i].k[a] < blo[a] || got[i].k[a] > bhi[a]) return fail("segment outside its bounds", ray, K, q0, q1, (long)j);
       }
       if (got.size() != ref.size()) return fail("voxel count", ray, K, q0, q1, (long)got.size());
       for (size_t i = 0; i < ref.size(); ++i)

@@ -105,3 +105,27 @@ def test_ndt_small_map_first_scan_equals_plain():
     o_occ, _, _, _ = oracle.integrate_count(mp, batch)
     k = update_counts(mp, batch, box_min, box_dim)
     assert np.all(np.abs(g["occ"] - o_occ) <= 1e-5 + k * 2.0 ** -33)
+
+
+def test_ndt_threshold_change_between_calls():
+    """Changing ndt_min_samples between calls (ohm_map_set_params) applies the
+    new threshold to every voxel's existing samples in the next call."""
+    mp, batch = scenes.config2(n_scans=4, first_scan=50)
+    m = ohm.OhmMap(mp, 1024, layers=ohm.LAYER_NDT, device=device())
+    o, s, off, w = to_dev(batch.scans(0, 2))
+    m.ndt_integrate(o, s, off, w)
+    mp3 = mp.replace(ndt_min_samples=3)
+    m.set_params(mp3)
+    o, s, off, w = to_dev(batch.scans(2, 2))
+    m.ndt_integrate(o, s, off, w)
+    occ = m.read_dense(ohm.READ_OCC, CFG1_BOX_MIN, CFG1_BOX_DIM).cpu().numpy()
+    n = m.read_dense(ohm.READ_NDT_COUNT, CFG1_BOX_MIN, CFG1_BOX_DIM).cpu().numpy().astype(np.uint32)
+    m.close()
+    o_occ, o_state, _, _ = oracle.ndt_integrate(mp, batch.scans(0, 2), CFG1_BOX_MIN, CFG1_BOX_DIM, mode=1)
+    o_occ, o_state, _, _ = oracle.ndt_integrate(mp3, batch.scans(2, 2), CFG1_BOX_MIN, CFG1_BOX_DIM, occ=o_occ,
+                                                state=o_state, mode=1)
+    assert np.array_equal(n, o_state.n)
+    k = update_counts(mp, batch, CFG1_BOX_MIN, CFG1_BOX_DIM)
+    assert np.all(np.abs(occ.astype(np.float64) - o_occ) <= 1e-5 + k * 2.0 ** -33)
+    # voxels holding exactly 3 samples after the first two scans take weighted misses now
+    assert (o_state.n == 3).sum() > 100

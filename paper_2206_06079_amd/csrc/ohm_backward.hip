@@ -63,13 +63,28 @@ __global__ __launch_bounds__(256) void clear_box_stats_kernel(DevMap m, GradBox 
   m.ndt[(size_t)slot * kRegionVoxels + local_index(x, y, z)] = NdtVoxel{};
 }
 
-__device__ __forceinline__ float grad_at(const GradBox& gb, int32_t x, int32_t y, int32_t z) {
-  const int32_t dx = x - gb.bmin[0], dy = y - gb.bmin[1], dz = z - gb.bmin[2];
-  if ((uint32_t)dx >= (uint32_t)gb.bdim[0] || (uint32_t)dy >= (uint32_t)gb.bdim[1] ||
-      (uint32_t)dz >= (uint32_t)gb.bdim[2])
-    return 0.f;
-  return gb.g[((size_t)dz * gb.bdim[1] + dy) * gb.bdim[0] + dx];
+// What the gradient needs of one visited voxel, loaded together: its
+// upstream gradient, clamp record and (NDT) sample count.  Voxels outside
+// the loss box have zero gradient and load nothing.
+struct VisitData {
+  float G;
+  uint32_t clamp;  // last scan whose pre-clamp value left the clamp range
+  uint32_t n;      // NDT sample count
+};
+
+template <bool kNdt>
+__device__ __forceinline__ VisitData visit_data(const DevMap& m, const GradBox& gb, bool alive, int32_t slot,
+                                                uint32_t lidx, int32_t x, int32_t y, int32_t z) {
+  VisitData d = {0.f, 0u, 0u};
+  if (alive && slot >= 0 && in_box(gb, x, y, z)) {
+    const size_t v = (size_t)slot * kRegionVoxels + lidx;
+    d.G = gb.g[((size_t)(z - gb.bmin[2]) * gb.bdim[1] + (y - gb.bmin[1])) * gb.bdim[0] + (x - gb.bmin[0])];
+    d.clamp = m.clampscan[v];
+    if (kNdt) d.n = m.ndt[v].n;
+  }
+  return d;
 }
+
 
 // NDT miss increment and its derivatives with respect to l_miss and sigma_n.
 __device__ void ndt_terms(const DevMap& m, const double o[3], const double d[3], double dd, const double c[3],
@@ -155,9 +170,9 @@ __device__ __forceinline__ void bwd_drain(const DevMap& m, const BwdPending* pen
 // One tile of 256 rays, walked segment by segment (see ohm_walk_seg.h).  A
 // ray's weight gradient is the sum over its segments (fp64 LDS atomics);
 // the scalar gradients are reduced per block.  `tag` is the scan's 1-based
-// index (compared with the clamp record); with kNdt the hit samples are
-// accumulated for the statistics replay, and the touched regions listed
-// under (fold_tag, fold_parity) for the fold that follows.
+// index (compared with the clamp record); with kNdt the touched regions are
+// listed under (fold_tag, fold_parity) for the statistics replay that
+// follows (the scan's hit samples in the box, then the fold).
 template <bool kNdt, bool kWeighted>
 __global__ __launch_bounds__(kBackwardMaxThreads, 4) void backward_seg_kernel(
     DevMap m, GradBox gb, const float* __restrict__ origins, uint32_t scan, const float* __restrict__ samples,
@@ -221,30 +236,26 @@ __global__ __launch_bounds__(kBackwardMaxThreads, 4) void backward_seg_kernel(
       lidx = local_index(s.k[0], s.k[1], s.k[2]);
     }
     double gw = 0.0;
+    // the current voxel's gradient data, loaded one step ahead so the loads'
+    // latency overlaps the previous voxel's work
+    VisitData vd = visit_data<kNdt>(m, gb, alive, slot, lidx, s.k[0], s.k[1], s.k[2]);
     while (__ballot(alive)) {
       bool deferred = false;
-      float G = 0.f;
+      const float G = vd.G;
       size_t v = 0;
       const int32_t k0 = s.k[0], k1 = s.k[1], k2 = s.k[2];
       bool last = false;
       if (alive) {
         last = s.w.total == 0;
         const bool is_hit = last && !trunc;
-        if (kNdt && is_hit && slot >= 0 && in_box(gb, k0, k1, k2)) {
-          // the statistics replay, for the voxels whose statistics the
-          // gradient reads (the box's): this sample's moments, as the forward adds them
-          const int32_t kh[3] = {k0, k1, k2};
-          ndt_add_sample(m, (size_t)slot * kRegionVoxels + lidx, samples + 3 * ((size_t)r0 + tr.src[ray_t]), kh);
-        }
-        G = grad_at(gb, k0, k1, k2);
         if (G != 0.f && slot >= 0) {
           v = (size_t)slot * kRegionVoxels + lidx;
-          if (tag > m.clampscan[v]) {
+          if (tag > vd.clamp) {
             const double Gd = (double)G;
             if (is_hit) {
               gw += Gd * (double)m.l_hit;
               g_hit += wt * Gd;
-            } else if (kNdt && m.ndt[v].n >= m.ndt_min_samples) {
+            } else if (kNdt && vd.n >= m.ndt_min_samples) {
               deferred = true;
             } else {
               gw += Gd * (double)m.l_miss;
@@ -255,6 +266,7 @@ __global__ __launch_bounds__(kBackwardMaxThreads, 4) void backward_seg_kernel(
         alive = !last && tile_advance<true>(m, rc, rw, s, M, slot, lidx);
         if (!alive && gw != 0.0) atomicAdd(&ray_gw[ray_t], gw);
       }
+      vd = visit_data<kNdt>(m, gb, alive, slot, lidx, s.k[0], s.k[1], s.k[2]);
       if (kNdt) {
         const unsigned long long dmask = __ballot(deferred);
         if (dmask) {
@@ -385,6 +397,18 @@ extern "C" ohm_status ohm_backward(ohm_map map, int32_t ndt, const float* d_grad
           hipLaunchKernelGGL((backward_seg_kernel<false, false>), tiles, threads, 0, st, bm, gb, d_origins, sc,
                              d_samples, d_weights, r0, n, K, tag, 0u, 0u, d_grad_weights, d_grad_scalars, sig_miss);
       }
+    }
+    if (ndt) {
+      // the statistics replay, for the voxels whose statistics the gradient
+      // reads (the box's): the scan's hit samples there, as the forward adds them
+      ProfScope ps(map, OHM_KERNEL_NDT_HIT, st);
+      HitBox box;
+      for (int a = 0; a < 3; ++a) {
+        const int64_t hi = (int64_t)gb.bmin[a] + gb.bdim[a];
+        box.lo[a] = gb.bmin[a];
+        box.hi[a] = hi > INT32_MAX ? INT32_MAX : (int32_t)hi;
+      }
+      launch_ndt_hits(bm, st, d_origins, sc, d_samples, d_weights, nullptr, r0, n, box);
     }
     if (ndt) {
       // fold only: the accumulators hold no increments, so occupancy is unchanged

@@ -88,6 +88,7 @@ struct DevMap {
   float* acc;         // [capacity][V][2]: miss weight, hit weight
   NdtVoxel* ndt;      // [capacity][V] or null
   uint32_t* ndt_ready;  // [capacity][V / 32]: bit set where the voxel holds >= ndt_min_samples samples
+  unsigned long long* ndt_ready_bricks;  // [capacity]: bit b set when brick b of the region may hold a ready voxel
   long long* nacc;    // NDT per-scan accumulators [capacity][V][kNaccWords] or null
   double* mom;        // NDT per-scan sample moments [capacity][V][kMomWords] or null
   uint32_t* clampscan;// [capacity][V] or null
@@ -380,6 +381,11 @@ __device__ __forceinline__ uint32_t local_index(int32_t kx, int32_t ky, int32_t 
   return ((uint32_t)(kz & kRegionMask) << (2 * kRegionLog2)) | ((uint32_t)(ky & kRegionMask) << kRegionLog2) |
          (uint32_t)(kx & kRegionMask);
 }
+
+// A box of voxel keys, [lo, hi) per axis.
+struct HitBox {
+  int32_t lo[3], hi[3];
+};
 
 // Slot of the region holding key k (negative when not allocated).
 __device__ __forceinline__ int32_t lookup_slot(const DevMap& m, int32_t kx, int32_t ky, int32_t kz) {

@@ -89,6 +89,12 @@ ohm_status map_initialise(ohm_map_s* map, hipStream_t st);
 ohm_status check_scans(ohm_map map, const float* d_origins, const float* d_samples, const uint32_t* h_offsets,
                        uint32_t n_scans);
 void clear_pending(ohm_map_s* map, hipStream_t st, bool prof = true);
+// Add the hit samples of one scan (n rays from r0, origin `scan`) whose end
+// voxels lie in `box` to the per-scan NDT moments and sample counts (and,
+// with intensities and an NDT-TM layer, the intensity sums), after the
+// scan's walk; weights (or null) as given to the walk.
+void launch_ndt_hits(const DevMap& m, hipStream_t st, const float* origins, uint32_t scan, const float* samples,
+                     const float* weights, const float* intensities, uint32_t r0, uint32_t n, HitBox box);
 // Brackets one kernel launch with HIP events when profiling is enabled.
 class ProfScope {
  public:

@@ -81,6 +81,14 @@ __device__ __forceinline__ bool ndt_is_ready(const DevMap& m, size_t v) {
   return ((m.ndt_ready[v >> 5] >> (v & 31u)) & 1u) != 0u;
 }
 
+// The same, with the 64 brick bits of v's region (rb: which 8^3 bricks may
+// hold a ready voxel, kept in registers per region) tested first: in free
+// space no bit is set and nothing is loaded.
+__device__ __forceinline__ bool ndt_ready_at(const DevMap& m, unsigned long long rb, int32_t slot, uint32_t lidx) {
+  if (slot < 0 || !((rb >> brick_of(lidx)) & 1ull)) return false;
+  return ndt_is_ready(m, (size_t)slot * kRegionVoxels + lidx);
+}
+
 // Phase 1 over a tile of 256 rays, walked segment by segment (see
 // ohm_walk_seg.h): the same per-voxel work as the occupancy walk, with the
 // NDT-weighted miss increment and the hit's sample moments.
@@ -241,12 +249,15 @@ __global__ __launch_bounds__(kNdtMaxThreads, 4) void ndt_seg_kernel(DevMap m, co
     // from the per-region bit mask (4 KB per region, cache-resident, where
     // the 40-byte statistics are not), loaded one step ahead so the load's
     // latency overlaps the previous voxel's update work
-    bool ready = (alive && slot >= 0) && ndt_is_ready(m, (size_t)slot * kRegionVoxels + lidx);
+    // the brick bits of the region being walked (reloaded when the walk
+    // crosses into another region)
+    int32_t rb_slot = (alive && slot >= 0) ? slot : -1;
+    unsigned long long rb = rb_slot >= 0 ? m.ndt_ready_bricks[rb_slot] : 0ull;
+    bool ready = alive && ndt_ready_at(m, rb, slot, lidx);
     while (__ballot(alive)) {
       const bool last = alive && s.w.total == 0;
       const bool is_hit = last && !trunc;
       const bool has = alive && slot >= 0;
-      const size_t v = has ? (size_t)slot * kRegionVoxels + lidx : 0;
       const int32_t k0 = s.k[0], k1 = s.k[1], k2 = s.k[2];  // this voxel (the walk steps on below)
       long long q = 0;
       // a miss whose increment the voxel's samples weight: queued, see NdtPending
@@ -271,7 +282,11 @@ __global__ __launch_bounds__(kNdtMaxThreads, 4) void ndt_seg_kernel(DevMap m, co
         }
         alive = !last && tile_advance<true>(m, rc, rw, s, M, slot, lidx);
       }
-      const bool ready_next = (alive && slot >= 0) && ndt_is_ready(m, (size_t)slot * kRegionVoxels + lidx);
+      if (alive && slot >= 0 && slot != rb_slot) {
+        rb_slot = slot;
+        rb = m.ndt_ready_bricks[slot];
+      }
+      const bool ready_next = alive && ndt_ready_at(m, rb, slot, lidx);
       const unsigned long long dmask = __ballot(deferred);
       if (dmask) {
         const uint32_t nd = (uint32_t)__popcll(dmask);
@@ -306,16 +321,7 @@ __global__ __launch_bounds__(kNdtMaxThreads, 4) void ndt_seg_kernel(DevMap m, co
         emit = has && run.tail && !deferred;
       }
       if (emit && !ndt_agg_add(agg_key, agg_val, id, qs)) ndt_apply<kCount>(m, id, qs);
-      if (has && is_hit) {
-        // the sample's moments (fp64, voxel-centred: x = sample - centre)
-        const int32_t kh[3] = {k0, k1, k2};
-        ndt_add_sample(m, v, samples + 3 * ray, kh);
-        if (kTm) {
-          const double in = (double)intensities[ray];
-          unsafeAtomicAdd(m.tm_mom + 2 * v, in);
-          unsafeAtomicAdd(m.tm_mom + 2 * v + 1, in * in);
-        }
-      }
+      // (the hit sample's moments are added by ndt_hit_kernel)
       ready = ready_next;
     }
   }
@@ -330,14 +336,142 @@ __global__ __launch_bounds__(kNdtMaxThreads, 4) void ndt_seg_kernel(DevMap m, co
   flush_tile_stats(m, t, n_hit, n_upd, n_drop);
 }
 
+// Sample moments of a scan's hits, after its walk (which adds each hit's
+// occupancy increment): each hit sample whose voxel lies in the key box
+// [lo, hi) joins the voxel's per-scan moments and sample count, and for
+// NDT-TM its intensity sums.  A block takes
+// kHitBlockRays consecutive rays of the scan.  Neighbouring beams often end
+// in one voxel (a block of 1024 rays of a spinning lidar holds about a fifth
+// as many distinct hit voxels as hits), so a block sums its hits per voxel
+// in LDS and sends each voxel's totals to memory once: about a fifth of the
+// fp64 atomics of adding every sample on its own, which otherwise bound the
+// NDT pass.  The sums are fp64 in any order (as the walk's were).
+constexpr uint32_t kHitBlockRays = 1024;
+constexpr uint32_t kHitThreads = 512;
+constexpr int kHitTableLog2 = 10;
+constexpr uint32_t kHitTableSize = 1u << kHitTableLog2;  // >= the block's rays: every hit voxel finds an entry
+static_assert(kHitTableSize >= kHitBlockRays, "a block's hit voxels must all fit the table");
+
+template <bool kWeighted, bool kTm>
+__global__ __launch_bounds__(kHitThreads) void ndt_hit_kernel(DevMap m, const float* __restrict__ origins,
+                                                              uint32_t scan, const float* __restrict__ samples,
+                                                              const float* __restrict__ weights,
+                                                              const float* __restrict__ intensities, uint32_t r0,
+                                                              uint32_t n, HitBox box) {
+#pragma clang fp contract(off)
+  constexpr int kSums = kTm ? 11 : 9;  // x (3), x x^T (6), then intensity and its square
+  __shared__ uint32_t key[kHitTableSize];
+  __shared__ uint32_t cnt[kHitTableSize];
+  __shared__ double sum[kSums][kHitTableSize];
+  const uint32_t tid = threadIdx.x;
+  for (uint32_t h = tid; h < kHitTableSize; h += kHitThreads) {
+    key[h] = kAggEmpty;
+    cnt[h] = 0u;
+    for (int c = 0; c < kSums; ++c) sum[c][h] = 0.0;
+  }
+  __syncthreads();
+  const float o[3] = {origins[3 * (size_t)scan], origins[3 * (size_t)scan + 1], origins[3 * (size_t)scan + 2]};
+  for (uint32_t j = 0; j < kHitBlockRays / kHitThreads; ++j) {
+    const uint32_t i = blockIdx.x * kHitBlockRays + j * kHitThreads + tid;
+    if (i >= n) break;
+    const size_t ray = (size_t)r0 + i;
+    const float e[3] = {samples[3 * ray], samples[3 * ray + 1], samples[3 * ray + 2]};
+    // the same ray preparation and checks as the walk: a hit is a valid,
+    // untruncated ray whose end voxel lies in the map, in an allocated region
+    Ray r;
+    int st = prepare_ray(m, o, e, r);
+    if (kWeighted) {
+      const float w = weights[ray];
+      if (!(w >= 0.f) || !__builtin_isfinite(w)) st = kRayInvalid;
+    }
+    if (st != kRayOk || r.truncated) continue;
+    bool inside = true;
+    for (int a = 0; a < 3; ++a) inside = inside && r.k1[a] >= m.kmin[a] && r.k1[a] < m.kmax[a];
+    for (int a = 0; a < 3; ++a) inside = inside && r.k1[a] >= box.lo[a] && r.k1[a] < box.hi[a];
+    if (!inside) continue;
+    const int32_t slot = lookup_slot(m, r.k1[0], r.k1[1], r.k1[2]);
+    if (slot < 0) continue;  // the walk dropped the hit too (pool exhausted)
+    const uint32_t v = (uint32_t)slot * (uint32_t)kRegionVoxels + local_index(r.k1[0], r.k1[1], r.k1[2]);
+    // voxel-centred sample: x = sample - centre
+    double x[3];
+    for (int a = 0; a < 3; ++a) x[a] = (double)e[a] - (m.origin[a] + ((double)r.k1[a] + 0.5) * m.voxel_size);
+    double terms[kSums];
+    terms[0] = x[0];
+    terms[1] = x[1];
+    terms[2] = x[2];
+    terms[3] = x[0] * x[0];
+    terms[4] = x[0] * x[1];
+    terms[5] = x[0] * x[2];
+    terms[6] = x[1] * x[1];
+    terms[7] = x[1] * x[2];
+    terms[8] = x[2] * x[2];
+    if (kTm) {
+      const double in = (double)intensities[ray];
+      terms[kSums - 2] = in;
+      terms[kSums - 1] = in * in;
+    }
+    // linear probing over the whole table: at most kHitTableSize distinct
+    // voxels, so the probe always ends at the voxel's entry
+    uint32_t h = (v * 0x9E3779B1u) >> (32 - kHitTableLog2);
+    for (uint32_t p = 0; p < kHitTableSize; ++p) {
+      uint32_t k = key[h];
+      if (k == kAggEmpty) {
+        const uint32_t old = atomicCAS(key + h, kAggEmpty, v);
+        k = old == kAggEmpty ? v : old;
+      }
+      if (k == v) break;
+      h = (h + 1u) & (kHitTableSize - 1u);
+    }
+    atomicAdd(cnt + h, 1u);
+    for (int c = 0; c < kSums; ++c) atomicAdd(&sum[c][h], terms[c]);
+  }
+  __syncthreads();
+  for (uint32_t h = tid; h < kHitTableSize; h += kHitThreads) {
+    const uint32_t v = key[h];
+    if (v == kAggEmpty) continue;
+    double* mo = m.mom + (size_t)v * kMomWords;
+    for (int c = 0; c < 9; ++c) unsafeAtomicAdd(mo + c, sum[c][h]);
+    atomicAdd(reinterpret_cast<unsigned long long*>(m.nacc + (size_t)v * kNaccWords + kNaccSamples),
+              (unsigned long long)cnt[h]);
+    if (kTm) {
+      unsafeAtomicAdd(m.tm_mom + 2 * (size_t)v, sum[kSums - 2][h]);
+      unsafeAtomicAdd(m.tm_mom + 2 * (size_t)v + 1, sum[kSums - 1][h]);
+    }
+  }
+}
+
+void launch_ndt_hits(const DevMap& m, hipStream_t st, const float* origins, uint32_t scan, const float* samples,
+                     const float* weights, const float* intensities, uint32_t r0, uint32_t n, HitBox box) {
+  if (n == 0) return;
+  const dim3 blocks((n + kHitBlockRays - 1) / kHitBlockRays);
+  const bool tm = intensities != nullptr && m.tm_mom != nullptr;
+  if (weights) {
+    if (tm)
+      hipLaunchKernelGGL((ndt_hit_kernel<true, true>), blocks, dim3(kHitThreads), 0, st, m, origins, scan, samples,
+                         weights, intensities, r0, n, box);
+    else
+      hipLaunchKernelGGL((ndt_hit_kernel<true, false>), blocks, dim3(kHitThreads), 0, st, m, origins, scan, samples,
+                         weights, intensities, r0, n, box);
+  } else {
+    if (tm)
+      hipLaunchKernelGGL((ndt_hit_kernel<false, true>), blocks, dim3(kHitThreads), 0, st, m, origins, scan, samples,
+                         weights, intensities, r0, n, box);
+    else
+      hipLaunchKernelGGL((ndt_hit_kernel<false, false>), blocks, dim3(kHitThreads), 0, st, m, origins, scan, samples,
+                         weights, intensities, r0, n, box);
+  }
+}
+
 // Recompute every ready bit from the sample counts (after ndt_min_samples
 // changed).  Each wave covers 64 consecutive voxels, two mask words.
 __global__ __launch_bounds__(256) void ndt_ready_rebuild_kernel(DevMap m) {
   const size_t nv = (size_t)m.capacity * kRegionVoxels;
   for (size_t v = (size_t)blockIdx.x * blockDim.x + threadIdx.x; v < nv; v += (size_t)gridDim.x * blockDim.x) {
-    const unsigned long long bal = __ballot(m.ndt[v].n >= m.ndt_min_samples);
+    const bool ready = m.ndt[v].n >= m.ndt_min_samples;
+    const unsigned long long bal = __ballot(ready);
     const uint32_t lane = lane_id();
     if ((lane & 31u) == 0u) m.ndt_ready[v >> 5] = (uint32_t)(bal >> lane);
+    if (ready) atomicOr(m.ndt_ready_bricks + (v >> 15), 1ull << brick_of((uint32_t)(v & (kRegionVoxels - 1))));
   }
 }
 
@@ -426,10 +560,14 @@ __global__ __launch_bounds__(256) void ndt_finalize_kernel(DevMap m, uint32_t pa
         const bool now_ready = nv.n >= m.ndt_min_samples;
         if (now_ready != was_ready) {
           uint32_t* w = m.ndt_ready + (v >> 5);
-          if (now_ready)
+          if (now_ready) {
             atomicOr(w, 1u << (v & 31u));
-          else
+            // the brick bit stays set when voxels become unready again (cleared
+            // statistics): it only says where to look
+            atomicOr(m.ndt_ready_bricks + (v >> 15), 1ull << brick_of((uint32_t)(v & (kRegionVoxels - 1))));
+          } else {
             atomicAnd(w, ~(1u << (v & 31u)));
+          }
         }
       }
       ap[0] = make_longlong2(0, 0);
@@ -468,6 +606,8 @@ ohm_status ndt_integrate_impl(ohm_map map, const float* d_origins, const float* 
   const bool weighted = d_weights != nullptr;
   const double sig_miss = 1.0 / (1.0 + exp(-(double)map->params.l_miss));
   if (map->ndt_ready_stale) {
+    hipLaunchKernelGGL(fill_u32_kernel, dim3(64), dim3(256), 0, st, reinterpret_cast<uint32_t*>(map->dm.ndt_ready_bricks),
+                       (size_t)map->dm.capacity * 2, 0u);
     hipLaunchKernelGGL(ndt_ready_rebuild_kernel, dim3(8192), dim3(256), 0, st, map->dm);
     map->ndt_ready_stale = false;
   }
@@ -498,6 +638,12 @@ ohm_status ndt_integrate_impl(ohm_map map, const float* d_origins, const float* 
           launch_ndt_seg<false, false>(map, tm, tiles, threads, st, d_origins, sc, d_samples, d_weights,
                                        d_intensities, r0, n, K, tag, parity, sig_miss);
       }
+    }
+    {
+      ProfScope ps(map, OHM_KERNEL_NDT_HIT, st);
+      const HitBox all = {{map->dm.kmin[0], map->dm.kmin[1], map->dm.kmin[2]},
+                          {map->dm.kmax[0], map->dm.kmax[1], map->dm.kmax[2]}};
+      launch_ndt_hits(map->dm, st, d_origins, sc, d_samples, d_weights, d_intensities, r0, n, all);
     }
     {
       ProfScope ps(map, OHM_KERNEL_NDT_HIT, st);

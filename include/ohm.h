@@ -380,7 +380,7 @@ typedef struct {
 
 typedef struct {
   uint32_t group_scans;      /* G: scans per map per launch group, 1..64 */
-  uint32_t seg_major_steps;  /* walk segment length, as in ohm_walk_tuning (0: 32) */
+  uint32_t seg_major_steps;  /* walk segment length, as in ohm_walk_tuning (0: 16) */
   uint32_t tile_threads;     /* threads per 256-ray tile: 256, 512 or 1024 (0: 512) */
   uint32_t keep_ray_order;   /* 0: each run walks every scan's rays in direction order
                                 (strips of azimuth, then elevation), which keeps a tile's
@@ -405,7 +405,7 @@ ohm_status ohm_batch_destroy(ohm_batch plan);
  * seg_major_steps crossings of its major axis (the axis it travels furthest
  * along); a block of tile_threads threads (256, 512 or 1024) processes the
  * segments of 256 consecutive rays.  Affects speed only, never results.
- * Defaults: 32 and 512. */
+ * Defaults: 16 and 512. */
 typedef struct {
   uint32_t seg_major_steps;
   uint32_t tile_threads;
@@ -454,6 +454,7 @@ enum {
   OHM_KERNEL_NDT_HIT = 3,   /* NDT sample fold (phase 2) */
   OHM_KERNEL_WALK_GROUP = 4,      /* voxel walk over a group of scans (OHM_LAYER_SCAN_GROUPS) */
   OHM_KERNEL_FINALIZE_GROUP = 5,  /* in-order apply of a group's scans */
+  OHM_KERNEL_NDT_SAMPLES = 6,     /* NDT hit samples into the per-scan moments */
   OHM_KERNEL_OTHER = 7,
   OHM_KERNEL_KINDS = 8
 };

@@ -86,7 +86,8 @@ class BatchTuning(ctypes.Structure):
                 ("tile_threads", ctypes.c_uint32), ("keep_ray_order", ctypes.c_uint32)]
 
 KERNEL_KINDS = 8
-KERNEL_NAMES = {0: "prepass", 1: "walk", 2: "finalize", 3: "ndt_hit", 4: "walk_group", 5: "finalize_group", 7: "other"}
+KERNEL_NAMES = {0: "prepass", 1: "walk", 2: "finalize", 3: "ndt_hit", 4: "walk_group", 5: "finalize_group",
+                6: "ndt_samples", 7: "other"}
 
 
 class OhmParams(ctypes.Structure):

@@ -401,14 +401,14 @@ extern "C" ohm_status ohm_backward(ohm_map map, int32_t ndt, const float* d_grad
     if (ndt) {
       // the statistics replay, for the voxels whose statistics the gradient
       // reads (the box's): the scan's hit samples there, as the forward adds them
-      ProfScope ps(map, OHM_KERNEL_NDT_HIT, st);
+      ProfScope ps(map, OHM_KERNEL_NDT_SAMPLES, st);
       HitBox box;
       for (int a = 0; a < 3; ++a) {
         const int64_t hi = (int64_t)gb.bmin[a] + gb.bdim[a];
         box.lo[a] = gb.bmin[a];
         box.hi[a] = hi > INT32_MAX ? INT32_MAX : (int32_t)hi;
       }
-      launch_ndt_hits(bm, st, d_origins, sc, d_samples, d_weights, nullptr, r0, n, box);
+      launch_ndt_hits(bm, st, d_origins, sc, d_samples, d_weights, r0, n, box);
     }
     if (ndt) {
       // fold only: the accumulators hold no increments, so occupancy is unchanged

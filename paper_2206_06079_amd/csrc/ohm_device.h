@@ -168,27 +168,6 @@ enum : int { kNaccMiss = 0, kNaccHit = 1, kNaccSamples = 2 };
 // minus voxel centre (metres)
 constexpr int kMomWords = 9;
 
-// Add one sample (e: the ray's sample, k: the key of its voxel, which the
-// ray hits) to voxel v's moments and sample count.
-__device__ __forceinline__ void ndt_add_sample(const DevMap& m, size_t v, const float* __restrict__ e,
-                                               const int32_t k[3]) {
-#pragma clang fp contract(off)
-  const double x0 = (double)e[0] - (m.origin[0] + ((double)k[0] + 0.5) * m.voxel_size);
-  const double x1 = (double)e[1] - (m.origin[1] + ((double)k[1] + 0.5) * m.voxel_size);
-  const double x2 = (double)e[2] - (m.origin[2] + ((double)k[2] + 0.5) * m.voxel_size);
-  double* mo = m.mom + v * kMomWords;
-  unsafeAtomicAdd(mo + 0, x0);
-  unsafeAtomicAdd(mo + 1, x1);
-  unsafeAtomicAdd(mo + 2, x2);
-  unsafeAtomicAdd(mo + 3, x0 * x0);
-  unsafeAtomicAdd(mo + 4, x0 * x1);
-  unsafeAtomicAdd(mo + 5, x0 * x2);
-  unsafeAtomicAdd(mo + 6, x1 * x1);
-  unsafeAtomicAdd(mo + 7, x1 * x2);
-  unsafeAtomicAdd(mo + 8, x2 * x2);
-  atomicAdd(reinterpret_cast<unsigned long long*>(m.nacc + v * kNaccWords + kNaccSamples), 1ull);
-}
-
 __device__ __forceinline__ uint32_t lane_id() {
   return __builtin_amdgcn_mbcnt_hi(~0u, __builtin_amdgcn_mbcnt_lo(~0u, 0u));
 }

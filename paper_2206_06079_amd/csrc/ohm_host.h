@@ -59,7 +59,7 @@ inline uint32_t group_slots_of(uint32_t layers) {
   if (n == 0) return kGroupSlots;
   return n <= kMaxGroupSlots ? n : 0u;
 }
-constexpr int kDefaultSegMajorSteps = 32;
+constexpr int kDefaultSegMajorSteps = 16;
 constexpr uint32_t kDefaultTileThreads = 512;
 
 // kernels shared across translation units
@@ -90,11 +90,12 @@ ohm_status check_scans(ohm_map map, const float* d_origins, const float* d_sampl
                        uint32_t n_scans);
 void clear_pending(ohm_map_s* map, hipStream_t st, bool prof = true);
 // Add the hit samples of one scan (n rays from r0, origin `scan`) whose end
-// voxels lie in `box` to the per-scan NDT moments and sample counts (and,
-// with intensities and an NDT-TM layer, the intensity sums), after the
-// scan's walk; weights (or null) as given to the walk.
+// voxels lie in `box` to the per-scan NDT moments and sample counts, after
+// a walk of the scan that allocated their regions; weights (or null) as
+// given to the walk.  (The NDT integration itself adds them in extra blocks
+// of its walk launch; this is the adjoint's statistics replay.)
 void launch_ndt_hits(const DevMap& m, hipStream_t st, const float* origins, uint32_t scan, const float* samples,
-                     const float* weights, const float* intensities, uint32_t r0, uint32_t n, HitBox box);
+                     const float* weights, uint32_t r0, uint32_t n, HitBox box);
 // Brackets one kernel launch with HIP events when profiling is enabled.
 class ProfScope {
  public:

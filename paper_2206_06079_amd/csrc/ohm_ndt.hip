@@ -13,7 +13,8 @@
 //     result does not depend on the order the GPU adds them in); in
 //     per-update mode the misses are instead applied at once by CAS.  A hit
 //     adds its sample's offset x from the voxel centre to the voxel's
-//     moments (sum x, sum x x^T, fp64) and counts one sample.
+//     moments (sum x, sum x x^T, fp64) and counts one sample; extra blocks
+//     of the same launch (ndt_hit_block) do this for the scan's hits.
 //   phase 2 (ndt_finalize_kernel): one thread per voxel of the scan's
 //     regions applies the occupancy update, clears the statistics of voxels
 //     that fell below ndt_clear_below, and merges the scan's sample moments
@@ -91,7 +92,7 @@ __device__ __forceinline__ bool ndt_ready_at(const DevMap& m, unsigned long long
 
 // Phase 1 over a tile of 256 rays, walked segment by segment (see
 // ohm_walk_seg.h): the same per-voxel work as the occupancy walk, with the
-// NDT-weighted miss increment and the hit's sample moments.
+// NDT-weighted miss increment (the hit samples' moments: ndt_hit_block).
 // Two 512-thread blocks per CU (four waves per SIMD): the kernel is held to
 // 128 VGPRs (the cold fp64 path of the queued misses spills) and the LDS
 // table below to 2048 entries, so two blocks' LDS fit in a CU.
@@ -184,19 +185,155 @@ __device__ __forceinline__ void ndt_drain(const DevMap& m, const NdtPending* pen
   }
 }
 
+// Sample moments of a scan's hits (each hit's occupancy increment is the
+// walk's): each hit sample whose voxel lies in the key box [lo, hi) joins
+// the voxel's per-scan moments and sample count, and for NDT-TM its
+// intensity sums.  A hit block takes kHitBlockRays consecutive rays of the
+// scan.  Neighbouring beams often end in one voxel (a block of 512 rays of
+// a spinning lidar holds about a quarter as many distinct hit voxels as
+// hits), so a block sums its hits per voxel in LDS and sends each voxel's
+// totals to memory once: about a quarter of the fp64 atomics of adding
+// every sample on its own, which otherwise bound the NDT pass.  The sums are
+// fp64 in any order.  The NDT integration runs these blocks as extra blocks
+// of the walk's launch, after its tiles, so that they fill the walk's tail;
+// with kAllocate they claim the hit voxels' regions as the walk does
+// (whichever comes first allocates).  The adjoint's statistics replay runs
+// them in a launch of their own after its walk (ndt_hit_kernel).
+constexpr uint32_t kHitBlockRays = 512;
+constexpr uint32_t kHitThreads = 512;
+constexpr int kHitTableLog2 = 9;
+constexpr uint32_t kHitTableSize = 1u << kHitTableLog2;  // >= the block's rays: every hit voxel finds an entry
+static_assert(kHitTableSize >= kHitBlockRays, "a block's hit voxels must all fit the table");
+
+struct NdtHitSmem {
+  uint32_t key[kHitTableSize];
+  uint32_t cnt[kHitTableSize];
+  double sum[11][kHitTableSize];  // x (3), x x^T (6), then intensity and its square (NDT-TM)
+};
+
+template <bool kWeighted, bool kTm, bool kAllocate>
+__device__ void ndt_hit_block(const DevMap& m, NdtHitSmem& sh, const float* __restrict__ origins, uint32_t scan,
+                              const float* __restrict__ samples, const float* __restrict__ weights,
+                              const float* __restrict__ intensities, uint32_t r0, uint32_t n, const HitBox& box,
+                              uint32_t blk) {
+#pragma clang fp contract(off)
+  constexpr int kSums = kTm ? 11 : 9;
+  const uint32_t tid = threadIdx.x;
+  for (uint32_t h = tid; h < kHitTableSize; h += blockDim.x) {
+    sh.key[h] = kAggEmpty;
+    sh.cnt[h] = 0u;
+    for (int c = 0; c < kSums; ++c) sh.sum[c][h] = 0.0;
+  }
+  __syncthreads();
+  const float o[3] = {origins[3 * (size_t)scan], origins[3 * (size_t)scan + 1], origins[3 * (size_t)scan + 2]};
+  const uint32_t first = blk * kHitBlockRays;
+  const uint32_t end = n - first < kHitBlockRays ? n : first + kHitBlockRays;
+  for (uint32_t i = first + tid; i < end; i += blockDim.x) {
+    const size_t ray = (size_t)r0 + i;
+    const float e[3] = {samples[3 * ray], samples[3 * ray + 1], samples[3 * ray + 2]};
+    // the same ray preparation and checks as the walk: a hit is a valid,
+    // untruncated ray whose end voxel lies in the map, in an allocated region
+    Ray r;
+    int st = prepare_ray(m, o, e, r);
+    if (kWeighted) {
+      const float w = weights[ray];
+      if (!(w >= 0.f) || !__builtin_isfinite(w)) st = kRayInvalid;
+    }
+    if (st != kRayOk || r.truncated) continue;
+    bool inside = true;
+    for (int a = 0; a < 3; ++a) inside = inside && r.k1[a] >= m.kmin[a] && r.k1[a] < m.kmax[a];
+    for (int a = 0; a < 3; ++a) inside = inside && r.k1[a] >= box.lo[a] && r.k1[a] < box.hi[a];
+    if (!inside) continue;
+    // the hit voxel lies on the ray's path, so the walk claims its region too
+    const int32_t ri = region_index(m, r.k1[0] >> kRegionLog2, r.k1[1] >> kRegionLog2, r.k1[2] >> kRegionLog2);
+    const int32_t slot = kAllocate ? resolve_region<false>(m, ri, 0u, 0u)
+                                   : __hip_atomic_load(m.table + ri, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    if (slot < 0) continue;  // the walk drops the hit too (pool exhausted)
+    const uint32_t v = (uint32_t)slot * (uint32_t)kRegionVoxels + local_index(r.k1[0], r.k1[1], r.k1[2]);
+    // voxel-centred sample: x = sample - centre
+    double x[3];
+    for (int a = 0; a < 3; ++a) x[a] = (double)e[a] - (m.origin[a] + ((double)r.k1[a] + 0.5) * m.voxel_size);
+    double terms[kSums];
+    terms[0] = x[0];
+    terms[1] = x[1];
+    terms[2] = x[2];
+    terms[3] = x[0] * x[0];
+    terms[4] = x[0] * x[1];
+    terms[5] = x[0] * x[2];
+    terms[6] = x[1] * x[1];
+    terms[7] = x[1] * x[2];
+    terms[8] = x[2] * x[2];
+    if (kTm) {
+      const double in = (double)intensities[ray];
+      terms[kSums - 2] = in;
+      terms[kSums - 1] = in * in;
+    }
+    // linear probing over the whole table: at most kHitTableSize distinct
+    // voxels, so the probe always ends at the voxel's entry
+    uint32_t h = (v * 0x9E3779B1u) >> (32 - kHitTableLog2);
+    for (uint32_t p = 0; p < kHitTableSize; ++p) {
+      uint32_t k = sh.key[h];
+      if (k == kAggEmpty) {
+        const uint32_t old = atomicCAS(sh.key + h, kAggEmpty, v);
+        k = old == kAggEmpty ? v : old;
+      }
+      if (k == v) break;
+      h = (h + 1u) & (kHitTableSize - 1u);
+    }
+    atomicAdd(sh.cnt + h, 1u);
+    for (int c = 0; c < kSums; ++c) atomicAdd(&sh.sum[c][h], terms[c]);
+  }
+  __syncthreads();
+  for (uint32_t h = tid; h < kHitTableSize; h += blockDim.x) {
+    const uint32_t v = sh.key[h];
+    if (v == kAggEmpty) continue;
+    double* mo = m.mom + (size_t)v * kMomWords;
+    for (int c = 0; c < 9; ++c) unsafeAtomicAdd(mo + c, sh.sum[c][h]);
+    atomicAdd(reinterpret_cast<unsigned long long*>(m.nacc + (size_t)v * kNaccWords + kNaccSamples),
+              (unsigned long long)sh.cnt[h]);
+    if (kTm) {
+      unsafeAtomicAdd(m.tm_mom + 2 * (size_t)v, sh.sum[kSums - 2][h]);
+      unsafeAtomicAdd(m.tm_mom + 2 * (size_t)v + 1, sh.sum[kSums - 1][h]);
+    }
+  }
+}
+
+// LDS of a walk tile; the launch's hit blocks use the same memory.
+struct NdtWalkSmem {
+  TileRays tr;
+  RegionCache rc;
+  double ray_end[3][kTileRays];  // world end point after truncation
+  uint32_t agg_key[kNdtAggSize];
+  unsigned long long agg_val[kNdtAggSize];
+  NdtPending pend[kNdtMaxThreads / 64][64];
+};
+union NdtSmem {
+  NdtWalkSmem w;
+  NdtHitSmem h;
+};
+
 template <bool kCount, bool kWeighted, bool kTm>
 __global__ __launch_bounds__(kNdtMaxThreads, 4) void ndt_seg_kernel(DevMap m, const float* __restrict__ origins, uint32_t scan,
                                                        const float* __restrict__ samples,
                                                        const float* __restrict__ weights,
                                                        const float* __restrict__ intensities, uint32_t r0, uint32_t n,
-                                                       int K, uint32_t tag, uint32_t parity, double sig_miss) {
+                                                       uint32_t n_tiles, int K, uint32_t tag, uint32_t parity,
+                                                       double sig_miss) {
 #pragma clang fp contract(off)
-  __shared__ TileRays tr;
-  __shared__ RegionCache rc;
-  __shared__ double ray_end[3][kTileRays];  // world end point after truncation
-  __shared__ uint32_t agg_key[kNdtAggSize];
-  __shared__ unsigned long long agg_val[kNdtAggSize];
-  __shared__ NdtPending pend[kNdtMaxThreads / 64][64];
+  __shared__ NdtSmem sm;
+  if (blockIdx.x >= n_tiles) {
+    // a hit block (after the tiles): the scan's hit samples
+    const HitBox all = {{m.kmin[0], m.kmin[1], m.kmin[2]}, {m.kmax[0], m.kmax[1], m.kmax[2]}};
+    ndt_hit_block<kWeighted, kTm, true>(m, sm.h, origins, scan, samples, weights, intensities, r0, n, all,
+                                        blockIdx.x - n_tiles);
+    return;
+  }
+  TileRays& tr = sm.w.tr;
+  RegionCache& rc = sm.w.rc;
+  double(*ray_end)[kTileRays] = sm.w.ray_end;
+  uint32_t* agg_key = sm.w.agg_key;
+  unsigned long long* agg_val = sm.w.agg_val;
+  NdtPending(*pend)[64] = sm.w.pend;
   const uint32_t tid = threadIdx.x;
   const uint32_t lane = lane_id();
   const uint32_t tile0 = blockIdx.x * kTileRays;
@@ -336,130 +473,25 @@ __global__ __launch_bounds__(kNdtMaxThreads, 4) void ndt_seg_kernel(DevMap m, co
   flush_tile_stats(m, t, n_hit, n_upd, n_drop);
 }
 
-// Sample moments of a scan's hits, after its walk (which adds each hit's
-// occupancy increment): each hit sample whose voxel lies in the key box
-// [lo, hi) joins the voxel's per-scan moments and sample count, and for
-// NDT-TM its intensity sums.  A block takes
-// kHitBlockRays consecutive rays of the scan.  Neighbouring beams often end
-// in one voxel (a block of 1024 rays of a spinning lidar holds about a fifth
-// as many distinct hit voxels as hits), so a block sums its hits per voxel
-// in LDS and sends each voxel's totals to memory once: about a fifth of the
-// fp64 atomics of adding every sample on its own, which otherwise bound the
-// NDT pass.  The sums are fp64 in any order (as the walk's were).
-constexpr uint32_t kHitBlockRays = 1024;
-constexpr uint32_t kHitThreads = 512;
-constexpr int kHitTableLog2 = 10;
-constexpr uint32_t kHitTableSize = 1u << kHitTableLog2;  // >= the block's rays: every hit voxel finds an entry
-static_assert(kHitTableSize >= kHitBlockRays, "a block's hit voxels must all fit the table");
-
 template <bool kWeighted, bool kTm>
 __global__ __launch_bounds__(kHitThreads) void ndt_hit_kernel(DevMap m, const float* __restrict__ origins,
                                                               uint32_t scan, const float* __restrict__ samples,
-                                                              const float* __restrict__ weights,
-                                                              const float* __restrict__ intensities, uint32_t r0,
+                                                              const float* __restrict__ weights, uint32_t r0,
                                                               uint32_t n, HitBox box) {
-#pragma clang fp contract(off)
-  constexpr int kSums = kTm ? 11 : 9;  // x (3), x x^T (6), then intensity and its square
-  __shared__ uint32_t key[kHitTableSize];
-  __shared__ uint32_t cnt[kHitTableSize];
-  __shared__ double sum[kSums][kHitTableSize];
-  const uint32_t tid = threadIdx.x;
-  for (uint32_t h = tid; h < kHitTableSize; h += kHitThreads) {
-    key[h] = kAggEmpty;
-    cnt[h] = 0u;
-    for (int c = 0; c < kSums; ++c) sum[c][h] = 0.0;
-  }
-  __syncthreads();
-  const float o[3] = {origins[3 * (size_t)scan], origins[3 * (size_t)scan + 1], origins[3 * (size_t)scan + 2]};
-  for (uint32_t j = 0; j < kHitBlockRays / kHitThreads; ++j) {
-    const uint32_t i = blockIdx.x * kHitBlockRays + j * kHitThreads + tid;
-    if (i >= n) break;
-    const size_t ray = (size_t)r0 + i;
-    const float e[3] = {samples[3 * ray], samples[3 * ray + 1], samples[3 * ray + 2]};
-    // the same ray preparation and checks as the walk: a hit is a valid,
-    // untruncated ray whose end voxel lies in the map, in an allocated region
-    Ray r;
-    int st = prepare_ray(m, o, e, r);
-    if (kWeighted) {
-      const float w = weights[ray];
-      if (!(w >= 0.f) || !__builtin_isfinite(w)) st = kRayInvalid;
-    }
-    if (st != kRayOk || r.truncated) continue;
-    bool inside = true;
-    for (int a = 0; a < 3; ++a) inside = inside && r.k1[a] >= m.kmin[a] && r.k1[a] < m.kmax[a];
-    for (int a = 0; a < 3; ++a) inside = inside && r.k1[a] >= box.lo[a] && r.k1[a] < box.hi[a];
-    if (!inside) continue;
-    const int32_t slot = lookup_slot(m, r.k1[0], r.k1[1], r.k1[2]);
-    if (slot < 0) continue;  // the walk dropped the hit too (pool exhausted)
-    const uint32_t v = (uint32_t)slot * (uint32_t)kRegionVoxels + local_index(r.k1[0], r.k1[1], r.k1[2]);
-    // voxel-centred sample: x = sample - centre
-    double x[3];
-    for (int a = 0; a < 3; ++a) x[a] = (double)e[a] - (m.origin[a] + ((double)r.k1[a] + 0.5) * m.voxel_size);
-    double terms[kSums];
-    terms[0] = x[0];
-    terms[1] = x[1];
-    terms[2] = x[2];
-    terms[3] = x[0] * x[0];
-    terms[4] = x[0] * x[1];
-    terms[5] = x[0] * x[2];
-    terms[6] = x[1] * x[1];
-    terms[7] = x[1] * x[2];
-    terms[8] = x[2] * x[2];
-    if (kTm) {
-      const double in = (double)intensities[ray];
-      terms[kSums - 2] = in;
-      terms[kSums - 1] = in * in;
-    }
-    // linear probing over the whole table: at most kHitTableSize distinct
-    // voxels, so the probe always ends at the voxel's entry
-    uint32_t h = (v * 0x9E3779B1u) >> (32 - kHitTableLog2);
-    for (uint32_t p = 0; p < kHitTableSize; ++p) {
-      uint32_t k = key[h];
-      if (k == kAggEmpty) {
-        const uint32_t old = atomicCAS(key + h, kAggEmpty, v);
-        k = old == kAggEmpty ? v : old;
-      }
-      if (k == v) break;
-      h = (h + 1u) & (kHitTableSize - 1u);
-    }
-    atomicAdd(cnt + h, 1u);
-    for (int c = 0; c < kSums; ++c) atomicAdd(&sum[c][h], terms[c]);
-  }
-  __syncthreads();
-  for (uint32_t h = tid; h < kHitTableSize; h += kHitThreads) {
-    const uint32_t v = key[h];
-    if (v == kAggEmpty) continue;
-    double* mo = m.mom + (size_t)v * kMomWords;
-    for (int c = 0; c < 9; ++c) unsafeAtomicAdd(mo + c, sum[c][h]);
-    atomicAdd(reinterpret_cast<unsigned long long*>(m.nacc + (size_t)v * kNaccWords + kNaccSamples),
-              (unsigned long long)cnt[h]);
-    if (kTm) {
-      unsafeAtomicAdd(m.tm_mom + 2 * (size_t)v, sum[kSums - 2][h]);
-      unsafeAtomicAdd(m.tm_mom + 2 * (size_t)v + 1, sum[kSums - 1][h]);
-    }
-  }
+  __shared__ NdtHitSmem sh;
+  ndt_hit_block<kWeighted, kTm, false>(m, sh, origins, scan, samples, weights, nullptr, r0, n, box, blockIdx.x);
 }
 
 void launch_ndt_hits(const DevMap& m, hipStream_t st, const float* origins, uint32_t scan, const float* samples,
-                     const float* weights, const float* intensities, uint32_t r0, uint32_t n, HitBox box) {
+                     const float* weights, uint32_t r0, uint32_t n, HitBox box) {
   if (n == 0) return;
   const dim3 blocks((n + kHitBlockRays - 1) / kHitBlockRays);
-  const bool tm = intensities != nullptr && m.tm_mom != nullptr;
-  if (weights) {
-    if (tm)
-      hipLaunchKernelGGL((ndt_hit_kernel<true, true>), blocks, dim3(kHitThreads), 0, st, m, origins, scan, samples,
-                         weights, intensities, r0, n, box);
-    else
-      hipLaunchKernelGGL((ndt_hit_kernel<true, false>), blocks, dim3(kHitThreads), 0, st, m, origins, scan, samples,
-                         weights, intensities, r0, n, box);
-  } else {
-    if (tm)
-      hipLaunchKernelGGL((ndt_hit_kernel<false, true>), blocks, dim3(kHitThreads), 0, st, m, origins, scan, samples,
-                         weights, intensities, r0, n, box);
-    else
-      hipLaunchKernelGGL((ndt_hit_kernel<false, false>), blocks, dim3(kHitThreads), 0, st, m, origins, scan, samples,
-                         weights, intensities, r0, n, box);
-  }
+  if (weights)
+    hipLaunchKernelGGL((ndt_hit_kernel<true, false>), blocks, dim3(kHitThreads), 0, st, m, origins, scan, samples,
+                       weights, r0, n, box);
+  else
+    hipLaunchKernelGGL((ndt_hit_kernel<false, false>), blocks, dim3(kHitThreads), 0, st, m, origins, scan, samples,
+                       weights, r0, n, box);
 }
 
 // Recompute every ready bit from the sample counts (after ndt_min_samples
@@ -588,12 +620,14 @@ template <bool kCount, bool kWeighted>
 void launch_ndt_seg(const ohm_map_s* map, bool tm, dim3 tiles, dim3 threads, hipStream_t st, const float* origins,
                     uint32_t sc, const float* samples, const float* weights, const float* intensities, uint32_t r0,
                     uint32_t n, int K, uint32_t tag, uint32_t parity, double sig_miss) {
+  // the walk's tiles, then the hit blocks
+  const dim3 grid(tiles.x + (n + kHitBlockRays - 1) / kHitBlockRays);
   if (tm)
-    hipLaunchKernelGGL((ndt_seg_kernel<kCount, kWeighted, true>), tiles, threads, 0, st, map->dm, origins, sc, samples,
-                       weights, intensities, r0, n, K, tag, parity, sig_miss);
+    hipLaunchKernelGGL((ndt_seg_kernel<kCount, kWeighted, true>), grid, threads, 0, st, map->dm, origins, sc, samples,
+                       weights, intensities, r0, n, tiles.x, K, tag, parity, sig_miss);
   else
-    hipLaunchKernelGGL((ndt_seg_kernel<kCount, kWeighted, false>), tiles, threads, 0, st, map->dm, origins, sc,
-                       samples, weights, intensities, r0, n, K, tag, parity, sig_miss);
+    hipLaunchKernelGGL((ndt_seg_kernel<kCount, kWeighted, false>), grid, threads, 0, st, map->dm, origins, sc,
+                       samples, weights, intensities, r0, n, tiles.x, K, tag, parity, sig_miss);
 }
 
 // Both NDT entry points: intensities non-null exactly for NDT-TM maps.
@@ -638,12 +672,6 @@ ohm_status ndt_integrate_impl(ohm_map map, const float* d_origins, const float* 
           launch_ndt_seg<false, false>(map, tm, tiles, threads, st, d_origins, sc, d_samples, d_weights,
                                        d_intensities, r0, n, K, tag, parity, sig_miss);
       }
-    }
-    {
-      ProfScope ps(map, OHM_KERNEL_NDT_HIT, st);
-      const HitBox all = {{map->dm.kmin[0], map->dm.kmin[1], map->dm.kmin[2]},
-                          {map->dm.kmax[0], map->dm.kmax[1], map->dm.kmax[2]}};
-      launch_ndt_hits(map->dm, st, d_origins, sc, d_samples, d_weights, d_intensities, r0, n, all);
     }
     {
       ProfScope ps(map, OHM_KERNEL_NDT_HIT, st);

@@ -208,7 +208,7 @@ class OhmMap:
               "ohm_backward")
         return grad_weights, gs
 
-    def set_tuning(self, seg_major_steps: int = 32, tile_threads: int = 512):
+    def set_tuning(self, seg_major_steps: int = 16, tile_threads: int = 512):
         t = _lib.WalkTuning(int(seg_major_steps), int(tile_threads))
         check(load().ohm_map_set_tuning(self.handle, ctypes.byref(t)), "ohm_map_set_tuning")
 

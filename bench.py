@@ -391,6 +391,10 @@ def run_ndt(args, params, batch, tm=False):
               + (COUNT_UPDATE_BYTES + NDT_SAMPLE_BYTES) * hits)
     out["kernel_us_per_scan"] = {k: round(v[1] / v[0] * 1e3, 1) for k, v in r["kernels"].items()}
     out["roofline_hbm"] = dict(hbm(walk_b, walk_ms), kernel="ndt_seg_kernel", unit="per scan")
+    if not tm:
+        counters = measured_counters("ndt_seg_kernel_config2")
+        out["roofline_hbm"]["traffic"] = counters.get("traffic_bytes_per_launch")
+        out["roofline_hbm"]["atomic_requests"] = counters.get("atomic_requests_per_launch")
     log(f"{name}: {r['ms_per_step']:.3f} ms per {scans}-scan pass")
     return out
 
@@ -460,6 +464,10 @@ def run_adjoint(args):
         "backward_rays_per_s": round(batch.n_rays / (b_ms * 1e-3), 1),
         "voxel_visits": int(visits),
         "roofline_hbm_backward": hbm(bwd_bytes, b_ms),
+        # HBM bytes of the backward walk per launch (one scan), from the
+        # committed counters, times the scans of a pass
+        "traffic_backward_walk": (traffic * batch.n_scans if (traffic := measured_counters(
+            "backward_seg_kernel_config4").get("traffic_bytes_per_launch")) else None),
     }
 
 

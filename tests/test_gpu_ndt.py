@@ -129,3 +129,48 @@ def test_ndt_threshold_change_between_calls():
     assert np.all(np.abs(occ.astype(np.float64) - o_occ) <= 1e-5 + k * 2.0 ** -33)
     # voxels holding exactly 3 samples after the first two scans take weighted misses now
     assert (o_state.n == 3).sum() > 100
+
+
+def hit_block_batch(seed=11):
+    """Scans of ragged sizes around the 512-ray hit blocks (1, 511, 512, 513,
+    1500, 3000 rays), half of each scan's rays ending within 1 cm of one of
+    three points (many hits in one voxel), the rest in random directions,
+    some beyond the 2.5 m range (truncated: no hit); a few NaN samples; 5 % of
+    the weights zero (a hit that adds its sample but no occupancy)."""
+    rng = np.random.default_rng(seed)
+    sizes = [1, 511, 512, 513, 1500, 3000]
+    targets = np.array([[1.23, 0.47, -0.66], [-0.91, 1.58, 0.35], [0.12, -1.74, 1.05]])
+    origins, samples = [], []
+    for s, n in enumerate(sizes):
+        o = np.array([0.01 * s, -0.02 * s, 0.015 * s])
+        d = rng.normal(size=(n, 3))
+        d /= np.linalg.norm(d, axis=1, keepdims=True)
+        pts = o + d * rng.uniform(0.3, 3.5, size=(n, 1))
+        near = rng.random(n) < 0.5
+        pts[near] = targets[rng.integers(0, 3, near.sum())] + rng.uniform(-0.01, 0.01, (near.sum(), 3))
+        origins.append(o)
+        samples.append(pts)
+    samples = np.concatenate(samples).astype(np.float32)
+    samples[rng.choice(samples.shape[0], 4, replace=False), 1] = np.nan
+    weights = rng.uniform(0.5, 1.0, samples.shape[0]).astype(np.float32)
+    weights[rng.random(samples.shape[0]) < 0.05] = 0.0
+    offsets = np.concatenate([[0], np.cumsum(sizes)]).astype(np.uint32)
+    return scenes.RayBatch(np.array(origins, np.float32), samples, offsets, weights)
+
+
+@pytest.mark.parametrize("weighted", [False, True])
+def test_ndt_hit_blocks_ragged_and_crowded(weighted):
+    """The hit samples are summed per voxel in 512-ray blocks of the walk's
+    launch: scans shorter than a block, a ragged last block, hundreds of
+    samples landing in one voxel, zero weights and invalid rays all give the
+    oracle's sample counts and statistics."""
+    mp = scenes.grid_map((-3.2, -3.2, -3.2), (3.2, 3.2, 3.2), 0.1, max_range=2.5)
+    batch = hit_block_batch()
+    if not weighted:
+        batch.weights = None
+    box_min, box_dim = (0, 0, 0), mp.dims
+    g = gpu_ndt(mp, batch, box_min, box_dim, capacity=16)
+    o_occ, o_state, _, _ = oracle.ndt_integrate(mp, batch, box_min, box_dim, mode=1)
+    assert o_state.n.max() > 200  # one voxel took hundreds of samples
+    k = update_counts(mp, batch, box_min, box_dim)
+    check_stats(g, o_occ, o_state, k)

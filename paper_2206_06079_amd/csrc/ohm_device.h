@@ -90,6 +90,7 @@ struct DevMap {
   uint32_t* ndt_ready;  // [capacity][V / 32]: bit set where the voxel holds >= ndt_min_samples samples
   unsigned long long* ndt_ready_bricks;  // [capacity]: bit b set when brick b of the region may hold a ready voxel
   long long* nacc;    // NDT per-scan accumulators [capacity][V][kNaccWords] or null
+  uint32_t* nsamp;    // NDT per-scan sample counts [capacity][V] or null
   double* mom;        // NDT per-scan sample moments [capacity][V][kMomWords] or null
   uint32_t* clampscan;// [capacity][V] or null
   // voxel mean layer (or null): per voxel the packed 10-bit sub-voxel codes
@@ -162,8 +163,8 @@ __device__ __forceinline__ float apply_wide(const DevMap& m, float l, long long 
 
 // NDT per-scan accumulators, exact integers: summed miss increment and summed
 // hit weight in Q32.32 fixed point, and the number of samples
-constexpr int kNaccWords = 4;
-enum : int { kNaccMiss = 0, kNaccHit = 1, kNaccSamples = 2 };
+constexpr int kNaccWords = 2;  // Q32.32 miss and hit sums (16 B: four voxels per 64-byte line)
+enum : int { kNaccMiss = 0, kNaccHit = 1 };
 // per-voxel sample moments of one scan: sum x (3), sum x x^T (6), x = sample
 // minus voxel centre (metres)
 constexpr int kMomWords = 9;

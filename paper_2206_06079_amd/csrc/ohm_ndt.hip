@@ -100,15 +100,16 @@ constexpr uint32_t kNdtMaxThreads = 512;
 
 // Per-tile LDS table of the NDT walk's increments (see the occupancy walk's
 // table): update id -> summed Q32.32 increment, two probes, laid out by
-// 64-byte accumulator line (two voxels' miss and hit words: 4 ids per
+// 64-byte accumulator line (four voxels' miss and hit words: 8 ids per
 // group).  The sums are exact integers, so the result does not depend on how
 // updates reach the table.
 constexpr int kNdtAggLog2 = 11;
 constexpr uint32_t kNdtAggSize = 1u << kNdtAggLog2;
-constexpr uint32_t kNdtAggLine = 4;
+constexpr int kNdtAggLineLog2 = 3;
+constexpr uint32_t kNdtAggLine = 1u << kNdtAggLineLog2;
 
 __device__ __forceinline__ bool ndt_agg_add(uint32_t* keys, unsigned long long* vals, uint32_t id, long long q) {
-  const uint32_t group = ((id / kNdtAggLine) * 0x9E3779B1u) >> (32 - (kNdtAggLog2 - 2));
+  const uint32_t group = ((id >> kNdtAggLineLog2) * 0x9E3779B1u) >> (32 - (kNdtAggLog2 - kNdtAggLineLog2));
   uint32_t h = group * kNdtAggLine + id % kNdtAggLine;
   for (int p = 0; p < 2; ++p) {
     uint32_t k = keys[h];
@@ -289,8 +290,7 @@ __device__ void ndt_hit_block(const DevMap& m, NdtHitSmem& sh, const float* __re
     if (v == kAggEmpty) continue;
     double* mo = m.mom + (size_t)v * kMomWords;
     for (int c = 0; c < 9; ++c) unsafeAtomicAdd(mo + c, sh.sum[c][h]);
-    atomicAdd(reinterpret_cast<unsigned long long*>(m.nacc + (size_t)v * kNaccWords + kNaccSamples),
-              (unsigned long long)sh.cnt[h]);
+    atomicAdd(m.nsamp + v, sh.cnt[h]);
     if (kTm) {
       unsafeAtomicAdd(m.tm_mom + 2 * (size_t)v, sh.sum[kSums - 2][h]);
       unsafeAtomicAdd(m.tm_mom + 2 * (size_t)v + 1, sh.sum[kSums - 1][h]);
@@ -458,7 +458,7 @@ __global__ __launch_bounds__(kNdtMaxThreads, 4) void ndt_seg_kernel(DevMap m, co
         emit = has && run.tail && !deferred;
       }
       if (emit && !ndt_agg_add(agg_key, agg_val, id, qs)) ndt_apply<kCount>(m, id, qs);
-      // (the hit sample's moments are added by ndt_hit_kernel)
+      // (the hit sample's moments are added by the launch's hit blocks)
       ready = ready_next;
     }
   }
@@ -522,9 +522,9 @@ __global__ __launch_bounds__(256) void ndt_finalize_kernel(DevMap m, uint32_t pa
     for (int j = threadIdx.x; j < kNdtChunk; j += blockDim.x) {
       const size_t v = base + j;
       longlong2* ap = reinterpret_cast<longlong2*>(m.nacc + v * kNaccWords);
-      const longlong2 a01 = ap[0];
-      const longlong2 a23 = ap[1];
-      if (a01.x == 0 && a01.y == 0 && a23.x == 0) continue;
+      const longlong2 a01 = *ap;
+      const uint32_t nb32 = m.nsamp[v];
+      if (a01.x == 0 && a01.y == 0 && nb32 == 0) continue;
       const double miss = (double)a01.x * kInvQ32;
       const double hitw = (double)a01.y * kInvQ32;
       double l = (double)m.occ[v];
@@ -543,7 +543,7 @@ __global__ __launch_bounds__(256) void ndt_finalize_kernel(DevMap m, uint32_t pa
         dirty = true;
         if (m.tm) m.tm[v] = TmVoxel{0u, 0.f, 0.f};
       }
-      const long long nb = a23.x;
+      const long long nb = nb32;
       if (nb > 0 && m.tm) {
         // NDT-TM intensity Gaussian: pairwise merge of the scan's moments
         // with the stored mean and variance (count: the NDT sample count)
@@ -602,8 +602,8 @@ __global__ __launch_bounds__(256) void ndt_finalize_kernel(DevMap m, uint32_t pa
           }
         }
       }
-      ap[0] = make_longlong2(0, 0);
-      ap[1] = make_longlong2(0, 0);
+      *ap = make_longlong2(0, 0);
+      if (nb32 != 0) m.nsamp[v] = 0u;
     }
   }
   if (blockIdx.x == 0 && threadIdx.x == 0)

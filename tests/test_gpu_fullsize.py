@@ -67,11 +67,15 @@ def test_headline_workload_equals_oracle(headline, layers):
     assert st["updates_dropped_pool"] == 0
 
 
-def test_headline_workload_batched_equals_oracle(headline):
+@pytest.mark.parametrize("seg_major_steps,keep_ray_order", [(16, 0), (32, 1)])
+def test_headline_workload_batched_equals_oracle(headline, seg_major_steps, keep_ray_order):
+    """The benchmark's batched leg on the headline scans, in the launch
+    configurations its autotuner chooses between (50 scans per group)."""
     mp, batch, (o_occ, _, _, o_st) = headline
     m = ohm.OhmMap(mp, 512, device=device())
     o, s, off, w = to_dev(batch)
-    plan = ohm.OhmBatch([ohm.ScanSetArgs(m, o, s, off, w)], 50)
+    plan = ohm.OhmBatch([ohm.ScanSetArgs(m, o, s, off, w)], 50, seg_major_steps=seg_major_steps, tile_threads=512,
+                        keep_ray_order=keep_ray_order)
     plan.run()
     torch.cuda.synchronize()
     occ = m.read_dense(ohm.READ_OCC, BOX_MIN, BOX_DIM).cpu().numpy()
@@ -119,7 +123,7 @@ def test_batched_streams_full_scan_sizes():
     params, batches = scenes.config3(n_streams=16, n_scans=128, jobs=16)
     print(f"batched: {[b.samples.shape[0] for b in batches]} rays per map", flush=True)
     maps, sets = make_sets(params, batches)
-    plan = ohm.OhmBatch(sets, 64, seg_major_steps=32, tile_threads=512, keep_ray_order=0)
+    plan = ohm.OhmBatch(sets, 64, seg_major_steps=16, tile_threads=512, keep_ray_order=0)
     plan.run()
     torch.cuda.synchronize()
     for mi, (p, b) in enumerate(zip(params, batches)):

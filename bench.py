@@ -616,6 +616,13 @@ def main():
         "at_8B_per_update": {"achieved": round(launch_bytes_f32 / (walk_avg_ms * 1e-3) / 1e9, 1),
                              "frac": round(launch_bytes_f32 / (walk_avg_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)},
     }
+    # the device's measured streaming bandwidth (1 GiB copy and read, well
+    # beyond the last-level cache) beside the published peak
+    stream_copy = ohm.probe_stream_rate(1 << 30) / 1e9
+    stream_read = ohm.probe_stream_rate(1 << 30, read_only=True) / 1e9
+    roofline["measured_stream"] = {"copy_gbs": round(stream_copy, 1), "read_gbs": round(stream_read, 1),
+                                   "frac_vs_copy": round(achieved / stream_copy, 4)}
+    log(f"stream: copy {stream_copy:.0f} GB/s, read {stream_read:.0f} GB/s")
     s_walk_avg, _ = kernel_avg_ms(single, "walk")
     one_launch_per_scan = leg_summary(single, f"the {scans} headline scans, one walk launch per scan")
     one_launch_per_scan.update({

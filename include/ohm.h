@@ -477,8 +477,21 @@ ohm_status ohm_map_kernel_times(ohm_map map, uint32_t* h_launches, double* h_ms)
  * Writes the rate in operations per second to *h_ops_per_s; synchronises
  * `stream`.  These are the ceilings that the walks' per-voxel atomic
  * updates are compared with at the footprint of the layer they update. */
-enum { OHM_PROBE_SEQUENTIAL = 1, OHM_PROBE_F32_CAS = 2, OHM_PROBE_U64_ADD = 4 };
+enum { OHM_PROBE_SEQUENTIAL = 1, OHM_PROBE_F32_CAS = 2, OHM_PROBE_U64_ADD = 4, OHM_PROBE_READ_ONLY = 8 };
 ohm_status ohm_probe_atomic_rate(void* d_buffer, size_t bytes, int flags, double* h_ops_per_s, void* stream);
+
+/* Measurement helper (not part of integration): the device's streaming
+ * bandwidth at a footprint.  Times a copy of `bytes` from d_src to d_dst
+ * (both device buffers of at least `bytes`, 16-byte aligned; d_dst is
+ * overwritten) or, with OHM_PROBE_READ_ONLY in flags, a read of d_src alone
+ * (d_dst then receives at most a few 16-byte words).  bytes must be a
+ * multiple of 16 and at least 16 MiB; flags other than OHM_PROBE_READ_ONLY
+ * are rejected (OHM_E_INVALID_ARG).  Writes the bytes moved per second
+ * (read plus written) to *h_bytes_per_s; synchronises `stream`.  The HBM
+ * rooflines of the walks quote the published peak with this measured rate
+ * beside it. */
+ohm_status ohm_probe_stream_rate(const void* d_src, void* d_dst, size_t bytes, int flags, double* h_bytes_per_s,
+                                 void* stream);
 
 /* Synchronise `stream` and read the map's statistics. */
 ohm_status ohm_map_sync_status(ohm_map map, void* stream, ohm_map_stats* out);

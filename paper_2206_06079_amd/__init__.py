@@ -17,5 +17,5 @@ from ._lib import (  # noqa: F401
     OHM_E_HIP, OHM_E_INVALID_ARG, OHM_E_NO_DEVICE, OHM_E_UNSUPPORTED, OHM_E_WORKSPACE_TOO_SMALL, OHM_OK,
     OhmError, scan_group_slots,
 )
-from .ohm import OhmIntegrate, OhmMap, probe_atomic_rate, regions_needed  # noqa: F401
+from .ohm import OhmIntegrate, OhmMap, probe_atomic_rate, probe_stream_rate, regions_needed  # noqa: F401
 from .batch import OhmBatch, ScanSetArgs, autotune  # noqa: F401

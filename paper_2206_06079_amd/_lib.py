@@ -51,6 +51,7 @@ READ_INTENSITY_MEAN = 15
 READ_INTENSITY_VAR = 16
 READ_TSDF_DISTANCE = 17
 READ_TSDF_WEIGHT = 18
+PROBE_SEQUENTIAL, PROBE_F32_CAS, PROBE_U64_ADD, PROBE_READ_ONLY = 1, 2, 4, 8
 
 # Every symbol include/ohm.h declares.
 EXPORTS = (
@@ -59,7 +60,8 @@ EXPORTS = (
     "ohm_debug_trace_rays", "ohm_map_sync_status", "ohm_status_string",
     "ohm_map_set_profiling", "ohm_map_kernel_times", "ohm_backward",
     "ohm_batch_workspace_size", "ohm_batch_create", "ohm_batch_run", "ohm_batch_destroy",
-    "ohm_map_set_tuning", "ohm_probe_atomic_rate", "ohm_ray_order_scratch_size", "ohm_map_set_ray_order",
+    "ohm_map_set_tuning", "ohm_probe_atomic_rate", "ohm_probe_stream_rate", "ohm_ray_order_scratch_size",
+    "ohm_map_set_ray_order",
     "ohm_build_source_digest", "ohm_ndt_tm_integrate", "ohm_tsdf_integrate", "ohm_integrate_rays_no_alloc",
 )
 
@@ -188,6 +190,7 @@ def load() -> ctypes.CDLL:
         "ohm_batch_destroy": [vp],
         "ohm_map_kernel_times": [vp, vp, vp],
         "ohm_probe_atomic_rate": [vp, ctypes.c_size_t, ctypes.c_int, P(ctypes.c_double), vp],
+        "ohm_probe_stream_rate": [vp, vp, ctypes.c_size_t, ctypes.c_int, P(ctypes.c_double), vp],
         "ohm_ray_order_scratch_size": [ctypes.c_uint32, P(ctypes.c_size_t)],
         "ohm_map_set_ray_order": [vp, vp, ctypes.c_size_t, ctypes.c_uint32],
     }

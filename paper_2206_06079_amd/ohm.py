@@ -263,6 +263,21 @@ def probe_atomic_rate(footprint_bytes: int, sequential: bool = False, op: str = 
     return float(rate.value)
 
 
+def probe_stream_rate(footprint_bytes: int, read_only: bool = False, device=None, stream=None) -> float:
+    """Streaming bandwidth in bytes per second (read plus written) of a copy
+    of footprint_bytes between two device buffers, or of a read alone (see
+    ohm_probe_stream_rate)."""
+    dev = torch.device("cuda", 0) if device is None else torch.device(device)
+    n = max(16 << 20, int(footprint_bytes)) // 16 * 16
+    src = torch.zeros(n, dtype=torch.uint8, device=dev)
+    dst = torch.empty(n, dtype=torch.uint8, device=dev)
+    rate = ctypes.c_double(0.0)
+    check(load().ohm_probe_stream_rate(ctypes.c_void_p(src.data_ptr()), ctypes.c_void_p(dst.data_ptr()), n,
+                                       _lib.PROBE_READ_ONLY if read_only else 0, ctypes.byref(rate),
+                                       _stream_ptr(stream)), "ohm_probe_stream_rate")
+    return float(rate.value)
+
+
 def regions_needed(params, margin: float = 1.25) -> int:
     """Upper bound on regions for a map whose whole extent may be touched
     (used for small maps where reserving every region is cheap)."""

@@ -152,3 +152,25 @@ def test_product_never_imports_oracle():
             if f.endswith((".py", ".hip", ".h", ".cpp")):
                 text = open(os.path.join(dirpath, f)).read()
                 assert "oracle" not in re.sub(r"#.*|//.*", "", text).lower() or f == "build.py", f
+
+
+def test_probe_arguments_are_validated():
+    """Both measurement probes reject bad arguments before any device call."""
+    lib = _lib.load()
+    rate = ctypes.c_double(0.0)
+    big, fake = 64 << 20, ctypes.c_void_p(1 << 20)  # never dereferenced: rejected first
+    # stream probe: null buffers, unaligned buffers, too small, not a multiple of 16, unknown flags
+    assert lib.ohm_probe_stream_rate(None, fake, big, 0, ctypes.byref(rate), None) == _lib.OHM_E_INVALID_ARG
+    assert lib.ohm_probe_stream_rate(fake, None, big, 0, ctypes.byref(rate), None) == _lib.OHM_E_INVALID_ARG
+    assert lib.ohm_probe_stream_rate(ctypes.c_void_p((1 << 20) + 8), fake, big, 0, ctypes.byref(rate),
+                                     None) == _lib.OHM_E_INVALID_ARG
+    assert lib.ohm_probe_stream_rate(fake, fake, 1 << 20, 0, ctypes.byref(rate), None) == _lib.OHM_E_INVALID_ARG
+    assert lib.ohm_probe_stream_rate(fake, fake, big + 8, 0, ctypes.byref(rate), None) == _lib.OHM_E_INVALID_ARG
+    assert lib.ohm_probe_stream_rate(fake, fake, big, _lib.PROBE_SEQUENTIAL, ctypes.byref(rate),
+                                     None) == _lib.OHM_E_INVALID_ARG
+    assert lib.ohm_probe_stream_rate(fake, fake, big, 0, None, None) == _lib.OHM_E_INVALID_ARG
+    # atomic probe: null buffer, too small, conflicting operations
+    assert lib.ohm_probe_atomic_rate(None, big, 0, ctypes.byref(rate), None) == _lib.OHM_E_INVALID_ARG
+    assert lib.ohm_probe_atomic_rate(fake, 2, 0, ctypes.byref(rate), None) == _lib.OHM_E_INVALID_ARG
+    assert lib.ohm_probe_atomic_rate(fake, big, _lib.PROBE_F32_CAS | _lib.PROBE_U64_ADD, ctypes.byref(rate),
+                                     None) == _lib.OHM_E_INVALID_ARG

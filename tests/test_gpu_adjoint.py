@@ -26,10 +26,12 @@ def setup_case(n_scans, ndt=True, beams=64, cols=2048):
     return params, batch, box_min, box_dim, labels, mask, ref
 
 
-def gpu_grads(params, batch, box_min, box_dim, labels, mask, ndt=True, extra_layers=0):
+def gpu_grads(params, batch, box_min, box_dim, labels, mask, ndt=True, extra_layers=0, tuning=None):
     dev = device()
     layers = ohm.LAYER_ADJOINT | (ohm.LAYER_NDT if ndt else 0) | extra_layers
     m = ohm.OhmMap(params, 256, layers=layers, device=dev)
+    if tuning is not None:
+        m.set_tuning(*tuning)
     o, s, off, w = to_dev(batch)
     (m.ndt_integrate if ndt else m.integrate)(o, s, off, w)
     occ = m.read_dense(ohm.READ_OCC, box_min, box_dim).double()
@@ -140,3 +142,22 @@ def test_autograd_function():
     check(w.grad.cpu().numpy().astype(np.float64),
           np.array([l_hit.grad.item(), l_miss.grad.item(), sn.grad.item()]), ref,
           in_box_counts(params, batch, box_min, box_dim), batch.n_scans)
+
+
+@pytest.fixture(scope="module")
+def two_scan_case():
+    return setup_case(2)
+
+
+@pytest.mark.parametrize("tuning", [(4, 256), (7, 512), (64, 512)], ids=["K4-T256", "K7-T512", "K64-T512"])
+def test_ndt_and_adjoint_independent_of_segment_length(two_scan_case, tuning):
+    """The NDT walk and the backward walk (which skips segments outside the
+    loss box by their bounds) give the oracle's results at any segment
+    length and tile width; K = 4 at 0.2 m also fills the 32-level cap, whose
+    last level runs to the ray's end."""
+    params, batch, box_min, box_dim, labels, mask, ref = two_scan_case
+    gw, gs, occ, n_after = gpu_grads(params, batch, box_min, box_dim, labels, mask, tuning=tuning)
+    np.testing.assert_allclose(occ, ref["occ"], atol=1e-5, rtol=0)
+    check(gw, gs, ref, in_box_counts(params, batch, box_min, box_dim), batch.n_scans)
+    _, o_state, _, _ = oracle.ndt_integrate(params, batch, box_min, box_dim)
+    assert np.array_equal(n_after.astype(np.uint32), o_state.n)

@@ -223,7 +223,7 @@ __global__ __launch_bounds__(kBackwardMaxThreads, 4) void backward_seg_kernel(
       if (alive) {
         // a segment whose voxels all lie outside the loss box contributes
         // nothing (zero upstream gradient there, and no replayed sample)
-        const int64_t q0[3] = {tr.q0[0][ray_t], tr.q0[1][ray_t], tr.q0[2][ray_t]};
+        const int64_t q0[3] = {tr.q0[0], tr.q0[1], tr.q0[2]};
         const int64_t q1[3] = {tr.q1[0][ray_t], tr.q1[1][ray_t], tr.q1[2][ray_t]};
         int32_t lo[3], hi[3];
         seg_bounds(s, q0, q1, M, K, level + 1 == (uint32_t)kMaxLevels, m.F, lo, hi);

@@ -182,8 +182,15 @@ struct GroupArgs {
   uint32_t tile_end[kMaxGroupSlots];  // exclusive end of the scan's blocks
 };
 
-template <bool kWeighted, bool kLayers = false>
-__global__ __launch_bounds__(1024) void walk_group_kernel(DevMap m, const float* __restrict__ origins,
+// Tiles of up to 512 threads of the plain walk run three blocks per CU (six
+// waves per SIMD: the kernel is held to 80 VGPRs, and its 52 KB of LDS fit
+// three times); the extra waves hide more of the voxel loop's latency than
+// the spilled registers cost.  With the layers (kLayers) the loop holds too
+// much for 80 VGPRs, and 1024-thread tiles (kWideTile) fit one block per
+// CU: both keep the 128-VGPR budget.
+template <bool kWeighted, bool kLayers = false, bool kWideTile = false>
+__global__ __launch_bounds__((kWideTile || kLayers) ? 1024 : 512, (kWideTile || kLayers) ? 1 : 6) void walk_group_kernel(
+    DevMap m, const float* __restrict__ origins,
                                                           const float* __restrict__ samples,
                                                           const float* __restrict__ weights, GroupArgs g, int K,
                                                           uint32_t tag, uint32_t parity) {
@@ -694,12 +701,22 @@ template <bool kWeighted>
 void launch_walk_group(const ohm_map_s* map, bool layers, dim3 grid, dim3 block, hipStream_t st,
                        const float* origins, const float* samples, const float* weights, const GroupArgs& g, int K,
                        uint32_t tag, uint32_t parity) {
-  if (layers)
-    hipLaunchKernelGGL((walk_group_kernel<kWeighted, true>), grid, block, 0, st, map->dm, origins, samples, weights,
-                       g, K, tag, parity);
-  else
-    hipLaunchKernelGGL((walk_group_kernel<kWeighted, false>), grid, block, 0, st, map->dm, origins, samples, weights,
-                       g, K, tag, parity);
+  const bool wide = block.x > 512;
+  if (layers) {
+    if (wide)
+      hipLaunchKernelGGL((walk_group_kernel<kWeighted, true, true>), grid, block, 0, st, map->dm, origins, samples,
+                         weights, g, K, tag, parity);
+    else
+      hipLaunchKernelGGL((walk_group_kernel<kWeighted, true, false>), grid, block, 0, st, map->dm, origins, samples,
+                         weights, g, K, tag, parity);
+  } else {
+    if (wide)
+      hipLaunchKernelGGL((walk_group_kernel<kWeighted, false, true>), grid, block, 0, st, map->dm, origins, samples,
+                         weights, g, K, tag, parity);
+    else
+      hipLaunchKernelGGL((walk_group_kernel<kWeighted, false, false>), grid, block, 0, st, map->dm, origins, samples,
+                         weights, g, K, tag, parity);
+  }
 }
 
 }  // namespace ohm

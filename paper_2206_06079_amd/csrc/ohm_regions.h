@@ -25,10 +25,16 @@ constexpr int32_t kSlotNotCached = -4;
 constexpr int32_t kWindowMarked = -5;  // window entry of a region some ray enters, not yet resolved
 constexpr int kAllocSpinLimit = 1 << 20;  // bounded wait for a slot another block is publishing
 
+// A block stages its regions either in the dense window or in the hash set
+// (never both), so the two share their LDS.
 struct RegionCache {
-  int32_t key[kRegionCacheSize];
-  int32_t slot[kRegionCacheSize];
-  int32_t win[kRegionWindow];  // dense window: slot per region of the box, kSlotEmpty where no ray enters
+  union {
+    struct {
+      int32_t key[kRegionCacheSize];
+      int32_t slot[kRegionCacheSize];
+    };
+    int32_t win[kRegionWindow];  // dense window: slot per region of the box, kSlotEmpty where no ray enters
+  };
   int32_t lo[3], hi[3];        // region bounding box of the block's rays
 };
 

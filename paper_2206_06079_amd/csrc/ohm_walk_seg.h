@@ -171,7 +171,7 @@ __device__ __forceinline__ void drain_cas(const DevMap& m, const uint32_t* qid, 
 
 // Per-ray data a tile keeps in LDS.
 struct TileRays {
-  long long q0[3][kTileRays];
+  long long q0[3];  // the scan origin, quantised: every ray of a tile starts there
   long long q1[3][kTileRays];
   uint8_t nseg[kTileRays];
   uint8_t trunc[kTileRays];
@@ -247,7 +247,7 @@ __device__ __forceinline__ uint32_t tile_prologue(const DevMap& m, TileRays& tr,
       t.clipped = w.clip != 0;
       t.voxels = walk_voxels(w, t.r.q0, t.r.q1, m.F);
       for (int a = 0; a < 3; ++a) {
-        tr.q0[a][tid] = t.r.q0[a];
+        tr.q0[a] = t.r.q0[a];  // the same value from every ray
         tr.q1[a][tid] = t.r.q1[a];
       }
       tr.trunc[tid] = t.r.truncated ? 1 : 0;
@@ -295,6 +295,15 @@ __device__ __forceinline__ uint32_t tile_prologue(const DevMap& m, TileRays& tr,
   return tr.level_base[levels];
 }
 
+// A 64-bit value every lane of the wave holds (the tile's quantised
+// origin), moved to scalar registers so that it costs no vector registers
+// in the loops.
+__device__ __forceinline__ int64_t wave_uniform(int64_t v) {
+  const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)(uint64_t)v);
+  const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)((uint64_t)v >> 32));
+  return (int64_t)(((uint64_t)hi << 32) | lo);
+}
+
 // Item `it` of the list: its tile-local ray, major axis and segment state
 // (and, when asked, its segment level).  False when the segment is empty
 // (its ray left the map before it starts).
@@ -305,7 +314,7 @@ __device__ __forceinline__ bool tile_item(const DevMap& m, const TileRays& tr, u
   uint32_t level = 0;
   while (level + 1 < levels && tr.level_base[level + 1] <= it) ++level;
   if (level_out) *level_out = level;
-  const int64_t q0[3] = {tr.q0[0][ray_t], tr.q0[1][ray_t], tr.q0[2][ray_t]};
+  const int64_t q0[3] = {wave_uniform(tr.q0[0]), wave_uniform(tr.q0[1]), wave_uniform(tr.q0[2])};
   const int64_t q1[3] = {tr.q1[0][ray_t], tr.q1[1][ray_t], tr.q1[2][ray_t]};
   seg_init(s, q0, q1, m, (int)level, K);
   M = ray_major_axis(q0, q1);
@@ -443,7 +452,7 @@ __device__ void walk_tile(const DevMap& m, const float* __restrict__ origin, con
       uint32_t level = 0;
       alive = tile_item(m, tr, it, K, s, ray_t, M, &level);
       if (kLayers && m.decay_len && alive) {
-        const int64_t q0[3] = {tr.q0[0][ray_t], tr.q0[1][ray_t], tr.q0[2][ray_t]};
+        const int64_t q0[3] = {wave_uniform(tr.q0[0]), wave_uniform(tr.q0[1]), wave_uniform(tr.q0[2])};
         const int64_t q1[3] = {tr.q1[0][ray_t], tr.q1[1][ray_t], tr.q1[2][ray_t]};
         decay_init(dec, m, q0, q1, s, (int)level, M);
       }

@@ -351,7 +351,8 @@ __global__ __launch_bounds__(kNdtMaxThreads, 4) void ndt_seg_kernel(DevMap m, co
     for (int a = 0; a < 3; ++a) ray_end[a][tid] = t.r.end[a];
   __syncthreads();
   const double od[3] = {(double)origin[0], (double)origin[1], (double)origin[2]};
-  uint32_t n_upd = 0, n_drop = 0, n_hit = 0;
+  flush_tile_stats(m, t, (t.ok && !t.clipped && !t.r.truncated) ? 1u : 0u, t.ok ? t.voxels : 0u, 0u);
+  uint32_t w_drop = 0, w_hit_drop = 0;  // this wave's dropped updates and hits (wave-uniform)
   uint32_t pend_n = 0;  // this wave's queued sample-weighted misses (wave-uniform)
   NdtPending* wpend = pend[tid >> 6];
 
@@ -410,15 +411,12 @@ __global__ __launch_bounds__(kNdtMaxThreads, 4) void ndt_seg_kernel(DevMap m, co
       }
       const uint32_t id = has ? (((uint32_t)slot * (uint32_t)kRegionVoxels + lidx) << 1) | (is_hit ? 1u : 0u)
                               : (0xFFFFFFFFu - lane);
-      if (alive) {
-        if (slot >= 0) {
-          ++n_upd;
-          n_hit += is_hit ? 1u : 0u;
-        } else {
-          ++n_drop;
-        }
-        alive = !last && tile_advance<true>(m, rc, rw, s, M, slot, lidx);
+      const unsigned long long dropped = __ballot(alive && slot < 0);
+      if (dropped) {
+        w_drop += (uint32_t)__popcll(dropped);
+        w_hit_drop += (uint32_t)__popcll(dropped & __ballot(is_hit));
       }
+      if (alive) alive = !last && tile_advance<true>(m, rc, rw, s, M, slot, lidx);
       if (alive && slot >= 0 && slot != rb_slot) {
         rb_slot = slot;
         rb = m.ndt_ready_bricks[slot];
@@ -470,7 +468,7 @@ __global__ __launch_bounds__(kNdtMaxThreads, 4) void ndt_seg_kernel(DevMap m, co
     const uint32_t k = agg_key[h];
     if (k != kAggEmpty) ndt_apply<kCount>(m, k, (long long)agg_val[h]);
   }
-  flush_tile_stats(m, t, n_hit, n_upd, n_drop);
+  drop_tile_stats(m, w_drop, w_hit_drop);
 }
 
 template <bool kWeighted, bool kTm>

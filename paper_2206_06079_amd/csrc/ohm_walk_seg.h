@@ -342,7 +342,12 @@ __device__ __forceinline__ bool tile_advance(const DevMap& m, const RegionCache&
   return moved;
 }
 
-// Block statistics of a tile walk (every thread must call it).
+// Block statistics of a tile walk (every thread must call it).  The walks
+// flush them before their voxel loops, while the prepared rays are at hand
+// (so that nothing of them stays live through the loop), counting every
+// visit as an update and every untruncated ray ending in the map as a hit;
+// the loops then count, per wave, the updates and hits they drop (regions
+// the pool could not hold) and take them off with drop_tile_stats.
 __device__ __forceinline__ void flush_tile_stats(const DevMap& m, const TileRay& t, uint32_t n_hit, uint32_t n_upd,
                                                  uint32_t n_drop) {
   uint32_t vals[kStatCount];
@@ -355,6 +360,16 @@ __device__ __forceinline__ void flush_tile_stats(const DevMap& m, const TileRay&
   vals[kStatUpdates] = n_upd;
   vals[kStatDropped] = n_drop;
   flush_stats(m, vals);
+}
+
+// Take one wave's dropped updates (of which `hits` were hits) off the
+// statistics (modulo-2^64 sums); called by every lane, wave-uniform counts.
+__device__ __forceinline__ void drop_tile_stats(const DevMap& m, uint32_t drops, uint32_t hits) {
+  if (drops != 0u && lane_id() == 0u) {
+    atomicAdd(m.stats + kStatUpdates, 0ull - (unsigned long long)drops);
+    atomicAdd(m.stats + kStatHits, 0ull - (unsigned long long)hits);
+    atomicAdd(m.stats + kStatDropped, (unsigned long long)drops);
+  }
 }
 
 // Occupancy walk of the tile of rays [tile0, tile0 + kTileRays) of a scan
@@ -431,7 +446,8 @@ __device__ void walk_tile(const DevMap& m, const float* __restrict__ origin, con
     ray_counts[ray] = t.ok ? t.voxels : 0u;
     ray_flags[ray] = flags;
   }
-  uint32_t n_drop = 0, n_hit_drop = 0;
+  flush_tile_stats(m, t, (t.ok && !t.clipped && !t.r.truncated) ? 1u : 0u, t.ok ? t.voxels : 0u, 0u);
+  uint32_t w_drop = 0, w_hit_drop = 0;  // this wave's dropped updates and hits (wave-uniform)
 
   // segment walks, one item per thread per round, with lane-run merging
   const uint32_t rounds = (items + blockDim.x - 1) / blockDim.x;
@@ -490,9 +506,10 @@ __device__ void walk_tile(const DevMap& m, const float* __restrict__ origin, con
         const uint32_t k = emit_here ? agg_key[kLine ? line_slot(id >> 4) : agg_slot(id)] : 0u;
         // updates and hits are counted per ray below; only drops (region
         // pool exhausted) are counted here
-        if (alive && !has) {
-          ++n_drop;
-          n_hit_drop += is_hit ? 1u : 0u;
+        const unsigned long long dropped = __ballot(alive && !has);
+        if (dropped) {
+          w_drop += (uint32_t)__popcll(dropped);
+          w_hit_drop += (uint32_t)__popcll(dropped & __ballot(is_hit));
         }
         if constexpr (kLayers) {
           if (m.decay_len) {
@@ -618,12 +635,7 @@ __device__ void walk_tile(const DevMap& m, const float* __restrict__ origin, con
       if (slot != kAggEmpty) atomicOr(m.brick_mask + slot, bk_mask[h]);
     }
   }
-  // every voxel a ray visits is an update unless dropped; a ray that ends
-  // inside the map and is not truncated ends in its hit (modulo-2^32 sums:
-  // only the block total matters)
-  const uint32_t ray_voxels = t.ok ? t.voxels : 0u;
-  const uint32_t ray_hit = (t.ok && !t.clipped && !t.r.truncated) ? 1u : 0u;
-  flush_tile_stats(m, t, ray_hit - n_hit_drop, ray_voxels - n_drop, n_drop);
+  drop_tile_stats(m, w_drop, w_hit_drop);
 }
 
 }  // namespace ohm

@@ -133,10 +133,12 @@ def timed(fn, steps, stream):
     return [a.elapsed_time(b) for a, b in ev]
 
 
-def run_map(args, params, batch, mode, layers=1, call="integrate", steps=None, capacity=None, extra=None):
+def run_map(args, params, batch, mode, layers=1, call="integrate", steps=None, capacity=None, extra=None,
+            column_rays=0):
     """Time `steps` calls of OhmMap.<call> over the whole batch on one map
     (after the warm-up calls); returns per-step times, kernel times and the
-    per-step rays and updates."""
+    per-step rays and updates.  column_rays: the scans' column layout
+    declared to the map (OhmMap.set_scan_layout), 0 for none."""
     import torch
 
     import paper_2206_06079_amd as ohm
@@ -146,6 +148,8 @@ def run_map(args, params, batch, mode, layers=1, call="integrate", steps=None, c
     s = torch.from_numpy(batch.samples).to(dev)
     off = batch.offsets
     m = ohm.OhmMap(params.replace(mode=mode), capacity or args.capacity, layers=layers, device=dev)
+    if column_rays:
+        m.set_scan_layout(column_rays)
     fn_call = getattr(m, call)
     x = extra or ()
     if call == "ndt_tm_integrate":
@@ -359,7 +363,7 @@ def run_layers(args, params, batch):
     groups = ohm.LAYER_SCAN_GROUPS | ohm.scan_group_slots(args.scan_group_slots)
     for name, layer in (("occupancy_with_mean", ohm.LAYER_MEAN), ("occupancy_with_decay_rate", ohm.LAYER_DECAY)):
         r = run_map(args, params, batch, ohm.MODE_COUNT_CLAMP, ohm.LAYER_OCC | groups | layer,
-                    steps=max(2, args.steps // 2))
+                    steps=max(2, args.steps // 2), column_rays=args.scan_layout)
         out[name] = leg_summary(r, f"the {batch.n_scans} headline scans, count mode, "
                                    f"{args.scan_group_slots}-scan groups, with the layer")
         log(f"{name}: {r['ms_per_step']:.3f} ms per step")
@@ -498,6 +502,9 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--scans", type=int, default=100)
     ap.add_argument("--capacity", type=int, default=512)
+    ap.add_argument("--scan-layout", type=int, default=64,
+                    help="rays per column declared for the grouped legs (the scans are column-major "
+                         "64-beam range images; 0: walk them in the given order)")
     ap.add_argument("--scan-group-slots", type=int, default=50,
                     help="accumulator slots of the headline map (scans walked per launch)")
     ap.add_argument("--cpu-scans", type=int, default=100)
@@ -557,7 +564,8 @@ def main():
     single = run_map(args, params, batch, ohm.MODE_COUNT_CLAMP)
     log(f"count mode, one launch per scan: {single['ms_per_step']:.3f} ms/step, kernels {single['kernels']}")
     res = run_map(args, params, batch, ohm.MODE_COUNT_CLAMP,
-                  ohm.LAYER_OCC | ohm.LAYER_SCAN_GROUPS | ohm.scan_group_slots(args.scan_group_slots))
+                  ohm.LAYER_OCC | ohm.LAYER_SCAN_GROUPS | ohm.scan_group_slots(args.scan_group_slots),
+                  column_rays=args.scan_layout)
     log(f"count mode, {args.scan_group_slots}-scan groups: {res['ms_per_step']:.3f} ms/step, kernels {res['kernels']}")
     scans = args.scans
     rays_per_scan = res["rays_per_step"] / scans
@@ -703,6 +711,7 @@ def main():
                         "0.1 m voxels, 32^3 regions over 200x200x40 m, 30 m max range",
             "mode": "count_clamp",
             "scan_groups": args.scan_group_slots,
+            "scan_layout_column_rays": args.scan_layout,
             "n_scans": scans,
             "rays_per_scan": int(rays_per_scan),
         },

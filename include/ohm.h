@@ -383,7 +383,9 @@ typedef struct {
   uint32_t seg_major_steps;  /* walk segment length, as in ohm_walk_tuning (0: 16) */
   uint32_t tile_threads;     /* threads per 256-ray tile: 256, 512 or 1024 (0: 512) */
   uint32_t keep_ray_order;   /* 0: each run walks every scan's rays in direction order
-                                (strips of azimuth, then elevation), which keeps a tile's
+                                (azimuth strips of about 2,048 rays, then elevation: a
+                                tile covers a patch of directions about as wide as it is
+                                tall), which keeps a tile's
                                 rays together when a scan's directions arrive unordered;
                                 nonzero: walk them in the given order (scans already in
                                 sensor order).  Never changes results. */
@@ -417,7 +419,8 @@ ohm_status ohm_map_set_tuning(ohm_map map, const ohm_walk_tuning* tuning);
  * tile works best when its 256 rays point close together, as a spinning
  * lidar's scan order gives; a scan whose ray directions arrive unordered can
  * instead be walked in direction order (azimuth strips of about 256 rays,
- * then elevation).  Attaching a scratch buffer turns this on for every scan
+ * then elevation: tiles of about equal work, which one scan's launch needs;
+ * the batched plan's strips are eight tiles wide).  Attaching a scratch buffer turns this on for every scan
  * of at most max_rays rays (longer scans walk in their given order); it
  * costs three small kernels per scan and never changes results.
  * ohm_ray_order_scratch_size gives the bytes for max_rays (> 0).
@@ -426,6 +429,21 @@ ohm_status ohm_map_set_tuning(ohm_map map, const ohm_walk_tuning* tuning);
  * calls on one map must not overlap while it is attached. */
 ohm_status ohm_ray_order_scratch_size(uint32_t max_rays, size_t* bytes);
 ohm_status ohm_map_set_ray_order(ohm_map map, void* d_scratch, size_t bytes, uint32_t max_rays);
+
+/* Column layout of the map's scans, for the walk order of the grouped walk
+ * (OHM_LAYER_SCAN_GROUPS, count mode).  column_rays = R > 0 declares that
+ * every scan arrives as a column-major range image of R rays per column
+ * (ray = column * R + beam), as a spinning multi-beam lidar (Table I)
+ * emits it: each full chunk of 32 columns is then walked as R / 8 tiles of
+ * 8 beams by 32 columns instead of 256 consecutive rays (4 columns of a
+ * 64-beam sensor), patches about square in angle whose rays share about
+ * twice as many voxels (a partial last chunk keeps the given order).  Only
+ * the order of the walk changes, never the result; a scan not laid out so
+ * is still integrated correctly, only without the gain.  The per-scan path
+ * keeps the given order: one scan's launch has too few tiles to even out
+ * the patches' unequal lengths.  R: 0 (the given order, the default) or a
+ * multiple of 8 up to 65536; anything else is OHM_E_INVALID_ARG. */
+ohm_status ohm_map_set_scan_layout(ohm_map map, uint32_t column_rays);
 
 /*
  * For callers that cannot allocate (code under HIP graph capture, tight

@@ -61,7 +61,7 @@ EXPORTS = (
     "ohm_map_set_profiling", "ohm_map_kernel_times", "ohm_backward",
     "ohm_batch_workspace_size", "ohm_batch_create", "ohm_batch_run", "ohm_batch_destroy",
     "ohm_map_set_tuning", "ohm_probe_atomic_rate", "ohm_probe_stream_rate", "ohm_ray_order_scratch_size",
-    "ohm_map_set_ray_order",
+    "ohm_map_set_ray_order", "ohm_map_set_scan_layout",
     "ohm_build_source_digest", "ohm_ndt_tm_integrate", "ohm_tsdf_integrate", "ohm_integrate_rays_no_alloc",
 )
 
@@ -193,6 +193,7 @@ def load() -> ctypes.CDLL:
         "ohm_probe_stream_rate": [vp, vp, ctypes.c_size_t, ctypes.c_int, P(ctypes.c_double), vp],
         "ohm_ray_order_scratch_size": [ctypes.c_uint32, P(ctypes.c_size_t)],
         "ohm_map_set_ray_order": [vp, vp, ctypes.c_size_t, ctypes.c_uint32],
+        "ohm_map_set_scan_layout": [vp, ctypes.c_uint32],
     }
     for name, args in sig.items():
         fn = getattr(lib, name)

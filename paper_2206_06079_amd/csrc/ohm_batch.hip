@@ -69,7 +69,8 @@ __global__ __launch_bounds__(256) void order_hist_kernel(const SetPtrs* __restri
   const uint32_t i = d.block * kTileRays + threadIdx.x;
   if (i >= d.n) return;
   const SetPtrs sp = sets[d.set];
-  order_count(sp.origins + 3 * (size_t)d.scan, sp.samples + 3 * (size_t)d.r0, d.n, i, hist + d.hbase);
+  order_count(sp.origins + 3 * (size_t)d.scan, sp.samples + 3 * (size_t)d.r0, d.n, kOrderStripRaysPlan, i,
+              hist + d.hbase);
 }
 
 // one block per strip of every scan (strip s of the plan: bins [256 s, 256 s + 256))
@@ -93,7 +94,8 @@ __global__ __launch_bounds__(256) void order_scatter_kernel(const SetPtrs* __res
   const uint32_t i = d.block * kTileRays + threadIdx.x;
   if (i >= d.n) return;
   const SetPtrs sp = sets[d.set];
-  order_place(sp.origins + 3 * (size_t)d.scan, sp.samples + 3 * (size_t)d.r0, d.n, i, hist + d.hbase,
+  order_place(sp.origins + 3 * (size_t)d.scan, sp.samples + 3 * (size_t)d.r0, d.n, kOrderStripRaysPlan, i,
+              hist + d.hbase,
               sums + d.sbase, sp.perm + d.r0);
 }
 
@@ -320,10 +322,11 @@ ohm_status plan_layout(const ohm_scan_set* sets, uint32_t n_sets, const ohm_batc
     for (uint32_t sc = 0; sc < sets[si].n_scans && order; ++sc) {
       const uint32_t n = sets[si].h_scan_offsets[sc + 1] - sets[si].h_scan_offsets[sc];
       if (n == 0) continue;
-      if ((strips + order_strips(n)) * kOrderElevationBins > 0xFFFFFFFFull) return OHM_E_UNSUPPORTED;
+      const uint32_t ns = order_strips(n, kOrderStripRaysPlan);
+      if ((strips + ns) * kOrderElevationBins > 0xFFFFFFFFull) return OHM_E_UNSUPPORTED;
       sbase[si][sc] = (uint32_t)strips;
-      L->host_scans.push_back({(uint32_t)strips, order_strips(n)});
-      strips += order_strips(n);
+      L->host_scans.push_back({(uint32_t)strips, ns});
+      strips += ns;
     }
   }
   L->strips = strips;

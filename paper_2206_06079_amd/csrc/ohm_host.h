@@ -29,6 +29,7 @@ struct ohm_map_s {
   bool kept_wide;          // ... as Q32.32 weight sums (a weighted scan), two f32 slots wide
   int seg_major_steps;     // walk tuning (ohm_map_set_tuning)
   uint32_t walk_threads;
+  uint32_t column_rays;    // scans' column layout (ohm_map_set_scan_layout), 0: none
   // direction ordering of scans (ohm_map_set_ray_order): caller scratch
   uint32_t* order_hist;
   uint32_t* order_sums;
@@ -60,6 +61,7 @@ inline uint32_t group_slots_of(uint32_t layers) {
   return n <= kMaxGroupSlots ? n : 0u;
 }
 constexpr int kDefaultSegMajorSteps = 16;
+constexpr uint32_t kMaxColumnRays = 65536;  // ohm_map_set_scan_layout
 constexpr uint32_t kDefaultTileThreads = 512;
 
 // kernels shared across translation units

@@ -74,7 +74,7 @@ __global__ __launch_bounds__(256) void scan_order_count_kernel(const float* __re
                                                                const float* __restrict__ samples, uint32_t n,
                                                                uint32_t* __restrict__ hist) {
   const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < n) order_count(origin, samples, n, i, hist);
+  if (i < n) order_count(origin, samples, n, kOrderStripRaysScan, i, hist);
 }
 
 __global__ __launch_bounds__(kOrderElevationBins) void scan_order_strip_kernel(uint32_t* __restrict__ hist,
@@ -93,7 +93,7 @@ __global__ __launch_bounds__(256) void scan_order_place_kernel(const float* __re
                                                                const uint32_t* __restrict__ sums,
                                                                uint32_t* __restrict__ perm) {
   const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < n) order_place(origin, samples, n, i, hist, sums, perm);
+  if (i < n) order_place(origin, samples, n, kOrderStripRaysScan, i, hist, sums, perm);
 }
 
 // ---------------------------------------------------------------------------
@@ -176,6 +176,7 @@ __global__ __launch_bounds__(256) void finalize_kernel(DevMap m, uint32_t parity
 // tiles alone leave most compute units idle behind its longest tiles.
 struct GroupArgs {
   uint32_t count;                  // scans in the group
+  uint32_t col_rays;               // column layout of the scans (column_patch_index), 0: none
   uint32_t scan[kMaxGroupSlots];      // scan index within the call
   uint32_t r0[kMaxGroupSlots];        // first ray
   uint32_t n[kMaxGroupSlots];         // rays
@@ -204,7 +205,7 @@ __global__ __launch_bounds__((kWideTile || kLayers) ? 1024 : 512, (kWideTile || 
     mj.mean_slot = j;
   }
   walk_tile<kSinkCount, kWeighted, kLayers>(mj, origins + 3 * (size_t)g.scan[j], samples, weights, nullptr, g.r0[j], g.n[j],
-                                   tile * kTileRays, K, tag, parity, nullptr, nullptr, nullptr, nullptr);
+                                   tile * kTileRays, K, tag, parity, nullptr, nullptr, nullptr, nullptr, g.col_rays);
 }
 
 constexpr int kGroupBatch = 8;  // accumulator slots loaded together by a group finalize
@@ -557,13 +558,13 @@ void launch_fill(void* p, size_t bytes, uint32_t v, hipStream_t st) {
 }  // namespace
 
 size_t order_scratch_bytes(uint32_t max_rays) {
-  return align_up((size_t)order_bins(max_rays) * sizeof(uint32_t)) +
+  return align_up((size_t)order_bins(max_rays, kOrderStripRaysScan) * sizeof(uint32_t)) +
          align_up((size_t)kOrderMaxStrips * sizeof(uint32_t)) + align_up((size_t)max_rays * sizeof(uint32_t));
 }
 
 OrderScratch order_scratch_at(void* base, uint32_t max_rays) {
   char* b = static_cast<char*>(base);
-  const size_t hist_bytes = align_up((size_t)order_bins(max_rays) * sizeof(uint32_t));
+  const size_t hist_bytes = align_up((size_t)order_bins(max_rays, kOrderStripRaysScan) * sizeof(uint32_t));
   const size_t sums_bytes = align_up((size_t)kOrderMaxStrips * sizeof(uint32_t));
   return OrderScratch{reinterpret_cast<uint32_t*>(b), reinterpret_cast<uint32_t*>(b + hist_bytes),
                       reinterpret_cast<uint32_t*>(b + hist_bytes + sums_bytes), max_rays};
@@ -774,6 +775,7 @@ ohm_status ohm_map_create(const ohm_params* params, uint32_t region_capacity, ui
   map->group_slots = group_slots_of(layers);
   map->seg_major_steps = kDefaultSegMajorSteps;
   map->walk_threads = kDefaultTileThreads;
+  map->column_rays = 0;
   map->order_hist = map->order_sums = map->order_perm = nullptr;
   map->order_max_rays = 0;
   map->regions = L.regions;
@@ -881,6 +883,7 @@ ohm_status integrate_rays_impl(ohm_map map, const float* d_origins, const float*
     uint32_t sc = 0;
     while (sc <= last && group_max > 0) {
       GroupArgs g = {};
+      g.col_rays = map->column_rays;
       uint32_t tiles = 0;
       for (; sc <= last && g.count < group_max; ++sc) {
         const uint32_t r0 = h_scan_offsets[sc];
@@ -946,7 +949,7 @@ ohm_status integrate_rays_impl(ohm_map map, const float* d_origins, const float*
       ProfScope ps(map, OHM_KERNEL_OTHER, st, prof);
       const float* o = d_origins + 3 * (size_t)sc;
       const float* smp = d_samples + 3 * (size_t)r0;
-      const uint32_t bins = order_bins(n), strips = order_strips(n);
+      const uint32_t bins = order_bins(n, kOrderStripRaysScan), strips = order_strips(n, kOrderStripRaysScan);
       hipLaunchKernelGGL(fill_u32_kernel, dim3((bins + 255) / 256 < 8192 ? (bins + 255) / 256 : 8192), dim3(256), 0,
                          st, ord.hist, (size_t)bins, 0u);
       hipLaunchKernelGGL(scan_order_count_kernel, dim3((n + 255) / 256), dim3(256), 0, st, o, smp, n,
@@ -1152,6 +1155,13 @@ ohm_status ohm_map_set_tuning(ohm_map map, const ohm_walk_tuning* t) {
   if (t->tile_threads != 256 && t->tile_threads != 512 && t->tile_threads != 1024) return OHM_E_INVALID_ARG;
   map->seg_major_steps = (int)t->seg_major_steps;
   map->walk_threads = t->tile_threads;
+  return OHM_OK;
+}
+
+ohm_status ohm_map_set_scan_layout(ohm_map map, uint32_t column_rays) {
+  if (!map) return OHM_E_INVALID_ARG;
+  if (column_rays % 8u != 0u || column_rays > kMaxColumnRays) return OHM_E_INVALID_ARG;
+  map->column_rays = column_rays;
   return OHM_OK;
 }
 

@@ -195,9 +195,28 @@ struct TileRay {
 // Region staging done by the prologue.
 enum : int { kStageNone = 0, kStageResolve = 1, kStageTouch = 2 };
 
+// Walk position i of a scan of n rays that arrives as a column-major range
+// image of R rays per column (ray = column * R + beam, R a multiple of 8):
+// every full chunk of 32 columns is walked as R / 8 tiles of 8 beams by 32
+// columns, consecutive walk positions (lanes) taking consecutive columns of
+// one beam; a partial last chunk keeps the given order.  A bijection on
+// each chunk.  A tile of the sensor's own order is 4 columns by 64 beams, a
+// sliver 0.7 by 45 degrees on a 64-beam spinning lidar; the 32-by-8 patch is
+// about square in angle and its rays share about twice as many voxels, so
+// the tile's table flushes half as many global atomics and adjacent lanes
+// more often step through the same voxel.
+__device__ __forceinline__ uint32_t column_patch_index(uint32_t i, uint32_t n, uint32_t R) {
+  const uint32_t chunk = 32u * R;
+  const uint32_t base = i - i % chunk;
+  if (n - base < chunk) return i;
+  const uint32_t j = i - base, u = j >> 8, p = j & 255u;
+  return base + (p & 31u) * R + u * 8u + (p >> 5);
+}
+
 // Prologue of a tile walk (every thread of the block must call it): threads
 // 0..255 prepare rays tile0.. of the scan in walk order (perm[i] is the scan
-// index of walk position i; null: the scan's own order), reject rays whose
+// index of walk position i; null: column_patch_index with col_rays = R when
+// it is nonzero, else the scan's own order), reject rays whose
 // weight (when weights is not null) is negative or not finite, and fill the LDS
 // ray table, the block stages the tile's regions in LDS (kStage), and the
 // level-major item list is built: level j lists, in ray order, the rays with
@@ -208,7 +227,8 @@ __device__ __forceinline__ uint32_t tile_prologue(const DevMap& m, TileRays& tr,
                                                   const float* __restrict__ origin, const float* __restrict__ samples,
                                                   const float* __restrict__ weights,
                                                   const uint32_t* __restrict__ perm, uint32_t r0, uint32_t n,
-                                                  uint32_t tile0, int K, uint32_t tag, uint32_t parity, TileRay& t) {
+                                                  uint32_t tile0, int K, uint32_t tag, uint32_t parity, TileRay& t,
+                                                  uint32_t col_rays = 0) {
   const uint32_t tid = threadIdx.x;
   const uint32_t lane = lane_id();
   const bool holds_ray = tid < (uint32_t)kTileRays;
@@ -220,7 +240,11 @@ __device__ __forceinline__ uint32_t tile_prologue(const DevMap& m, TileRays& tr,
   if (tid == 0) tr.max_seg = 0;
   bool bad_weight = false;
   if (t.inrange) {
-    const uint32_t src = perm ? perm[tile0 + tid] : tile0 + tid;
+    uint32_t src = tile0 + tid;
+    if (perm)
+      src = perm[src];
+    else if (col_rays)
+      src = column_patch_index(src, n, col_rays);
     tr.src[tid] = src;
     const size_t ray = (size_t)r0 + src;
     const float o[3] = {origin[0], origin[1], origin[2]};
@@ -377,15 +401,16 @@ __device__ __forceinline__ void drop_tile_stats(const DevMap& m, uint32_t drops,
 // kLayers the voxel mean and decay-rate layers the map holds are updated
 // too (ohm_layers.h); with kBricks (count sink) the bricks that received
 // counts are marked in m.brick_mask, and with kLineTable (unit-weight count
-// sink) updates aggregate in the line table instead of the id table.  Every
-// thread of the block must call it.
+// sink) updates aggregate in the line table instead of the id table.
+// col_rays: the scan's column layout for the walk order (tile_prologue).
+// Every thread of the block must call it.
 template <int kSink, bool kWeighted, bool kLayers = false, bool kBricks = false, bool kLineTable = false>
 __device__ void walk_tile(const DevMap& m, const float* __restrict__ origin, const float* __restrict__ samples,
                           const float* __restrict__ weights, const uint32_t* __restrict__ perm, uint32_t r0,
                           uint32_t n, uint32_t tile0, int K,
                           uint32_t tag, uint32_t parity, uint32_t* __restrict__ ray_counts,
                           int32_t* __restrict__ ray_flags, const int64_t* __restrict__ ray_offsets,
-                          int32_t* __restrict__ updates) {
+                          int32_t* __restrict__ updates, uint32_t col_rays = 0) {
   constexpr bool kAccum = kSink == kSinkCount || kSink == kSinkCas;
   constexpr int kStage = kSink == kSinkCount ? kStageTouch : (kSink == kSinkCas ? kStageResolve : kStageNone);
   constexpr bool kLine = kLineTable && kSink == kSinkCount && !kWeighted;
@@ -431,7 +456,7 @@ __device__ void walk_tile(const DevMap& m, const float* __restrict__ origin, con
   RegionWindow rw;
   const uint32_t items =
       tile_prologue<kStage>(m, tr, rc, rw, origin, samples, kWeighted ? weights : nullptr, perm, r0, n, tile0, K,
-                            tag, parity, t);
+                            tag, parity, t, col_rays);
 
   if (kSink == kSinkTraceCount && t.inrange) {
     int32_t flags = 0;

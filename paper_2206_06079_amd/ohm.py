@@ -212,6 +212,13 @@ class OhmMap:
         t = _lib.WalkTuning(int(seg_major_steps), int(tile_threads))
         check(load().ohm_map_set_tuning(self.handle, ctypes.byref(t)), "ohm_map_set_tuning")
 
+    def set_scan_layout(self, column_rays: int):
+        """Declare the scans column-major range images of ``column_rays``
+        rays per column (ohm_map_set_scan_layout): the grouped walk then
+        takes 8-beam by 32-column patches as tiles; 0 restores the given
+        order."""
+        check(load().ohm_map_set_scan_layout(self.handle, int(column_rays)), "ohm_map_set_scan_layout")
+
     def set_ray_order(self, max_rays: int):
         """Walk every scan of at most ``max_rays`` rays in direction order
         (ohm_map_set_ray_order); 0 turns it off.  The scratch buffer is held

@@ -142,6 +142,7 @@ def test_ray_order_scratch_arguments():
     # 512 strips x 256 elevation bins, plus one permutation entry per ray, 4 bytes each
     assert sz.value >= 4 * (512 * 256 + 131072)
     assert lib.ohm_map_set_ray_order(None, None, 0, 0) == _lib.OHM_E_INVALID_ARG
+    assert lib.ohm_map_set_scan_layout(None, 64) == _lib.OHM_E_INVALID_ARG
 
 
 def test_product_never_imports_oracle():

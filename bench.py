@@ -662,7 +662,7 @@ def main():
         # what reaches memory: the L2 atomic requests per launch (counter
         # TCC_ATOMIC), their share of the updates and their rate
         "atomic_requests_per_launch": requests,
-        "merge_factor": round(requests / launch_upd, 4) if requests else None,
+        "merge_factor": round(launch_upd / requests, 2) if requests else None,  # updates per atomic request
         "request_rate_per_s": round(requests / (walk_avg_ms * 1e-3), 1) if requests else None,
         "request_frac_vs_random": round(requests / (walk_avg_ms * 1e-3) / ceiling, 4) if requests else None,
     }

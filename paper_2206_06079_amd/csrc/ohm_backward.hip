@@ -185,7 +185,7 @@ __global__ __launch_bounds__(kBackwardMaxThreads, 4) void backward_seg_kernel(
   __shared__ double ray_gw[kTileRays];
   __shared__ BwdPending pend[kBackwardMaxThreads / 64][64];
   const uint32_t tid = threadIdx.x;
-  const uint32_t tile0 = blockIdx.x * kTileRays;
+  const uint32_t tile0 = xcd_tile(blockIdx.x, gridDim.x) * kTileRays;
   const float* origin = origins + 3 * (size_t)scan;
   TileRay t;
   RegionWindow rw;

@@ -103,6 +103,11 @@ template <bool kWeighted>
 __global__ __launch_bounds__(1024) void batch_walk_kernel(const DevMap* __restrict__ maps,
                                                           const SetPtrs* __restrict__ sets,
                                                           const BlockDesc* __restrict__ descs, int K) {
+  // blocks stay dealt round-robin over the XCDs (no xcd_tile): a plan's
+  // launch mixes maps of different voxel sizes and scans of very different
+  // lengths, and a contiguous eighth of it per XCD leaves the XCD holding the
+  // finer map's tiles as the launch's tail (17 % slower on the 16-stream
+  // workload, where the single-map walks gain 6-15 %)
   const BlockDesc d = descs[blockIdx.x];
   DevMap m = maps[d.set];
   m.acc += (size_t)d.pos * acc_slot_floats(m, kWeighted);

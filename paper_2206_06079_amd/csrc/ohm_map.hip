@@ -65,7 +65,8 @@ __global__ __launch_bounds__(1024) void walk_seg_kernel(DevMap m, const float* _
                                                         const int64_t* __restrict__ ray_offsets,
                                                         int32_t* __restrict__ updates) {
   walk_tile<kSink, kWeighted, kLayers>(m, origins + 3 * (size_t)scan, samples, weights, perm, r0, n,
-                                       blockIdx.x * kTileRays, K, tag, parity, ray_counts, ray_flags, ray_offsets,
+                                       xcd_tile(blockIdx.x, gridDim.x) * kTileRays, K, tag, parity, ray_counts,
+                                       ray_flags, ray_offsets,
                                        updates);
 }
 
@@ -195,9 +196,10 @@ __global__ __launch_bounds__((kWideTile || kLayers) ? 1024 : 512, (kWideTile || 
                                                           const float* __restrict__ samples,
                                                           const float* __restrict__ weights, GroupArgs g, int K,
                                                           uint32_t tag, uint32_t parity) {
+  const uint32_t lb = xcd_tile(blockIdx.x, gridDim.x);  // the launch's tile index
   uint32_t j = 0;  // the block's scan (uniform over the block)
-  while (j + 1 < g.count && blockIdx.x >= g.tile_end[j]) ++j;
-  const uint32_t tile = blockIdx.x - (j ? g.tile_end[j - 1] : 0u);
+  while (j + 1 < g.count && lb >= g.tile_end[j]) ++j;
+  const uint32_t tile = lb - (j ? g.tile_end[j - 1] : 0u);
   DevMap mj = m;
   mj.acc += (size_t)j * acc_slot_floats(m, kWeighted);
   if (kLayers && mj.mean) {

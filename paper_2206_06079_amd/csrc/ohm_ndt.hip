@@ -336,7 +336,7 @@ __global__ __launch_bounds__(kNdtMaxThreads, 4) void ndt_seg_kernel(DevMap m, co
   NdtPending(*pend)[64] = sm.w.pend;
   const uint32_t tid = threadIdx.x;
   const uint32_t lane = lane_id();
-  const uint32_t tile0 = blockIdx.x * kTileRays;
+  const uint32_t tile0 = xcd_tile(blockIdx.x, n_tiles) * kTileRays;  // blocks < n_tiles are tiles
   const float* origin = origins + 3 * (size_t)scan;
   for (uint32_t h = tid; h < kNdtAggSize; h += blockDim.x) {
     agg_key[h] = kAggEmpty;

@@ -8,6 +8,18 @@
 
 namespace ohm {
 
+// The tile a block of a tiled launch of nb blocks walks.  The device deals
+// a launch's blocks to its 8 XCDs round-robin (block b to XCD b % 8), and
+// each XCD has its own L2; this mapping gives every XCD a contiguous eighth
+// of the tiles instead, so that neighbouring tiles of a scan, which share
+// the voxels, regions and accumulator lines near their sensor, meet in one
+// L2.  A bijection on [0, nb); the first nb % 8 XCDs take one tile more.
+__device__ __forceinline__ uint32_t xcd_tile(uint32_t b, uint32_t nb) {
+  constexpr uint32_t kXcds = 8;
+  const uint32_t per = nb / kXcds, rem = nb % kXcds, x = b % kXcds;
+  return x * per + (x < rem ? x : rem) + b / kXcds;
+}
+
 // value of lane (l - 1); lane 0 receives `fill` (DPP wave_shr:1)
 __device__ __forceinline__ uint32_t wave_shr1(uint32_t v, uint32_t fill) {
   return (uint32_t)__builtin_amdgcn_update_dpp((int)fill, (int)v, 0x138, 0xf, 0xf, false);

@@ -336,7 +336,9 @@ __global__ __launch_bounds__(kNdtMaxThreads, 4) void ndt_seg_kernel(DevMap m, co
   NdtPending(*pend)[64] = sm.w.pend;
   const uint32_t tid = threadIdx.x;
   const uint32_t lane = lane_id();
-  const uint32_t tile0 = xcd_tile(blockIdx.x, n_tiles) * kTileRays;  // blocks < n_tiles are tiles
+  // blocks < n_tiles are tiles; per-update mode (compare-and-swap) keeps the
+  // round-robin deal over the XCDs, as the occupancy walk does
+  const uint32_t tile0 = (kCount ? xcd_tile(blockIdx.x, n_tiles) : blockIdx.x) * kTileRays;
   const float* origin = origins + 3 * (size_t)scan;
   for (uint32_t h = tid; h < kNdtAggSize; h += blockDim.x) {
     agg_key[h] = kAggEmpty;

@@ -88,7 +88,6 @@ struct DevMap {
   float* acc;         // [capacity][V][2]: miss weight, hit weight
   NdtVoxel* ndt;      // [capacity][V] or null
   uint32_t* ndt_ready;  // [capacity][V / 32]: bit set where the voxel holds >= ndt_min_samples samples
-  unsigned long long* ndt_ready_bricks;  // [capacity]: bit b set when brick b of the region may hold a ready voxel
   long long* nacc;    // NDT per-scan accumulators [capacity][V][kNaccWords] or null
   uint32_t* nsamp;    // NDT per-scan sample counts [capacity][V] or null
   double* mom;        // NDT per-scan sample moments [capacity][V][kMomWords] or null

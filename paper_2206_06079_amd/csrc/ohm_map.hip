@@ -398,7 +398,7 @@ inline size_t align_up(size_t v) { return (v + kAlign - 1) & ~(kAlign - 1); }
 
 struct Layout {
   size_t hdr, stats, table, stamp, touched, occ, acc, ndt, nacc, mom, clampscan, mean, mean_acc, mean_mask,
-      decay_len, decay_hits, tm, tm_mom, tsdf, tsdf_acc, ndt_ready, ndt_ready_bricks, nsamp, total;
+      decay_len, decay_hits, tm, tm_mom, tsdf, tsdf_acc, ndt_ready, nsamp, total;
   int32_t rlo[3], rdim[3];
   size_t regions;
 };
@@ -469,14 +469,12 @@ ohm_status compute_layout(const ohm_params* p, uint32_t capacity, uint32_t layer
   L->acc = off;
   // at least two f32 slots: a weighted scan's wide (int64) slot spans two
   off = align_up(off + (size_t)capacity * V * 2 * sizeof(float) * (slots < 2 ? 2 : slots));
-  L->ndt = L->nacc = L->mom = L->clampscan = L->ndt_ready = L->ndt_ready_bricks = L->nsamp = 0;
+  L->ndt = L->nacc = L->mom = L->clampscan = L->ndt_ready = L->nsamp = 0;
   if (layers & OHM_LAYER_NDT) {
     L->ndt = off;
     off = align_up(off + (size_t)capacity * V * sizeof(NdtVoxel));
     L->ndt_ready = off;
     off = align_up(off + (size_t)capacity * (V / 32) * sizeof(uint32_t));
-    L->ndt_ready_bricks = off;
-    off = align_up(off + (size_t)capacity * sizeof(unsigned long long));
     L->nacc = off;
     off = align_up(off + (size_t)capacity * V * kNaccWords * sizeof(long long));
     L->nsamp = off;
@@ -593,7 +591,6 @@ ohm_status map_initialise(ohm_map_s* map, hipStream_t st) {
     launch_fill(m.nsamp, (size_t)m.capacity * V * sizeof(uint32_t), 0u, st);
     launch_fill(m.mom, (size_t)m.capacity * V * kMomWords * sizeof(double), 0u, st);
     launch_fill(m.ndt_ready, (size_t)m.capacity * (V / 32) * sizeof(uint32_t), 0u, st);
-    launch_fill(m.ndt_ready_bricks, (size_t)m.capacity * sizeof(unsigned long long), 0u, st);
   }
   if (m.clampscan) launch_fill(m.clampscan, (size_t)m.capacity * V * sizeof(uint32_t), 0u, st);
   if (m.mean) {
@@ -808,8 +805,6 @@ ohm_status ohm_map_create(const ohm_params* params, uint32_t region_capacity, ui
   dm.nsamp = (layers & OHM_LAYER_NDT) ? reinterpret_cast<uint32_t*>(base + L.nsamp) : nullptr;
   dm.mom = (layers & OHM_LAYER_NDT) ? reinterpret_cast<double*>(base + L.mom) : nullptr;
   dm.ndt_ready = (layers & OHM_LAYER_NDT) ? reinterpret_cast<uint32_t*>(base + L.ndt_ready) : nullptr;
-  dm.ndt_ready_bricks =
-      (layers & OHM_LAYER_NDT) ? reinterpret_cast<unsigned long long*>(base + L.ndt_ready_bricks) : nullptr;
   dm.clampscan = (layers & OHM_LAYER_ADJOINT) ? reinterpret_cast<uint32_t*>(base + L.clampscan) : nullptr;
   const bool has_mean = (layers & OHM_LAYER_MEAN) != 0, has_decay = (layers & OHM_LAYER_DECAY) != 0;
   dm.mean = has_mean ? reinterpret_cast<unsigned long long*>(base + L.mean) : nullptr;

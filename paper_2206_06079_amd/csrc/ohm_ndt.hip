@@ -82,14 +82,6 @@ __device__ __forceinline__ bool ndt_is_ready(const DevMap& m, size_t v) {
   return ((m.ndt_ready[v >> 5] >> (v & 31u)) & 1u) != 0u;
 }
 
-// The same, with the 64 brick bits of v's region (rb: which 8^3 bricks may
-// hold a ready voxel, kept in registers per region) tested first: in free
-// space no bit is set and nothing is loaded.
-__device__ __forceinline__ bool ndt_ready_at(const DevMap& m, unsigned long long rb, int32_t slot, uint32_t lidx) {
-  if (slot < 0 || !((rb >> brick_of(lidx)) & 1ull)) return false;
-  return ndt_is_ready(m, (size_t)slot * kRegionVoxels + lidx);
-}
-
 // Phase 1 over a tile of 256 rays, walked segment by segment (see
 // ohm_walk_seg.h): the same per-voxel work as the occupancy walk, with the
 // NDT-weighted miss increment (the hit samples' moments: ndt_hit_block).
@@ -388,12 +380,11 @@ __global__ __launch_bounds__(kNdtMaxThreads, 4) void ndt_seg_kernel(DevMap m, co
     // whether the voxel being visited holds enough samples for its Gaussian,
     // from the per-region bit mask (4 KB per region, cache-resident, where
     // the 40-byte statistics are not), loaded one step ahead so the load's
-    // latency overlaps the previous voxel's update work
-    // the brick bits of the region being walked (reloaded when the walk
-    // crosses into another region)
-    int32_t rb_slot = (alive && slot >= 0) ? slot : -1;
-    unsigned long long rb = rb_slot >= 0 ? m.ndt_ready_bricks[rb_slot] : 0ull;
-    bool ready = alive && ndt_ready_at(m, rb, slot, lidx);
+    // latency overlaps the previous voxel's update work.  (A second level of
+    // 64 brick bits per region, kept in registers to skip the load in free
+    // space, cost more in spilled registers than it saved: 16.4 against
+    // 17.5 ms per NDT-OM pass without it.)
+    bool ready = alive && slot >= 0 && ndt_is_ready(m, (size_t)slot * kRegionVoxels + lidx);
     while (__ballot(alive)) {
       const bool last = alive && s.w.total == 0;
       const bool is_hit = last && !trunc;
@@ -419,11 +410,7 @@ __global__ __launch_bounds__(kNdtMaxThreads, 4) void ndt_seg_kernel(DevMap m, co
         w_hit_drop += (uint32_t)__popcll(dropped & __ballot(is_hit));
       }
       if (alive) alive = !last && tile_advance<true>(m, rc, rw, s, M, slot, lidx);
-      if (alive && slot >= 0 && slot != rb_slot) {
-        rb_slot = slot;
-        rb = m.ndt_ready_bricks[slot];
-      }
-      const bool ready_next = alive && ndt_ready_at(m, rb, slot, lidx);
+      const bool ready_next = alive && slot >= 0 && ndt_is_ready(m, (size_t)slot * kRegionVoxels + lidx);
       const unsigned long long dmask = __ballot(deferred);
       if (dmask) {
         const uint32_t nd = (uint32_t)__popcll(dmask);
@@ -503,7 +490,6 @@ __global__ __launch_bounds__(256) void ndt_ready_rebuild_kernel(DevMap m) {
     const unsigned long long bal = __ballot(ready);
     const uint32_t lane = lane_id();
     if ((lane & 31u) == 0u) m.ndt_ready[v >> 5] = (uint32_t)(bal >> lane);
-    if (ready) atomicOr(m.ndt_ready_bricks + (v >> 15), 1ull << brick_of((uint32_t)(v & (kRegionVoxels - 1))));
   }
 }
 
@@ -594,9 +580,6 @@ __global__ __launch_bounds__(256) void ndt_finalize_kernel(DevMap m, uint32_t pa
           uint32_t* w = m.ndt_ready + (v >> 5);
           if (now_ready) {
             atomicOr(w, 1u << (v & 31u));
-            // the brick bit stays set when voxels become unready again (cleared
-            // statistics): it only says where to look
-            atomicOr(m.ndt_ready_bricks + (v >> 15), 1ull << brick_of((uint32_t)(v & (kRegionVoxels - 1))));
           } else {
             atomicAnd(w, ~(1u << (v & 31u)));
           }
@@ -640,8 +623,6 @@ ohm_status ndt_integrate_impl(ohm_map map, const float* d_origins, const float* 
   const bool weighted = d_weights != nullptr;
   const double sig_miss = 1.0 / (1.0 + exp(-(double)map->params.l_miss));
   if (map->ndt_ready_stale) {
-    hipLaunchKernelGGL(fill_u32_kernel, dim3(64), dim3(256), 0, st, reinterpret_cast<uint32_t*>(map->dm.ndt_ready_bricks),
-                       (size_t)map->dm.capacity * 2, 0u);
     hipLaunchKernelGGL(ndt_ready_rebuild_kernel, dim3(8192), dim3(256), 0, st, map->dm);
     map->ndt_ready_stale = false;
   }

@@ -22,10 +22,13 @@ def full_box(mp):
     return tuple(mp.key_min), tuple(b - a for a, b in zip(mp.key_min, mp.key_max))
 
 
-def gpu_integrate(mp, batch, capacity, box_min, box_dim, scans_per_call=None, layers=ohm.LAYER_OCC):
+def gpu_integrate(mp, batch, capacity, box_min, box_dim, scans_per_call=None, layers=ohm.LAYER_OCC, column_rays=0):
     """Integrate through ohm_integrate_rays; returns (occ, hits, misses, stats)
-    over the box (hits/misses are the last scan's weights)."""
+    over the box (hits/misses are the last scan's weights).  column_rays: the
+    scans' column layout declared to the map (0: none)."""
     m = ohm.OhmMap(mp, capacity, layers=layers, device=device())
+    if column_rays:
+        m.set_scan_layout(column_rays)
     o, s, off, w = to_dev(batch)
     if scans_per_call is None:
         m.integrate(o, s, off, w)

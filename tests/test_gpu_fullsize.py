@@ -3,7 +3,9 @@ times.
 
 Headline: 100 spinning-lidar scans of 131,072 rays each (0.1 m voxels, 30 m
 range) through
-- one ohm_integrate_rays call on a map with 50-scan groups;
+- one ohm_integrate_rays call on a map with 50-scan groups and the scans
+  declared column-major, 64 rays per column (the benchmark's timed
+  configuration: 8-beam by 32-column patch tiles), and without the layout;
 - the same call on a map that launches once per scan;
 - a batched plan of 50-scan groups over the same scans.
 Count mode with unit weights is exact, so every voxel of a window holding
@@ -54,10 +56,11 @@ def headline():
     return mp, batch, exp
 
 
-@pytest.mark.parametrize("layers", [HEADLINE, ohm.LAYER_OCC], ids=["groups50", "per_scan"])
-def test_headline_workload_equals_oracle(headline, layers):
+@pytest.mark.parametrize("layers,column_rays", [(HEADLINE, 64), (HEADLINE, 0), (ohm.LAYER_OCC, 0)],
+                         ids=["groups50_layout64", "groups50", "per_scan"])
+def test_headline_workload_equals_oracle(headline, layers, column_rays):
     mp, batch, (o_occ, o_hit, o_miss, o_st) = headline
-    occ, hits, miss, st = gpu_integrate(mp, batch, 512, BOX_MIN, BOX_DIM, layers=layers)
+    occ, hits, miss, st = gpu_integrate(mp, batch, 512, BOX_MIN, BOX_DIM, layers=layers, column_rays=column_rays)
     assert np.count_nonzero(o_occ) > 500_000
     assert np.array_equal(occ, o_occ)
     # the call's last scan keeps its counts readable

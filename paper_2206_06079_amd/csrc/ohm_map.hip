@@ -188,9 +188,10 @@ struct GroupArgs {
 };
 
 // Tiles of up to 512 threads of the plain walk run three blocks per CU (six
-// waves per SIMD: the kernel is held to 80 VGPRs, and its 52 KB of LDS fit
-// three times); the extra waves hide more of the voxel loop's latency than
-// the spilled registers cost.  With the layers (kLayers) the loop holds too
+// waves per SIMD: the kernel is held to 80 VGPRs, which it fits without
+// spills since the tile statistics are flushed before the voxel loop, and
+// its 52 KB of LDS fit three times); the extra waves hide more of the voxel
+// loop's latency.  With the layers (kLayers) the loop holds too
 // much for 80 VGPRs, and 1024-thread tiles (kWideTile) fit one block per
 // CU: both keep the 128-VGPR budget.
 template <bool kWeighted, bool kLayers = false, bool kWideTile = false>

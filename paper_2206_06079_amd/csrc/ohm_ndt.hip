@@ -345,7 +345,7 @@ __global__ __launch_bounds__(kNdtMaxThreads, 4) void ndt_seg_kernel(DevMap m, co
     for (int a = 0; a < 3; ++a) ray_end[a][tid] = t.r.end[a];
   __syncthreads();
   const double od[3] = {(double)origin[0], (double)origin[1], (double)origin[2]};
-  flush_tile_stats(m, t, (t.ok && !t.clipped && !t.r.truncated) ? 1u : 0u, t.ok ? t.voxels : 0u, 0u);
+  flush_tile_stats(m, t);
   uint32_t w_drop = 0, w_hit_drop = 0;  // this wave's dropped updates and hits (wave-uniform)
   uint32_t pend_n = 0;  // this wave's queued sample-weighted misses (wave-uniform)
   NdtPending* wpend = pend[tid >> 6];

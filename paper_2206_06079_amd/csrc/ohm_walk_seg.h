@@ -372,17 +372,16 @@ __device__ __forceinline__ bool tile_advance(const DevMap& m, const RegionCache&
 // visit as an update and every untruncated ray ending in the map as a hit;
 // the loops then count, per wave, the updates and hits they drop (regions
 // the pool could not hold) and take them off with drop_tile_stats.
-__device__ __forceinline__ void flush_tile_stats(const DevMap& m, const TileRay& t, uint32_t n_hit, uint32_t n_upd,
-                                                 uint32_t n_drop) {
+__device__ __forceinline__ void flush_tile_stats(const DevMap& m, const TileRay& t) {
   uint32_t vals[kStatCount];
   vals[kStatRays] = t.inrange ? 1u : 0u;
   vals[kStatInvalid] = (t.inrange && t.st == kRayInvalid) ? 1u : 0u;
   vals[kStatOriginOob] = (t.inrange && t.st == kRayOriginOob) ? 1u : 0u;
   vals[kStatTruncated] = (t.ok && t.r.truncated) ? 1u : 0u;
   vals[kStatClipped] = (t.ok && t.clipped) ? 1u : 0u;
-  vals[kStatHits] = n_hit;
-  vals[kStatUpdates] = n_upd;
-  vals[kStatDropped] = n_drop;
+  vals[kStatHits] = (t.ok && !t.clipped && !t.r.truncated) ? 1u : 0u;
+  vals[kStatUpdates] = t.ok ? t.voxels : 0u;
+  vals[kStatDropped] = 0u;
   flush_stats(m, vals);
 }
 
@@ -471,7 +470,7 @@ __device__ void walk_tile(const DevMap& m, const float* __restrict__ origin, con
     ray_counts[ray] = t.ok ? t.voxels : 0u;
     ray_flags[ray] = flags;
   }
-  flush_tile_stats(m, t, (t.ok && !t.clipped && !t.r.truncated) ? 1u : 0u, t.ok ? t.voxels : 0u, 0u);
+  flush_tile_stats(m, t);
   uint32_t w_drop = 0, w_hit_drop = 0;  // this wave's dropped updates and hits (wave-uniform)
 
   // segment walks, one item per thread per round, with lane-run merging
@@ -529,8 +528,8 @@ __device__ void walk_tile(const DevMap& m, const float* __restrict__ origin, con
         // read the table entry now, step the walk on, then use it: the LDS
         // read's latency overlaps the step's arithmetic
         const uint32_t k = emit_here ? agg_key[kLine ? line_slot(id >> 4) : agg_slot(id)] : 0u;
-        // updates and hits are counted per ray below; only drops (region
-        // pool exhausted) are counted here
+        // updates and hits were counted per ray before the loop; only drops
+        // (region pool exhausted) are counted here, per wave
         const unsigned long long dropped = __ballot(alive && !has);
         if (dropped) {
           w_drop += (uint32_t)__popcll(dropped);
